@@ -1,0 +1,280 @@
+"""FP64 oracle of the Tamm-Dancoff BSE hot path: H, projection, eigh, spectrum.
+
+Paper passages followed (REVTeX source, equations by label):
+  * Eq. (BSE-eigval): H = (e_ku - e_ko) delta + vbar-term - W-term, Hermitian in
+    the Tamm-Dancoff approximation (Sec. II, last paragraph); spin factor 2 in
+    front of vbar for a non-magnetic system without spin-orbit coupling.
+  * Eq. (w_interaction2): each interaction element is a vector-matrix-vector
+    product over the mixed-basis index with prefactor 1/N_k.
+  * Eq. (projection), Sec. III.C.4: P_mu = d_mu/|S| sum_s chi_mu(s)* Gamma(s),
+    applied to unit vectors orbit by orbit and orthonormalised by SVD; U_mu
+    collects the vectors, H_mu = U_mu^dag H U_mu (Eq. (transformationU)).
+  * Eqs. (macro_diel), (reducible_polar), (oscillatorA): eps2(w) =
+    (8 pi / N_k) sum_l |B_l|^2 [L(w - W_l) + L(w + W_l)], L(x) = eta/(x^2+eta^2),
+    with the spin factor 2 and V_uc = 1.
+
+Index layout: a = (k nv + v) nc + c.  Block layout of H_mu: orbits in id order,
+then the orbit's basis vectors, then (v, c) with c fastest.
+"""
+import numpy as np
+
+import synth
+from . import groups, orbits
+
+
+# ----------------------------------------------------------------------------
+# problem assembly: the oracle's own tables feed the shared input generator
+# ----------------------------------------------------------------------------
+def make_problem(cfg, vector_dipole=True, zero_interaction=False):
+    """Tables (oracle's own) plus seeded inputs for one synthetic system."""
+    lattice = cfg.get("lattice", "cubic")
+    g = groups.group("Oh" if lattice == "cubic" else "D6h")
+    grid = tuple(cfg["grid"])
+    T = orbits.tables(grid, g["kmat"])
+    nv, nc, nmb, seed = cfg["nv"], cfg["nc"], cfg["nmb"], cfg["seed"]
+    kfrac = orbits.kgrid(grid) / np.asarray(grid, dtype=np.float64)
+    ev, ec = synth.band_energies(seed, lattice, grid, kfrac, T["krep_of_k"], nv, nc)
+    vd = synth.coulomb_diag(nmb)
+    mx = synth.exchange_vectors(seed, T["korb_reps"], nv, nc, nmb)
+    mv = synth.pair_vectors(seed, "mv", T["class_rep"], T["class_selfswap"], nv, nmb)
+    mc = synth.pair_vectors(seed, "mc", T["class_rep"], T["class_selfswap"], nc, nmb)
+    w = synth.screened_w(seed, T["korb_reps"], nmb)
+    B = synth.dipoles(seed, T["kperm"], g["rcart"], T["krep_of_k"], nv, nc,
+                      vector=vector_dipole).reshape(-1)
+    if zero_interaction:
+        vd = np.zeros_like(vd)
+        w = np.zeros_like(w)
+    return dict(cfg=cfg, group=g, T=T, nk=T["nk"], nv=nv, nc=nc, nmb=nmb,
+                N=T["nk"] * nv * nc, ev=ev, ec=ec, vdiag=vd, mx=mx, mv=mv, mc=mc,
+                w=w, B=B)
+
+
+def pair_block(P, name, k, kq):
+    """M_name(k, k') for arrays k, k' (gathered from the class storage)."""
+    T = P["T"]
+    nk = P["nk"]
+    p = k * nk + kq
+    M = P[name][T["pidx"][p]]
+    cj = T["pconj"][p].astype(bool)
+    if cj.any():
+        M = M.copy()
+        M[cj] = np.conj(np.swapaxes(M[cj], 1, 2))
+    return M
+
+
+# ----------------------------------------------------------------------------
+# H, Eq. (BSE-eigval) with Eq. (w_interaction2)
+# ----------------------------------------------------------------------------
+def diagonal(P):
+    """(e_c(k) - e_v(k)) on the diagonal, a = (k nv + v) nc + c."""
+    return (P["ec"][:, None, :] - P["ev"][:, :, None]).reshape(-1)
+
+
+def exchange(P):
+    """2/N_k sum_I M_x[k,v,c,I] v_I conj(M_x[k',v',c',I])  (N x N)."""
+    T = P["T"]
+    Mx = P["mx"][T["korb"]].reshape(P["N"], P["nmb"])
+    return (2.0 / P["nk"]) * (Mx * P["vdiag"][None, :]) @ Mx.conj().T
+
+
+def direct(P):
+    """1/N_k sum_IJ conj(M_c[k,k'][c,c',I]) W_IJ(k-k') M_v[k,k'][v,v',J]  (N x N).
+
+    Loop over q outermost (Sec. III.C.2), all k for each q.
+    """
+    nk, nv, nc = P["nk"], P["nv"], P["nc"]
+    T = P["T"]
+    D = np.zeros((nk, nv, nc, nk, nv, nc), dtype=np.complex128)
+    qidx = T["qidx"].reshape(nk, nk)
+    kk = np.arange(nk)
+    for q in range(nk):
+        kq = np.array([int(np.nonzero(qidx[k] == q)[0][0]) for k in kk])  # k' = k - q
+        W = P["w"][T["qorb"][q]]
+        Mv = pair_block(P, "mv", kk, kq)       # [nk, nv, nv, nmb]
+        Mc = pair_block(P, "mc", kk, kq)       # [nk, nc, nc, nmb]
+        Tq = Mv @ W.T                           # sum_J W_IJ Mv[..., J]
+        Dq = np.einsum("kcdi,kvwi->kvcwd", Mc.conj(), Tq)
+        D[kk, :, :, kq, :, :] = Dq
+    return D.reshape(P["N"], P["N"]) / nk
+
+
+def hamiltonian(P):
+    """Full unsymmetrised H (complex128, N x N)."""
+    H = exchange(P) - direct(P)
+    H[np.diag_indices_from(H)] += diagonal(P)
+    return H
+
+
+def hamiltonian_element(P, a, b):
+    """H[a, b] straight from the definition, one element at a time."""
+    nv, nc, nk = P["nv"], P["nc"], P["nk"]
+    T = P["T"]
+    k, v, c = a // (nv * nc), (a // nc) % nv, a % nc
+    k2, v2, c2 = b // (nv * nc), (b // nc) % nv, b % nc
+    val = 0j
+    if a == b:
+        val += P["ec"][k, c] - P["ev"][k, v]
+    mx1 = P["mx"][T["korb"][k], v, c]
+    mx2 = P["mx"][T["korb"][k2], v2, c2]
+    val += (2.0 / nk) * np.sum(mx1 * P["vdiag"] * np.conj(mx2))
+    Mv = pair_block(P, "mv", np.array([k]), np.array([k2]))[0]
+    Mc = pair_block(P, "mc", np.array([k]), np.array([k2]))[0]
+    W = P["w"][T["qorb"][T["qidx"][k * nk + k2]]]
+    val -= (1.0 / nk) * (np.conj(Mc[c, c2]) @ W @ Mv[v, v2])
+    return val
+
+
+# ----------------------------------------------------------------------------
+# symmetry-adapted basis, Eq. (projection) and Eq. (transformationU)
+# ----------------------------------------------------------------------------
+def orbit_members(P):
+    T = P["T"]
+    return [np.nonzero(T["korb"] == o)[0] for o in range(T["nkorb"])]
+
+
+def orbit_projector(P, chi, d, members):
+    """P_mu restricted to the k orbit (the band indices are spectators)."""
+    kp = P["T"]["kperm"]
+    pos = {int(k): i for i, k in enumerate(members)}
+    m = len(members)
+    Pm = np.zeros((m, m))
+    for s in range(kp.shape[0]):
+        for i, k in enumerate(members):
+            Pm[pos[int(kp[s, k])], i] += chi[s]
+    return Pm * (d / kp.shape[0])
+
+
+def isotypic_basis(P, irrep_name):
+    """Per-orbit orthonormal bases of the irrep's isotypic subspace.
+
+    Returns dict(n, orb_off[nkorb], orb_dim[nkorb], basis=list of (members, U_O)).
+    orb_dim[O] = d_mu m_mu(O), the rank of P_mu on the orbit.
+    """
+    d, chi = groups.irrep(P["group"], irrep_name)
+    nb = P["nv"] * P["nc"]
+    mem = orbit_members(P)
+    offs, dims, basis = [], [], []
+    off = 0
+    for o, members in enumerate(mem):
+        Pm = orbit_projector(P, chi, d, members)
+        u, s, _ = np.linalg.svd(Pm)
+        r = int(np.sum(s > 0.5))
+        offs.append(off)
+        dims.append(r)
+        basis.append((members, u[:, :r]))
+        off += r * nb
+    return dict(irrep=irrep_name, d=d, n=off, orb_off=np.array(offs, dtype=np.int64),
+                orb_dim=np.array(dims, dtype=np.int64), basis=basis)
+
+
+def basis_matrix(P, blk):
+    """Dense U_mu (N x n_mu) with the canonical block layout."""
+    nv, nc = P["nv"], P["nc"]
+    nb = nv * nc
+    U = np.zeros((P["N"], blk["n"]))
+    for o, (members, Uo) in enumerate(blk["basis"]):
+        for j in range(Uo.shape[1]):
+            for i, k in enumerate(members):
+                U[k * nb:(k + 1) * nb, blk["orb_off"][o] + j * nb + np.arange(nb)] = \
+                    np.eye(nb) * Uo[i, j]
+    return U
+
+
+def full_projector(P, irrep_name):
+    """Dense P_mu on the whole product space (small systems only)."""
+    d, chi = groups.irrep(P["group"], irrep_name)
+    kp = P["T"]["kperm"]
+    nb = P["nv"] * P["nc"]
+    N = P["N"]
+    Pm = np.zeros((N, N))
+    for s in range(kp.shape[0]):
+        for k in range(P["nk"]):
+            Pm[kp[s, k] * nb + np.arange(nb), k * nb + np.arange(nb)] += chi[s]
+    return Pm * (d / kp.shape[0])
+
+
+def gamma_perm(P, s):
+    """Gamma(s) as an index map: e_(k,v,c) -> e_(s k, v, c)."""
+    nb = P["nv"] * P["nc"]
+    kp = P["T"]["kperm"][s]
+    return (kp[:, None] * nb + np.arange(nb)[None, :]).reshape(-1)
+
+
+def block_dims_closed_form(P):
+    """dim_mu = nv nc d_mu (1/|G|) sum_s chi_mu(s) fix(s) for every irrep."""
+    kp = P["T"]["kperm"]
+    fix = (kp == np.arange(P["nk"])[None, :]).sum(axis=1)
+    out = {}
+    for nm, d, chi in P["group"]["irreps"]:
+        val = d * float(chi @ fix) / kp.shape[0]
+        out[nm] = int(round(val)) * P["nv"] * P["nc"]
+    return out
+
+
+def project(H, U):
+    return U.T @ H @ U
+
+
+def dipole_active(P, tol=1e-12):
+    """Irreps whose projected dipole carries weight (Sec. III.D.1)."""
+    nb2 = np.sum(np.abs(P["B"]) ** 2)
+    act = []
+    for nm, d, chi in P["group"]["irreps"]:
+        blk = isotypic_basis(P, nm)
+        if blk["n"] == 0:
+            continue
+        Bm = basis_matrix(P, blk).T @ P["B"]
+        if np.sum(np.abs(Bm) ** 2) > tol * nb2:
+            act.append(nm)
+    return act
+
+
+# ----------------------------------------------------------------------------
+# eigenpairs, oscillator strengths and eps2
+# ----------------------------------------------------------------------------
+def eigh(H):
+    return np.linalg.eigh(H)
+
+
+def clusters(w, rel=1e-9):
+    """Group ascending eigenvalues whose gaps are below rel*max(1,|w|)."""
+    starts = [0]
+    for i in range(1, len(w)):
+        if w[i] - w[i - 1] > rel * max(1.0, abs(w[i])):
+            starts.append(i)
+    return starts + [len(w)]
+
+
+def oscillator_strengths(w, A, B):
+    """|B_l|^2 = |A_l^dag B|^2 summed within degenerate clusters.
+
+    Returns (cluster energies, cluster weights, cluster sizes).
+    """
+    b = np.abs(A.conj().T @ B) ** 2
+    st = clusters(w)
+    e = np.array([w[st[i]:st[i + 1]].mean() for i in range(len(st) - 1)])
+    s = np.array([b[st[i]:st[i + 1]].sum() for i in range(len(st) - 1)])
+    m = np.array([st[i + 1] - st[i] for i in range(len(st) - 1)])
+    return e, s, m
+
+
+def eps2(omega_l, weight_l, nk, eta, wgrid):
+    """(8 pi / N_k) sum_l |B_l|^2 [L(w - W_l) + L(w + W_l)]."""
+    x1 = wgrid[:, None] - omega_l[None, :]
+    x2 = wgrid[:, None] + omega_l[None, :]
+    L = eta / (x1 * x1 + eta * eta) + eta / (x2 * x2 + eta * eta)
+    return (8 * np.pi / nk) * (L @ weight_l)
+
+
+def solve_block(P, irrep_name, H=None, nlow=100):
+    """Oracle pipeline for one irrep block: H_mu, its spectrum, weights, eps2."""
+    if H is None:
+        H = hamiltonian(P)
+    blk = isotypic_basis(P, irrep_name)
+    U = basis_matrix(P, blk)
+    Hm = project(H, U)
+    Bm = U.T @ P["B"]
+    w, A = eigh(Hm)
+    e, s, m = oscillator_strengths(w, A, Bm)
+    return dict(blk=blk, Hmu=Hm, Bmu=Bm, omega=w, A=A, cl_e=e, cl_w=s, cl_m=m,
+                lowest=w[:nlow])

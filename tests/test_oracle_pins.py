@@ -1,0 +1,349 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage or the mathematical fact it checks.  None of these
+re-types an oracle formula and compares the oracle with itself: they use
+invariants (Hermiticity, commutation, projector algebra), closed forms
+(Burnside/Frobenius counts, non-interacting and k-independent limits,
+Lorentzian integrals), brute force (orbit closure by search) and the values the
+paper prints (table dimension ratios).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse, groups, orbits
+
+
+# --------------------------------------------------------------------------
+# groups: Eq. (LOT), the footnote sum |S| = sum d^2, vector irreps
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name,order", [("Oh", 48), ("D6h", 24)])
+def test_character_orthogonality(name, order):
+    g = groups.group(name)
+    assert len(g["kmat"]) == order
+    chis = np.array([c for _, _, c in g["irreps"]])
+    assert np.allclose(chis @ chis.T / order, np.eye(len(chis)), atol=1e-14)
+    assert sum(d * d for _, d, _ in g["irreps"]) == order
+    for _, d, chi in g["irreps"]:
+        assert chi[0] == d  # identity first
+
+
+@pytest.mark.parametrize("name", ["Oh", "D6h"])
+def test_group_closure_and_class_functions(name):
+    g = groups.group(name)
+    t = groups.multiplication_table(g["kmat"])  # raises KeyError if not closed
+    n = len(t)
+    inv = [int(np.where(t[a] == 0)[0][0]) for a in range(n)]
+    for _, _, chi in g["irreps"]:
+        for a in range(n):
+            for b in range(n):
+                assert chi[t[t[b, a], inv[b]]] == chi[a]
+    # the Cartesian matrices form the same group (homomorphism)
+    R = g["rcart"]
+    for a in range(n):
+        for b in range(n):
+            assert np.allclose(R[a] @ R[b], R[t[a, b]], atol=1e-12)
+
+
+def test_vector_irreps():
+    oh = groups.group("Oh")
+    d, chi = groups.irrep(oh, "T1u")
+    assert d == 3 and np.allclose(chi, [np.trace(R) for R in oh["rcart"]])
+    d6 = groups.group("D6h")
+    d, chi = groups.irrep(d6, "E1u")
+    assert d == 2 and np.allclose(chi, [np.trace(R[:2, :2]) for R in d6["rcart"]])
+    d, chi = groups.irrep(d6, "A2u")  # z vector
+    assert np.allclose(chi, [R[2, 2] for R in d6["rcart"]])
+
+
+# --------------------------------------------------------------------------
+# orbits: Burnside counts and brute-force closure
+# --------------------------------------------------------------------------
+def _bfs_orbits(points, act):
+    seen, orbs = set(), []
+    for p in points:
+        if p in seen:
+            continue
+        orb, stack = {p}, [p]
+        while stack:
+            x = stack.pop()
+            for y in act(x):
+                if y not in orb:
+                    orb.add(y)
+                    stack.append(y)
+        seen |= orb
+        orbs.append(min(orb))
+    return sorted(orbs)
+
+
+@pytest.mark.parametrize("grid,name", [((2, 2, 2), "Oh"), ((3, 3, 3), "Oh"), ((4, 4, 4), "Oh"),
+                                       ((6, 6, 1), "D6h"), ((5, 5, 1), "D6h")])
+def test_orbits_brute_force(grid, name):
+    g = groups.group(name)
+    T = orbits.tables(grid, g["kmat"])
+    kp = T["kperm"]
+    nk = T["nk"]
+    for row in kp:
+        assert sorted(row) == list(range(nk))
+    assert _bfs_orbits(range(nk), lambda k: [int(kp[s, k]) for s in range(len(kp))]) \
+        == list(T["korb_reps"])
+    pairs = _bfs_orbits(range(nk * nk), lambda p: [int(kp[s, p // nk] * nk + kp[s, p % nk])
+                                                   for s in range(len(kp))])
+    assert pairs == list(T["porb_reps"])
+    # Burnside: #orbits = mean number of fixed points
+    fix = (kp == np.arange(nk)[None, :]).sum(axis=1)
+    assert T["nkorb"] * len(kp) == fix.sum()
+    assert T["nporb"] * len(kp) == (fix.astype(np.int64) ** 2).sum()
+
+
+def test_orbit_counts_at_config_sizes():
+    oh = groups.group("Oh")
+    for n, nko, npo in [(4, 10, 220), (8, 35, 7140), (12, 84, 70300)]:
+        kp = orbits.kperm((n, n, n), oh["kmat"])
+        fix = (kp == np.arange(n ** 3)[None, :]).sum(axis=1)
+        assert fix.sum() // 48 == nko and (fix.astype(np.int64) ** 2).sum() // 48 == npo
+        if n <= 8:
+            T = orbits.tables((n, n, n), oh["kmat"])
+            assert (T["nkorb"], T["nporb"]) == (nko, npo)
+    # every op acts as a distinct permutation on these grids
+    kp = orbits.kperm((4, 4, 4), oh["kmat"])
+    assert len({r.tobytes() for r in kp}) == 48
+    kp2 = orbits.kperm((2, 2, 2), oh["kmat"])
+    assert len({r.tobytes() for r in kp2}) == 6  # non-faithful action at n = 2
+
+
+def test_swap_classes():
+    oh = groups.group("Oh")
+    T = orbits.tables((4, 4, 4), oh["kmat"])
+    sw = T["pswap_partner"]
+    assert np.all(sw[sw] == np.arange(T["nporb"]))
+    nk = T["nk"]
+    p = np.arange(nk * nk)
+    pt = (p % nk) * nk + p // nk
+    # (k,k') and (k',k) share the class; exactly one of them is conjugated unless self-swap
+    assert np.all(T["pidx"][p] == T["pidx"][pt])
+    ss = T["class_selfswap"][T["pidx"][p]]
+    assert np.all((T["pconj"][p] ^ T["pconj"][pt])[~ss] == 1)
+    assert np.all(T["pconj"][p][ss] == 0)
+
+
+# --------------------------------------------------------------------------
+# H: Hermiticity (TDA), symmetry, signs, limits
+# --------------------------------------------------------------------------
+def test_hermitian_and_commutes(cfg1_problem, cfg1_h):
+    H = cfg1_h
+    assert np.abs(H - H.conj().T).max() <= 1e-15 * np.abs(H).max() * 4
+    for s in range(48):
+        g = bse.gamma_perm(cfg1_problem, s)
+        assert np.abs(H[np.ix_(g, g)] - H).max() < 1e-12
+
+
+def test_element_formula_matches_dense(cfg1_problem, cfg1_h):
+    rng = np.random.default_rng(0)
+    N = cfg1_problem["N"]
+    for a, b in rng.integers(0, N, size=(40, 2)):
+        assert abs(bse.hamiltonian_element(cfg1_problem, a, b) - cfg1_h[a, b]) < 1e-12
+
+
+def _small(grid=(2, 2, 2), nv=2, nc=2, nmb=8, seed=11, **kw):
+    c = dict(lattice="cubic", grid=grid, nv=nv, nc=nc, nmb=nmb, seed=seed, name="small")
+    c.update(kw)
+    return c
+
+
+def test_non_interacting_limit():
+    """W = v = 0: eigenvalues are E_c - E_v, eigenvectors unit vectors (Eq. BSE-eigval)."""
+    P = bse.make_problem(_small(grid=(3, 3, 3)), zero_interaction=True)
+    H = bse.hamiltonian(P)
+    de = bse.diagonal(P)
+    assert np.allclose(np.linalg.eigvalsh(H), np.sort(de), atol=1e-14)
+    # block spectrum: each orbit value appears d_mu m_mu(O) times per band pair
+    r = bse.solve_block(P, "T1u", H)
+    blk = r["blk"]
+    nb = P["nv"] * P["nc"]
+    expect = []
+    for o, (members, Uo) in enumerate(blk["basis"]):
+        k = members[0]
+        expect += list(de[k * nb:(k + 1) * nb]) * Uo.shape[1]
+    assert np.allclose(r["omega"], np.sort(expect), atol=1e-14)
+    # eps2 closed form: Lorentzians at E_c - E_v with weights |B_a|^2
+    wg = np.linspace(-1, 6, 500)
+    e2 = bse.eps2(r["cl_e"], r["cl_w"], P["nk"], 0.05, wg)
+    x1 = wg[:, None] - de[None, :]
+    x2 = wg[:, None] + de[None, :]
+    ref = (8 * np.pi / P["nk"]) * ((0.05 / (x1 ** 2 + 0.05 ** 2) + 0.05 / (x2 ** 2 + 0.05 ** 2))
+                                   @ np.abs(P["B"]) ** 2)
+    assert np.abs(e2 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_k_independent_inputs_closed_form():
+    """Constant M, W, E over the grid: H = I x dE + (1/Nk) J x (2X - D).
+
+    The uniform k combination carries eig(dE + 2X - D); the other Nk - 1
+    combinations carry dE.  Pins the 1/N_k of Eq. (w_interaction2), the spin
+    factor 2 on the exchange and the minus sign of the direct term.
+    """
+    P = bse.make_problem(_small(grid=(3, 3, 3), nv=2, nc=3, nmb=6))
+    nv, nc, nmb, nk = P["nv"], P["nc"], P["nmb"], P["nk"]
+    rng = np.random.default_rng(5)
+    cplx = lambda *s: rng.normal(size=s) + 1j * rng.normal(size=s)
+    mv = cplx(nv, nv, nmb); mv = mv + np.conj(np.swapaxes(mv, 0, 1))
+    mc = cplx(nc, nc, nmb); mc = mc + np.conj(np.swapaxes(mc, 0, 1))
+    mx = cplx(nv, nc, nmb)
+    G = rng.normal(size=(nmb, nmb)); W = G @ G.T
+    P["mv"][:] = mv; P["mc"][:] = mc; P["mx"][:] = mx; P["w"][:] = W
+    ev = rng.normal(size=nv) - 1; ec = rng.normal(size=nc) + 1
+    P["ev"][:] = ev; P["ec"][:] = ec
+    H = bse.hamiltonian(P)
+    # explicit small problem
+    dE = (ec[None, :] - ev[:, None]).reshape(-1)
+    X = np.einsum("vci,i,wdi->vcwd", mx, P["vdiag"], mx.conj()).reshape(nv * nc, nv * nc)
+    D = np.einsum("cdi,ij,vwj->vcwd", mc.conj(), W, mv).reshape(nv * nc, nv * nc)
+    h1 = np.diag(dE) + 2 * X - D
+    expect = np.sort(np.concatenate([np.linalg.eigvalsh(h1), np.tile(dE, nk - 1)]))
+    assert np.allclose(np.linalg.eigvalsh(H), expect, atol=1e-10)
+
+
+def test_signs_binding_and_repulsion():
+    """Direct term alone binds (lowest level below the gap), exchange alone repels."""
+    cfg = _small(grid=(3, 3, 3), nmb=16)
+    P = bse.make_problem(cfg)
+    gap = bse.diagonal(P).min()
+    Pd = dict(P); Pd["vdiag"] = np.zeros_like(P["vdiag"])
+    assert np.linalg.eigvalsh(bse.hamiltonian(Pd))[0] < gap - 1e-3
+    Px = dict(P); Px["w"] = np.zeros_like(P["w"])
+    assert np.linalg.eigvalsh(bse.hamiltonian(Px))[0] >= gap - 1e-12
+
+
+def test_nk1_matches_lapack():
+    """N_k = 1: H is the N_v N_c matrix dE + 2X - D; spectrum by plain LAPACK."""
+    P = bse.make_problem(_small(grid=(1, 1, 1), nv=3, nc=2, nmb=5))
+    H = bse.hamiltonian(P)
+    assert H.shape == (6, 6)
+    assert np.allclose(np.linalg.eigvalsh(H), np.linalg.eigvalsh(0.5 * (H + H.conj().T)))
+    # the Gamma point is its own orbit, its pair data is band-Hermitian
+    assert P["T"]["class_selfswap"].all()
+
+
+# --------------------------------------------------------------------------
+# projection: Eq. (projection), great orthogonality (Eq. Hblock), exactness
+# --------------------------------------------------------------------------
+def test_projector_algebra(cfg1_problem):
+    P = cfg1_problem
+    Ps = {nm: bse.full_projector(P, nm) for nm, _, _ in P["group"]["irreps"]}
+    tot = np.zeros_like(next(iter(Ps.values())))
+    for a, Pa in Ps.items():
+        assert np.abs(Pa @ Pa - Pa).max() < 1e-13
+        assert np.abs(Pa - Pa.T).max() < 1e-13
+        for b, Pb in Ps.items():
+            if a < b:
+                assert np.abs(Pa @ Pb).max() < 1e-13
+        tot += Pa
+    assert np.abs(tot - np.eye(len(tot))).max() < 1e-13
+
+
+def test_block_dims_closed_form(cfg1_problem):
+    """SVD ranks equal the Frobenius multiplicities nv nc d (1/|G|) sum chi fix."""
+    P = cfg1_problem
+    cf = bse.block_dims_closed_form(P)
+    for nm, _, _ in P["group"]["irreps"]:
+        assert bse.isotypic_basis(P, nm)["n"] == cf[nm]
+    assert sum(cf.values()) == P["N"]
+    # the paper's dipole-active block for the cubic case (T1u)
+    assert cf["T1u"] == 162 and cf["A1g"] == 90
+
+
+def test_basis_orthonormal_and_in_range(cfg1_problem):
+    P = cfg1_problem
+    for nm in ("T1u", "A1g", "Eg"):
+        blk = bse.isotypic_basis(P, nm)
+        U = bse.basis_matrix(P, blk)
+        Pm = bse.full_projector(P, nm)
+        assert np.abs(U.T @ U - np.eye(blk["n"])).max() < 1e-13
+        assert np.abs(Pm @ U - U).max() < 1e-13
+        assert np.all(blk["orb_dim"] <= 9)  # |S| d_max^2 bound per orbit and band pair
+
+
+def test_off_block_zero_and_union_of_spectra(cfg1_problem, cfg1_h):
+    P, H = cfg1_problem, cfg1_h
+    Us, spec = {}, []
+    for nm, d, _ in P["group"]["irreps"]:
+        blk = bse.isotypic_basis(P, nm)
+        if blk["n"]:
+            Us[nm] = (d, bse.basis_matrix(P, blk))
+    names = list(Us)
+    for i, a in enumerate(names):
+        for b in names[i + 1:]:
+            assert np.abs(Us[a][1].T @ H @ Us[b][1]).max() < 1e-12 * np.abs(H).max()
+    for nm, (d, U) in Us.items():
+        w = np.linalg.eigvalsh(U.T @ H @ U)
+        spec.append(w)
+        # d_mu-fold degeneracy inside the block (multiple of the identity)
+        st = bse.clusters(w, rel=1e-9)
+        assert all((st[i + 1] - st[i]) % d == 0 for i in range(len(st) - 1))
+    full = np.linalg.eigvalsh(H)
+    assert np.abs(np.sort(np.concatenate(spec)) - full).max() < 1e-11
+
+
+def test_exchange_lives_in_a1g(cfg1_problem):
+    """Orbit-invariant M_x: the exchange has range in A1g x bands."""
+    P = cfg1_problem
+    X = bse.exchange(P)
+    for nm in ("T1u", "Eg", "T2u"):
+        U = bse.basis_matrix(P, bse.isotypic_basis(P, nm))
+        assert np.abs(U.T @ X @ U).max() < 1e-12 * np.abs(X).max()
+
+
+@pytest.mark.parametrize("vector,active", [(True, "T1u"), (False, "A1g")])
+def test_sum_rule_and_single_active_block(vector, active):
+    """Sum of oscillator strengths equals |B|^2, all of it in one block (Sec. III.D.1)."""
+    P = bse.make_problem(synth.config("cfg1"), vector_dipole=vector)
+    assert bse.dipole_active(P) == [active]
+    r = bse.solve_block(P, active)
+    nb2 = np.sum(np.abs(P["B"]) ** 2)
+    assert abs(r["cl_w"].sum() - nb2) < 1e-10 * nb2
+    assert abs(np.sum(np.abs(r["Bmu"]) ** 2) - nb2) < 1e-10 * nb2
+
+
+def test_eps2_lorentzian_integral(cfg1_problem):
+    """int eps2 over [a, b] equals (8 pi/Nk) sum w [atan terms] (Lorentzian area pi)."""
+    P = cfg1_problem
+    om = np.array([-1.0, 0.5, 2.0])
+    wt = np.array([0.3, 1.0, 0.7])
+    eta = 0.05
+    a, b = -3.0, 4.0
+    wg = np.linspace(a, b, 200001)
+    e2 = bse.eps2(om, wt, P["nk"], eta, wg)
+    num = np.trapezoid(e2, wg)
+    at = lambda x: np.arctan(x / eta)
+    ana = (8 * np.pi / P["nk"]) * np.sum(wt * (at(b - om) - at(a - om) + at(b + om) - at(a + om)))
+    assert abs(num - ana) < 1e-6 * ana
+
+
+def test_paper_table_ratios():
+    """Full/block dimension ratios printed in the paper's Si and MoS2 tables tend to
+    |S|/d_mu^2 (48/9 for T1u of Oh, 24/4 for E1u of D6h): the blocks are whole
+    isotypic components.  Sc-grid closed-form ratios approach the same limit."""
+    import json, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_block_dims.json")) as f:
+        gold = json.load(f)
+    si = gold["Si"]["rows"]
+    r_last = si[-1][1] / si[-1][2]
+    assert abs(r_last - 48 / 9) < 0.05
+    ratios = [r[1] / r[2] for r in si]
+    assert ratios[-1] > ratios[0]
+    mos2 = gold["MoS2"]["rows"]
+    assert abs(mos2[-1][1] / mos2[-1][2] - 6.0) < 0.05
+    # closed-form full/T1u ratio on simple-cubic grids increases toward 48/9
+    oh = groups.group("Oh")
+    _, chi = groups.irrep(oh, "T1u")
+    prev = 0
+    for n, expect in ((6, 3.60), (8, 3.79), (12, 4.11), (16, 4.33)):
+        kp = orbits.kperm((n, n, n), oh["kmat"])
+        fix = (kp == np.arange(n ** 3)[None, :]).sum(axis=1)
+        ratio = n ** 3 / (3 * float(chi @ fix) / 48)
+        assert prev < ratio < 48 / 9 and abs(ratio - expect) < 0.005
+        prev = ratio
