@@ -1,0 +1,223 @@
+/*
+ * bse.h -- C ABI of the symmetry-blocked Bethe-Salpeter hot path for MI355X.
+ *
+ * The library builds the Tamm-Dancoff electron-hole Hamiltonian
+ *     H[(k v c),(k' v' c')] = delta (E_c(k) - E_v(k))
+ *                           + (2/N_k) sum_I Mx[k,v,c,I] v_I conj(Mx[k',v',c',I])
+ *                           - (1/N_k) sum_IJ conj(Mc[k,k'][c,c',I]) W_IJ(k-k') Mv[k,k'][v,v',J]
+ * (paper: Eq. (BSE-eigval) with the vector-matrix-vector form of Eq.
+ * (w_interaction2); the spin factor 2 on the bare exchange for a non-magnetic
+ * system is stated at the end of Sec. II), projects it onto symmetry-adapted
+ * irrep blocks H_mu = U_mu^T H U_mu (Eq. (projection), Eq. (transformationU),
+ * Sec. III.C.4), diagonalises the dipole-active block (Sec. III.D.1) and forms
+ * eps2(w) (Eqs. (macro_diel), (reducible_polar), (oscillatorA)).
+ *
+ * Conventions shared by every entry point
+ *   - k linear index  lin(k) = (k1 n2 + k2) n3 + k3; product index
+ *     a = (k nv + v) nc + c; pair index p = k nk + k'; q = k - k' (mod grid).
+ *   - Complex numbers are interleaved (re, im); all arrays are row-major.
+ *   - Pointers named h_* are host memory; every other array pointer is device
+ *     memory (hipMalloc / a torch CUDA tensor).  The caller owns all memory;
+ *     the library never frees or keeps a caller pointer after a call returns.
+ *   - Device work is enqueued on `stream` (a hipStream_t, NULL = default
+ *     stream) and is complete when the stream is synchronised.
+ *   - Every entry point validates shapes and ranges before launching anything
+ *     and returns BSE_ESHAPE / BSE_EINVAL without touching outputs.  A HIP error
+ *     maps to BSE_EDEVICE.  bse_last_error() returns a thread-local message for
+ *     the last non-OK status.  No C++ exception crosses this interface.
+ *   - Calls on one stream are serialised by the stream; concurrent calls on
+ *     different streams are safe when their output buffers do not overlap.
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *bse_stream; /* hipStream_t */
+
+enum {
+  BSE_OK = 0,
+  BSE_EINVAL = -1,       /* bad argument value (NULL pointer, unknown enum)  */
+  BSE_ESHAPE = -2,       /* inconsistent or unsupported sizes                */
+  BSE_EWORKSPACE = -3,   /* workspace smaller than the *_ws query requires   */
+  BSE_EDEVICE = -4,      /* a HIP runtime call failed                        */
+  BSE_ENOCONV = -5,      /* an iteration did not converge                    */
+  BSE_EUNSUPPORTED = -6  /* valid request this build does not implement      */
+};
+
+enum { /* arithmetic of the contractions */
+  BSE_FP64 = 0,   /* complex FP64 inputs, FP64 MFMA, FP64 H                   */
+  BSE_FP32 = 1,   /* complex FP32 inputs, FP32 MFMA, FP32 H                   */
+  BSE_BF16X3 = 2  /* FP32 inputs split hi+lo into BF16, three BF16 MFMA
+                     products (hi*hi + hi*lo + lo*hi) accumulated in FP32     */
+};
+
+enum { BSE_GROUP_OH = 0, BSE_GROUP_D6H = 1 };
+
+const char *bse_last_error(void);
+const char *bse_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Point groups (Sec. III.C.1, Eq. (sk); characters Sec. III.C.4, Eq. (LOT)).
+ * Oh: the 48 signed permutation matrices acting on cubic reduced k.
+ * D6h: 24 operations, reduced reciprocal basis b1 = (1, 1/sqrt3),
+ * b2 = (0, 2/sqrt3); two-fold axes C2' along a1, a2, a1+a2.
+ * ------------------------------------------------------------------------- */
+int32_t bse_group_order(int32_t group);                  /* 48, 24, or <0    */
+int32_t bse_group_nirreps(int32_t group);                /* 10, 12, or <0    */
+/* h_kmat[nops][3][3]: integer action on reduced k; h_rcart[nops][3][3]:
+ * Cartesian matrix (either may be NULL). */
+int32_t bse_group_ops(int32_t group, int32_t *h_kmat, double *h_rcart);
+/* name (NUL-terminated, <= 7 chars), dimension and characters chi[nops]. */
+int32_t bse_group_irrep(int32_t group, int32_t irrep, char *h_name8, int32_t *h_dim,
+                        double *h_chi);
+
+/* ---------------------------------------------------------------------------
+ * Integer tables (host).  Orbits under the group action on the grid
+ * (Sec. III.C.2: pairs related by one operation share their elements; q loop
+ * outermost).  Canonical orbit representative = smallest linear index; orbit
+ * ids increase with the representative.  Pair orbits are taken under the
+ * diagonal action (k,k') -> (s k, s k'); the swap partner of a pair orbit is
+ * the orbit of (k', k).  A storage class is {orbit, swap partner}, stored once
+ * in the orientation of the smaller orbit id; classes are numbered by that id.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t grid[3];
+  int32_t nk, nops, nkorb, nporb, ncls;
+} bse_dims;
+
+typedef struct {              /* host buffers, sizes from bse_dims           */
+  int32_t *kperm;             /* [nops][nk]   lin(A_s k mod grid)            */
+  int32_t *korb;              /* [nk]         k-orbit id (also the q orbit)  */
+  int32_t *korb_rep;          /* [nkorb]      representative k of each orbit */
+  int32_t *porb;              /* [nk*nk]      pair-orbit id of (k,k')        */
+  int32_t *porb_rep;          /* [nporb]      representative pair index      */
+  int32_t *pidx;              /* [nk*nk]      storage class of (k,k')        */
+  uint8_t *pconj;             /* [nk*nk]      1: M(k,k') is the band-conjugate
+                                              transpose of the stored class */
+  int32_t *cls_rep;           /* [ncls]       pair index of the stored orientation */
+  uint8_t *cls_selfswap;      /* [ncls]       class orbit is its own swap partner */
+} bse_tables;
+
+int32_t bse_dims_get(int32_t group, const int32_t *h_grid3, bse_dims *h_out);
+/* Any member pointer of `out` may be NULL to skip that table. */
+int32_t bse_tables_build(int32_t group, const int32_t *h_grid3, const bse_tables *h_out);
+
+/* ---------------------------------------------------------------------------
+ * Symmetry-adapted basis of one irrep (host, FP64).  For every k orbit O the
+ * projector P_mu = d_mu/|S| sum_s chi_mu(s) Gamma(s) (Eq. (projection)) is
+ * applied to the orbit's unit vectors and the result orthonormalised
+ * (Sec. III.C.4: the projector acts within one orbit, at most |S| d_max^2
+ * non-zeros per vector).  The band indices are spectators (the single-particle
+ * representation is the identity on bands), so the block basis is
+ * U_O (x) identity(nv nc).  Block layout: orbits in id order, then the
+ * orbit's r_O basis vectors, then (v, c) with c fastest:
+ *     row = orb_off[O] + j nv nc + v nc + c.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t n;        /* block dimension                                       */
+  int32_t nmem;     /* = nk                                                   */
+  int64_t nub;      /* number of basis coefficients: sum_O |O| r_O            */
+} bse_block_dims;
+
+int32_t bse_block_dims_get(int32_t group, const int32_t *h_grid3, int32_t irrep, int32_t nv,
+                           int32_t nc, bse_block_dims *h_out);
+/* h_mem_off[nkorb+1], h_members[nk]: k points of each orbit, ascending;
+ * h_orb_off[nkorb]: first block row; h_orb_dim[nkorb]: r_O;
+ * h_ub_off[nkorb+1], h_ubasis[nub]: U_O row-major |O| x r_O (FP64). */
+int32_t bse_block_basis(int32_t group, const int32_t *h_grid3, int32_t irrep, int32_t nv,
+                        int32_t nc, int32_t *h_mem_off, int32_t *h_members,
+                        int64_t *h_orb_off, int32_t *h_orb_dim, int64_t *h_ub_off,
+                        double *h_ubasis);
+
+/* ---------------------------------------------------------------------------
+ * bse_build: H (N x N, N = nk nv nc) from orbit-compressed inputs.
+ * Dense mode: every (k, k') pair is contracted (the kernels never assume that
+ * symmetric pairs hold equal data).  All device pointers.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t grid[3];
+  int32_t nv, nc, nmb;
+  int32_t nkorb, ncls, nqorb;
+  const int32_t *korb;   /* [nk]     k-orbit id of each k (indexes mx)          */
+  const int32_t *qorb;   /* [nk]     q-orbit id of each q (indexes w)           */
+  const int32_t *pidx;   /* [nk*nk]  storage class of (k,k') (indexes mv, mc)   */
+  const uint8_t *pconj;  /* [nk*nk]  1: use the band-conjugate transpose        */
+  const double *ev;      /* [nk][nv] valence energies (eV)                      */
+  const double *ec;      /* [nk][nc] conduction energies (eV)                   */
+  const double *vdiag;   /* [nmb]    diagonal bare Coulomb matrix v_I           */
+  const void *mx;        /* [nkorb][nv][nc][nmb] complex                        */
+  const void *mv;        /* [ncls][nv][nv][nmb]  complex                        */
+  const void *mc;        /* [ncls][nc][nc][nmb]  complex                        */
+  const void *w;         /* [nqorb][nmb][nmb]    real symmetric                 */
+  int32_t in_fp64;       /* element type of mx, mv, mc, w: 1 double, 0 float    */
+} bse_problem;
+
+/* Workspace bytes that let bse_build run its direct term in the fewest passes
+ * (capped; any size >= bse_build_ws_min works). */
+size_t bse_build_ws(const bse_problem *p, int32_t prec);
+size_t bse_build_ws_min(const bse_problem *p, int32_t prec);
+/* H: complex double (prec FP64) or complex float (FP32, BF16X3), leading
+ * dimension ldh >= N elements.  prec FP64 needs in_fp64 = 1, the others 0. */
+int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_t ldh, void *ws,
+                  size_t ws_bytes, bse_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * bse_project_blocks: H_mu = U_mu^T H U_mu and B_mu = U_mu^T B for nblk blocks
+ * (Eq. (transformationU) applied irrep-wise).  Per block, Hmu[i] may be NULL
+ * (only B_mu wanted) and Bmu[i] may be NULL.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t n;                 /* block dimension                               */
+  const int32_t *mem_off;    /* device [nkorb+1]                              */
+  const int32_t *members;    /* device [nk]                                   */
+  const int64_t *orb_off;    /* device [nkorb]                                */
+  const int32_t *orb_dim;    /* device [nkorb]                                */
+  const int64_t *ub_off;     /* device [nkorb+1]                              */
+  const double *ubasis;      /* device [nub]                                  */
+} bse_block;
+
+/* H element type: h_fp64 = 1 complex double, 0 complex float; H_mu has the
+ * same type with leading dimension ldmu[i] >= n.  B, B_mu: complex double. */
+int32_t bse_project_blocks(const bse_problem *p, const void *H, int64_t ldh, int32_t h_fp64,
+                           const void *B, int32_t nblk, const bse_block *h_blk,
+                           void *const *h_Hmu, const int64_t *h_ldmu, void *const *h_Bmu,
+                           bse_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * bse_block_eigh: eigenvalues of the Hermitian block and the oscillator
+ * strengths |B_l|^2 = |A_l^dag B_mu|^2 (Eq. (oscillatorA)).
+ * Method: a Householder reflection maps B_mu onto |B_mu| e_1; a blocked
+ * Householder tridiagonalisation that leaves e_1 fixed follows; then
+ * |B_l|^2 = |B_mu|^2 z_l(1)^2 with z_l the eigenvectors of the real
+ * tridiagonal T, so eps2 needs no eigenvectors.  Only the leading unreduced
+ * block of T (the Krylov space of B_mu) carries weight.
+ * Outputs (device FP64): omega[n] all eigenvalues ascending (with
+ * multiplicity); pole[n], osc[n]: the optical poles and their strengths,
+ * padded with zero strength.  Hmu is read only.
+ * prec: FP64 (all FP64), FP32 (FP32 trailing updates and HEMV storage, FP64
+ * panel, tridiagonal step and refinement).  nrefine > 0 asks for FP64
+ * Rayleigh-Ritz refinement of the lowest nrefine eigenvalues against Hmu.
+ * ------------------------------------------------------------------------- */
+size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int32_t nrefine);
+int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, const void *Bmu,
+                       int32_t prec, int32_t nrefine, double *omega, double *pole,
+                       double *osc, void *ws, size_t ws_bytes, bse_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * bse_spectrum: eps2[j] = pref sum_l osc[l] [L(w_j - pole_l) + L(w_j + pole_l)],
+ * L(x) = eta / (x^2 + eta^2); pref = 8 pi / N_k for the spin-degenerate case
+ * (Eqs. (macro_diel), (reducible_polar)).  Device FP64 arrays.
+ * ------------------------------------------------------------------------- */
+int32_t bse_spectrum(int64_t n, const double *pole, const double *osc, double pref, double eta,
+                     int64_t nw, const double *w, double *eps2, bse_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSE_H */

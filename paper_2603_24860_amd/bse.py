@@ -1,0 +1,159 @@
+"""Python binding of the C ABI (include/bse.h): argument marshalling only.
+
+Every function here converts numpy arrays or torch tensors into the pointers
+and sizes the C entry points take, calls the library, and raises BseError on a
+non-OK status.  All arithmetic of the hot path runs in the library's kernels.
+PyTorch provides device memory and the current HIP stream.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import BseError, FP32, FP64, BF16X3, GROUP_OH, GROUP_D6H, check, lib  # noqa: F401
+
+GROUPS = {"Oh": GROUP_OH, "D6h": GROUP_D6H}
+
+
+def _ptr(a):
+    """Device or host address of a torch tensor / numpy array (None -> NULL)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+def _gid(group):
+    return GROUPS[group] if isinstance(group, str) else int(group)
+
+
+def _grid(grid):
+    return np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
+
+
+# --------------------------------------------------------------------------
+# groups and tables (host)
+# --------------------------------------------------------------------------
+def bse_group_ops(group):
+    g = _gid(group)
+    n = check(lib.bse_group_order(g))
+    kmat = np.zeros((n, 3, 3), dtype=np.int32)
+    rcart = np.zeros((n, 3, 3), dtype=np.float64)
+    check(lib.bse_group_ops(g, _ptr(kmat), _ptr(rcart)))
+    return kmat, rcart
+
+
+def bse_group_irreps(group):
+    g = _gid(group)
+    n = check(lib.bse_group_order(g))
+    out = []
+    for i in range(check(lib.bse_group_nirreps(g))):
+        name = ctypes.create_string_buffer(8)
+        dim = ctypes.c_int32()
+        chi = np.zeros(n)
+        check(lib.bse_group_irrep(g, i, name, ctypes.byref(dim), _ptr(chi)))
+        out.append((name.value.decode(), dim.value, chi))
+    return out
+
+
+def irrep_index(group, name):
+    for i, (nm, _, _) in enumerate(bse_group_irreps(group)):
+        if nm == name:
+            return i
+    raise KeyError(name)
+
+
+def bse_dims_get(group, grid):
+    d = _lib.Dims()
+    g = _grid(grid)
+    check(lib.bse_dims_get(_gid(group), _ptr(g), ctypes.byref(d)))
+    return dict(grid=tuple(d.grid), nk=d.nk, nops=d.nops, nkorb=d.nkorb, nporb=d.nporb,
+                ncls=d.ncls)
+
+
+def bse_tables_build(group, grid):
+    d = bse_dims_get(group, grid)
+    nk = d["nk"]
+    t = dict(kperm=np.zeros((d["nops"], nk), np.int32), korb=np.zeros(nk, np.int32),
+             korb_rep=np.zeros(d["nkorb"], np.int32), porb=np.zeros(nk * nk, np.int32),
+             porb_rep=np.zeros(d["nporb"], np.int32), pidx=np.zeros(nk * nk, np.int32),
+             pconj=np.zeros(nk * nk, np.uint8), cls_rep=np.zeros(d["ncls"], np.int32),
+             cls_selfswap=np.zeros(d["ncls"], np.uint8))
+    s = _lib.Tables(*[_ptr(t[f]) for f, _ in _lib.Tables._fields_])
+    g = _grid(grid)
+    check(lib.bse_tables_build(_gid(group), _ptr(g), ctypes.byref(s)))
+    t.update(d)
+    return t
+
+
+def bse_block_basis(group, grid, irrep, nv, nc):
+    g = _grid(grid)
+    gid = _gid(group)
+    ir = irrep_index(group, irrep) if isinstance(irrep, str) else int(irrep)
+    bd = _lib.BlockDims()
+    check(lib.bse_block_dims_get(gid, _ptr(g), ir, nv, nc, ctypes.byref(bd)))
+    nkorb = bse_dims_get(group, grid)["nkorb"]
+    out = dict(n=bd.n, mem_off=np.zeros(nkorb + 1, np.int32), members=np.zeros(bd.nmem, np.int32),
+               orb_off=np.zeros(nkorb, np.int64), orb_dim=np.zeros(nkorb, np.int32),
+               ub_off=np.zeros(nkorb + 1, np.int64), ubasis=np.zeros(max(bd.nub, 1), np.float64))
+    check(lib.bse_block_basis(gid, _ptr(g), ir, nv, nc, _ptr(out["mem_off"]), _ptr(out["members"]),
+                              _ptr(out["orb_off"]), _ptr(out["orb_dim"]), _ptr(out["ub_off"]),
+                              _ptr(out["ubasis"])))
+    return out
+
+
+# --------------------------------------------------------------------------
+# device entry points
+# --------------------------------------------------------------------------
+def bse_build_ws(problem, prec):
+    return lib.bse_build_ws(ctypes.byref(problem), prec)
+
+
+def bse_build_ws_min(problem, prec):
+    return lib.bse_build_ws_min(ctypes.byref(problem), prec)
+
+
+def bse_build(problem, prec, H, ws, stream=None):
+    """H: complex tensor (N x N, complex128 for FP64 else complex64) on the GPU."""
+    ldh = H.stride(0)
+    nbytes = ws.numel() * ws.element_size()
+    check(lib.bse_build(ctypes.byref(problem), prec, _ptr(H), ldh, _ptr(ws), nbytes,
+                        _stream(stream)))
+
+
+def bse_project_blocks(problem, H, B, blocks, Hmu, Bmu, stream=None):
+    """blocks: list of _lib.Block; Hmu / Bmu: lists of tensors or None."""
+    nb = len(blocks)
+    arr = (_lib.Block * max(nb, 1))(*blocks)
+    hp = (ctypes.c_void_p * max(nb, 1))(*[(h.data_ptr() if h is not None else None) for h in Hmu])
+    ld = (ctypes.c_int64 * max(nb, 1))(*[(h.stride(0) if h is not None else 0) for h in Hmu])
+    bp = (ctypes.c_void_p * max(nb, 1))(*[(b.data_ptr() if b is not None else None) for b in Bmu])
+    h_fp64 = 1 if (H is not None and H.dtype.itemsize == 16) else 0
+    check(lib.bse_project_blocks(ctypes.byref(problem), _ptr(H), H.stride(0) if H is not None else 0,
+                                 h_fp64, _ptr(B), nb, arr, hp, ld, bp, _stream(stream)))
+
+
+def bse_block_eigh_ws(n, h_fp64, prec, nrefine=0):
+    return lib.bse_block_eigh_ws(n, h_fp64, prec, nrefine)
+
+
+def bse_block_eigh(Hmu, Bmu, prec, omega, pole, osc, ws, nrefine=0, stream=None):
+    n = Hmu.shape[0]
+    h_fp64 = 1 if Hmu.dtype.itemsize == 16 else 0
+    nbytes = ws.numel() * ws.element_size()
+    check(lib.bse_block_eigh(n, _ptr(Hmu), Hmu.stride(0), h_fp64, _ptr(Bmu), prec, nrefine,
+                             _ptr(omega), _ptr(pole), _ptr(osc), _ptr(ws), nbytes,
+                             _stream(stream)))
+
+
+def bse_spectrum(pole, osc, pref, eta, w, eps2, stream=None):
+    check(lib.bse_spectrum(pole.numel(), _ptr(pole), _ptr(osc), float(pref), float(eta),
+                           w.numel(), _ptr(w), _ptr(eps2), _stream(stream)))

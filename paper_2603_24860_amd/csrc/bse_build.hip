@@ -1,0 +1,416 @@
+// bse_build: the Tamm-Dancoff electron-hole Hamiltonian on MFMA.
+//
+//   H[(k v c),(k' v' c')] = delta (E_c(k) - E_v(k))
+//        + (2/N_k) sum_I Mx[k,v,c,I] v_I conj(Mx[k',v',c',I])            exchange
+//        - (1/N_k) sum_IJ conj(Mc[k,k'][c,c',I]) W_IJ(k-k') Mv[k,k'][v,v',J]   direct
+//
+// Paper: Eq. (BSE-eigval) with Eq. (w_interaction2) (vector-matrix-vector
+// products over the mixed-basis index, prefactor 1/N_k); spin factor 2 on the
+// bare exchange (Sec. II); the loop over q = k - k' is outermost (Sec. III.C.2).
+//
+// Three kernels, all dense contractions on MFMA 16x16x4 (f32 or f64):
+//   k_exchange   writes every H element: diagonal + exchange (a complex
+//                Hermitian rank-Nmb product, rows gathered through the k-orbit map)
+//   k_direct_t   for a batch of q: T_q = Mv(k, k-q) W(q) for all k at once
+//                (M = 2 nk nv^2 real rows, N = K = Nmb), written to workspace
+//   k_direct_d   per pair (k, k-q): D = conj(Mc) T^T (2 nc^2 x nv^2, K = 2 Nmb)
+//                and H -= D / N_k (each H element is owned by one pair)
+// Complex products run as real GEMMs with the reduction index interleaved as
+// (I, re/im): for x, y complex rows, x conj(y) = [(re, im).(re', im')] +
+// i [(im, -re).(re', im')], and conj(x) y = [(re, im).(re', im')] +
+// i [(-im, re).(re', im')].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "bse_internal.h"
+#include "mfma_tile.h"
+
+namespace bse {
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T> struct BuildTile;
+template <> struct BuildTile<float> { static constexpr int BM = 128, BN = 128, BK = 32; };
+template <> struct BuildTile<double> { static constexpr int BM = 128, BN = 128, BK = 16; };
+
+__device__ __forceinline__ int kminus(int k, int q, int n1, int n2, int n3) {
+  const int k3 = k % n3, k2 = (k / n3) % n2, k1 = k / (n2 * n3);
+  const int q3 = q % n3, q2 = (q / n3) % n2, q1 = q / (n2 * n3);
+  int a = k1 - q1, b = k2 - q2, c = k3 - q3;
+  a += a < 0 ? n1 : 0;
+  b += b < 0 ? n2 : 0;
+  c += c < 0 ? n3 : 0;
+  return (a * n2 + b) * n3 + c;
+}
+
+// ---------------------------------------------------------------------------
+// exchange + diagonal
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_exchange(int nk, int nv, int nc, int nmb,
+                                                 const int32_t *__restrict__ korb,
+                                                 const T *__restrict__ mx,
+                                                 const double *__restrict__ vdiag,
+                                                 const double *__restrict__ ev,
+                                                 const double *__restrict__ ec, T *__restrict__ H,
+                                                 int64_t ldh, double scale) {
+  constexpr int BM = BuildTile<T>::BM, BN = BuildTile<T>::BN, BK = BuildTile<T>::BK;
+  constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32, KC = BK / 2;
+  constexpr int NA = (BM / 2) * KC / NT, NB = BN * KC / NT;
+  __shared__ __attribute__((aligned(16))) T As[BM * P];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * P];
+  typedef typename Cplx<T>::type C2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = nv * nc;
+  const int64_t N = int64_t(nk) * nb;
+  const int64_t a0 = int64_t(blockIdx.y) * (BM / 2), b0 = int64_t(blockIdx.x) * BN;
+  // row pointers of the rows this thread loads
+  const C2 *arow[NA];
+  const C2 *brow[NB];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int64_t a = a0 + (tid + NT * u) / KC;
+    arow[u] = a < N ? reinterpret_cast<const C2 *>(mx) +
+                          (int64_t(korb[a / nb]) * nb + a % nb) * nmb
+                    : nullptr;
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int64_t b = b0 + (tid + NT * u) / KC;
+    brow[u] = b < N ? reinterpret_cast<const C2 *>(mx) +
+                          (int64_t(korb[b / nb]) * nb + b % nb) * nmb
+                    : nullptr;
+  }
+  typename Mfma<T>::acc_t acc[MI][NI];
+  acc_zero<T, MI, NI>(acc);
+  const int wm0 = (wv >> 1) * (BM / 2), wn0 = (wv & 1) * (BN / 2);
+  for (int i0 = 0; i0 < nmb; i0 += KC) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int it = tid + NT * u, r = it / KC, i = it % KC, I = i0 + i;
+      C2 x = {T(0), T(0)};
+      T vI = T(0);
+      if (arow[u] && I < nmb) {
+        x = arow[u][I];
+        vI = T(vdiag[I]);
+      }
+      *reinterpret_cast<C2 *>(As + (2 * r) * P + 2 * i) = C2{x.x * vI, x.y * vI};
+      *reinterpret_cast<C2 *>(As + (2 * r + 1) * P + 2 * i) = C2{x.y * vI, -x.x * vI};
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int it = tid + NT * u, r = it / KC, i = it % KC, I = i0 + i;
+      C2 x = {T(0), T(0)};
+      if (brow[u] && I < nmb) x = brow[u][I];
+      *reinterpret_cast<C2 *>(Bs + r * P + 2 * i) = x;
+    }
+    __syncthreads();
+    mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, wn0, lane);
+    __syncthreads();
+  }
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const int64_t b = b0 + wn0 + 16 * ni + r16;
+      const int64_t a = a0 + (wm0 + 16 * mi + 4 * g) / 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t aa = a + h;
+        if (aa < N && b < N) {
+          double re = scale * double(acc[mi][ni][2 * h]);
+          const double im = scale * double(acc[mi][ni][2 * h + 1]);
+          if (aa == b) {
+            const int k = int(aa / nb), v = int((aa / nc) % nv), c = int(aa % nc);
+            re += ec[int64_t(k) * nc + c] - ev[int64_t(k) * nv + v];
+          }
+          reinterpret_cast<C2 *>(H)[aa * ldh + b] = C2{T(re), T(im)};
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct term, stage 1: T_q[(k,v,v')][I] = sum_J Mv(k,k-q)[v,v',J] W_q[I][J]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_direct_t(int n1, int n2, int n3, int nv, int nmb, int q0,
+                                                 const int32_t *__restrict__ qorb,
+                                                 const int32_t *__restrict__ pidx,
+                                                 const uint8_t *__restrict__ pconj,
+                                                 const T *__restrict__ mv,
+                                                 const T *__restrict__ w, T *__restrict__ Tq) {
+  constexpr int BM = BuildTile<T>::BM, BN = BuildTile<T>::BN, BK = BuildTile<T>::BK;
+  constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32;
+  constexpr int NA = (BM / 2) * BK / NT, NB = BN * BK / NT;
+  __shared__ __attribute__((aligned(16))) T As[BM * P];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * P];
+  typedef typename Cplx<T>::type C2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nk = n1 * n2 * n3, nvv = nv * nv;
+  const int q = q0 + blockIdx.z;
+  const int64_t M = int64_t(nk) * nvv;  // complex rows
+  const int64_t r0 = int64_t(blockIdx.y) * (BM / 2);
+  const int c0 = blockIdx.x * BN;
+  const T *wq = w + int64_t(qorb[q]) * nmb * nmb;
+  const C2 *arow[NA];
+  T asgn[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int64_t r = r0 + (tid + NT * u) / BK;
+    arow[u] = nullptr;
+    asgn[u] = T(1);
+    if (r < M) {
+      const int k = int(r / nvv), vv = int(r % nvv), v = vv / nv, v2 = vv % nv;
+      const int kq = kminus(k, q, n1, n2, n3);
+      const int64_t p = int64_t(k) * nk + kq;
+      const int cls = pidx[p];
+      const bool cj = pconj[p] != 0;
+      const int s1 = cj ? v2 : v, s2 = cj ? v : v2;
+      arow[u] = reinterpret_cast<const C2 *>(mv) + ((int64_t(cls) * nv + s1) * nv + s2) * nmb;
+      asgn[u] = cj ? T(-1) : T(1);
+    }
+  }
+  typename Mfma<T>::acc_t acc[MI][NI];
+  acc_zero<T, MI, NI>(acc);
+  const int wm0 = (wv >> 1) * (BM / 2), wn0 = (wv & 1) * (BN / 2);
+  for (int j0 = 0; j0 < nmb; j0 += BK) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int it = tid + NT * u, r = it / BK, j = it % BK, J = j0 + j;
+      C2 x = {T(0), T(0)};
+      if (arow[u] && J < nmb) x = arow[u][J];
+      As[(2 * r) * P + j] = x.x;
+      As[(2 * r + 1) * P + j] = asgn[u] * x.y;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int it = tid + NT * u, c = it / BK, j = it % BK, I = c0 + c, J = j0 + j;
+      Bs[c * P + j] = (I < nmb && J < nmb) ? wq[int64_t(I) * nmb + J] : T(0);
+    }
+    __syncthreads();
+    mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, wn0, lane);
+    __syncthreads();
+  }
+  C2 *out = reinterpret_cast<C2 *>(Tq) + int64_t(blockIdx.z) * M * nmb;
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const int I = c0 + wn0 + 16 * ni + r16;
+      const int64_t r = r0 + (wm0 + 16 * mi + 4 * g) / 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (r + h < M && I < nmb)
+          out[(r + h) * nmb + I] = C2{acc[mi][ni][2 * h], acc[mi][ni][2 * h + 1]};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct term, stage 2: one wave per pair (k, k-q)
+//   D[(c,c')][(v,v')] = sum_I conj(Mc(k,k-q)[c,c',I]) T_q[(k,v,v')][I]
+//   H[(k v c),(k-q v' c')] -= D / N_k
+// ---------------------------------------------------------------------------
+constexpr int D_MB = 5;  // row blocks: 2 nc^2 <= 80
+constexpr int D_NB = 3;  // column blocks: nv^2 <= 48
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_direct_d(int n1, int n2, int n3, int nv, int nc, int nmb,
+                                                 int q0, const int32_t *__restrict__ pidx,
+                                                 const uint8_t *__restrict__ pconj,
+                                                 const T *__restrict__ mc,
+                                                 const T *__restrict__ Tq, T *__restrict__ H,
+                                                 int64_t ldh, double scale) {
+  typedef typename Cplx<T>::type C2;
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nk = n1 * n2 * n3, nvv = nv * nv, ncc = nc * nc;
+  const int k = blockIdx.x * (NT / 64) + wv;
+  if (k >= nk) return;
+  const int q = q0 + blockIdx.y;
+  const int kq = kminus(k, q, n1, n2, n3);
+  const int64_t p = int64_t(k) * nk + kq;
+  const int cls = pidx[p];
+  const bool cj = pconj[p] != 0;
+  const T sg = cj ? T(-1) : T(1);
+  const int mb = (2 * ncc + 15) / 16, nb = (nvv + 15) / 16;
+  const int r16 = lane & 15, g = lane >> 4;
+  // per-lane source rows
+  const C2 *arow[D_MB];
+  int at[D_MB];
+#pragma unroll
+  for (int mi = 0; mi < D_MB; ++mi) {
+    const int R = 16 * mi + r16;
+    arow[mi] = nullptr;
+    at[mi] = R & 1;
+    if (mi < mb && R < 2 * ncc) {
+      const int cc = R >> 1, c = cc / nc, c2 = cc % nc;
+      const int s1 = cj ? c2 : c, s2 = cj ? c : c2;
+      arow[mi] = reinterpret_cast<const C2 *>(mc) + ((int64_t(cls) * nc + s1) * nc + s2) * nmb;
+    }
+  }
+  const C2 *brow[D_NB];
+  const C2 *tbase = reinterpret_cast<const C2 *>(Tq) + int64_t(blockIdx.y) * nk * nvv * nmb;
+#pragma unroll
+  for (int ni = 0; ni < D_NB; ++ni) {
+    const int C = 16 * ni + r16;
+    brow[ni] = (ni < nb && C < nvv) ? tbase + (int64_t(k) * nvv + C) * nmb : nullptr;
+  }
+  acc_t acc[D_MB][D_NB];
+#pragma unroll
+  for (int mi = 0; mi < D_MB; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < D_NB; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[mi][ni][j] = T(0);
+  for (int i0 = 0; i0 < nmb; i0 += 8) {
+    const int I = i0 + 2 * g;
+    typename Mfma<T>::frag_t af[D_MB], bf[D_NB];
+#pragma unroll
+    for (int mi = 0; mi < D_MB; ++mi) {
+      C2 x0 = {T(0), T(0)}, x1 = {T(0), T(0)};
+      if (arow[mi]) {
+        if (I < nmb) x0 = arow[mi][I];
+        if (I + 1 < nmb) x1 = arow[mi][I + 1];
+      }
+      const T a0 = x0.x, b0 = sg * x0.y, a1 = x1.x, b1 = sg * x1.y;
+      if (at[mi] == 0) {
+        af[mi][0] = a0; af[mi][1] = b0; af[mi][2] = a1; af[mi][3] = b1;
+      } else {
+        af[mi][0] = -b0; af[mi][1] = a0; af[mi][2] = -b1; af[mi][3] = a1;
+      }
+    }
+#pragma unroll
+    for (int ni = 0; ni < D_NB; ++ni) {
+      C2 y0 = {T(0), T(0)}, y1 = {T(0), T(0)};
+      if (brow[ni]) {
+        if (I < nmb) y0 = brow[ni][I];
+        if (I + 1 < nmb) y1 = brow[ni][I + 1];
+      }
+      bf[ni][0] = y0.x; bf[ni][1] = y0.y; bf[ni][2] = y1.x; bf[ni][3] = y1.y;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int mi = 0; mi < D_MB; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < D_NB; ++ni)
+          if (mi < mb && ni < nb) acc[mi][ni] = Mfma<T>::mma(af[mi][i], bf[ni][i], acc[mi][ni]);
+  }
+  C2 *Hc = reinterpret_cast<C2 *>(H);
+#pragma unroll
+  for (int mi = 0; mi < D_MB; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < D_NB; ++ni) {
+      if (mi >= mb || ni >= nb) continue;
+      const int C = 16 * ni + r16;
+      if (C >= nvv) continue;
+      const int v = C / nv, v2 = C % nv;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cc = (16 * mi + 4 * g) / 2 + h;
+        if (cc >= ncc) continue;
+        const int c = cc / nc, c2 = cc % nc;
+        const int64_t a = (int64_t(k) * nv + v) * nc + c;
+        const int64_t b = (int64_t(kq) * nv + v2) * nc + c2;
+        C2 hv = Hc[a * ldh + b];
+        hv.x -= T(scale * double(acc[mi][ni][2 * h]));
+        hv.y -= T(scale * double(acc[mi][ni][2 * h + 1]));
+        Hc[a * ldh + b] = hv;
+      }
+    }
+}
+
+int32_t check_problem(const bse_problem *p, int32_t prec) {
+  if (!p) return fail(BSE_EINVAL, "problem is NULL");
+  if (prec != BSE_FP64 && prec != BSE_FP32 && prec != BSE_BF16X3)
+    return fail(BSE_EINVAL, "unknown precision %d", prec);
+  if ((prec == BSE_FP64) != (p->in_fp64 != 0))
+    return fail(BSE_EINVAL, "input element type does not match the precision");
+  if (p->grid[0] < 1 || p->grid[1] < 1 || p->grid[2] < 1) return fail(BSE_ESHAPE, "bad grid");
+  const int64_t nk = int64_t(p->grid[0]) * p->grid[1] * p->grid[2];
+  if (nk * nk >= (int64_t(1) << 31)) return fail(BSE_ESHAPE, "nk too large");
+  if (p->nv < 1 || p->nc < 1 || p->nmb < 1) return fail(BSE_ESHAPE, "nv, nc, nmb must be >= 1");
+  if (p->nv * p->nv > 16 * D_NB || 2 * p->nc * p->nc > 16 * D_MB)
+    return fail(BSE_EUNSUPPORTED, "nv <= 6 and nc <= 6 are supported (got %d, %d)", p->nv, p->nc);
+  if (p->nkorb < 1 || p->ncls < 1 || p->nqorb < 1) return fail(BSE_ESHAPE, "empty orbit tables");
+  if (!p->korb || !p->qorb || !p->pidx || !p->pconj || !p->ev || !p->ec || !p->vdiag || !p->mx ||
+      !p->mv || !p->mc || !p->w)
+    return fail(BSE_EINVAL, "NULL device pointer in problem");
+  return BSE_OK;
+}
+
+size_t per_q_bytes(const bse_problem *p, int32_t prec) {
+  const size_t el = prec == BSE_FP64 ? 16 : 8;
+  const size_t nk = size_t(p->grid[0]) * p->grid[1] * p->grid[2];
+  return nk * size_t(p->nv) * p->nv * p->nmb * el;
+}
+
+}  // namespace
+
+// used by other translation units (BF16 split form)
+int32_t build_check_problem(const bse_problem *p, int32_t prec) { return check_problem(p, prec); }
+
+}  // namespace bse
+
+using namespace bse;
+
+extern "C" size_t bse_build_ws_min(const bse_problem *p, int32_t prec) {
+  if (check_problem(p, prec)) return 0;
+  return per_q_bytes(p, prec);
+}
+
+extern "C" size_t bse_build_ws(const bse_problem *p, int32_t prec) {
+  if (check_problem(p, prec)) return 0;
+  const size_t pq = per_q_bytes(p, prec);
+  const size_t nk = size_t(p->grid[0]) * p->grid[1] * p->grid[2];
+  const size_t cap = size_t(1) << 30;  // 1 GiB of q-batch buffer is plenty to saturate
+  return pq * std::max<size_t>(1, std::min(nk, cap / pq));
+}
+
+extern "C" int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_t ldh, void *ws,
+                             size_t ws_bytes, bse_stream stream) {
+  int32_t st = check_problem(p, prec);
+  if (st) return st;
+  if (prec == BSE_BF16X3) return build_bf16x3(p, H, ldh, ws, ws_bytes, stream);
+  const int n1 = p->grid[0], n2 = p->grid[1], n3 = p->grid[2];
+  const int nk = n1 * n2 * n3;
+  const int64_t N = int64_t(nk) * p->nv * p->nc;
+  if (!H) return fail(BSE_EINVAL, "H is NULL");
+  if (ldh < N) return fail(BSE_ESHAPE, "ldh %lld < N %lld", (long long)ldh, (long long)N);
+  const size_t pq = per_q_bytes(p, prec);
+  if (!ws || ws_bytes < pq)
+    return fail(BSE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, pq);
+  const int qb = int(std::min<size_t>(nk, ws_bytes / pq));
+  hipStream_t s = (hipStream_t)stream;
+  const double inv_nk = 1.0 / nk;
+  auto launch = [&](auto tag) -> int32_t {
+    typedef decltype(tag) T;
+    constexpr int BM = BuildTile<T>::BM, BN = BuildTile<T>::BN;
+    dim3 gx((unsigned)((N + BN - 1) / BN), (unsigned)((2 * N + BM - 1) / BM));
+    if (gx.y > 65535u) return fail(BSE_ESHAPE, "N too large for the exchange grid");
+    hipLaunchKernelGGL(k_exchange<T>, gx, dim3(NT), 0, s, nk, p->nv, p->nc, p->nmb, p->korb,
+                       (const T *)p->mx, p->vdiag, p->ev, p->ec, (T *)H, ldh, 2.0 * inv_nk);
+    BSE_HIP_CHECK(hipGetLastError());
+    const int64_t M = 2 * int64_t(nk) * p->nv * p->nv;
+    for (int q0 = 0; q0 < nk; q0 += qb) {
+      const int nq = std::min(qb, nk - q0);
+      dim3 g1((unsigned)((p->nmb + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)nq);
+      hipLaunchKernelGGL(k_direct_t<T>, g1, dim3(NT), 0, s, n1, n2, n3, p->nv, p->nmb, q0,
+                         p->qorb, p->pidx, p->pconj, (const T *)p->mv, (const T *)p->w, (T *)ws);
+      BSE_HIP_CHECK(hipGetLastError());
+      dim3 g2((unsigned)((nk + 3) / 4), (unsigned)nq);
+      hipLaunchKernelGGL(k_direct_d<T>, g2, dim3(NT), 0, s, n1, n2, n3, p->nv, p->nc, p->nmb, q0,
+                         p->pidx, p->pconj, (const T *)p->mc, (const T *)ws, (T *)H, ldh, inv_nk);
+      BSE_HIP_CHECK(hipGetLastError());
+    }
+    return BSE_OK;
+  };
+  if (prec == BSE_FP64) return launch(double(0));
+  return launch(float(0));
+}

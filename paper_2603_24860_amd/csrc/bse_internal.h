@@ -1,0 +1,50 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bse.h"
+
+namespace bse {
+
+// Records a thread-local message for bse_last_error() and returns `st`.
+int32_t fail(int32_t st, const char *fmt, ...);
+
+// Point group data built on the host.
+struct Group {
+  int nops = 0;
+  std::vector<int32_t> kmat;    // [nops][9] action on reduced k
+  std::vector<double> rcart;    // [nops][9] Cartesian matrix
+  struct Irrep {
+    std::string name;
+    int dim;
+    std::vector<double> chi;    // [nops]
+  };
+  std::vector<Irrep> irreps;
+};
+
+// Returns nullptr for an unknown group id.
+const Group *get_group(int32_t group);
+
+// Grid helpers (k linear index = (k1 n2 + k2) n3 + k3).
+struct Grid {
+  int n1, n2, n3;
+  int64_t nk() const { return int64_t(n1) * n2 * n3; }
+};
+
+// Split-BF16 form of bse_build (arguments already validated).
+int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_t ws_bytes,
+                     bse_stream stream);
+
+}  // namespace bse
+
+#define BSE_HIP_CHECK(expr)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return bse::fail(BSE_EDEVICE, "%s failed: %s (%s:%d)", #expr,                \
+                       hipGetErrorString(e_), __FILE__, __LINE__);                 \
+  } while (0)

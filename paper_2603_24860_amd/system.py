@@ -1,0 +1,168 @@
+"""Device-resident BSE system and the solve sequence.
+
+DeviceSystem uploads one system's inputs (band energies, orbit-compressed pair
+vectors, W per q orbit, dipoles) and the library's integer tables to the GPU
+once; solve() then runs the hot path entirely through the C ABI:
+bse_build -> bse_project_blocks -> bse_block_eigh -> bse_spectrum.
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from . import bse as B
+
+CDT = {B.FP64: torch.complex128, B.FP32: torch.complex64, B.BF16X3: torch.complex64}
+RDT = {B.FP64: torch.float64, B.FP32: torch.float32, B.BF16X3: torch.float32}
+
+
+def _dev(a, dtype=None, device="cuda"):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device)
+
+
+class DeviceBlock:
+    def __init__(self, group, grid, irrep, nv, nc, device="cuda"):
+        b = B.bse_block_basis(group, grid, irrep, nv, nc)
+        self.irrep = irrep
+        self.n = int(b["n"])
+        self.host = b
+        self.t = {k: _dev(v, device=device) for k, v in b.items() if k != "n"}
+        self.c = _lib.Block(self.n, *[ctypes.c_void_p(self.t[f].data_ptr())
+                                     for f in ("mem_off", "members", "orb_off", "orb_dim",
+                                               "ub_off", "ubasis")])
+
+
+class DeviceSystem:
+    """One system resident on the GPU.
+
+    inputs: dict with ev[nk,nv], ec[nk,nc], vdiag[nmb], mx[nkorb,nv,nc,nmb],
+    mv[ncls,nv,nv,nmb], mc[ncls,nc,nc,nmb], w[nqorb,nmb,nmb], B[nk*nv*nc] (numpy).
+    tables: output of bse.bse_tables_build for (group, grid).
+    """
+
+    def __init__(self, group, grid, nv, nc, nmb, tables, inputs, prec, device="cuda"):
+        self.group, self.grid = group, tuple(grid)
+        self.nv, self.nc, self.nmb, self.prec = nv, nc, nmb, prec
+        self.nk = int(np.prod(grid))
+        self.N = self.nk * nv * nc
+        self.device = device
+        self.tables = tables
+        cdt, rdt = CDT[prec], RDT[prec]
+        t = dict(korb=_dev(tables["korb"], device=device),
+                 pidx=_dev(tables["pidx"], device=device),
+                 pconj=_dev(tables["pconj"], device=device),
+                 ev=_dev(inputs["ev"], torch.float64, device),
+                 ec=_dev(inputs["ec"], torch.float64, device),
+                 vdiag=_dev(inputs["vdiag"], torch.float64, device),
+                 mx=_dev(inputs["mx"], cdt, device), mv=_dev(inputs["mv"], cdt, device),
+                 mc=_dev(inputs["mc"], cdt, device), w=_dev(inputs["w"], rdt, device),
+                 B=_dev(inputs["B"], torch.complex128, device))
+        self.t = t
+        ptr = lambda x: ctypes.c_void_p(x.data_ptr())
+        self.problem = _lib.Problem(
+            (ctypes.c_int32 * 3)(*self.grid), nv, nc, nmb, tables["nkorb"], tables["ncls"],
+            tables["nkorb"], ptr(t["korb"]), ptr(t["korb"]), ptr(t["pidx"]), ptr(t["pconj"]),
+            ptr(t["ev"]), ptr(t["ec"]), ptr(t["vdiag"]), ptr(t["mx"]), ptr(t["mv"]),
+            ptr(t["mc"]), ptr(t["w"]), 1 if prec == B.FP64 else 0)
+        self.blocks = {}
+        self.H = None
+        self.ws = None
+
+    # -- allocation -------------------------------------------------------
+    def alloc_build(self, ws_bytes=None):
+        if self.H is None:
+            self.H = torch.empty((self.N, self.N), dtype=CDT[self.prec], device=self.device)
+        want = ws_bytes or B.bse_build_ws(self.problem, self.prec)
+        if want == 0:
+            raise B.BseError(-1, B.lib.bse_last_error().decode())
+        if self.ws is None or self.ws.numel() < want:
+            self.ws = torch.empty(want, dtype=torch.uint8, device=self.device)
+
+    def block(self, irrep):
+        if irrep not in self.blocks:
+            self.blocks[irrep] = DeviceBlock(self.group, self.grid, irrep, self.nv, self.nc,
+                                             self.device)
+        return self.blocks[irrep]
+
+    # -- pieces of the path ----------------------------------------------
+    def build(self):
+        self.alloc_build()
+        B.bse_build(self.problem, self.prec, self.H, self.ws)
+        return self.H
+
+    def dipole_weights(self):
+        """|U_mu^T B|^2 for every irrep with a non-empty block (one host sync)."""
+        names = [nm for nm, _, _ in B.bse_group_irreps(self.group)]
+        blks, outs, keep = [], [], []
+        for nm in names:
+            b = self.block(nm)
+            if b.n == 0:
+                continue
+            keep.append(nm)
+            blks.append(b.c)
+            outs.append(torch.empty(b.n, dtype=torch.complex128, device=self.device))
+        B.bse_project_blocks(self.problem, None, self.t["B"], blks, [None] * len(blks), outs)
+        return {nm: float((o.abs() ** 2).sum()) for nm, o in zip(keep, outs)}
+
+    def active_irrep(self):
+        w = self.dipole_weights()
+        tot = sum(w.values())
+        act = [nm for nm, x in w.items() if x > 1e-12 * tot]
+        return max(act, key=lambda nm: w[nm]), w
+
+
+class Solver:
+    """Reusable buffers for repeated solves of one block of one system."""
+
+    def __init__(self, system, irrep, eig_prec=None, nrefine=0, wgrid=None, eta=0.05):
+        self.s = system
+        self.blk = system.block(irrep)
+        n = self.blk.n
+        dev = system.device
+        self.eig_prec = system.prec if eig_prec is None else eig_prec
+        if self.eig_prec == B.BF16X3:
+            self.eig_prec = B.FP32
+        self.nrefine = nrefine
+        self.Hmu = torch.empty((n, n), dtype=CDT[system.prec], device=dev)
+        self.Bmu = torch.empty(n, dtype=torch.complex128, device=dev)
+        h64 = 1 if self.Hmu.dtype == torch.complex128 else 0
+        self.ws = torch.empty(B.bse_block_eigh_ws(n, h64, self.eig_prec, nrefine),
+                              dtype=torch.uint8, device=dev)
+        self.omega = torch.empty(n, dtype=torch.float64, device=dev)
+        self.pole = torch.empty(n, dtype=torch.float64, device=dev)
+        self.osc = torch.empty(n, dtype=torch.float64, device=dev)
+        self.eta = eta
+        self.set_grid(wgrid if wgrid is not None else np.linspace(-10, 20, 2000))
+
+    def set_grid(self, wgrid):
+        self.w = torch.as_tensor(np.asarray(wgrid, dtype=np.float64), device=self.s.device)
+        self.eps2 = torch.empty_like(self.w)
+
+    def project(self):
+        B.bse_project_blocks(self.s.problem, self.s.H, self.s.t["B"], [self.blk.c], [self.Hmu],
+                             [self.Bmu])
+
+    def eigh(self):
+        B.bse_block_eigh(self.Hmu, self.Bmu, self.eig_prec, self.omega, self.pole, self.osc,
+                         self.ws, nrefine=self.nrefine)
+
+    def spectrum(self):
+        B.bse_spectrum(self.pole, self.osc, 8 * math.pi / self.s.nk, self.eta, self.w, self.eps2)
+
+    def step(self):
+        """One pass of the hot path: build, project, block eigh, spectrum."""
+        self.s.build()
+        self.project()
+        self.eigh()
+        self.spectrum()
+
+    def results(self, nlow=100):
+        torch.cuda.synchronize()
+        return dict(omega=self.omega.cpu().numpy(), pole=self.pole.cpu().numpy(),
+                    osc=self.osc.cpu().numpy(), eps2=self.eps2.cpu().numpy(),
+                    lowest=self.omega[:nlow].cpu().numpy())

@@ -1,0 +1,119 @@
+"""C ABI: the library loads, exports what include/bse.h declares, its host-side
+integer tables equal the oracle's bit for bit, its per-orbit bases span the
+oracle's projector ranges, and invalid arguments are rejected before any
+device work.  No compute kernel is launched here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse as OB, groups, orbits
+from paper_2603_24860_amd import _lib, bse as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "bse.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"\b(bse_[a-z0-9_]+)\s*\(", hdr))
+    assert len(declared) >= 15
+    so = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared:
+        assert hasattr(so, name), name
+    assert declared == set(_lib.EXPORTS)
+
+
+@pytest.mark.parametrize("gname,grid", [("Oh", (2, 2, 2)), ("Oh", (3, 3, 3)), ("Oh", (4, 4, 4)),
+                                        ("Oh", (8, 8, 8)), ("D6h", (6, 6, 1)),
+                                        ("D6h", (12, 12, 1)), ("D6h", (5, 5, 1)),
+                                        ("D6h", (6, 6, 3)), ("Oh", (1, 1, 1))])
+def test_tables_bit_exact(gname, grid):
+    g = groups.group(gname)
+    T = B.bse_tables_build(gname, grid)
+    O = orbits.tables(grid, g["kmat"])
+    assert np.array_equal(T["korb"], O["korb"])
+    assert np.array_equal(T["korb_rep"], O["korb_reps"])
+    assert np.array_equal(T["porb"], O["porb"])
+    assert np.array_equal(T["porb_rep"], O["porb_reps"])
+    assert np.array_equal(T["pidx"], O["pidx"])
+    assert np.array_equal(T["pconj"], O["pconj"])
+    assert np.array_equal(T["cls_rep"], O["class_rep"])
+    assert np.array_equal(T["cls_selfswap"].astype(bool), O["class_selfswap"])
+    key = lambda a: sorted(r.tobytes() for r in np.asarray(a, dtype=np.int64))
+    assert key(T["kperm"]) == key(O["kperm"])
+
+
+@pytest.mark.parametrize("gname", ["Oh", "D6h"])
+def test_group_ops_and_characters(gname):
+    kmat, rcart = B.bse_group_ops(gname)
+    g = groups.group(gname)
+    idx = {m.astype(np.int64).tobytes(): i for i, m in enumerate(g["kmat"])}
+    perm = [idx[m.astype(np.int64).tobytes()] for m in kmat]
+    assert sorted(perm) == list(range(len(kmat)))
+    assert np.allclose(rcart, g["rcart"][perm])
+    for (nm, d, chi), (nm2, d2, chi2) in zip(B.bse_group_irreps(gname), g["irreps"]):
+        assert (nm, d) == (nm2, d2) and np.array_equal(chi, chi2[perm])
+
+
+@pytest.mark.parametrize("cfg", [dict(lattice="cubic", grid=(4, 4, 4), nv=3, nc=3),
+                                 dict(lattice="cubic", grid=(3, 3, 3), nv=2, nc=1),
+                                 dict(lattice="hex", grid=(6, 6, 1), nv=2, nc=2)])
+def test_block_basis_matches_projector(cfg):
+    c = dict(cfg, nmb=4, seed=1, name="t")
+    P = OB.make_problem(c)
+    gname = "Oh" if cfg["lattice"] == "cubic" else "D6h"
+    nb = cfg["nv"] * cfg["nc"]
+    for nm, d, chi in P["group"]["irreps"]:
+        b = B.bse_block_basis(gname, cfg["grid"], nm, cfg["nv"], cfg["nc"])
+        ob = OB.isotypic_basis(P, nm)
+        assert b["n"] == ob["n"]
+        assert np.array_equal(b["orb_dim"], ob["orb_dim"])
+        assert np.array_equal(b["orb_off"], ob["orb_off"])
+        if b["n"] == 0:
+            continue
+        # U assembled from the library's per-orbit coefficients
+        U = np.zeros((P["N"], b["n"]))
+        for o in range(len(b["orb_dim"])):
+            mem = b["members"][b["mem_off"][o]:b["mem_off"][o + 1]]
+            r = b["orb_dim"][o]
+            Uo = b["ubasis"][b["ub_off"][o]:b["ub_off"][o + 1]].reshape(len(mem), r)
+            for j in range(r):
+                for i, k in enumerate(mem):
+                    U[k * nb + np.arange(nb), b["orb_off"][o] + j * nb + np.arange(nb)] = Uo[i, j]
+        Pm = OB.full_projector(P, nm)
+        assert np.abs(U.T @ U - np.eye(b["n"])).max() < 1e-13
+        assert np.abs(Pm @ U - U).max() < 1e-13
+
+
+def test_invalid_arguments_rejected_on_host():
+    assert B.lib.bse_group_order(7) == _lib.EINVAL
+    with pytest.raises(B.BseError):
+        B.bse_tables_build("Oh", (4, 4, 3))  # grid not invariant under Oh
+    with pytest.raises(B.BseError):
+        B.bse_block_basis("Oh", (2, 2, 2), 99, 1, 1)
+    p = _lib.Problem()
+    assert B.lib.bse_build(ctypes.byref(p), 0, None, 0, None, 0, None) == _lib.EINVAL
+    p.grid[:] = [2, 2, 2]
+    p.nv, p.nc, p.nmb, p.nkorb, p.ncls, p.nqorb, p.in_fp64 = 7, 1, 4, 1, 1, 1, 1
+    assert B.lib.bse_build(ctypes.byref(p), 0, None, 0, None, 0, None) == _lib.EUNSUPPORTED
+    assert B.lib.bse_block_eigh(0, None, 0, 1, None, 0, 0, None, None, None, None, 0,
+                                None) == _lib.ESHAPE
+    assert B.lib.bse_spectrum(4, None, None, 1.0, 0.05, 10, None, None, None) == _lib.EINVAL
+    assert B.lib.bse_spectrum(0, None, None, 1.0, 0.05, 0, None, None, None) == _lib.OK
+    assert "NULL" in B.lib.bse_last_error().decode() or B.lib.bse_last_error() is not None
+
+
+def test_workload_inputs_identical_to_oracle_inputs():
+    """GPU-side inputs come from the library's tables, the oracle's from its
+    own; both key the same generator, so the arrays must be identical."""
+    import workloads
+    cfg = synth.config("cfg1")
+    _, _, T, inp = workloads.host_inputs(cfg)
+    P = OB.make_problem(cfg)
+    for k in ("ev", "ec", "vdiag", "mx", "mv", "mc", "w"):
+        assert np.array_equal(inp[k], P[k]), k
+    assert np.allclose(inp["B"], P["B"], atol=1e-15)

@@ -1,0 +1,47 @@
+"""Synthetic workloads for the GPU path: library tables + seeded generator.
+
+The library computes its own group operations and orbit tables (host C++);
+they key the seeded generator in `synth`, exactly as the oracle's own tables
+do on the CPU side.  Nothing here touches the oracle.
+"""
+import numpy as np
+
+import synth
+from paper_2603_24860_amd import bse as B
+
+
+def group_of(cfg):
+    return "Oh" if cfg.get("lattice", "cubic") == "cubic" else "D6h"
+
+
+def host_inputs(cfg, vector_dipole=True):
+    """Tables from the library and generated inputs (numpy, FP64)."""
+    group = group_of(cfg)
+    grid = tuple(cfg["grid"])
+    T = B.bse_tables_build(group, grid)
+    _, rcart = B.bse_group_ops(group)
+    nv, nc, nmb, seed = cfg["nv"], cfg["nc"], cfg["nmb"], cfg["seed"]
+    nk = T["nk"]
+    kl = np.arange(nk)
+    kfrac = np.stack([kl // (grid[1] * grid[2]), (kl // grid[2]) % grid[1], kl % grid[2]],
+                     axis=1) / np.asarray(grid, dtype=np.float64)
+    krep = T["korb_rep"][T["korb"]]
+    ev, ec = synth.band_energies(seed, cfg.get("lattice", "cubic"), grid, kfrac, krep, nv, nc)
+    inputs = dict(
+        ev=ev, ec=ec, vdiag=synth.coulomb_diag(nmb),
+        mx=synth.exchange_vectors(seed, T["korb_rep"], nv, nc, nmb),
+        mv=synth.pair_vectors(seed, "mv", T["cls_rep"], T["cls_selfswap"].astype(bool), nv, nmb),
+        mc=synth.pair_vectors(seed, "mc", T["cls_rep"], T["cls_selfswap"].astype(bool), nc, nmb),
+        w=synth.screened_w(seed, T["korb_rep"], nmb),
+        B=synth.dipoles(seed, T["kperm"], rcart, krep, nv, nc, vector=vector_dipole).reshape(-1),
+    )
+    return group, grid, T, inputs
+
+
+def device_system(cfg, prec, vector_dipole=True, zero_interaction=False, device="cuda"):
+    from paper_2603_24860_amd.system import DeviceSystem
+    group, grid, T, inputs = host_inputs(cfg, vector_dipole)
+    if zero_interaction:
+        inputs["vdiag"] = np.zeros_like(inputs["vdiag"])
+        inputs["w"] = np.zeros_like(inputs["w"])
+    return DeviceSystem(group, grid, cfg["nv"], cfg["nc"], cfg["nmb"], T, inputs, prec, device)
