@@ -217,6 +217,21 @@ int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, c
 int32_t bse_spectrum(int64_t n, const double *pole, const double *osc, double pref, double eta,
                      int64_t nw, const double *w, double *eps2, bse_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing (host).  bse_prof_enable(prefix) brackets every subsequent
+ * launch of a library kernel whose name starts with `prefix` with two HIP
+ * events on the launch stream ("" or NULL disables; "k_" times every kernel).
+ * bse_prof_collect() waits for the recorded events and adds their elapsed time
+ * to per-name totals; bse_prof_get() reads name (<= 31 chars), total
+ * milliseconds and launch count of entry i < bse_prof_count().  Timing adds
+ * two event records per launch, so enable it only for the kernels measured.
+ * ------------------------------------------------------------------------- */
+int32_t bse_prof_enable(const char *prefix);
+int32_t bse_prof_collect(void);
+int32_t bse_prof_count(void);
+int32_t bse_prof_get(int32_t i, char *h_name32, double *h_total_ms, int64_t *h_launches);
+int32_t bse_prof_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

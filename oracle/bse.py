@@ -77,17 +77,18 @@ def exchange(P):
     return (2.0 / P["nk"]) * (Mx * P["vdiag"][None, :]) @ Mx.conj().T
 
 
-def direct(P):
+def direct(P, qs=None):
     """1/N_k sum_IJ conj(M_c[k,k'][c,c',I]) W_IJ(k-k') M_v[k,k'][v,v',J]  (N x N).
 
-    Loop over q outermost (Sec. III.C.2), all k for each q.
+    Loop over q outermost (Sec. III.C.2), all k for each q.  `qs` restricts the
+    loop to a subset of q (the other pairs stay zero); used to time a sample.
     """
     nk, nv, nc = P["nk"], P["nv"], P["nc"]
     T = P["T"]
     D = np.zeros((nk, nv, nc, nk, nv, nc), dtype=np.complex128)
     qidx = T["qidx"].reshape(nk, nk)
     kk = np.arange(nk)
-    for q in range(nk):
+    for q in (range(nk) if qs is None else qs):
         kq = np.array([int(np.nonzero(qidx[k] == q)[0][0]) for k in kk])  # k' = k - q
         W = P["w"][T["qorb"][q]]
         Mv = pair_block(P, "mv", kk, kq)       # [nk, nv, nv, nmb]

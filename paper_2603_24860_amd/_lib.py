@@ -52,6 +52,11 @@ class Block(ctypes.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime with the same SONAME (libamdhip64.so.7)
+    # as the ROCm one libbse.so is linked against.  Loading torch first makes
+    # the library bind to that runtime, so kernels launched here and the torch
+    # allocations and streams they use live in one HIP runtime instance.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2603_24860_amd.build_lib`")
@@ -76,6 +81,11 @@ def _load():
         "bse_block_eigh": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp,
                                  ctypes.c_size_t, vp]),
         "bse_spectrum": (i32, [i64, vp, vp, f64, f64, i64, vp, vp, vp]),
+        "bse_prof_enable": (i32, [ctypes.c_char_p]),
+        "bse_prof_collect": (i32, []),
+        "bse_prof_count": (i32, []),
+        "bse_prof_get": (i32, [i32, ctypes.c_char_p, P(f64), P(i64)]),
+        "bse_prof_reset": (i32, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

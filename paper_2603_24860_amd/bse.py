@@ -157,3 +157,27 @@ def bse_block_eigh(Hmu, Bmu, prec, omega, pole, osc, ws, nrefine=0, stream=None)
 def bse_spectrum(pole, osc, pref, eta, w, eps2, stream=None):
     check(lib.bse_spectrum(pole.numel(), _ptr(pole), _ptr(osc), float(pref), float(eta),
                            w.numel(), _ptr(w), _ptr(eps2), _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# kernel timing
+# --------------------------------------------------------------------------
+def bse_prof_enable(prefix):
+    check(lib.bse_prof_enable(prefix.encode() if prefix else None))
+
+
+def bse_prof_collect():
+    """Wait for the recorded events; returns {kernel: (total_ms, launches)}."""
+    check(lib.bse_prof_collect())
+    out = {}
+    for i in range(check(lib.bse_prof_count())):
+        name = ctypes.create_string_buffer(32)
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        check(lib.bse_prof_get(i, name, ctypes.byref(ms), ctypes.byref(cnt)))
+        out[name.value.decode()] = (ms.value, cnt.value)
+    return out
+
+
+def bse_prof_reset():
+    check(lib.bse_prof_reset())

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_direct_d(int n1, int n2, int n3, int nv,
   int at[D_MB];
 #pragma unroll
   for (int mi = 0; mi < D_MB; ++mi) {
-    const int R = 16 * mi + r16;
+    const int R = 16 * mi + Mfma<T>::arow(r16);
     arow[mi] = nullptr;
     at[mi] = R & 1;
     if (mi < mb && R < 2 * ncc) {
@@ -394,18 +394,18 @@ extern "C" int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_
     constexpr int BM = BuildTile<T>::BM, BN = BuildTile<T>::BN;
     dim3 gx((unsigned)((N + BN - 1) / BN), (unsigned)((2 * N + BM - 1) / BM));
     if (gx.y > 65535u) return fail(BSE_ESHAPE, "N too large for the exchange grid");
-    hipLaunchKernelGGL(k_exchange<T>, gx, dim3(NT), 0, s, nk, p->nv, p->nc, p->nmb, p->korb,
+    BSE_LAUNCH("k_exchange", k_exchange<T>, gx, dim3(NT), 0, s, nk, p->nv, p->nc, p->nmb, p->korb,
                        (const T *)p->mx, p->vdiag, p->ev, p->ec, (T *)H, ldh, 2.0 * inv_nk);
     BSE_HIP_CHECK(hipGetLastError());
     const int64_t M = 2 * int64_t(nk) * p->nv * p->nv;
     for (int q0 = 0; q0 < nk; q0 += qb) {
       const int nq = std::min(qb, nk - q0);
       dim3 g1((unsigned)((p->nmb + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)nq);
-      hipLaunchKernelGGL(k_direct_t<T>, g1, dim3(NT), 0, s, n1, n2, n3, p->nv, p->nmb, q0,
+      BSE_LAUNCH("k_direct_t", k_direct_t<T>, g1, dim3(NT), 0, s, n1, n2, n3, p->nv, p->nmb, q0,
                          p->qorb, p->pidx, p->pconj, (const T *)p->mv, (const T *)p->w, (T *)ws);
       BSE_HIP_CHECK(hipGetLastError());
       dim3 g2((unsigned)((nk + 3) / 4), (unsigned)nq);
-      hipLaunchKernelGGL(k_direct_d<T>, g2, dim3(NT), 0, s, n1, n2, n3, p->nv, p->nc, p->nmb, q0,
+      BSE_LAUNCH("k_direct_d", k_direct_d<T>, g2, dim3(NT), 0, s, n1, n2, n3, p->nv, p->nc, p->nmb, q0,
                          p->pidx, p->pconj, (const T *)p->mc, (const T *)ws, (T *)H, ldh, inv_nk);
       BSE_HIP_CHECK(hipGetLastError());
     }

@@ -11,19 +11,23 @@
 //     is annihilated below the subdiagonal by a reflector acting on rows
 //     j+1..n-1, so Q e_1 = e_1 stays true.  Within a panel of NBK columns the
 //     trailing matrix is updated lazily (A - V W^dag - W V^dag); after the panel
-//     the rank-2 NBK update runs on MFMA.  Per column: K_refl (one workgroup:
-//     reflector scalars), K_hemv (y = A22 v plus the panel dot products, bound
-//     by HBM bandwidth), K_reduce, K_w (w = tau (y - V q - W p)), K_col
-//     (finish w, update the next column).  The panel and all scalar work are
-//     FP64; A is stored in FP64 or (prec FP32) FP32.
+//     the rank-2 NBK update runs on MFMA.  Three kernels per column, one per
+//     global dependency: k_hemv2 (reflector scalars from the column norm, then
+//     y = A22 v, bound by HBM bandwidth), k_w (w = tau (y - V q - W p)), k_col
+//     (finish w with its global dot product, update the next column, partial
+//     norm and panel dot products for the next reflector).  The panel and all
+//     scalar work are FP64; A is stored in FP64 or (prec FP32) FP32.
 //  3. T is real symmetric tridiagonal (the reflectors make the subdiagonal
 //     real).  All eigenvalues by bisection on Sturm counts (one thread per
 //     eigenvalue, FP64).  Because Q0 Q maps e_1 to e_1,
-//     |B_l|^2 = beta0^2 z_l(0)^2 with z_l the eigenvectors of T; only the
-//     leading unreduced block of T (the Krylov space of B_mu) has z_l(0) != 0,
-//     and there z_l(0)^2 = 1 / h'(Omega_l) for the continued fraction
-//     h(x) = x - d_0 - e_0^2 / (x - d_1 - e_1^2 / ...), whose zeros are the
-//     block's eigenvalues.
+//     |B_l|^2 = beta0^2 z_l(0)^2 with z_l the eigenvectors of T, and for a
+//     cluster of (numerically) degenerate eigenvalues the summed weight is the
+//     residue of G(z) = [(z - T)^-1]_00 = 1 / (z - d_0 - e_0^2 / (z - d_1 - ...))
+//     at the cluster.  It is computed by the trapezoidal rule on a circle
+//     around the cluster whose radius is the geometric mean of the cluster
+//     width and the distance to the next eigenvalue (error decays like
+//     (width / distance)^(M/2) with M nodes); off the real axis the continued
+//     fraction has no vanishing pivots.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -80,13 +84,15 @@ struct Ws {
   double2 *y;        // [n] hemv output
   double2 *wraw;     // [n]
   double2 *vbuf;     // [n] current reflector
-  double2 *part;     // [PMAX][2 NBK]
+  double2 *part;     // [PMAX][2 NBK] panel dot partials (k_col)
   double2 *part2;    // [PMAX]
   double *part3;     // [PMAX]
   double2 *pq;       // [2 NBK]
   double2 *tau;      // [n + 1], index j + 1
   double2 *scl;      // [n + 1]
   double *d, *e;     // [n]
+  double *e2;        // [n] squared subdiagonal
+  double *tsc;       // [8] tridiagonal scalars
   double *beta0;     // [1]
 };
 constexpr int PMAX = 1024;
@@ -121,6 +127,8 @@ size_t ws_layout(int64_t n, bool a_fp64, Ws *w, char *base) {
   t.scl = (double2 *)take(size_t(n + 1) * 16);
   t.d = (double *)take(size_t(n) * 8);
   t.e = (double *)take(size_t(n) * 8);
+  t.e2 = (double *)take(size_t(n) * 8);
+  t.tsc = (double *)take(8 * 8);
   t.beta0 = (double *)take(8);
   if (w) *w = t;
   return off;
@@ -156,76 +164,75 @@ __global__ void k_load_b(int64_t n, const double2 *__restrict__ B, double2 *__re
     for (int i = gridDim.x; i < np3; ++i) part3[i] = 0;
 }
 
-// Reflector for column jr (acting on rows jr+1..n-1), LAPACK zlarfg semantics:
-// (I - tau v v^dag)^dag (alpha, x) = (beta, 0), v = (1, x / (alpha - beta)).
-// Writes d[jr], e[jr] (or beta0 for jr = -1), tau, scale, vbuf and V[:, ir].
-__global__ __launch_bounds__(RNT) void k_refl(int64_t n, int64_t jr, int64_t j0, int ir,
-                                              const double2 *__restrict__ col,
-                                              const double *__restrict__ part3, int np3,
-                                              double *__restrict__ d, double *__restrict__ e,
-                                              double *__restrict__ beta0, double2 *__restrict__ tau,
-                                              double2 *__restrict__ scl,
-                                              double2 *__restrict__ vbuf,
-                                              double2 *__restrict__ V) {
-  __shared__ double sh[RNT / 64];
-  __shared__ double2 s_scale;
-  double s = 0;
-  for (int i = threadIdx.x; i < np3; i += RNT) s += part3[i];
-  const double xn2 = block_sum<RNT>(s, sh);
-  if (threadIdx.x == 0) {
-    if (jr >= 0) d[jr] = col[jr].x;
-    double2 t = {0, 0}, sc = {0, 0};
-    if (jr + 1 < n) {
-      const double2 al = col[jr + 1];
-      double beta;
-      if (xn2 == 0.0 && al.y == 0.0) {
-        beta = al.x;
-      } else {
-        const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
-        beta = al.x >= 0 ? -nrm : nrm;
-        t = double2{(beta - al.x) / beta, -al.y / beta};
-        const double2 den = {al.x - beta, al.y};  // 1 / (alpha - beta)
-        const double dd = den.x * den.x + den.y * den.y;
-        sc = double2{den.x / dd, -den.y / dd};
-      }
-      if (jr >= 0)
-        e[jr] = beta;
-      else
-        beta0[0] = beta;
-    }
-    tau[jr + 1] = t;
-    scl[jr + 1] = sc;
-    s_scale = sc;
-  }
-  __syncthreads();
-  const double2 sc = s_scale;
-  const int64_t lo = jr < 0 ? 0 : std::min<int64_t>(jr, j0);
-  for (int64_t r = lo + threadIdx.x; r < n; r += RNT) {
-    double2 v = {0, 0};
-    if (r == jr + 1)
-      v = double2{1, 0};
-    else if (r > jr + 1)
-      v = cmul(col[r], sc);
-    if (r >= 0) vbuf[r] = v;
-    if (ir >= 0 && r >= j0) V[r * NBK + ir] = v;
-  }
-}
-
-// y[r] = sum_{c >= m0} A[r][c] v[c] for r >= m0, plus the panel dot products
-// p_l = sum_r conj(V[r][l]) v[r], q_l = sum_r conj(W[r][l]) v[r] (l < i) over
-// this workgroup's rows.  One wave per row.
+// Reflector of column jr (acting on rows jr+1..n-1) with LAPACK's zlarfg
+// semantics, (I - tau v v^dag)^dag (alpha, x) = (beta, 0) and
+// v = (1, x / (alpha - beta)), followed by y[r] = sum_{c > jr} A[r][c] v[c]
+// for r > jr (one wave per row).  Every workgroup recomputes the scalars from
+// the column norm partials (a few dozen values); workgroup 0 stores them, the
+// panel dot products p_l = V[:,l]^dag v and q_l = W[:,l]^dag v (l < ir, from
+// k_col's partials) and the zeros of v above row jr+1.  v is formed on the fly
+// from the updated column, and each wave stores v and V[:, ir] for its rows.
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_hemv(int64_t n, int64_t m0, int i, int rpw,
-                                              const TA *__restrict__ A, int64_t lda,
-                                              const double2 *__restrict__ vbuf,
-                                              const double2 *__restrict__ V,
-                                              const double2 *__restrict__ W,
-                                              double2 *__restrict__ y, double2 *__restrict__ part) {
+__global__ __launch_bounds__(ENT) void k_hemv2(int64_t n, int64_t jr, int64_t j0, int ir, int rpw,
+                                               const TA *__restrict__ A, int64_t lda,
+                                               const double2 *__restrict__ col,
+                                               const double *__restrict__ part3,
+                                               const double2 *__restrict__ partd, int np3,
+                                               double *__restrict__ d, double *__restrict__ e,
+                                               double *__restrict__ beta0,
+                                               double2 *__restrict__ tau,
+                                               double2 *__restrict__ scl,
+                                               double2 *__restrict__ vbuf,
+                                               double2 *__restrict__ V,
+                                               const double2 *__restrict__ W,
+                                               double2 *__restrict__ y, double2 *__restrict__ pq) {
   typedef typename C2T<TA>::t CA;
-  __shared__ double2 sdot[ENT / 64][2 * NBK];
+  __shared__ double sh[ENT / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t m0 = jr + 1;
+  double s = 0;
+  for (int p = threadIdx.x; p < np3; p += ENT) s += part3[p];
+  const double xn2 = block_sum<ENT>(s, sh);
+  const double2 al = col[m0];
+  double beta;
+  double2 t = {0, 0}, sc = {0, 0};
+  if (xn2 == 0.0 && al.y == 0.0) {
+    beta = al.x;
+  } else {
+    const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+    beta = al.x >= 0 ? -nrm : nrm;
+    t = double2{(beta - al.x) / beta, -al.y / beta};
+    const double2 den = {al.x - beta, al.y};
+    const double dd = den.x * den.x + den.y * den.y;
+    sc = double2{den.x / dd, -den.y / dd};
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      if (jr >= 0) {
+        d[jr] = col[jr].x;
+        e[jr] = beta;
+      } else {
+        beta0[0] = beta;
+      }
+      tau[jr + 1] = t;
+      scl[jr + 1] = sc;
+    }
+    if (threadIdx.x < 2 * NBK) {  // panel dot products for k_w
+      const int slot = threadIdx.x, l = slot % NBK;
+      double2 acc = {0, 0};
+      if (l < ir) {
+        for (int p = 0; p < np3; ++p) acc = cadd(acc, partd[int64_t(p) * 2 * NBK + slot]);
+        const double2 head = slot < NBK ? V[m0 * NBK + l] : W[m0 * NBK + l];
+        acc = cadd(double2{head.x, -head.y}, cmul(sc, acc));
+      }
+      pq[slot] = acc;
+    }
+    for (int64_t r = std::max<int64_t>(0, ir >= 0 ? j0 : 0) + threadIdx.x; r < m0; r += ENT) {
+      vbuf[r] = double2{0, 0};
+      if (ir >= 0) V[r * NBK + ir] = double2{0, 0};
+    }
+  }
   const int64_t rbase = m0 + (int64_t(blockIdx.x) * (ENT / 64) + wv) * rpw;
-  double2 dp = {0, 0}, dq = {0, 0};  // lane l < i: p_l, q_l partial; lane holds index lane
   for (int rr = 0; rr < rpw; ++rr) {
     const int64_t r = rbase + rr;
     if (r >= n) break;
@@ -233,45 +240,18 @@ __global__ __launch_bounds__(ENT) void k_hemv(int64_t n, int64_t m0, int i, int 
     double sr = 0, si = 0;
     for (int64_t c = m0 + lane; c < n; c += 64) {
       const double2 a = to_d2(arow[c]);
-      const double2 v = vbuf[c];
+      const double2 v = c == m0 ? double2{1, 0} : cmul(col[c], sc);
       sr += a.x * v.x - a.y * v.y;
       si += a.x * v.y + a.y * v.x;
     }
     sr = wave_sum(sr);
     si = wave_sum(si);
-    if (lane == 0) y[r] = double2{sr, si};
-    if (lane < i) {
-      const double2 vr = vbuf[r];
-      dp = cadd(dp, cmulc(V[r * NBK + lane], vr));
-      dq = cadd(dq, cmulc(W[r * NBK + lane], vr));
+    if (lane == 0) {
+      y[r] = double2{sr, si};
+      const double2 v = r == m0 ? double2{1, 0} : cmul(col[r], sc);
+      vbuf[r] = v;
+      if (ir >= 0) V[r * NBK + ir] = v;
     }
-  }
-  if (lane < NBK) {
-    sdot[wv][lane] = dp;
-    sdot[wv][NBK + lane] = dq;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * NBK) {
-    double2 s = {0, 0};
-    for (int w = 0; w < ENT / 64; ++w) s = cadd(s, sdot[w][threadIdx.x]);
-    part[int64_t(blockIdx.x) * 2 * NBK + threadIdx.x] = s;
-  }
-}
-
-__global__ __launch_bounds__(RNT) void k_reduce(int np, int i, const double2 *__restrict__ part,
-                                                double2 *__restrict__ pq) {
-  // pq[l] = sum over workgroups of part[.][l] for l < i (p) and NBK + l (q)
-  __shared__ double2 sh[RNT];
-  const int slot = threadIdx.x % (2 * NBK), grp = threadIdx.x / (2 * NBK);
-  constexpr int G = RNT / (2 * NBK);
-  double2 s = {0, 0};
-  for (int p = grp; p < np; p += G) s = cadd(s, part[int64_t(p) * 2 * NBK + slot]);
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < 2 * NBK) {
-    double2 t = {0, 0};
-    for (int g = 0; g < G; ++g) t = cadd(t, sh[g * 2 * NBK + threadIdx.x]);
-    pq[threadIdx.x] = t;
   }
 }
 
@@ -311,7 +291,10 @@ __global__ __launch_bounds__(ENT) void k_w(int64_t n, int64_t m0, int i, int64_t
 // Finish W[:, i] = wraw + alpha v (alpha = -tau_j (w^dag v) / 2) for column j
 // (fin != 0), then update column jr (panel index ir) with the panel's
 // reflectors: col[r] = A[r][jr] - sum_{l < ir} (V[r][l] conj(W[jr][l]) +
-// W[r][l] conj(V[jr][l])), and partial |col[r]|^2 over r >= jr + 2.
+// W[r][l] conj(V[jr][l])).  Per workgroup it stores the partial |col[r]|^2 and
+// the partial sums conj(V[r][l]) col[r], conj(W[r][l]) col[r] (l < ir) over
+// rows r >= jr + 2, which k_hemv2 turns into the next reflector and its panel
+// dot products.  For jr = n - 1 it stores the last diagonal element.
 template <typename TA>
 __global__ __launch_bounds__(ENT) void k_col(int64_t n, int64_t rlo, int fin, int64_t j, int i,
                                              int64_t j0, int64_t jr, int ir,
@@ -322,10 +305,14 @@ __global__ __launch_bounds__(ENT) void k_col(int64_t n, int64_t rlo, int fin, in
                                              const double2 *__restrict__ part2, int np2,
                                              const double2 *__restrict__ tau,
                                              double2 *__restrict__ col,
-                                             double *__restrict__ part3) {
+                                             double *__restrict__ part3,
+                                             double2 *__restrict__ partd,
+                                             double *__restrict__ d) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
   __shared__ double2 swj[NBK], svj[NBK];
+  __shared__ double2 scol[ENT];
+  __shared__ double2 sdot[4][2 * NBK];
   double2 alpha = {0, 0};
   if (fin) {
     double sr = 0, si = 0;
@@ -354,13 +341,14 @@ __global__ __launch_bounds__(ENT) void k_col(int64_t n, int64_t rlo, int fin, in
   __syncthreads();
   const int64_t r = rlo + int64_t(blockIdx.x) * ENT + threadIdx.x;
   double s = 0;
+  double2 a = {0, 0};
   if (r < n) {
     if (fin && r >= j0) {
       const double2 w = r >= j + 1 ? cadd(wraw[r], cmul(alpha, vbuf[r])) : double2{0, 0};
       W[r * NBK + i] = w;
     }
     if (jr >= 0 && r >= jr) {
-      double2 a = to_d2(reinterpret_cast<const CA *>(A)[r * lda + jr]);
+      a = to_d2(reinterpret_cast<const CA *>(A)[r * lda + jr]);
       for (int l = 0; l < ir; ++l) {
         const double2 vrl = V[r * NBK + l];
         const double2 wrl = (fin && l == i) ? (r >= j + 1 ? cadd(wraw[r], cmul(alpha, vbuf[r]))
@@ -371,11 +359,37 @@ __global__ __launch_bounds__(ENT) void k_col(int64_t n, int64_t rlo, int fin, in
         a = csub(a, cmul(wrl, double2{svj[l].x, -svj[l].y}));
       }
       col[r] = a;
+      if (r == n - 1 && jr == n - 1) d[n - 1] = a.x;
       if (r >= jr + 2) s = a.x * a.x + a.y * a.y;
     }
   }
   s = block_sum<ENT>(s, sh);
   if (threadIdx.x == 0) part3[blockIdx.x] = s;
+  if (ir > 0) {
+    // partial panel dot products over this workgroup's rows r >= jr + 2
+    scol[threadIdx.x] = (r < n && r >= jr + 2) ? a : double2{0, 0};
+    __syncthreads();  // also orders the W[:, i] stores above
+    const int slot = threadIdx.x % (2 * NBK), q = threadIdx.x / (2 * NBK), l = slot % NBK;
+    double2 acc = {0, 0};
+    if (l < ir) {
+      const int64_t rb = rlo + int64_t(blockIdx.x) * ENT;
+      for (int t = q * 64; t < q * 64 + 64; ++t) {
+        const int64_t rr = rb + t;
+        if (rr >= n) break;
+        const double2 c = scol[t];
+        if (c.x == 0.0 && c.y == 0.0) continue;
+        const double2 m = slot < NBK ? V[rr * NBK + l] : W[rr * NBK + l];
+        acc = cadd(acc, cmulc(m, c));
+      }
+    }
+    sdot[q][slot] = acc;
+    __syncthreads();
+    if (threadIdx.x < 2 * NBK) {
+      double2 t4 = {0, 0};
+      for (int qq = 0; qq < 4; ++qq) t4 = cadd(t4, sdot[qq][threadIdx.x]);
+      partd[int64_t(blockIdx.x) * 2 * NBK + threadIdx.x] = t4;
+    }
+  }
 }
 
 // Initial two-sided reflection: A -= v w^dag + w v^dag with w = wraw + alpha v.
@@ -474,85 +488,141 @@ __global__ __launch_bounds__(ENT) void k_her2k(int64_t n, int64_t c0, int nbk,
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal eigenvalues (bisection) and leading-block weights
+// tridiagonal eigenvalues (bisection) and cluster weights
 // ---------------------------------------------------------------------------
-__device__ int sturm_count(const double *d, const double *e, int64_t lo, int64_t hi, double x,
-                           double pivmin) {
-  // number of eigenvalues of T[lo..hi] below x
+// 1 / x to full double precision: hardware estimate plus two Newton steps
+// (arguments are kept away from zero and denormals by the pivot guard).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// scalars: [0] Gershgorin low, [1] high, [2] |T| (max row sum), [3] pivmin,
+// [4] cluster gap tolerance
+__global__ __launch_bounds__(RNT) void k_tri_prep(int64_t n, const double *__restrict__ d,
+                                                  const double *__restrict__ e, double ctol_rel,
+                                                  double *__restrict__ e2,
+                                                  double *__restrict__ sc) {
+  __shared__ double s_lo[RNT / 64], s_hi[RNT / 64], s_tn[RNT / 64];
+  double lo = 1e300, hi = -1e300, tn = 0;
+  for (int64_t k = threadIdx.x; k < n; k += RNT) {
+    const double el = k > 0 ? fabs(e[k - 1]) : 0.0, er = k + 1 < n ? fabs(e[k]) : 0.0;
+    lo = fmin(lo, d[k] - el - er);
+    hi = fmax(hi, d[k] + el + er);
+    tn = fmax(tn, fabs(d[k]) + el + er);
+    if (k + 1 < n) e2[k] = e[k] * e[k];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    tn = fmax(tn, __shfl_xor(tn, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[w] = lo;
+    s_hi[w] = hi;
+    s_tn[w] = tn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < RNT / 64; ++i) {
+      lo = fmin(lo, s_lo[i]);
+      hi = fmax(hi, s_hi[i]);
+      tn = fmax(tn, s_tn[i]);
+    }
+    lo = fmin(lo, s_lo[0]);
+    hi = fmax(hi, s_hi[0]);
+    tn = fmax(tn, s_tn[0]);
+    const double pivmin = 1e-100 * fmax(1.0, tn);
+    const double pad = 4.4e-16 * fmax(1.0, tn) * double(n) + pivmin;
+    sc[0] = lo - pad;
+    sc[1] = hi + pad;
+    sc[2] = tn;
+    sc[3] = pivmin;
+    sc[4] = ctol_rel * fmax(1.0, tn);
+  }
+}
+
+// number of eigenvalues of T below x (LDL^T Sturm sequence with pivot guard)
+__device__ __forceinline__ int sturm_count(const double *__restrict__ d,
+                                           const double *__restrict__ e2, int64_t n, double x,
+                                           double pivmin) {
   int cnt = 0;
-  double q = 1.0;
-  for (int64_t k = lo; k <= hi; ++k) {
-    const double off = k > lo ? e[k - 1] : 0.0;
-    q = d[k] - x - (k > lo ? off * off / q : 0.0);
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0;
+  for (int64_t k = 1; k < n; ++k) {
+    q = d[k] - x - e2[k - 1] * rcp64(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0;
   }
   return cnt;
 }
 
-__device__ double bisect(const double *d, const double *e, int64_t lo, int64_t hi, int64_t idx,
-                         double glo, double ghi, double pivmin) {
-  double a = glo, b = ghi;
-  for (int it = 0; it < 200; ++it) {
+__global__ void k_bisect(int64_t n, const double *__restrict__ d, const double *__restrict__ e2,
+                         const double *__restrict__ sc, double *__restrict__ omega) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = sc[0], b = sc[1];
+  const double pivmin = sc[3];
+  for (int it = 0; it < 128; ++it) {
     const double mid = 0.5 * (a + b);
     if (mid <= a || mid >= b) break;
-    if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
-    if (sturm_count(d, e, lo, hi, mid, pivmin) > idx)
+    if (b - a <= 2.3e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+    if (sturm_count(d, e2, n, mid, pivmin) > i)
       b = mid;
     else
       a = mid;
   }
-  return 0.5 * (a + b);
+  omega[i] = 0.5 * (a + b);
 }
 
-__global__ void k_tridiag(int64_t n, const double *__restrict__ d, const double *__restrict__ e,
-                          const double *__restrict__ beta0, double split_rel,
-                          double *__restrict__ omega, double *__restrict__ pole,
+// Weights: a cluster is a maximal run of eigenvalues whose consecutive gaps
+// are <= sc[4]; its head (first index) gets the cluster centre as pole and
+// beta0^2 times the residue of G(z) = [(z - T)^-1]_00 as strength, the other
+// members get zero strength.
+constexpr int NCONT = 64;  // trapezoidal nodes on the circle
+__global__ void k_weights(int64_t n, const double *__restrict__ d, const double *__restrict__ e2,
+                          const double *__restrict__ sc, const double *__restrict__ beta0,
+                          const double *__restrict__ omega, double *__restrict__ pole,
                           double *__restrict__ osc) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  // norm and Gershgorin interval of T
-  double tn = 0, glo = 1e300, ghi = -1e300;
-  for (int64_t k = 0; k < n; ++k) {
-    const double r = (k > 0 ? fabs(e[k - 1]) : 0.0) + (k + 1 < n ? fabs(e[k]) : 0.0);
-    glo = fmin(glo, d[k] - r);
-    ghi = fmax(ghi, d[k] + r);
-    tn = fmax(tn, fabs(d[k]) + r);
+  const double ctol = sc[4];
+  const double li = omega[i];
+  if (i > 0 && li - omega[i - 1] <= ctol) {
+    pole[i] = li;
+    osc[i] = 0.0;
+    return;
   }
-  const double pivmin = 1e-100 * fmax(1.0, tn);
-  const double pad = 4.4e-16 * fmax(1.0, tn) * n + pivmin;
-  glo -= pad;
-  ghi += pad;
-  omega[i] = bisect(d, e, 0, n - 1, i, glo, ghi, pivmin);
-  // leading unreduced block [0, s]
-  const double tol = split_rel * tn;
-  int64_t s = n - 1;
-  for (int64_t k = 0; k + 1 < n; ++k)
-    if (fabs(e[k]) <= tol) {
-      s = k;
-      break;
+  int64_t j = i;
+  while (j + 1 < n && omega[j + 1] - omega[j] <= ctol) ++j;
+  const double c = 0.5 * (omega[i] + omega[j]), half = 0.5 * (omega[j] - omega[i]);
+  double g = 1e300;
+  if (i > 0) g = fmin(g, c - omega[i - 1]);
+  if (j + 1 < n) g = fmin(g, omega[j + 1] - c);
+  if (g > 1e299) g = fmax(1.0, sc[2]);
+  const double rad = sqrt(fmax(half, 1e-6 * g) * g);
+  double wsum = 0.0;
+  for (int m = 0; m < NCONT / 2; ++m) {
+    const double th = 6.283185307179586 * (m + 0.5) / NCONT;
+    const double zx = c + rad * cos(th), zy = rad * sin(th);
+    // h = z - d_{n-1}; h = z - d_k - e_k^2 / h, k = n-2 .. 0; G = 1 / h
+    double hx = zx - d[n - 1], hy = zy;
+    for (int64_t k = n - 2; k >= 0; --k) {
+      const double inv = e2[k] / (hx * hx + hy * hy);
+      hx = zx - d[k] - hx * inv;
+      hy = zy + hy * inv;
     }
-  double p = 0, w = 0;
-  if (i <= s) {
-    double blo = 1e300, bhi = -1e300;
-    for (int64_t k = 0; k <= s; ++k) {
-      const double r = (k > 0 ? fabs(e[k - 1]) : 0.0) + (k < s ? fabs(e[k]) : 0.0);
-      blo = fmin(blo, d[k] - r);
-      bhi = fmax(bhi, d[k] + r);
-    }
-    p = bisect(d, e, 0, s, i, blo - pad, bhi + pad, pivmin);
-    // h(x) = x - d_k - e_k^2 / h_{k+1}, h' = 1 + (e_k^2 / h_{k+1}^2) h'_{k+1}
-    double h = p - d[s], hp = 1.0;
-    for (int64_t k = s - 1; k >= 0; --k) {
-      if (fabs(h) < pivmin) h = h < 0 ? -pivmin : pivmin;
-      const double t = e[k] * e[k] / h;
-      hp = 1.0 + (t / h) * hp;
-      h = p - d[k] - t;
-    }
-    w = beta0[0] * beta0[0] / hp;
+    const double den = hx * hx + hy * hy;
+    const double gx = hx / den, gy = -hy / den;
+    // Re[G (z - c)] with z - c = rad (cos, sin)
+    wsum += gx * rad * cos(th) - gy * rad * sin(th);
   }
-  pole[i] = p;
-  osc[i] = w;
+  pole[i] = c;
+  osc[i] = beta0[0] * beta0[0] * wsum * 2.0 / NCONT;
 }
 
 }  // namespace
@@ -577,63 +647,52 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, int32_
   const int64_t lda = w.lda;
   {
     dim3 g((unsigned)std::min<int64_t>((n + ENT - 1) / ENT, 64), (unsigned)n);
-    hipLaunchKernelGGL((k_copy_in<TH, TA>), g, dim3(ENT), 0, s, n, (const TH *)Hmu, ld, A, lda);
+    BSE_LAUNCH("k_copy_in", (k_copy_in<TH, TA>), g, dim3(ENT), 0, s, n, (const TH *)Hmu, ld, A, lda);
   }
   auto nwg_rows = [](int64_t m) { return (unsigned)std::max<int64_t>(1, (m + ENT - 1) / ENT); };
-  // ---- initial reflection: B -> beta0 e_1 ----
+  auto hemv = [&](int64_t jr, int64_t j0, int ir, int np3) {
+    const int64_t m = n - (jr + 1);
+    const int rpw = hemv_rpw(m);
+    const unsigned gh = (unsigned)std::max<int64_t>(1, (m + 4 * rpw - 1) / (4 * rpw));
+    BSE_LAUNCH("k_hemv2", k_hemv2<TA>, dim3(gh), dim3(ENT), 0, s, n, jr, j0, ir, rpw, A, lda,
+               w.col, w.part3, w.part, np3, w.d, w.e, w.beta0, w.tau, w.scl, w.vbuf, w.V, w.W,
+               w.y, w.pq);
+  };
+  // ---- initial reflection: B -> beta0 e_1, A <- Q0^dag A Q0 ----
   {
     const unsigned g = std::min<unsigned>(nwg_rows(n), PMAX);
-    hipLaunchKernelGGL(k_load_b, dim3(g), dim3(ENT), 0, s, n, (const double2 *)Bmu, w.col,
-                       w.part3, (int)g);
-    hipLaunchKernelGGL(k_refl, dim3(1), dim3(RNT), 0, s, n, int64_t(-1), int64_t(0), -1, w.col,
-                       w.part3, (int)g, w.d, w.e, w.beta0, w.tau, w.scl, w.vbuf, w.V);
-    const int rpw = hemv_rpw(n);
-    const unsigned gh = (unsigned)((n + 4 * rpw - 1) / (4 * rpw));
-    hipLaunchKernelGGL(k_hemv<TA>, dim3(gh), dim3(ENT), 0, s, n, int64_t(0), 0, rpw, A, lda,
-                       w.vbuf, w.V, w.W, w.y, w.part);
+    BSE_LAUNCH("k_load_b", k_load_b, dim3(g), dim3(ENT), 0, s, n, (const double2 *)Bmu, w.col,
+               w.part3, (int)g);
+    hemv(-1, 0, -1, (int)g);
     const unsigned gw = nwg_rows(n);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RNT), 0, s, 0, 0, w.part, w.pq);
-    hipLaunchKernelGGL(k_w, dim3(gw), dim3(ENT), 0, s, n, int64_t(0), 0, int64_t(0), w.V, w.W, w.y,
-                       w.pq, w.vbuf, w.tau, w.wraw, w.part2);
+    BSE_LAUNCH("k_w", k_w, dim3(gw), dim3(ENT), 0, s, n, int64_t(0), 0, int64_t(0), w.V, w.W, w.y,
+               w.pq, w.vbuf, w.tau, w.wraw, w.part2);
     dim3 gr((unsigned)std::min<int64_t>((n + ENT - 1) / ENT, 16), (unsigned)n);
-    hipLaunchKernelGGL(k_rank2<TA>, gr, dim3(ENT), 0, s, n, A, lda, w.wraw, w.vbuf, w.part2,
-                       (int)gw, w.tau);
+    BSE_LAUNCH("k_rank2", k_rank2<TA>, gr, dim3(ENT), 0, s, n, A, lda, w.wraw, w.vbuf, w.part2,
+               (int)gw, w.tau);
     BSE_HIP_CHECK(hipGetLastError());
   }
   // ---- blocked tridiagonalisation ----
-  int np2 = 0;
   for (int64_t j0 = 0; j0 < n; j0 += NBK) {
     const int nbk = (int)std::min<int64_t>(NBK, n - j0);
-    // first column of the panel: plain copy (no pending panel updates)
-    {
-      const unsigned g = nwg_rows(n - j0);
-      hipLaunchKernelGGL(k_col<TA>, dim3(g), dim3(ENT), 0, s, n, j0, 0, int64_t(-1), 0, j0, j0, 0,
-                         A, lda, w.V, w.W, w.wraw, w.vbuf, w.part2, 0, w.tau, w.col, w.part3);
-      hipLaunchKernelGGL(k_refl, dim3(1), dim3(RNT), 0, s, n, j0, j0, 0, w.col, w.part3, (int)g,
-                         w.d, w.e, w.beta0, w.tau, w.scl, w.vbuf, w.V);
-    }
+    // first column of the panel: no pending panel updates
+    unsigned gc = nwg_rows(n - j0);
+    BSE_LAUNCH("k_col", k_col<TA>, dim3(gc), dim3(ENT), 0, s, n, j0, 0, int64_t(-1), 0, j0, j0, 0,
+               A, lda, w.V, w.W, w.wraw, w.vbuf, w.part2, 0, w.tau, w.col, w.part3, w.part, w.d);
     for (int i = 0; i < nbk; ++i) {
       const int64_t j = j0 + i;
-      if (j + 1 >= n) break;  // last diagonal element already recorded
+      if (j + 1 >= n) break;  // the last diagonal element is stored by k_col
+      hemv(j, j0, i, (int)gc);
       const int64_t m0 = j + 1, m = n - m0;
-      const int rpw = hemv_rpw(m);
-      const unsigned gh = (unsigned)((m + 4 * rpw - 1) / (4 * rpw));
-      hipLaunchKernelGGL(k_hemv<TA>, dim3(gh), dim3(ENT), 0, s, n, m0, i, rpw, A, lda, w.vbuf,
-                         w.V, w.W, w.y, w.part);
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RNT), 0, s, (int)gh, i, w.part, w.pq);
       const unsigned gw = nwg_rows(m);
-      hipLaunchKernelGGL(k_w, dim3(gw), dim3(ENT), 0, s, n, m0, i, j + 1, w.V, w.W, w.y, w.pq,
-                         w.vbuf, w.tau, w.wraw, w.part2);
-      np2 = (int)gw;
+      BSE_LAUNCH("k_w", k_w, dim3(gw), dim3(ENT), 0, s, n, m0, i, j + 1, w.V, w.W, w.y, w.pq,
+                 w.vbuf, w.tau, w.wraw, w.part2);
       const bool more = (i + 1 < nbk);  // next column still in this panel
       const int64_t jr = more ? j + 1 : int64_t(-1);
-      const unsigned gc = nwg_rows(n - j0);
-      hipLaunchKernelGGL(k_col<TA>, dim3(gc), dim3(ENT), 0, s, n, j0, 1, j, i, j0, jr,
-                         more ? i + 1 : 0, A, lda, w.V, w.W, w.wraw, w.vbuf, w.part2, np2, w.tau,
-                         w.col, w.part3);
-      if (more)
-        hipLaunchKernelGGL(k_refl, dim3(1), dim3(RNT), 0, s, n, jr, j0, i + 1, w.col, w.part3,
-                           (int)gc, w.d, w.e, w.beta0, w.tau, w.scl, w.vbuf, w.V);
+      gc = nwg_rows(n - j0);
+      BSE_LAUNCH("k_col", k_col<TA>, dim3(gc), dim3(ENT), 0, s, n, j0, 1, j, i, j0, jr,
+                 more ? i + 1 : 0, A, lda, w.V, w.W, w.wraw, w.vbuf, w.part2, (int)gw, w.tau,
+                 w.col, w.part3, w.part, w.d);
     }
     BSE_HIP_CHECK(hipGetLastError());
     // trailing update of the rows/columns after the panel
@@ -642,13 +701,18 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, int32_
       constexpr int BM = HerTile<TA>::BM, BN = HerTile<TA>::BN;
       const int64_t m = n - c0;
       dim3 g((unsigned)((m + BN - 1) / BN), (unsigned)((2 * m + BM - 1) / BM));
-      hipLaunchKernelGGL(k_her2k<TA>, g, dim3(ENT), 0, s, n, c0, nbk, w.V, w.W, A, lda);
+      BSE_LAUNCH("k_her2k", k_her2k<TA>, g, dim3(ENT), 0, s, n, c0, nbk, w.V, w.W, A, lda);
       BSE_HIP_CHECK(hipGetLastError());
     }
   }
-  const double split_rel = (sizeof(TA) == 8 ? 2.2e-16 : 1.2e-7) * 64.0 * std::sqrt(double(n));
-  hipLaunchKernelGGL(k_tridiag, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, w.d, w.e,
-                     w.beta0, split_rel, omega, pole, osc);
+  // ---- tridiagonal eigenvalues and optical weights ----
+  const double eps_w = sizeof(TA) == 8 ? 2.2e-16 : 1.2e-7;
+  const double ctol_rel = 8.0 * eps_w * std::sqrt(double(n));
+  BSE_LAUNCH("k_tri_prep", k_tri_prep, dim3(1), dim3(RNT), 0, s, n, w.d, w.e, ctol_rel, w.e2, w.tsc);
+  BSE_LAUNCH("k_bisect", k_bisect, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, w.d, w.e2,
+             w.tsc, omega);
+  BSE_LAUNCH("k_weights", k_weights, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, w.d, w.e2,
+             w.tsc, w.beta0, omega, pole, osc);
   BSE_HIP_CHECK(hipGetLastError());
   return BSE_OK;
 }

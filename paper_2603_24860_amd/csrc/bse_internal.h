@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/bse.h"
 
 namespace bse {
@@ -34,6 +36,25 @@ struct Grid {
   int n1, n2, n3;
   int64_t nk() const { return int64_t(n1) * n2 * n3; }
 };
+
+// RAII bracket of one kernel launch for the opt-in event profiler.
+class ProfScope {
+ public:
+  ProfScope(const char *name, hipStream_t s);
+  ~ProfScope();
+
+ private:
+  hipStream_t stream_;
+  int idx_;
+};
+
+// Launch `kernel` (a __global__ symbol or template instance in parentheses)
+// under the profiler name `name`.
+#define BSE_LAUNCH(name, kernel, grid, block, lds, stream, ...)               \
+  do {                                                                      \
+    bse::ProfScope prof_scope_(name, stream);                               \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);      \
+  } while (0)
 
 // Split-BF16 form of bse_build (arguments already validated).
 int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_t ws_bytes,

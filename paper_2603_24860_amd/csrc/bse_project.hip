@@ -158,18 +158,18 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
       if (lds > 160 * 1024) return fail(BSE_EUNSUPPORTED, "projection tile exceeds LDS");
       dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
       if (h_fp64)
-        hipLaunchKernelGGL(k_project<double>, g, dim3(PNT), lds, s, p->nv, p->nc,
+        BSE_LAUNCH("k_project", k_project<double>, g, dim3(PNT), lds, s, p->nv, p->nc,
                            (const double *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
                            b.ub_off, b.ubasis, (double *)Hmu[ib], ldmu[ib], maxL);
       else
-        hipLaunchKernelGGL(k_project<float>, g, dim3(PNT), lds, s, p->nv, p->nc,
+        BSE_LAUNCH("k_project", k_project<float>, g, dim3(PNT), lds, s, p->nv, p->nc,
                            (const float *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
                            b.ub_off, b.ubasis, (float *)Hmu[ib], ldmu[ib], maxL);
       BSE_HIP_CHECK(hipGetLastError());
     }
     if (Bmu && Bmu[ib]) {
       if (!B) return fail(BSE_EINVAL, "B is NULL");
-      hipLaunchKernelGGL(k_project_vec, dim3((unsigned)p->nkorb), dim3(256), 0, s, p->nkorb,
+      BSE_LAUNCH("k_project_vec", k_project_vec, dim3((unsigned)p->nkorb), dim3(256), 0, s, p->nkorb,
                          (int)nb, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis,
                          (const double2 *)B, (double2 *)Bmu[ib]);
       BSE_HIP_CHECK(hipGetLastError());

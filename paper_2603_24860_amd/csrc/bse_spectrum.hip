@@ -50,7 +50,7 @@ extern "C" int32_t bse_spectrum(int64_t n, const double *pole, const double *osc
   if (nw == 0) return BSE_OK;
   if ((n > 0 && (!pole || !osc)) || !w || !eps2) return fail(BSE_EINVAL, "NULL pointer");
   if (!(eta > 0)) return fail(BSE_EINVAL, "eta must be > 0");
-  hipLaunchKernelGGL(k_spectrum, dim3((unsigned)((nw + SNT - 1) / SNT)), dim3(SNT), 0,
+  BSE_LAUNCH("k_spectrum", k_spectrum, dim3((unsigned)((nw + SNT - 1) / SNT)), dim3(SNT), 0,
                      (hipStream_t)stream, n, pole, osc, pref, eta, nw, w, eps2);
   BSE_HIP_CHECK(hipGetLastError());
   return BSE_OK;

@@ -8,7 +8,9 @@
 // consecutive K values kk + 4 (l >> 4) + i (i = 0..3) with one vector LDS
 // read and feeds them to four successive MFMAs.  The output layout of the
 // 16x16 block is: lane l holds column (l & 15), rows 4 (l >> 4) + j, j = 0..3
-// (same for the f32 and f64 instructions).
+// for the f32 instruction.  The f64 instruction places row g + 4 j in lane
+// (g, j) instead; Mfma<double>::arow() permutes which A row each lane feeds so
+// that both types end with the f32 output layout.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,6 +23,8 @@ template <typename T> struct Mfma;
 template <> struct Mfma<float> {
   typedef f32x4 acc_t;
   typedef f32x4 frag_t;
+  // A row (within the 16-row fragment) that lane row r feeds
+  static __device__ __forceinline__ int arow(int r) { return r; }
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -28,6 +32,7 @@ template <> struct Mfma<float> {
 template <> struct Mfma<double> {
   typedef f64x4 acc_t;
   typedef f64x4 frag_t;
+  static __device__ __forceinline__ int arow(int r) { return 4 * (r & 3) + (r >> 2); }
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -62,7 +67,7 @@ __device__ __forceinline__ void mfma_slab(typename Mfma<T>::acc_t (&acc)[MI][NI]
     typename Mfma<T>::frag_t a[MI], b[NI];
 #pragma unroll
     for (int mi = 0; mi < MI; ++mi)
-      a[mi] = lds_frag<T>(As + (wm0 + 16 * mi + r) * P + kk + 4 * g);
+      a[mi] = lds_frag<T>(As + (wm0 + 16 * mi + Mfma<T>::arow(r)) * P + kk + 4 * g);
 #pragma unroll
     for (int ni = 0; ni < NI; ++ni)
       b[ni] = lds_frag<T>(Bs + (wn0 + 16 * ni + r) * P + kk + 4 * g);
