@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bse_internal.h"
 #include "mfma_tile.h"
@@ -326,6 +327,232 @@ __global__ __launch_bounds__(NT) void k_direct_d(int n1, int n2, int n3, int nv,
     }
 }
 
+// Stores one 16-byte vector of complex Mv values as separate re / im LDS rows.
+template <int VEC> __device__ __forceinline__ void split_store(float4 x, float *dre, float *dim,
+                                                               int c, float sg) {
+  *reinterpret_cast<float2 *>(dre + 2 * c) = float2{x.x, x.z};
+  *reinterpret_cast<float2 *>(dim + 2 * c) = float2{sg * x.y, sg * x.w};
+}
+template <int VEC> __device__ __forceinline__ void split_store(double2 x, double *dre,
+                                                               double *dim, int c, double sg) {
+  dre[c] = x.x;
+  dim[c] = sg * x.y;
+}
+
+// ---------------------------------------------------------------------------
+// direct term, fused: one workgroup per (q, KC consecutive k), all Nmb rows.
+//   stage 1  T^T[I][(k, t, vv')] = sum_J W_q[I][J] Re/Im(Mv(k, k-q)[vv'][J])
+//            wave w owns rows I in [w 16 MI, (w+1) 16 MI), all KC k's;
+//   stage 2  D[cc'][vv'] = sum_I conj(Mc(k, k-q)[cc'][I]) T[vv'][I]
+//            straight from the accumulators: in the MFMA output layout lane
+//            (g, c) holds T^T rows 4g + j at column c, which is exactly the
+//            B operand of a 16x16x4 step whose K slot g is row 4g + j.  Each
+//            wave contracts its own I range; the four partial D are summed in
+//            LDS and subtracted from H.  T never leaves the registers.
+// Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48.
+// ---------------------------------------------------------------------------
+template <typename T, int MI, int KC>
+__global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int nv, int nc,
+                                                     const int32_t *__restrict__ qorb,
+                                                     const int32_t *__restrict__ pidx,
+                                                     const uint8_t *__restrict__ pconj,
+                                                     const T *__restrict__ mv,
+                                                     const T *__restrict__ mc,
+                                                     const T *__restrict__ w, T *__restrict__ H,
+                                                     int64_t ldh, double scale) {
+  constexpr int BK = 16, P = Pitch<T, BK>::value;  // 16-deep slabs: two workgroups per CU
+  constexpr int NMB = 64 * MI;             // rows of W handled by the workgroup
+  constexpr int NI = 2 * KC;               // column blocks: (k, re/im)
+  constexpr int NCOL = 16 * NI;            // B rows in LDS
+  constexpr int VEC = 16 / sizeof(T);      // elements per 16-byte load
+  constexpr int NA = NMB * BK / VEC / NT;  // A loads per thread per slab
+  constexpr int BPR = 2 * BK / VEC;        // 16-byte loads per B row per slab (BK complex)
+  constexpr int NB = KC * 16 * BPR / NT;   // B loads per thread per slab
+  static_assert(NA >= 1 && NB >= 1, "tile too small");
+  constexpr int STAGE = (NMB + NCOL) * P;  // staging elements
+  constexpr int NCB = 3;                   // c c' row blocks of stage 2
+  constexpr int RED = 4 * NCB * 16 * 16 * 2;
+  __shared__ __attribute__((aligned(16))) T lds[STAGE > RED ? STAGE : RED];
+  T *As = lds, *Bs = lds + NMB * P;
+  typedef typename Cplx<T>::type C2;
+  typedef typename Mfma<T>::acc_t acc_t;
+  typedef typename Mfma<T>::frag_t frag_t;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nk = n1 * n2 * n3, nvv = nv * nv, ncc = nc * nc;
+  const int nmb = NMB;
+  const int q = blockIdx.y;
+  const int k0 = blockIdx.x * KC;
+  const T *wq = w + int64_t(qorb[q]) * nmb * nmb;
+  // B-row sources: row = kk * 16 + vv' (re and im rows of one complex row)
+  const C2 *brow[NB];
+  T bsgn[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int it = tid + NT * u, row = it / BPR, kk = row / 16, vv = row % 16;
+    const int k = k0 + kk;
+    brow[u] = nullptr;
+    bsgn[u] = T(1);
+    if (k < nk && vv < nvv) {
+      const int kq = kminus(k, q, n1, n2, n3);
+      const int64_t p = int64_t(k) * nk + kq;
+      const bool cj = pconj[p] != 0;
+      const int v = vv / nv, v2 = vv % nv;
+      const int s1 = cj ? v2 : v, s2 = cj ? v : v2;
+      brow[u] = reinterpret_cast<const C2 *>(mv) +
+                ((int64_t(pidx[p]) * nv + s1) * nv + s2) * nmb;
+      bsgn[u] = cj ? T(-1) : T(1);
+    }
+  }
+  acc_t acc[MI][NI];
+  acc_zero<T, MI, NI>(acc);
+  const int wm0 = wv * 16 * MI;
+  // per-thread load slots of the W rows (A) and the split Mv rows (B)
+  typedef typename std::conditional<VEC == 4, float4, double2>::type V16;
+  __shared__ __attribute__((aligned(16))) C2 bzero_s[4];  // source of rows without data
+  if (tid < 4) bzero_s[tid] = C2{T(0), T(0)};
+  __syncthreads();
+  const T *wrow[NA];
+  int aoff[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int it = tid + NT * u, row = it / (BK / VEC), c = it % (BK / VEC);
+    wrow[u] = wq + int64_t(row) * nmb + c * VEC;
+    aoff[u] = row * P + c * VEC;
+  }
+  const C2 *bsrc[NB];
+  int bstride[NB], boff[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int it = tid + NT * u, row = it / BPR, c = it % BPR, kk = row / 16, vv = row % 16;
+    bsrc[u] = brow[u] ? brow[u] + (VEC == 4 ? 2 * c : c) : bzero_s;
+    bstride[u] = brow[u] ? 1 : 0;
+    boff[u] = ((2 * kk) * 16 + vv) * P + (VEC == 4 ? 2 * c : c);
+  }
+  // Two workgroups per CU hide the load latency better than an in-register
+  // prefetch of the next slab, which would cost the second workgroup.
+  for (int j0 = 0; j0 < nmb; j0 += BK) {
+    V16 ra[NA], rb[NB];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) ra[u] = *reinterpret_cast<const V16 *>(wrow[u] + j0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) rb[u] = *reinterpret_cast<const V16 *>(bsrc[u] + bstride[u] * j0);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) *reinterpret_cast<V16 *>(As + aoff[u]) = ra[u];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      split_store<VEC>(rb[u], Bs + boff[u], Bs + boff[u] + 16 * P, 0, bsgn[u]);
+    __syncthreads();
+    mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, 0, lane);
+    __syncthreads();
+  }
+  // ---- stage 2 ----
+  const int r16 = lane & 15, g = lane >> 4;
+  const int ncb = (ncc + 15) / 16;
+  C2 *red = reinterpret_cast<C2 *>(lds);  // [4][NCB*16][16]
+  C2 *Hc = reinterpret_cast<C2 *>(H);
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const int k = k0 + kk;
+    acc_t dre[NCB], dim[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dre[cb][j] = dim[cb][j] = T(0);
+    int kq = 0;
+    if (k < nk) {
+      kq = kminus(k, q, n1, n2, n3);
+      const int64_t p = int64_t(k) * nk + kq;
+      const bool cj = pconj[p] != 0;
+      const T sg = cj ? T(-1) : T(1);
+      const int cls = pidx[p];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        if (cb >= ncb) break;
+        const int cc = 16 * cb + Mfma<T>::arow(r16);
+        const C2 *arowp = nullptr;
+        if (cc < ncc) {
+          const int c = cc / nc, c2 = cc % nc;
+          const int s1 = cj ? c2 : c, s2 = cj ? c : c2;
+          arowp = reinterpret_cast<const C2 *>(mc) + ((int64_t(cls) * nc + s1) * nc + s2) * nmb;
+        }
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi) {
+          const int I0 = wm0 + 16 * mi + 4 * g;
+          C2 m[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) m[j] = arowp ? arowp[I0 + j] : C2{T(0), T(0)};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const T are = m[j].x, aim = sg * m[j].y;   // Mc = are + i aim
+            const T tre = acc[mi][2 * kk][j], tim = acc[mi][2 * kk + 1][j];
+            // conj(Mc) T = (are tre + aim tim) + i (are tim - aim tre)
+            dre[cb] = Mfma<T>::mma(are, tre, dre[cb]);
+            dre[cb] = Mfma<T>::mma(aim, tim, dre[cb]);
+            dim[cb] = Mfma<T>::mma(are, tim, dim[cb]);
+            dim[cb] = Mfma<T>::mma(-aim, tre, dim[cb]);
+          }
+        }
+      }
+    }
+    // partial D of this wave -> LDS, then the sum over waves -> H
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        red[(wv * NCB * 16 + 16 * cb + 4 * g + j) * 16 + r16] = C2{dre[cb][j], dim[cb][j]};
+    __syncthreads();
+    if (k < nk) {
+      for (int e = tid; e < ncc * nvv; e += NT) {
+        const int cc = e / nvv, vv = e % nvv;
+        C2 sum = {T(0), T(0)};
+#pragma unroll
+        for (int w4 = 0; w4 < 4; ++w4) {
+          const C2 x = red[(w4 * NCB * 16 + cc) * 16 + vv];
+          sum.x += x.x;
+          sum.y += x.y;
+        }
+        const int c = cc / nc, c2 = cc % nc, v = vv / nv, v2 = vv % nv;
+        const int64_t a = (int64_t(k) * nv + v) * nc + c;
+        const int64_t b = (int64_t(kq) * nv + v2) * nc + c2;
+        C2 hv = Hc[a * ldh + b];
+        hv.x -= T(scale * double(sum.x));
+        hv.y -= T(scale * double(sum.y));
+        Hc[a * ldh + b] = hv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int KC>
+int32_t launch_fused(int MI, dim3 g, hipStream_t s, const bse_problem *p, void *H, int64_t ldh,
+                     double scale) {
+#define BSE_FUSED_CASE(M)                                                                     \
+  case M:                                                                                   \
+    BSE_LAUNCH("k_direct_fused", (k_direct_fused<T, M, KC>), g, dim3(NT), 0, s,                \
+               p->grid[0],                                                                  \
+               p->grid[1], p->grid[2], p->nv, p->nc, p->qorb, p->pidx, p->pconj,             \
+               (const T *)p->mv, (const T *)p->mc, (const T *)p->w, (T *)H, ldh, scale);    \
+    break;
+  switch (MI) {
+    BSE_FUSED_CASE(1)
+    BSE_FUSED_CASE(2)
+    BSE_FUSED_CASE(3)
+    BSE_FUSED_CASE(4)
+    BSE_FUSED_CASE(5)
+    BSE_FUSED_CASE(6)
+    default:
+      return fail(BSE_EUNSUPPORTED, "fused direct kernel: nmb = 64 MI with MI <= 6");
+  }
+#undef BSE_FUSED_CASE
+  BSE_HIP_CHECK(hipGetLastError());
+  return BSE_OK;
+}
+
+bool fused_ok(const bse_problem *p) {
+  return p->nmb % 64 == 0 && p->nmb <= 384 && p->nv * p->nv <= 16 && p->nc * p->nc <= 48;
+}
+
 int32_t check_problem(const bse_problem *p, int32_t prec) {
   if (!p) return fail(BSE_EINVAL, "problem is NULL");
   if (prec != BSE_FP64 && prec != BSE_FP32 && prec != BSE_BF16X3)
@@ -362,11 +589,13 @@ using namespace bse;
 
 extern "C" size_t bse_build_ws_min(const bse_problem *p, int32_t prec) {
   if (check_problem(p, prec)) return 0;
+  if (prec != BSE_BF16X3 && fused_ok(p)) return 256;  // the fused direct term needs no buffer
   return per_q_bytes(p, prec);
 }
 
 extern "C" size_t bse_build_ws(const bse_problem *p, int32_t prec) {
   if (check_problem(p, prec)) return 0;
+  if (prec != BSE_BF16X3 && fused_ok(p)) return 256;
   const size_t pq = per_q_bytes(p, prec);
   const size_t nk = size_t(p->grid[0]) * p->grid[1] * p->grid[2];
   const size_t cap = size_t(1) << 30;  // 1 GiB of q-batch buffer is plenty to saturate
@@ -383,10 +612,11 @@ extern "C" int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_
   const int64_t N = int64_t(nk) * p->nv * p->nc;
   if (!H) return fail(BSE_EINVAL, "H is NULL");
   if (ldh < N) return fail(BSE_ESHAPE, "ldh %lld < N %lld", (long long)ldh, (long long)N);
+  const bool fused = fused_ok(p);
   const size_t pq = per_q_bytes(p, prec);
-  if (!ws || ws_bytes < pq)
+  if (!fused && (!ws || ws_bytes < pq))
     return fail(BSE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, pq);
-  const int qb = int(std::min<size_t>(nk, ws_bytes / pq));
+  const int qb = fused ? 1 : int(std::min<size_t>(nk, ws_bytes / pq));
   hipStream_t s = (hipStream_t)stream;
   const double inv_nk = 1.0 / nk;
   auto launch = [&](auto tag) -> int32_t {
@@ -397,6 +627,11 @@ extern "C" int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_
     BSE_LAUNCH("k_exchange", k_exchange<T>, gx, dim3(NT), 0, s, nk, p->nv, p->nc, p->nmb, p->korb,
                        (const T *)p->mx, p->vdiag, p->ev, p->ec, (T *)H, ldh, 2.0 * inv_nk);
     BSE_HIP_CHECK(hipGetLastError());
+    if (fused) {
+      constexpr int KC = 2;  // k points per workgroup
+      dim3 gf((unsigned)((nk + KC - 1) / KC), (unsigned)nk);
+      return launch_fused<T, KC>(p->nmb / 64, gf, s, p, H, ldh, inv_nk);
+    }
     const int64_t M = 2 * int64_t(nk) * p->nv * p->nv;
     for (int q0 = 0; q0 < nk; q0 += qb) {
       const int nq = std::min(qb, nk - q0);
