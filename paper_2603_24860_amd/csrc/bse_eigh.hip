@@ -10,24 +10,28 @@
 //  2. Blocked Householder tridiagonalisation in LAPACK's lower form: column j
 //     is annihilated below the subdiagonal by a reflector acting on rows
 //     j+1..n-1, so Q e_1 = e_1 stays true.  Within a panel of NBK columns the
-//     trailing matrix is updated lazily (A - V W^dag - W V^dag); after the panel
-//     the rank-2 NBK update runs on MFMA.  Three kernels per column, one per
-//     global dependency: k_hemv2 (reflector scalars from the column norm, then
-//     y = A22 v, bound by HBM bandwidth), k_w (w = tau (y - V q - W p)), k_col
-//     (finish w with its global dot product, update the next column, partial
-//     norm and panel dot products for the next reflector).  The panel and all
-//     scalar work are FP64; A is stored in FP64 or (prec FP32) FP32.
+//     trailing matrix is updated lazily, A - V W^dag - W V^dag (V, W column
+//     major); after the panel the rank-2 NBK update runs on MFMA.
+//     Each column costs two kernels, one per global dependency:
+//       k_colA: reflector of column j from the reduced partial sums, then
+//               y = A22 v (rows split over workgroups, bound by HBM bandwidth)
+//               and the partial sums of y^dag v;
+//       k_colB: w^dag v follows from y^dag v and the panel dot products
+//               (w^dag v = conj(tau) (y^dag v - 2 Re(p^dag q)) with p = V^dag v,
+//               q = W^dag v), so the final column of W, the fully updated
+//               column j+1 and the partial sums of its norm and of its dot
+//               products with V and W come out of one pass.
+//     All scalar work is FP64; A is stored in FP64 or (prec FP32) FP32.
 //  3. T is real symmetric tridiagonal (the reflectors make the subdiagonal
-//     real).  All eigenvalues by bisection on Sturm counts (one thread per
-//     eigenvalue, FP64).  Because Q0 Q maps e_1 to e_1,
+//     real).  All eigenvalues by 64-way multisection on Sturm counts (one wave
+//     per eigenvalue, FP64).  Because Q0 Q maps e_1 to e_1,
 //     |B_l|^2 = beta0^2 z_l(0)^2 with z_l the eigenvectors of T, and for a
 //     cluster of (numerically) degenerate eigenvalues the summed weight is the
 //     residue of G(z) = [(z - T)^-1]_00 = 1 / (z - d_0 - e_0^2 / (z - d_1 - ...))
-//     at the cluster.  It is computed by the trapezoidal rule on a circle
-//     around the cluster whose radius is the geometric mean of the cluster
-//     width and the distance to the next eigenvalue (error decays like
-//     (width / distance)^(M/2) with M nodes); off the real axis the continued
-//     fraction has no vanishing pivots.
+//     at the cluster, computed by the trapezoidal rule on a circle around the
+//     cluster (one wave per cluster, one node per lane); the radius is the
+//     geometric mean of the cluster width and the distance to the next
+//     eigenvalue, so the error decays like (width / distance)^(M/2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +46,11 @@ namespace {
 constexpr int ENT = 256;     // threads per workgroup
 constexpr int NBK = 32;      // panel width
 constexpr int RNT = 1024;    // threads of the single-workgroup kernels
+constexpr int PMAX = 1024;   // partial-sum records (k_colB has at most 65536 / 64 workgroups)
+constexpr int PAMAX = 16384; // k_colA partial sums (one wave per row, 4 rows per workgroup)
+// partial-sum record of one k_colB workgroup (complex entries):
+//   [0] (S1, 0) = sum |col|^2, [1 + l] BV_l, [1 + NBK + l] BW_l
+constexpr int PS = 1 + 2 * NBK;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -49,8 +58,10 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) b
   return double2{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
 }
+__device__ __forceinline__ double2 cconj(double2 a) { return double2{a.x, -a.y}; }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return double2{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return double2{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return double2{s * a.x, s * a.y}; }
 
 template <typename T> struct C2T;
 template <> struct C2T<float> { typedef float2 t; };
@@ -64,7 +75,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-wide sum of one double (RNT or ENT threads); result valid in all threads.
+// Block-wide sum of one double (NTH threads); result valid in all threads.
 template <int NTH> __device__ __forceinline__ double block_sum(double v, double *sh) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -78,26 +89,24 @@ template <int NTH> __device__ __forceinline__ double block_sum(double v, double 
 
 struct Ws {
   void *A;
-  int64_t lda;
-  double2 *V, *W;    // [n][NBK]
-  double2 *col;      // [n] updated current column
-  double2 *y;        // [n] hemv output
-  double2 *wraw;     // [n]
-  double2 *vbuf;     // [n] current reflector
-  double2 *part;     // [PMAX][2 NBK] panel dot partials (k_col)
-  double2 *part2;    // [PMAX]
-  double *part3;     // [PMAX]
-  double2 *pq;       // [2 NBK]
+  int64_t lda, ldv;
+  double2 *V, *W;    // [NBK][ldv] column major
+  double2 *col;      // [n] current column
+  double2 *y;        // [n] y = A22 v
+  double2 *wraw;     // [n] initial reflection: w before the alpha v term
+  double2 *vbuf;     // [n] initial reflector
+  double2 *partb;    // [2][PMAX][PS] partial sums of k_colB / k_col0 (alternating)
+  double2 *parta;    // [PAMAX] partial sums of conj(y) v of k_colA
+  double2 *part2;    // [PMAX] initial reflection: partial w^dag v
+  double *part3;     // [PMAX] initial reflection: partial norm
+  double2 *scl;      // [n + 1] reflector scale 1 / (alpha - beta), index j + 1
   double2 *tau;      // [n + 1], index j + 1
-  double2 *scl;      // [n + 1]
   double *d, *e;     // [n]
   double *e2;        // [n] squared subdiagonal
   double *tsc;       // [8] tridiagonal scalars
   double *beta0;     // [1]
 };
-constexpr int PMAX = 1024;
 
-// rows per wave of k_hemv: at most 512 workgroups of 4 waves (PMAX partials)
 int hemv_rpw(int64_t m) { return (int)std::max<int64_t>(1, (m + 4 * 512 - 1) / (4 * 512)); }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -109,22 +118,23 @@ size_t ws_layout(int64_t n, bool a_fp64, Ws *w, char *base) {
     off += align256(bytes);
     return p;
   };
-  const int64_t lda = (n + 15) / 16 * 16;
+  const int64_t lda = (n + 15) / 16 * 16, ldv = (n + 63) / 64 * 64;
   Ws t;
   t.lda = lda;
+  t.ldv = ldv;
   t.A = take(size_t(n) * lda * (a_fp64 ? 16 : 8));
-  t.V = (double2 *)take(size_t(n) * NBK * 16);
-  t.W = (double2 *)take(size_t(n) * NBK * 16);
+  t.V = (double2 *)take(size_t(ldv) * NBK * 16);
+  t.W = (double2 *)take(size_t(ldv) * NBK * 16);
   t.col = (double2 *)take(size_t(n) * 16);
   t.y = (double2 *)take(size_t(n) * 16);
   t.wraw = (double2 *)take(size_t(n) * 16);
   t.vbuf = (double2 *)take(size_t(n) * 16);
-  t.part = (double2 *)take(size_t(PMAX) * 2 * NBK * 16);
+  t.partb = (double2 *)take(size_t(2) * PMAX * PS * 16);
+  t.parta = (double2 *)take(size_t(PAMAX) * 16);
   t.part2 = (double2 *)take(size_t(PMAX) * 16);
   t.part3 = (double *)take(size_t(PMAX) * 8);
-  t.pq = (double2 *)take(2 * NBK * 16);
-  t.tau = (double2 *)take(size_t(n + 1) * 16);
   t.scl = (double2 *)take(size_t(n + 1) * 16);
+  t.tau = (double2 *)take(size_t(n + 1) * 16);
   t.d = (double *)take(size_t(n) * 8);
   t.e = (double *)take(size_t(n) * 8);
   t.e2 = (double *)take(size_t(n) * 8);
@@ -132,6 +142,25 @@ size_t ws_layout(int64_t n, bool a_fp64, Ws *w, char *base) {
   t.beta0 = (double *)take(8);
   if (w) *w = t;
   return off;
+}
+
+// Reflector scalars with LAPACK zlarfg semantics:
+// (I - tau v v^dag)^dag (alpha, x) = (beta, 0), v = (1, x / (alpha - beta)),
+// given alpha and |x|^2.
+__device__ __forceinline__ void householder(double2 al, double xn2, double &beta, double2 &tau,
+                                            double2 &scale) {
+  tau = double2{0, 0};
+  scale = double2{0, 0};
+  if (xn2 == 0.0 && al.y == 0.0) {
+    beta = al.x;
+    return;
+  }
+  const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+  beta = al.x >= 0 ? -nrm : nrm;
+  tau = double2{(beta - al.x) / beta, -al.y / beta};
+  const double2 den = {al.x - beta, al.y};
+  const double dd = den.x * den.x + den.y * den.y;
+  scale = double2{den.x / dd, -den.y / dd};
 }
 
 // ---------------------------------------------------------------------------
@@ -148,9 +177,11 @@ __global__ void k_copy_in(int64_t n, const TH *__restrict__ H, int64_t ldh, TA *
   }
 }
 
-// col[r] = B[r] (the "column" whose reflector maps B onto beta0 e_1)
+// ---------------------------------------------------------------------------
+// initial reflection B -> beta0 e_1 (whole matrix, once per solve)
+// ---------------------------------------------------------------------------
 __global__ void k_load_b(int64_t n, const double2 *__restrict__ B, double2 *__restrict__ col,
-                         double *__restrict__ part3, int np3) {
+                         double *__restrict__ part3) {
   __shared__ double sh[ENT / 64];
   double s = 0;
   for (int64_t r = int64_t(blockIdx.x) * ENT + threadIdx.x; r < n; r += int64_t(gridDim.x) * ENT) {
@@ -160,87 +191,39 @@ __global__ void k_load_b(int64_t n, const double2 *__restrict__ B, double2 *__re
   }
   s = block_sum<ENT>(s, sh);
   if (threadIdx.x == 0) part3[blockIdx.x] = s;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    for (int i = gridDim.x; i < np3; ++i) part3[i] = 0;
 }
 
-// Reflector of column jr (acting on rows jr+1..n-1) with LAPACK's zlarfg
-// semantics, (I - tau v v^dag)^dag (alpha, x) = (beta, 0) and
-// v = (1, x / (alpha - beta)), followed by y[r] = sum_{c > jr} A[r][c] v[c]
-// for r > jr (one wave per row).  Every workgroup recomputes the scalars from
-// the column norm partials (a few dozen values); workgroup 0 stores them, the
-// panel dot products p_l = V[:,l]^dag v and q_l = W[:,l]^dag v (l < ir, from
-// k_col's partials) and the zeros of v above row jr+1.  v is formed on the fly
-// from the updated column, and each wave stores v and V[:, ir] for its rows.
+// v from the loaded B (scalars from the norm partials), then y = A v.
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_hemv2(int64_t n, int64_t jr, int64_t j0, int ir, int rpw,
-                                               const TA *__restrict__ A, int64_t lda,
-                                               const double2 *__restrict__ col,
-                                               const double *__restrict__ part3,
-                                               const double2 *__restrict__ partd, int np3,
-                                               double *__restrict__ d, double *__restrict__ e,
+__global__ __launch_bounds__(ENT) void k_hemv0(int64_t n, int rpw, const TA *__restrict__ A,
+                                               int64_t lda, const double2 *__restrict__ col,
+                                               const double *__restrict__ part3, int np3,
                                                double *__restrict__ beta0,
                                                double2 *__restrict__ tau,
-                                               double2 *__restrict__ scl,
                                                double2 *__restrict__ vbuf,
-                                               double2 *__restrict__ V,
-                                               const double2 *__restrict__ W,
-                                               double2 *__restrict__ y, double2 *__restrict__ pq) {
+                                               double2 *__restrict__ y) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t m0 = jr + 1;
   double s = 0;
   for (int p = threadIdx.x; p < np3; p += ENT) s += part3[p];
   const double xn2 = block_sum<ENT>(s, sh);
-  const double2 al = col[m0];
   double beta;
-  double2 t = {0, 0}, sc = {0, 0};
-  if (xn2 == 0.0 && al.y == 0.0) {
-    beta = al.x;
-  } else {
-    const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
-    beta = al.x >= 0 ? -nrm : nrm;
-    t = double2{(beta - al.x) / beta, -al.y / beta};
-    const double2 den = {al.x - beta, al.y};
-    const double dd = den.x * den.x + den.y * den.y;
-    sc = double2{den.x / dd, -den.y / dd};
+  double2 t, sc;
+  householder(col[0], xn2, beta, t, sc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    beta0[0] = beta;
+    tau[0] = t;
   }
-  if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) {
-      if (jr >= 0) {
-        d[jr] = col[jr].x;
-        e[jr] = beta;
-      } else {
-        beta0[0] = beta;
-      }
-      tau[jr + 1] = t;
-      scl[jr + 1] = sc;
-    }
-    if (threadIdx.x < 2 * NBK) {  // panel dot products for k_w
-      const int slot = threadIdx.x, l = slot % NBK;
-      double2 acc = {0, 0};
-      if (l < ir) {
-        for (int p = 0; p < np3; ++p) acc = cadd(acc, partd[int64_t(p) * 2 * NBK + slot]);
-        const double2 head = slot < NBK ? V[m0 * NBK + l] : W[m0 * NBK + l];
-        acc = cadd(double2{head.x, -head.y}, cmul(sc, acc));
-      }
-      pq[slot] = acc;
-    }
-    for (int64_t r = std::max<int64_t>(0, ir >= 0 ? j0 : 0) + threadIdx.x; r < m0; r += ENT) {
-      vbuf[r] = double2{0, 0};
-      if (ir >= 0) V[r * NBK + ir] = double2{0, 0};
-    }
-  }
-  const int64_t rbase = m0 + (int64_t(blockIdx.x) * (ENT / 64) + wv) * rpw;
+  const int64_t rbase = (int64_t(blockIdx.x) * (ENT / 64) + wv) * rpw;
   for (int rr = 0; rr < rpw; ++rr) {
     const int64_t r = rbase + rr;
     if (r >= n) break;
     const CA *arow = reinterpret_cast<const CA *>(A) + r * lda;
     double sr = 0, si = 0;
-    for (int64_t c = m0 + lane; c < n; c += 64) {
+    for (int64_t c = lane; c < n; c += 64) {
       const double2 a = to_d2(arow[c]);
-      const double2 v = c == m0 ? double2{1, 0} : cmul(col[c], sc);
+      const double2 v = c == 0 ? double2{1, 0} : cmul(col[c], sc);
       sr += a.x * v.x - a.y * v.y;
       si += a.x * v.y + a.y * v.x;
     }
@@ -248,36 +231,22 @@ __global__ __launch_bounds__(ENT) void k_hemv2(int64_t n, int64_t jr, int64_t j0
     si = wave_sum(si);
     if (lane == 0) {
       y[r] = double2{sr, si};
-      const double2 v = r == m0 ? double2{1, 0} : cmul(col[r], sc);
-      vbuf[r] = v;
-      if (ir >= 0) V[r * NBK + ir] = v;
+      vbuf[r] = r == 0 ? double2{1, 0} : cmul(col[r], sc);
     }
   }
 }
 
-// wraw[r] = tau_j (y[r] - sum_l V[r][l] q_l - sum_l W[r][l] p_l), partial conj(w).v
-__global__ __launch_bounds__(ENT) void k_w(int64_t n, int64_t m0, int i, int64_t jt,
-                                           const double2 *__restrict__ V,
-                                           const double2 *__restrict__ W,
-                                           const double2 *__restrict__ y,
-                                           const double2 *__restrict__ pq,
-                                           const double2 *__restrict__ vbuf,
-                                           const double2 *__restrict__ tau,
-                                           double2 *__restrict__ wraw,
-                                           double2 *__restrict__ part2) {
+// wraw = tau y and the partial conj(wraw) v
+__global__ __launch_bounds__(ENT) void k_w0(int64_t n, const double2 *__restrict__ y,
+                                            const double2 *__restrict__ vbuf,
+                                            const double2 *__restrict__ tau,
+                                            double2 *__restrict__ wraw,
+                                            double2 *__restrict__ part2) {
   __shared__ double sh[ENT / 64];
-  __shared__ double2 spq[2 * NBK];
-  if (threadIdx.x < 2 * NBK) spq[threadIdx.x] = pq[threadIdx.x];
-  __syncthreads();
-  const int64_t r = m0 + int64_t(blockIdx.x) * ENT + threadIdx.x;
+  const int64_t r = int64_t(blockIdx.x) * ENT + threadIdx.x;
   double sr = 0, si = 0;
   if (r < n) {
-    double2 w = y[r];
-    for (int l = 0; l < i; ++l) {
-      w = csub(w, cmul(V[r * NBK + l], spq[NBK + l]));
-      w = csub(w, cmul(W[r * NBK + l], spq[l]));
-    }
-    w = cmul(tau[jt], w);
+    const double2 w = cmul(tau[0], y[r]);
     wraw[r] = w;
     const double2 c = cmulc(w, vbuf[r]);
     sr = c.x;
@@ -288,111 +257,7 @@ __global__ __launch_bounds__(ENT) void k_w(int64_t n, int64_t m0, int i, int64_t
   if (threadIdx.x == 0) part2[blockIdx.x] = double2{sr, si};
 }
 
-// Finish W[:, i] = wraw + alpha v (alpha = -tau_j (w^dag v) / 2) for column j
-// (fin != 0), then update column jr (panel index ir) with the panel's
-// reflectors: col[r] = A[r][jr] - sum_{l < ir} (V[r][l] conj(W[jr][l]) +
-// W[r][l] conj(V[jr][l])).  Per workgroup it stores the partial |col[r]|^2 and
-// the partial sums conj(V[r][l]) col[r], conj(W[r][l]) col[r] (l < ir) over
-// rows r >= jr + 2, which k_hemv2 turns into the next reflector and its panel
-// dot products.  For jr = n - 1 it stores the last diagonal element.
-template <typename TA>
-__global__ __launch_bounds__(ENT) void k_col(int64_t n, int64_t rlo, int fin, int64_t j, int i,
-                                             int64_t j0, int64_t jr, int ir,
-                                             const TA *__restrict__ A, int64_t lda,
-                                             double2 *__restrict__ V, double2 *__restrict__ W,
-                                             const double2 *__restrict__ wraw,
-                                             const double2 *__restrict__ vbuf,
-                                             const double2 *__restrict__ part2, int np2,
-                                             const double2 *__restrict__ tau,
-                                             double2 *__restrict__ col,
-                                             double *__restrict__ part3,
-                                             double2 *__restrict__ partd,
-                                             double *__restrict__ d) {
-  typedef typename C2T<TA>::t CA;
-  __shared__ double sh[ENT / 64];
-  __shared__ double2 swj[NBK], svj[NBK];
-  __shared__ double2 scol[ENT];
-  __shared__ double2 sdot[4][2 * NBK];
-  double2 alpha = {0, 0};
-  if (fin) {
-    double sr = 0, si = 0;
-    for (int p = threadIdx.x; p < np2; p += ENT) {
-      sr += part2[p].x;
-      si += part2[p].y;
-    }
-    sr = block_sum<ENT>(sr, sh);
-    si = block_sum<ENT>(si, sh);
-    const double2 t = tau[j + 1];
-    alpha = cmul(double2{-0.5 * t.x, -0.5 * t.y}, double2{sr, si});
-  }
-  if (jr >= 0 && threadIdx.x < NBK) {
-    const int l = threadIdx.x;
-    double2 wv = {0, 0}, vv = {0, 0};
-    if (l < ir) {
-      vv = V[jr * NBK + l];
-      if (fin && l == i)
-        wv = cadd(wraw[jr], cmul(alpha, vbuf[jr]));
-      else
-        wv = W[jr * NBK + l];
-    }
-    swj[l] = wv;
-    svj[l] = vv;
-  }
-  __syncthreads();
-  const int64_t r = rlo + int64_t(blockIdx.x) * ENT + threadIdx.x;
-  double s = 0;
-  double2 a = {0, 0};
-  if (r < n) {
-    if (fin && r >= j0) {
-      const double2 w = r >= j + 1 ? cadd(wraw[r], cmul(alpha, vbuf[r])) : double2{0, 0};
-      W[r * NBK + i] = w;
-    }
-    if (jr >= 0 && r >= jr) {
-      a = to_d2(reinterpret_cast<const CA *>(A)[r * lda + jr]);
-      for (int l = 0; l < ir; ++l) {
-        const double2 vrl = V[r * NBK + l];
-        const double2 wrl = (fin && l == i) ? (r >= j + 1 ? cadd(wraw[r], cmul(alpha, vbuf[r]))
-                                                          : double2{0, 0})
-                                            : W[r * NBK + l];
-        // V[r][l] conj(W[jr][l]) + W[r][l] conj(V[jr][l])
-        a = csub(a, cmul(vrl, double2{swj[l].x, -swj[l].y}));
-        a = csub(a, cmul(wrl, double2{svj[l].x, -svj[l].y}));
-      }
-      col[r] = a;
-      if (r == n - 1 && jr == n - 1) d[n - 1] = a.x;
-      if (r >= jr + 2) s = a.x * a.x + a.y * a.y;
-    }
-  }
-  s = block_sum<ENT>(s, sh);
-  if (threadIdx.x == 0) part3[blockIdx.x] = s;
-  if (ir > 0) {
-    // partial panel dot products over this workgroup's rows r >= jr + 2
-    scol[threadIdx.x] = (r < n && r >= jr + 2) ? a : double2{0, 0};
-    __syncthreads();  // also orders the W[:, i] stores above
-    const int slot = threadIdx.x % (2 * NBK), q = threadIdx.x / (2 * NBK), l = slot % NBK;
-    double2 acc = {0, 0};
-    if (l < ir) {
-      const int64_t rb = rlo + int64_t(blockIdx.x) * ENT;
-      for (int t = q * 64; t < q * 64 + 64; ++t) {
-        const int64_t rr = rb + t;
-        if (rr >= n) break;
-        const double2 c = scol[t];
-        if (c.x == 0.0 && c.y == 0.0) continue;
-        const double2 m = slot < NBK ? V[rr * NBK + l] : W[rr * NBK + l];
-        acc = cadd(acc, cmulc(m, c));
-      }
-    }
-    sdot[q][slot] = acc;
-    __syncthreads();
-    if (threadIdx.x < 2 * NBK) {
-      double2 t4 = {0, 0};
-      for (int qq = 0; qq < 4; ++qq) t4 = cadd(t4, sdot[qq][threadIdx.x]);
-      partd[int64_t(blockIdx.x) * 2 * NBK + threadIdx.x] = t4;
-    }
-  }
-}
-
-// Initial two-sided reflection: A -= v w^dag + w v^dag with w = wraw + alpha v.
+// A -= v w^dag + w v^dag with w = wraw + alpha v
 template <typename TA>
 __global__ __launch_bounds__(ENT) void k_rank2(int64_t n, TA *__restrict__ A, int64_t lda,
                                                const double2 *__restrict__ wraw,
@@ -416,13 +281,328 @@ __global__ __launch_bounds__(ENT) void k_rank2(int64_t n, TA *__restrict__ A, in
     const double2 vc = vbuf[c], wc = cadd(wraw[c], cmul(alpha, vc));
     CA *p = reinterpret_cast<CA *>(A) + r * lda + c;
     double2 a = to_d2(*p);
-    a = csub(a, cmul(vr, double2{wc.x, -wc.y}));
-    a = csub(a, cmul(wr, double2{vc.x, -vc.y}));
+    a = csub(a, cmul(vr, cconj(wc)));
+    a = csub(a, cmul(wr, cconj(vc)));
     *p = CA{TA(a.x), TA(a.y)};
   }
 }
 
-// Trailing update on MFMA: A[r][c] -= sum_l V[r][l] conj(W[c][l]) + W[r][l] conj(V[c][l])
+// ---------------------------------------------------------------------------
+// panel start: col = A[:, j0] (rows >= j0) and partial |col|^2 over rows >= j0 + 2
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(ENT) void k_col0(int64_t n, int64_t j0, const TA *__restrict__ A,
+                                              int64_t lda, double2 *__restrict__ col,
+                                              double2 *__restrict__ partb) {
+  typedef typename C2T<TA>::t CA;
+  __shared__ double sh[ENT / 64];
+  const int64_t r = j0 + int64_t(blockIdx.x) * ENT + threadIdx.x;
+  double s = 0;
+  if (r < n) {
+    const double2 a = to_d2(reinterpret_cast<const CA *>(A)[r * lda + j0]);
+    col[r] = a;
+    if (r >= j0 + 2) s = a.x * a.x + a.y * a.y;
+  }
+  s = block_sum<ENT>(s, sh);
+  if (threadIdx.x == 0) partb[int64_t(blockIdx.x) * PS] = double2{s, 0};
+}
+
+// ---------------------------------------------------------------------------
+// k_colA: reflector of column jn from its final entries col[jn..n) and the
+// partial sums S1 = sum_{r >= jn+2} |col|^2 of k_colB (or k_col0 at a panel
+// start): beta, tau and v = (1, scale col[jn+2..]) on rows m0 = jn+1 .. n-1,
+// then y = A22 v.  The row sums do not wait for the scalars:
+//   y[r] = A[r][m0] + scale * sum_{c > m0} A[r][c] col[c],
+// so the loads of A overlap the reduction of S1.  A row is split over WPR
+// waves (contiguous column ranges, combined in LDS), each streaming its range
+// with a two-stage software pipeline of HU loads per lane.  Every workgroup
+// leaves its partial sum of conj(y) v.
+// ---------------------------------------------------------------------------
+constexpr int HU = 4;
+
+template <typename TA, int WPR>
+__global__ __launch_bounds__(ENT) void k_colA(int64_t n, int64_t jn, int ir,
+                                              const TA *__restrict__ A, int64_t lda,
+                                              double2 *__restrict__ V, int64_t ldv,
+                                              const double2 *__restrict__ col,
+                                              const double2 *__restrict__ partb, int np,
+                                              double2 *__restrict__ tau,
+                                              double2 *__restrict__ scl, double *__restrict__ d,
+                                              double *__restrict__ e, double2 *__restrict__ y,
+                                              double2 *__restrict__ parta) {
+  typedef typename C2T<TA>::t CA;
+  constexpr int RT = (ENT / 64) / WPR;  // rows per workgroup
+  __shared__ double sh[ENT / 64];
+  __shared__ double2 srow[ENT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m0 = jn + 1;
+  const int64_t r = m0 + int64_t(blockIdx.x) * RT + wv / WPR;
+  const int part = wv % WPR;
+  // ---- independent loads: every global load is issued from a clamped,
+  // in-bounds index before any value is used, so none waits for another ----
+  const bool last = m0 >= n;
+  const int64_t rc = std::min<int64_t>(r, n - 1), mc = std::min<int64_t>(m0, n - 1);
+  double2 px[PMAX / ENT];  // np <= PMAX = 4 ENT records
+#pragma unroll
+  for (int u = 0; u < PMAX / ENT; ++u) px[u] = partb[int64_t(std::min(tid + ENT * u, np - 1)) * PS];
+  const double2 cjn = col[jn], cm0 = col[mc], cr = col[rc];
+  const double2 a0 = to_d2(reinterpret_cast<const CA *>(A)[rc * lda + mc]);
+  const bool lead = lane == 0 && part == 0 && r < n;
+  // ---- row sums over this wave's column range ----
+  double sr = 0, si = 0;
+  if (r < n) {
+    const int64_t len = n - (m0 + 1);
+    const int64_t per = ((len + WPR - 1) / WPR + 63) / 64 * 64;
+    const int64_t cs = m0 + 1 + part * per, ce = std::min<int64_t>(n, cs + per);
+    const CA *arow = reinterpret_cast<const CA *>(A) + r * lda;
+    CA an[HU];
+    double2 cn[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int64_t c = std::min<int64_t>(cs + lane + 64 * u, n - 1);
+      an[u] = arow[c];
+      cn[u] = col[c];
+    }
+    for (int64_t c0 = cs; c0 < ce; c0 += 64 * HU) {
+      CA ac[HU];
+      double2 cc[HU];
+#pragma unroll
+      for (int u = 0; u < HU; ++u) {
+        ac[u] = an[u];
+        cc[u] = cn[u];
+      }
+      const int64_t c1 = c0 + 64 * HU;  // next pass, loaded while this one is summed
+#pragma unroll
+      for (int u = 0; u < HU; ++u) {
+        const int64_t c = std::min<int64_t>(c1 + lane + 64 * u, n - 1);
+        an[u] = arow[c];
+        cn[u] = col[c];
+      }
+#pragma unroll
+      for (int u = 0; u < HU; ++u) {
+        const bool ok = c0 + lane + 64 * u < ce;
+        const double2 a = ok ? to_d2(ac[u]) : double2{0, 0};
+        sr += a.x * cc[u].x - a.y * cc[u].y;
+        si += a.x * cc[u].y + a.y * cc[u].x;
+      }
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+  }
+  double s1 = 0;
+#pragma unroll
+  for (int u = 0; u < PMAX / ENT; ++u)
+    if (tid + ENT * u < np) s1 += px[u].x;
+  if (lane == 0) srow[wv] = double2{sr, si};
+  // ---- reflector scalars (every workgroup) ----
+  const double S1 = block_sum<ENT>(s1, sh);  // also publishes srow
+  if (blockIdx.x == 0 && tid == 0) d[jn] = cjn.x;
+  if (last) return;
+  double beta;
+  double2 tj, sc;
+  householder(cm0, S1, beta, tj, sc);
+  if (blockIdx.x == 0 && tid == 0) {
+    e[jn] = beta;
+    tau[m0] = tj;
+    scl[m0] = sc;
+  }
+  double2 yv = {0, 0};
+  if (lead) {
+    double2 rs = srow[wv];
+#pragma unroll
+    for (int k = 1; k < WPR; ++k) rs = cadd(rs, srow[wv + k]);
+    const double2 yr = cadd(a0, cmul(sc, rs));
+    const double2 v = r == m0 ? double2{1, 0} : cmul(sc, cr);  // lead: r < n, so rc = r
+    y[r] = yr;
+    V[int64_t(ir) * ldv + r] = v;
+    yv = cmulc(yr, v);
+  }
+  const double yr = block_sum<ENT>(yv.x, sh);
+  const double yi = block_sum<ENT>(yv.y, sh);
+  if (tid == 0) parta[blockIdx.x] = double2{yr, yi};
+}
+
+// sum of part[0..np) with eight loads in flight per thread
+__device__ __forceinline__ double2 gather_sum(const double2 *__restrict__ part, int np, int tid) {
+  double2 acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int p = tid + ENT * u;
+    acc[u] = p < np ? part[p] : double2{0, 0};
+  }
+  for (int p = tid + 8 * ENT; p < np; p += ENT) acc[0] = cadd(acc[0], part[p]);
+#pragma unroll
+  for (int u = 1; u < 8; ++u) acc[0] = cadd(acc[0], acc[u]);
+  return acc[0];
+}
+
+// ---------------------------------------------------------------------------
+// k_colB: column jn (panel index ir), rows r >= jx = jn + 1, RB rows per
+// workgroup.  With the panel dot products of the new reflector
+//   p_l = V_l^dag v = conj(V_l[jx]) + scale BV_l,  q_l = W_l^dag v = conj(W_l[jx]) + scale BW_l
+// (l < ir, from the partial sums of the previous column) and
+//   w^dag v = conj(tau) (y^dag v - 2 Re(p^dag q)),  alpha = -tau (w^dag v) / 2:
+//   W_ir[r] = tau (y[r] - sum_{l<ir} (V_l[r] q_l + W_l[r] p_l)) + alpha v[r]
+// and, if column jx is in the panel, its entries with every update
+//   col[r] = A[r][jx] - sum_{l<=ir} (V_l[r] conj(W_l[jx]) + W_l[r] conj(V_l[jx]))
+// together with the partial sums over rows >= jx + 2 that the next column needs.
+// Record of one workgroup: [0] (S1, 0), [1 + l] BV_l, [1 + NBK + l] BW_l.
+// The workgroup's rows of V_0..V_ir, W_0..W_ir are staged in LDS once; four
+// threads share a row (sums over l) or a column (sums over rows).
+// ---------------------------------------------------------------------------
+constexpr int RB = 64;        // rows per k_colB workgroup
+constexpr int TP = RB + 1;    // LDS pitch of one panel column
+
+__device__ __forceinline__ double2 shfl_sum4(double2 x) {
+  x.x += __shfl_xor(x.x, 1, 64);
+  x.y += __shfl_xor(x.y, 1, 64);
+  x.x += __shfl_xor(x.x, 2, 64);
+  x.y += __shfl_xor(x.y, 2, 64);
+  return x;
+}
+
+template <typename TA>
+__global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int more,
+                                              const TA *__restrict__ A, int64_t lda,
+                                              const double2 *__restrict__ V,
+                                              double2 *__restrict__ W, int64_t ldv,
+                                              const double2 *__restrict__ y,
+                                              const double2 *__restrict__ parta, int npa,
+                                              const double2 *__restrict__ pin, int npin,
+                                              const double2 *__restrict__ tau,
+                                              const double2 *__restrict__ scl,
+                                              double2 *__restrict__ col,
+                                              double2 *__restrict__ pout) {
+  typedef typename C2T<TA>::t CA;
+  __shared__ double sh[ENT / 64];
+  __shared__ double2 tile[2 * NBK * TP];  // [V_0..V_{NBK-1} | W_0..W_{NBK-1}] x rows
+  __shared__ double2 sred[ENT / 64][2 * NBK];
+  __shared__ double2 spq[2 * NBK], shd[2 * NBK];  // p | q, head V_l[jx] | W_l[jx]
+  __shared__ double2 sy[RB], sa[RB], sv[RB], sw[RB], sc_[RB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t jx = jn + 1;
+  const int64_t rb = jx + int64_t(blockIdx.x) * RB;
+  // ---- loads: every global load is issued from a clamped, in-bounds index
+  // before any value is consumed, so none waits for another ----
+  constexpr int NP = 16;                // record groups held in registers
+  constexpr int NT = 2 * NBK * RB / ENT;  // tile entries per thread
+  const int i = tid % RB, k0 = tid / RB;
+  const int64_t r0 = rb + i, rcl = std::min<int64_t>(r0, n - 1);
+  double2 px[NP];  // lane = slot of the record, wave = record group
+#pragma unroll
+  for (int u = 0; u < NP; ++u)
+    px[u] = pin[int64_t(std::min(wv + (ENT / 64) * u, npin - 1)) * PS + 1 + lane];
+  double2 tx[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int k = k0 + (ENT / RB) * u, l = k % NBK;  // uniform over the wave
+    tx[u] = l < ir ? (k < NBK ? V : W)[int64_t(l) * ldv + rcl] : double2{0, 0};
+  }
+  const double2 hx = (tid < NBK ? V : W)[int64_t(tid % NBK) * ldv + jx];
+  const double2 yx = y[rcl], vx = V[int64_t(ir) * ldv + rcl];
+  const double2 ax = to_d2(reinterpret_cast<const CA *>(A)[rcl * lda + jx]);
+  double2 gx[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) gx[u] = parta[std::min(tid + ENT * u, npa - 1)];
+  const double2 t = tau[jx], sc = scl[jx];
+  const double2 yjx = y[jx];
+  // ---- consume ----
+  {
+    const int l = lane % NBK;
+    double2 b = {0, 0};
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+      if (wv + (ENT / 64) * u < npin) b = cadd(b, px[u]);
+    for (int p = wv + (ENT / 64) * NP; p < npin; p += ENT / 64)
+      b = cadd(b, pin[int64_t(p) * PS + 1 + lane]);
+    sred[wv][lane] = l < ir ? b : double2{0, 0};
+  }
+  if (tid < 2 * NBK) shd[tid] = tid % NBK < ir ? hx : double2{0, 0};
+#pragma unroll
+  for (int u = 0; u < NT; ++u) tile[(k0 + (ENT / RB) * u) * TP + i] = r0 < n ? tx[u] : double2{0, 0};
+  if (tid < RB) {
+    sy[i] = r0 < n ? yx : double2{0, 0};
+    sv[i] = r0 < n ? vx : double2{0, 0};
+    sa[i] = (more && r0 < n) ? ax : double2{0, 0};
+  }
+  double2 ypart = {0, 0};
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (tid + ENT * u < npa) ypart = cadd(ypart, gx[u]);
+  for (int p = tid + 8 * ENT; p < npa; p += ENT) ypart = cadd(ypart, parta[p]);
+  const double yr = block_sum<ENT>(ypart.x, sh);  // also publishes the LDS stores above
+  const double yi = block_sum<ENT>(ypart.y, sh);
+  if (tid < 2 * NBK) {
+    double2 o = {0, 0};
+    if (tid % NBK < ir) {
+      const double2 bs = cadd(cadd(sred[0][tid], sred[1][tid]), cadd(sred[2][tid], sred[3][tid]));
+      o = cadd(cconj(shd[tid]), cmul(sc, bs));
+    }
+    spq[tid] = o;
+  }
+  __syncthreads();
+  double pq_re = 0;  // Re(p^dag q)
+  for (int l = 0; l < ir; ++l) pq_re += spq[l].x * spq[NBK + l].x + spq[l].y * spq[NBK + l].y;
+  const double2 wdv = cmulc(t, double2{yr - 2.0 * pq_re, yi});
+  const double2 alpha = cmul(double2{-0.5 * t.x, -0.5 * t.y}, wdv);
+  // ---- head entry W_ir[jx] (every wave, lane l takes panel column l) ----
+  double2 wh = {0, 0};
+  if (more) {
+    double2 h = {0, 0};
+    if (lane < ir)
+      h = cadd(cmul(shd[lane], spq[NBK + lane]), cmul(shd[NBK + lane], spq[lane]));
+    h.x = wave_sum(h.x);
+    h.y = wave_sum(h.y);
+    wh = cadd(cmul(t, csub(yjx, h)), alpha);  // v[jx] = 1
+  }
+  // ---- rows: four threads per row, panel columns l = part, part + 4, ... ----
+  const int row = tid >> 2, part = tid & 3;
+  const int64_t r = rb + row;
+  double2 hw = {0, 0}, hc = {0, 0};
+#pragma unroll
+  for (int l0 = 0; l0 < NBK; l0 += 4) {
+    const int l = l0 + part;
+    if (l < ir) {
+      const double2 vl = tile[l * TP + row], wl = tile[(NBK + l) * TP + row];
+      hw = cadd(hw, cadd(cmul(vl, spq[NBK + l]), cmul(wl, spq[l])));
+      hc = cadd(hc, cadd(cmul(vl, cconj(shd[NBK + l])), cmul(wl, cconj(shd[l]))));
+    }
+  }
+  hw = shfl_sum4(hw);
+  hc = shfl_sum4(hc);
+  const double2 v = sv[row];
+  const double2 w = cadd(cmul(t, csub(sy[row], hw)), cmul(alpha, v));
+  double2 c = {0, 0};
+  if (more) c = csub(csub(csub(sa[row], hc), cmul(v, cconj(wh))), w);  // conj(V_ir[jx]) = 1
+  if (part == 0) {
+    if (r < n) {
+      W[int64_t(ir) * ldv + r] = w;
+      if (more) col[r] = c;
+    }
+    sw[row] = r < n ? w : double2{0, 0};
+    sc_[row] = (r < n && r >= jx + 2) ? c : double2{0, 0};
+  }
+  if (!more) return;
+  double s1 = (part == 0 && r < n && r >= jx + 2) ? c.x * c.x + c.y * c.y : 0.0;
+  s1 = block_sum<ENT>(s1, sh);  // also publishes sw, sc_
+  double2 *pr = pout + int64_t(blockIdx.x) * PS;
+  if (tid == 0) pr[0] = double2{s1, 0};
+  // ---- BV_l, BW_l (l <= ir): four threads per panel column ----
+  const int k = tid >> 2, l = k % NBK;
+  const bool isw = k >= NBK;
+  if (l <= ir) {
+    double2 acc = {0, 0};
+#pragma unroll 4
+    for (int i = part; i < RB; i += 4) {
+      const double2 m = l < ir ? tile[k * TP + i] : (isw ? sw[i] : sv[i]);
+      acc = cadd(acc, cmulc(m, sc_[i]));
+    }
+    acc = shfl_sum4(acc);  // the four lanes of a column are active together
+    if (part == 0) pr[1 + k] = acc;
+  }
+}
+
+// Trailing update on MFMA: A[r][c] -= sum_l V_l[r] conj(W_l[c]) + W_l[r] conj(V_l[c])
 // for r, c >= c0; real GEMM with K = 4 nbk (x conj(y) interleave, see bse_build).
 template <typename T> struct HerTile;
 template <> struct HerTile<float> { static constexpr int BM = 128, BN = 64, BK = 32; };
@@ -431,8 +611,8 @@ template <> struct HerTile<double> { static constexpr int BM = 128, BN = 64, BK 
 template <typename T>
 __global__ __launch_bounds__(ENT) void k_her2k(int64_t n, int64_t c0, int nbk,
                                                const double2 *__restrict__ V,
-                                               const double2 *__restrict__ W, T *__restrict__ A,
-                                               int64_t lda) {
+                                               const double2 *__restrict__ W, int64_t ldv,
+                                               T *__restrict__ A, int64_t lda) {
   constexpr int BM = HerTile<T>::BM, BN = HerTile<T>::BN, BK = HerTile<T>::BK;
   constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32, KC = BK / 2;
   constexpr int NA = (BM / 2) * KC / ENT, NB = BN * KC / ENT;
@@ -448,20 +628,20 @@ __global__ __launch_bounds__(ENT) void k_her2k(int64_t n, int64_t c0, int nbk,
   const int K2 = 2 * nbk;  // complex reduction length: [V | W] against [W | V]
   for (int i0 = 0; i0 < K2; i0 += KC) {
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int it = tid + ENT * u, r = it / KC, ii = it % KC, I = i0 + ii;
+    for (int u = 0; u < NA; ++u) {  // consecutive threads: consecutive rows (column major V, W)
+      const int it = tid + ENT * u, r = it % (BM / 2), ii = it / (BM / 2), I = i0 + ii;
       const int64_t a = a0 + r;
       double2 x = {0, 0};
-      if (a < n && I < K2) x = I < nbk ? V[a * NBK + I] : W[a * NBK + (I - nbk)];
+      if (a < n && I < K2) x = I < nbk ? V[int64_t(I) * ldv + a] : W[int64_t(I - nbk) * ldv + a];
       *reinterpret_cast<C2 *>(As + (2 * r) * P + 2 * ii) = C2{T(x.x), T(x.y)};
       *reinterpret_cast<C2 *>(As + (2 * r + 1) * P + 2 * ii) = C2{T(x.y), T(-x.x)};
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int it = tid + ENT * u, r = it / KC, ii = it % KC, I = i0 + ii;
+      const int it = tid + ENT * u, r = it % BN, ii = it / BN, I = i0 + ii;
       const int64_t b = b0 + r;
       double2 x = {0, 0};
-      if (b < n && I < K2) x = I < nbk ? W[b * NBK + I] : V[b * NBK + (I - nbk)];
+      if (b < n && I < K2) x = I < nbk ? W[int64_t(I) * ldv + b] : V[int64_t(I - nbk) * ldv + b];
       *reinterpret_cast<C2 *>(Bs + r * P + 2 * ii) = C2{T(x.x), T(x.y)};
     }
     __syncthreads();
@@ -488,7 +668,7 @@ __global__ __launch_bounds__(ENT) void k_her2k(int64_t n, int64_t c0, int nbk,
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal eigenvalues (bisection) and cluster weights
+// tridiagonal eigenvalues (multisection) and cluster weights
 // ---------------------------------------------------------------------------
 // 1 / x to full double precision: hardware estimate plus two Newton steps
 // (arguments are kept away from zero and denormals by the pivot guard).
@@ -527,14 +707,11 @@ __global__ __launch_bounds__(RNT) void k_tri_prep(int64_t n, const double *__res
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < RNT / 64; ++i) {
+    for (int i = 0; i < RNT / 64; ++i) {
       lo = fmin(lo, s_lo[i]);
       hi = fmax(hi, s_hi[i]);
       tn = fmax(tn, s_tn[i]);
     }
-    lo = fmin(lo, s_lo[0]);
-    hi = fmax(hi, s_hi[0]);
-    tn = fmax(tn, s_tn[0]);
     const double pivmin = 1e-100 * fmax(1.0, tn);
     const double pad = 4.4e-16 * fmax(1.0, tn) * double(n) + pivmin;
     sc[0] = lo - pad;
@@ -561,40 +738,56 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d,
   return cnt;
 }
 
-__global__ void k_bisect(int64_t n, const double *__restrict__ d, const double *__restrict__ e2,
-                         const double *__restrict__ sc, double *__restrict__ omega) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// One wave per eigenvalue index: each pass evaluates 64 Sturm counts at the
+// interior points of the current interval (lane l at a + (l+1)(b-a)/65) and
+// keeps the sub-interval holding eigenvalue i; ~9 passes reach FP64 resolution.
+__global__ __launch_bounds__(256) void k_bisect(int64_t n, const double *__restrict__ d,
+                                                const double *__restrict__ e2,
+                                                const double *__restrict__ sc,
+                                                double *__restrict__ omega) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
   double a = sc[0], b = sc[1];
   const double pivmin = sc[3];
-  for (int it = 0; it < 128; ++it) {
-    const double mid = 0.5 * (a + b);
-    if (mid <= a || mid >= b) break;
+  for (int pass = 0; pass < 24; ++pass) {
     if (b - a <= 2.3e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
-    if (sturm_count(d, e2, n, mid, pivmin) > i)
-      b = mid;
-    else
-      a = mid;
+    const double x = a + (b - a) * double(lane + 1) / 65.0;
+    const int cnt = sturm_count(d, e2, n, x, pivmin);
+    // first lane whose point has more than i eigenvalues below it
+    const unsigned long long m = __ballot(cnt > i);
+    const int f = m ? __builtin_ctzll(m) : 64;
+    const double na = f == 0 ? a : a + (b - a) * double(f) / 65.0;
+    const double nb = f == 64 ? b : a + (b - a) * double(f + 1) / 65.0;
+    if (!(na > a || nb < b)) break;  // no progress at this resolution
+    a = na;
+    b = nb;
   }
-  omega[i] = 0.5 * (a + b);
+  if (lane == 0) omega[i] = 0.5 * (a + b);
 }
 
 // Weights: a cluster is a maximal run of eigenvalues whose consecutive gaps
 // are <= sc[4]; its head (first index) gets the cluster centre as pole and
 // beta0^2 times the residue of G(z) = [(z - T)^-1]_00 as strength, the other
-// members get zero strength.
-constexpr int NCONT = 64;  // trapezoidal nodes on the circle
-__global__ void k_weights(int64_t n, const double *__restrict__ d, const double *__restrict__ e2,
-                          const double *__restrict__ sc, const double *__restrict__ beta0,
-                          const double *__restrict__ omega, double *__restrict__ pole,
-                          double *__restrict__ osc) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// members get zero strength.  One wave per index; lanes are contour nodes.
+constexpr int NCONT = 64;  // trapezoidal nodes on the circle (32 in the upper half)
+__global__ __launch_bounds__(256) void k_weights(int64_t n, const double *__restrict__ d,
+                                                 const double *__restrict__ e2,
+                                                 const double *__restrict__ sc,
+                                                 const double *__restrict__ beta0,
+                                                 const double *__restrict__ omega,
+                                                 double *__restrict__ pole,
+                                                 double *__restrict__ osc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
   const double ctol = sc[4];
   const double li = omega[i];
   if (i > 0 && li - omega[i - 1] <= ctol) {
-    pole[i] = li;
-    osc[i] = 0.0;
+    if (lane == 0) {
+      pole[i] = li;
+      osc[i] = 0.0;
+    }
     return;
   }
   int64_t j = i;
@@ -606,23 +799,26 @@ __global__ void k_weights(int64_t n, const double *__restrict__ d, const double 
   if (g > 1e299) g = fmax(1.0, sc[2]);
   const double rad = sqrt(fmax(half, 1e-6 * g) * g);
   double wsum = 0.0;
-  for (int m = 0; m < NCONT / 2; ++m) {
-    const double th = 6.283185307179586 * (m + 0.5) / NCONT;
-    const double zx = c + rad * cos(th), zy = rad * sin(th);
+  if (lane < NCONT / 2) {
+    const double th = 6.283185307179586 * (lane + 0.5) / NCONT;
+    const double ct = cos(th), st = sin(th);
+    const double zx = c + rad * ct, zy = rad * st;
     // h = z - d_{n-1}; h = z - d_k - e_k^2 / h, k = n-2 .. 0; G = 1 / h
     double hx = zx - d[n - 1], hy = zy;
     for (int64_t k = n - 2; k >= 0; --k) {
-      const double inv = e2[k] / (hx * hx + hy * hy);
+      const double inv = e2[k] * rcp64(hx * hx + hy * hy);
       hx = zx - d[k] - hx * inv;
       hy = zy + hy * inv;
     }
-    const double den = hx * hx + hy * hy;
-    const double gx = hx / den, gy = -hy / den;
-    // Re[G (z - c)] with z - c = rad (cos, sin)
-    wsum += gx * rad * cos(th) - gy * rad * sin(th);
+    const double den = rcp64(hx * hx + hy * hy);
+    const double gx = hx * den, gy = -hy * den;
+    wsum = gx * rad * ct - gy * rad * st;  // Re[G (z - c)]
   }
-  pole[i] = c;
-  osc[i] = beta0[0] * beta0[0] * wsum * 2.0 / NCONT;
+  wsum = wave_sum(wsum);
+  if (lane == 0) {
+    pole[i] = c;
+    osc[i] = beta0[0] * beta0[0] * wsum * 2.0 / NCONT;
+  }
 }
 
 }  // namespace
@@ -639,80 +835,86 @@ extern "C" size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int
 
 namespace bse {
 template <typename TH, typename TA>
-int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, int32_t prec,
-                 double *omega, double *pole, double *osc, void *ws, hipStream_t s) {
+int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
+                 double *pole, double *osc, void *ws, hipStream_t s) {
   Ws w;
   ws_layout(n, sizeof(TA) == 8, &w, (char *)ws);
   TA *A = (TA *)w.A;
-  const int64_t lda = w.lda;
+  const int64_t lda = w.lda, ldv = w.ldv;
   {
     dim3 g((unsigned)std::min<int64_t>((n + ENT - 1) / ENT, 64), (unsigned)n);
-    BSE_LAUNCH("k_copy_in", (k_copy_in<TH, TA>), g, dim3(ENT), 0, s, n, (const TH *)Hmu, ld, A, lda);
+    BSE_LAUNCH("k_copy_in", (k_copy_in<TH, TA>), g, dim3(ENT), 0, s, n, (const TH *)Hmu, ld, A,
+               lda);
   }
-  auto nwg_rows = [](int64_t m) { return (unsigned)std::max<int64_t>(1, (m + ENT - 1) / ENT); };
-  auto hemv = [&](int64_t jr, int64_t j0, int ir, int np3) {
-    const int64_t m = n - (jr + 1);
-    const int rpw = hemv_rpw(m);
-    const unsigned gh = (unsigned)std::max<int64_t>(1, (m + 4 * rpw - 1) / (4 * rpw));
-    BSE_LAUNCH("k_hemv2", k_hemv2<TA>, dim3(gh), dim3(ENT), 0, s, n, jr, j0, ir, rpw, A, lda,
-               w.col, w.part3, w.part, np3, w.d, w.e, w.beta0, w.tau, w.scl, w.vbuf, w.V, w.W,
-               w.y, w.pq);
-  };
+  auto nwg = [](int64_t m) { return (unsigned)std::max<int64_t>(1, (m + ENT - 1) / ENT); };
   // ---- initial reflection: B -> beta0 e_1, A <- Q0^dag A Q0 ----
   {
-    const unsigned g = std::min<unsigned>(nwg_rows(n), PMAX);
+    const unsigned g = std::min<unsigned>(nwg(n), PMAX);
     BSE_LAUNCH("k_load_b", k_load_b, dim3(g), dim3(ENT), 0, s, n, (const double2 *)Bmu, w.col,
-               w.part3, (int)g);
-    hemv(-1, 0, -1, (int)g);
-    const unsigned gw = nwg_rows(n);
-    BSE_LAUNCH("k_w", k_w, dim3(gw), dim3(ENT), 0, s, n, int64_t(0), 0, int64_t(0), w.V, w.W, w.y,
-               w.pq, w.vbuf, w.tau, w.wraw, w.part2);
+               w.part3);
+    const int rpw = hemv_rpw(n);
+    const unsigned gh = (unsigned)((n + 4 * rpw - 1) / (4 * rpw));
+    BSE_LAUNCH("k_hemv0", k_hemv0<TA>, dim3(gh), dim3(ENT), 0, s, n, rpw, A, lda, w.col,
+               w.part3, (int)g, w.beta0, w.tau, w.vbuf, w.y);
+    const unsigned gw = nwg(n);
+    BSE_LAUNCH("k_w0", k_w0, dim3(gw), dim3(ENT), 0, s, n, w.y, w.vbuf, w.tau, w.wraw, w.part2);
     dim3 gr((unsigned)std::min<int64_t>((n + ENT - 1) / ENT, 16), (unsigned)n);
     BSE_LAUNCH("k_rank2", k_rank2<TA>, gr, dim3(ENT), 0, s, n, A, lda, w.wraw, w.vbuf, w.part2,
                (int)gw, w.tau);
     BSE_HIP_CHECK(hipGetLastError());
   }
-  // ---- blocked tridiagonalisation ----
+  // ---- blocked tridiagonalisation, two kernels per column ----
+  int cur = 0;  // partial-sum record buffer written last
   for (int64_t j0 = 0; j0 < n; j0 += NBK) {
     const int nbk = (int)std::min<int64_t>(NBK, n - j0);
-    // first column of the panel: no pending panel updates
-    unsigned gc = nwg_rows(n - j0);
-    BSE_LAUNCH("k_col", k_col<TA>, dim3(gc), dim3(ENT), 0, s, n, j0, 0, int64_t(-1), 0, j0, j0, 0,
-               A, lda, w.V, w.W, w.wraw, w.vbuf, w.part2, 0, w.tau, w.col, w.part3, w.part, w.d);
+    unsigned np = nwg(n - j0);
+    BSE_LAUNCH("k_col0", k_col0<TA>, dim3(np), dim3(ENT), 0, s, n, j0, A, lda, w.col,
+               w.partb + cur * PMAX * PS);
     for (int i = 0; i < nbk; ++i) {
-      const int64_t j = j0 + i;
-      if (j + 1 >= n) break;  // the last diagonal element is stored by k_col
-      hemv(j, j0, i, (int)gc);
-      const int64_t m0 = j + 1, m = n - m0;
-      const unsigned gw = nwg_rows(m);
-      BSE_LAUNCH("k_w", k_w, dim3(gw), dim3(ENT), 0, s, n, m0, i, j + 1, w.V, w.W, w.y, w.pq,
-                 w.vbuf, w.tau, w.wraw, w.part2);
-      const bool more = (i + 1 < nbk);  // next column still in this panel
-      const int64_t jr = more ? j + 1 : int64_t(-1);
-      gc = nwg_rows(n - j0);
-      BSE_LAUNCH("k_col", k_col<TA>, dim3(gc), dim3(ENT), 0, s, n, j0, 1, j, i, j0, jr,
-                 more ? i + 1 : 0, A, lda, w.V, w.W, w.wraw, w.vbuf, w.part2, (int)gw, w.tau,
-                 w.col, w.part3, w.part, w.d);
+      const int64_t jn = j0 + i;
+      const int64_t m = n - jn - 1;  // rows below the new reflector's head
+      const double2 *pin = w.partb + cur * PMAX * PS;
+      // waves per row: enough workgroups to fill the chip, at most PAMAX partial sums
+      const int wpr = m <= 2560 ? 4 : (m <= 8192 ? 2 : 1);
+      const unsigned gh = (unsigned)std::max<int64_t>(1, (m + 4 / wpr - 1) / (4 / wpr));
+#define BSE_COLA(WPR)                                                                            \
+  BSE_LAUNCH("k_colA", (k_colA<TA, WPR>), dim3(gh), dim3(ENT), 0, s, n, jn, i, A, lda, w.V, ldv, \
+             w.col, pin, (int)np, w.tau, w.scl, w.d, w.e, w.y, w.parta)
+      if (wpr == 4)
+        BSE_COLA(4);
+      else if (wpr == 2)
+        BSE_COLA(2);
+      else
+        BSE_COLA(1);
+#undef BSE_COLA
+      if (m <= 0) break;  // last diagonal element recorded; nothing below it
+      const int more = (i + 1 < nbk) ? 1 : 0;
+      const unsigned nb = (unsigned)((m + RB - 1) / RB);
+      BSE_LAUNCH("k_colB", k_colB<TA>, dim3(nb), dim3(ENT), 0, s, n, jn, i, more, A, lda, w.V,
+                 w.W, ldv, w.y, w.parta, (int)gh, pin, (int)np, w.tau, w.scl, w.col,
+                 w.partb + (cur ^ 1) * PMAX * PS);
+      cur ^= 1;
+      np = nb;
     }
     BSE_HIP_CHECK(hipGetLastError());
-    // trailing update of the rows/columns after the panel
     const int64_t c0 = j0 + nbk;
     if (c0 < n) {
       constexpr int BM = HerTile<TA>::BM, BN = HerTile<TA>::BN;
       const int64_t m = n - c0;
       dim3 g((unsigned)((m + BN - 1) / BN), (unsigned)((2 * m + BM - 1) / BM));
-      BSE_LAUNCH("k_her2k", k_her2k<TA>, g, dim3(ENT), 0, s, n, c0, nbk, w.V, w.W, A, lda);
+      BSE_LAUNCH("k_her2k", k_her2k<TA>, g, dim3(ENT), 0, s, n, c0, nbk, w.V, w.W, ldv, A, lda);
       BSE_HIP_CHECK(hipGetLastError());
     }
   }
   // ---- tridiagonal eigenvalues and optical weights ----
   const double eps_w = sizeof(TA) == 8 ? 2.2e-16 : 1.2e-7;
   const double ctol_rel = 8.0 * eps_w * std::sqrt(double(n));
-  BSE_LAUNCH("k_tri_prep", k_tri_prep, dim3(1), dim3(RNT), 0, s, n, w.d, w.e, ctol_rel, w.e2, w.tsc);
-  BSE_LAUNCH("k_bisect", k_bisect, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, w.d, w.e2,
-             w.tsc, omega);
-  BSE_LAUNCH("k_weights", k_weights, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, w.d, w.e2,
-             w.tsc, w.beta0, omega, pole, osc);
+  BSE_LAUNCH("k_tri_prep", k_tri_prep, dim3(1), dim3(RNT), 0, s, n, w.d, w.e, ctol_rel, w.e2,
+             w.tsc);
+  const unsigned gw = (unsigned)((n + 3) / 4);
+  BSE_LAUNCH("k_bisect", k_bisect, dim3(gw), dim3(256), 0, s, n, w.d, w.e2, w.tsc, omega);
+  BSE_LAUNCH("k_weights", k_weights, dim3(gw), dim3(256), 0, s, n, w.d, w.e2, w.tsc, w.beta0,
+             omega, pole, osc);
   BSE_HIP_CHECK(hipGetLastError());
   return BSE_OK;
 }
@@ -733,8 +935,8 @@ extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_
     return fail(BSE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t s = (hipStream_t)stream;
   if (prec == BSE_FP64)
-    return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, prec, omega, pole, osc, ws, s)
-                  : eigh_run<float, double>(n, Hmu, ld, Bmu, prec, omega, pole, osc, ws, s);
-  return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, prec, omega, pole, osc, ws, s)
-                : eigh_run<float, float>(n, Hmu, ld, Bmu, prec, omega, pole, osc, ws, s);
+    return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
+                  : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
+  return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
+                : eigh_run<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
 }
