@@ -501,9 +501,10 @@ __global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int
   const double2 hx = (tid < NBK ? V : W)[int64_t(tid % NBK) * ldv + jx];
   const double2 yx = y[rcl], vx = V[int64_t(ir) * ldv + rcl];
   const double2 ax = to_d2(reinterpret_cast<const CA *>(A)[rcl * lda + jx]);
-  double2 gx[8];
+  constexpr int NG = 16;  // partial sums of k_colA held in registers per thread
+  double2 gx[NG];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) gx[u] = parta[std::min(tid + ENT * u, npa - 1)];
+  for (int u = 0; u < NG; ++u) gx[u] = parta[std::min(tid + ENT * u, npa - 1)];
   const double2 t = tau[jx], sc = scl[jx];
   const double2 yjx = y[jx];
   // ---- consume ----
@@ -527,34 +528,43 @@ __global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int
   }
   double2 ypart = {0, 0};
 #pragma unroll
-  for (int u = 0; u < 8; ++u)
+  for (int u = 0; u < NG; ++u)
     if (tid + ENT * u < npa) ypart = cadd(ypart, gx[u]);
-  for (int p = tid + 8 * ENT; p < npa; p += ENT) ypart = cadd(ypart, parta[p]);
+  for (int p = tid + NG * ENT; p < npa; p += ENT) ypart = cadd(ypart, parta[p]);
   const double yr = block_sum<ENT>(ypart.x, sh);  // also publishes the LDS stores above
   const double yi = block_sum<ENT>(ypart.y, sh);
-  if (tid < 2 * NBK) {
-    double2 o = {0, 0};
-    if (tid % NBK < ir) {
-      const double2 bs = cadd(cadd(sred[0][tid], sred[1][tid]), cadd(sred[2][tid], sred[3][tid]));
-      o = cadd(cconj(shd[tid]), cmul(sc, bs));
+  // wave 0, lane l < NBK: p_l, q_l, Re(conj(p_l) q_l) and the head term
+  // V_l[jx] q_l + W_l[jx] p_l, summed over l in one pass
+  __shared__ double ssum[3];
+  if (wv == 0) {
+    double2 pl = {0, 0}, ql = {0, 0}, hl = {0, 0};
+    if (lane < ir) {
+      const double2 bv = cadd(cadd(sred[0][lane], sred[1][lane]), cadd(sred[2][lane], sred[3][lane]));
+      const int lw = NBK + lane;
+      const double2 bw = cadd(cadd(sred[0][lw], sred[1][lw]), cadd(sred[2][lw], sred[3][lw]));
+      pl = cadd(cconj(shd[lane]), cmul(sc, bv));
+      ql = cadd(cconj(shd[lw]), cmul(sc, bw));
+      hl = cadd(cmul(shd[lane], ql), cmul(shd[lw], pl));
     }
-    spq[tid] = o;
+    if (lane < NBK) {
+      spq[lane] = pl;
+      spq[NBK + lane] = ql;
+    }
+    const double pr = wave_sum(pl.x * ql.x + pl.y * ql.y);
+    const double hr = wave_sum(hl.x), hi = wave_sum(hl.y);
+    if (lane == 0) {
+      ssum[0] = pr;
+      ssum[1] = hr;
+      ssum[2] = hi;
+    }
   }
   __syncthreads();
-  double pq_re = 0;  // Re(p^dag q)
-  for (int l = 0; l < ir; ++l) pq_re += spq[l].x * spq[NBK + l].x + spq[l].y * spq[NBK + l].y;
+  const double pq_re = ssum[0];  // Re(p^dag q)
   const double2 wdv = cmulc(t, double2{yr - 2.0 * pq_re, yi});
   const double2 alpha = cmul(double2{-0.5 * t.x, -0.5 * t.y}, wdv);
-  // ---- head entry W_ir[jx] (every wave, lane l takes panel column l) ----
-  double2 wh = {0, 0};
-  if (more) {
-    double2 h = {0, 0};
-    if (lane < ir)
-      h = cadd(cmul(shd[lane], spq[NBK + lane]), cmul(shd[NBK + lane], spq[lane]));
-    h.x = wave_sum(h.x);
-    h.y = wave_sum(h.y);
-    wh = cadd(cmul(t, csub(yjx, h)), alpha);  // v[jx] = 1
-  }
+  // head entry W_ir[jx] (v[jx] = 1)
+  const double2 wh = more ? cadd(cmul(t, csub(yjx, double2{ssum[1], ssum[2]})), alpha)
+                          : double2{0, 0};
   // ---- rows: four threads per row, panel columns l = part, part + 4, ... ----
   const int row = tid >> 2, part = tid & 3;
   const int64_t r = rb + row;
