@@ -70,6 +70,31 @@ def cpu_baseline(cfg, nq, log_fn):
                       f"{t2 - t0:.1f} s"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_direct_fused_cfg2_fp32.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_24860_amd", "csrc", f)
+                  for f in ("bse_build.hip", "mfma_tile.h")]
+
+
+def measured_traffic(workload, prec):
+    """HBM bytes per launch of k_direct_fused from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (copy-calibrated), or None when the kernel
+    sources changed since the counters were taken or the workload differs."""
+    import hashlib
+    if (workload, prec) != ("cfg2", "fp32") or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        k, _, v = line.strip().partition(": ")
+        if k in ("traffic_bytes_per_launch", "source_sha256"):
+            vals[k] = v
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +104,9 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-q", type=int, default=32)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times) and exit: "
+                         "the reference for scaling HBM byte counters")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel (adds event records; breakdown on stderr)")
     args = ap.parse_args()
@@ -90,6 +118,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * 2**18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        return
     import synth
     import workloads
     from paper_2603_24860_amd import bse as B
@@ -176,7 +212,9 @@ def main():
             "peak": pk,
             "unit": "TFLOP/s",
             "frac": round(achieved / pk, 4) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, args.prec),
+            "traffic_unit": "B/launch (HBM fetch + write, rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                            "copy-calibrated)",
             "flops_per_launch": kflops / max(1, kt_n // args.steps),
             "avg_launch_ms": kt_ms / kt_n if kt_n else None,
         },
