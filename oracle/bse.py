@@ -25,8 +25,28 @@ from . import groups, orbits
 # ----------------------------------------------------------------------------
 # problem assembly: the oracle's own tables feed the shared input generator
 # ----------------------------------------------------------------------------
-def make_problem(cfg, vector_dipole=True, zero_interaction=False):
-    """Tables (oracle's own) plus seeded inputs for one synthetic system."""
+class _ClassSubset:
+    """M_v or M_c for a subset of swap classes, indexed by class id.
+
+    The generator keys every draw by the class's representative pair, so the
+    subset holds exactly the values the full array would hold for those ids."""
+
+    def __init__(self, ids, M):
+        self.pos = {int(c): i for i, c in enumerate(ids)}
+        self.M = M
+
+    def __getitem__(self, cls):
+        cls = np.atleast_1d(np.asarray(cls))
+        return self.M[np.array([self.pos[int(c)] for c in cls.ravel()])].reshape(
+            cls.shape + self.M.shape[1:])
+
+
+def make_problem(cfg, vector_dipole=True, zero_interaction=False, pairs=None):
+    """Tables (oracle's own) plus seeded inputs for one synthetic system.
+
+    pairs: optional iterable of k-pair ids k N_k + k'; M_v and M_c are then
+    drawn only for the swap classes of those pairs, which is enough for the
+    single elements H[(k,v,c), (k',v',c')] of a large system."""
     lattice = cfg.get("lattice", "cubic")
     g = groups.group("Oh" if lattice == "cubic" else "D6h")
     grid = tuple(cfg["grid"])
@@ -36,8 +56,14 @@ def make_problem(cfg, vector_dipole=True, zero_interaction=False):
     ev, ec = synth.band_energies(seed, lattice, grid, kfrac, T["krep_of_k"], nv, nc)
     vd = synth.coulomb_diag(nmb)
     mx = synth.exchange_vectors(seed, T["korb_reps"], nv, nc, nmb)
-    mv = synth.pair_vectors(seed, "mv", T["class_rep"], T["class_selfswap"], nv, nmb)
-    mc = synth.pair_vectors(seed, "mc", T["class_rep"], T["class_selfswap"], nc, nmb)
+    if pairs is None:
+        mv = synth.pair_vectors(seed, "mv", T["class_rep"], T["class_selfswap"], nv, nmb)
+        mc = synth.pair_vectors(seed, "mc", T["class_rep"], T["class_selfswap"], nc, nmb)
+    else:
+        ids = np.unique(T["pidx"][np.asarray(list(pairs), dtype=np.int64)])
+        reps, ss = T["class_rep"][ids], T["class_selfswap"][ids]
+        mv = _ClassSubset(ids, synth.pair_vectors(seed, "mv", reps, ss, nv, nmb))
+        mc = _ClassSubset(ids, synth.pair_vectors(seed, "mc", reps, ss, nc, nmb))
     w = synth.screened_w(seed, T["korb_reps"], nmb)
     B = synth.dipoles(seed, T["kperm"], g["rcart"], T["krep_of_k"], nv, nc,
                       vector=vector_dipole).reshape(-1)

@@ -1,0 +1,161 @@
+"""GPU parity at the full workload sizes, in the configuration bench.py times.
+
+* cfg2 (Oh 8x8x8, N = 8192, T1u n = 2160): the whole path (build, projection,
+  block eigh, eps2) against the FP64 oracle's solution stored in
+  tests/golden/cfg2_t1u_oracle.json (written by make_cfg2_reference.py from
+  the oracle alone).  Lowest 100 energies within 1e-5 eV (FP32 path) /
+  1e-9 eV (FP64 path), eps2 within 1e-4 relative, cumulative strengths.
+* cfg2 and cfg3 (Oh 12^3, N = 41472): H elements sampled across the matrix
+  (corners, conjugated classes, k = k', the diagonal, random pairs) against
+  the oracle's element-by-element definition.  FP32 tolerance 2e-6 max|H|.
+* cfg3: properties that hold at any size: the T1u block has the closed-form
+  dimension 10080, and its oscillator strengths sum to |B|^2 (all dipole
+  weight lies in T1u), with |B|^2 from the oracle's own dipoles.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bse as OB
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_t1u_oracle.json")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2603_24860_amd import bse as B
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return B
+
+
+def _match_cumulative(pole, osc, ce, cw, tol, wtol):
+    """Cumulative oscillator strength agrees at every point further than tol
+    from all poles; every oracle pole with weight has a GPU pole within tol."""
+    tot = cw.sum()
+    keep = osc > 1e-14 * tot
+    p, o = pole[keep], osc[keep]
+    for e, w in zip(ce, cw):
+        if w > 1e-8 * tot:
+            assert np.abs(p - e).min() < tol, (e, np.abs(p - e).min())
+    allp = np.sort(np.concatenate([p, ce]))
+    gaps = allp[1:] - allp[:-1]
+    xs = (0.5 * (allp[1:] + allp[:-1]))[gaps > 2 * tol]
+    for x in xs:
+        assert abs(o[p < x].sum() - cw[ce < x].sum()) <= wtol * tot, x
+    assert abs(osc.sum() - tot) <= wtol * tot
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precname,tol,wtol", [("FP32", 1e-5, 1e-3), ("FP64", 1e-9, 1e-6)])
+def test_cfg2_end_to_end(lib, precname, tol, wtol):
+    import workloads
+    from paper_2603_24860_amd.system import Solver
+    ref = json.load(open(GOLD))
+    cfg = synth.config("cfg2")
+    say("cfg2 e2e", precname)
+    S = workloads.device_system(cfg, getattr(lib, precname))
+    act, _ = S.active_irrep()
+    assert act == ref["irrep"]
+    wgrid = np.linspace(ref["wmin"], ref["wmax"], ref["nw"])
+    sv = Solver(S, act, wgrid=wgrid)
+    assert sv.blk.n == ref["n"]
+    sv.step()
+    res = sv.results()
+    lowest = np.asarray(ref["omega"][:100])
+    err = np.abs(res["lowest"] - lowest).max()
+    say("  lowest-100 max err (eV)", err)
+    assert err < tol
+    e2 = np.asarray(ref["eps2"])
+    e2err = np.abs(res["eps2"] - e2).max() / np.abs(e2).max()
+    say("  eps2 rel err", e2err)
+    assert e2err <= 1e-4
+    _match_cumulative(res["pole"], res["osc"], np.asarray(ref["cl_e"]), np.asarray(ref["cl_w"]),
+                      100 * tol, wtol)
+    del sv, S
+    torch.cuda.empty_cache()
+
+
+def _sample_pairs(P, rng, nrand):
+    """(a, b) element indices: corners, the diagonal, k = k', conjugated
+    classes and random pairs."""
+    N, nk, per = P["N"], P["nk"], P["nv"] * P["nc"]
+    ab = [(0, 0), (N - 1, N - 1), (0, N - 1), (N - 1, 0), (per - 1, per), (N // 2, N // 2 + 1)]
+    ab += [(int(a), int(a)) for a in rng.integers(0, N, 8)]
+    for k in rng.integers(0, nk, 6):
+        ab.append((int(k) * per + int(rng.integers(per)), int(k) * per + int(rng.integers(per))))
+    ab += [tuple(int(x) for x in rng.integers(0, N, 2)) for _ in range(nrand)]
+    return ab
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+def test_sampled_elements_full_size(lib, name):
+    import workloads
+    cfg = synth.config(name)
+    say("sampled H elements", name, "FP32: generating inputs")
+    S = workloads.device_system(cfg, lib.FP32)
+    say("  building H, N =", S.N)
+    H = S.build()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    N, nk = S.N, S.nk
+    per = S.nv * S.nc
+    Pt = OB.make_problem(cfg, pairs=[0])  # tables only, to find conjugated classes
+    conj_pairs = np.nonzero(Pt["T"]["pconj"])[0]
+    ab = _sample_pairs(Pt, rng, 200)
+    for p in rng.choice(conj_pairs, 6, replace=False):
+        k, k2 = divmod(int(p), nk)
+        ab.append((k * per + int(rng.integers(per)), k2 * per + int(rng.integers(per))))
+    pairs = [(a // per) * nk + b // per for a, b in ab]
+    say("  oracle elements for", len(ab), "samples")
+    P = OB.make_problem(cfg, pairs=pairs)
+    ref = np.array([OB.hamiltonian_element(P, a, b) for a, b in ab])
+    flat = H.view(-1)
+    ld = H.stride(0)
+    idx = torch.tensor([a * ld + b for a, b in ab], dtype=torch.int64, device=H.device)
+    got = flat[idx].cpu().numpy().astype(np.complex128)
+    hmax = 0.0
+    for r0 in range(0, N, 4096):  # max |H| without a full-size temporary
+        hmax = max(hmax, float(H[r0:r0 + 4096].abs().max()))
+    err = np.abs(got - ref).max()
+    say("  max |dH| / max|H| =", err / hmax, " max|H| =", hmax)
+    assert err <= 2e-6 * hmax
+    del H, S, flat
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_cfg3_block_properties(lib):
+    import workloads
+    from paper_2603_24860_amd.system import Solver
+    cfg = synth.config("cfg3")
+    say("cfg3 T1u block properties FP32: generating inputs")
+    S = workloads.device_system(cfg, lib.FP32)
+    P = OB.make_problem(cfg, pairs=[0])
+    dims = OB.block_dims_closed_form(P)
+    act, _ = S.active_irrep()
+    assert act == "T1u"
+    sv = Solver(S, act, wgrid=np.linspace(-20, 20, 200))
+    assert sv.blk.n == dims["T1u"] == 10080
+    say("  solve n =", sv.blk.n)
+    sv.step()
+    res = sv.results()
+    b2 = float(np.sum(np.abs(P["B"]) ** 2))
+    say("  sum osc / |B|^2 - 1 =", res["osc"].sum() / b2 - 1)
+    assert abs(res["osc"].sum() - b2) <= 1e-6 * b2
+    assert np.all(np.diff(res["omega"]) >= 0)
+    del sv, S
+    torch.cuda.empty_cache()

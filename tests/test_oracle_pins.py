@@ -347,3 +347,17 @@ def test_paper_table_ratios():
         ratio = n ** 3 / (3 * float(chi @ fix) / 48)
         assert prev < ratio < 48 / 9 and abs(ratio - expect) < 0.005
         prev = ratio
+
+
+def test_pair_subset_problem_matches_full():
+    """Elements from a problem holding M only for the sampled pairs' classes
+    equal those of the full problem (the generator keys draws by class rep)."""
+    cfg = synth.config("cfg1")
+    P = bse.make_problem(cfg)
+    rng = np.random.default_rng(3)
+    ab = rng.integers(0, P["N"], size=(40, 2))
+    per = P["nv"] * P["nc"]
+    pairs = [(a // per) * P["nk"] + b // per for a, b in ab]
+    Ps = bse.make_problem(cfg, pairs=pairs)
+    for a, b in ab:
+        assert bse.hamiltonian_element(Ps, a, b) == bse.hamiltonian_element(P, a, b)
