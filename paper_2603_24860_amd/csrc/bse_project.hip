@@ -8,11 +8,13 @@
 //       sum_{k in O, k' in O'} U_O[k,j] H[(k,v,c),(k',v',c')] U_O'[k',j'].
 //
 // Kernel k_project: one workgroup per (row band (v,c), column orbit O', row
-// orbit O).  For every k in O it stages the H row (k,v,c) restricted to the
-// columns of O' (|O'| runs of nv nc contiguous complex values) in LDS, contracts
-// it with U_O' (thread = output column (j', v', c')), and accumulates
-// U_O[k, j] times that into registers.  Each H element is read exactly once
-// per projected block; the kernel is bound by HBM bandwidth.
+// orbit O).  The members of both orbits and both bases are staged in LDS once.
+// The H rows (k,v,c), k in O, restricted to the columns of O' (|O'| runs of
+// nv nc contiguous complex values) are fetched RU rows at a time, up to PCH
+// elements, with every load of a chunk issued before any is stored to LDS.
+// Each chunk is contracted with U_O' (thread = output column (j', v', c')) and
+// accumulated, times U_O[k, j], into registers.  Each H element is read exactly
+// once per projected block; the kernel is bound by HBM bandwidth.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -25,6 +27,8 @@ namespace {
 constexpr int PNT = 256;
 constexpr int PMAXR = 9;     // basis vectors per orbit: d_mu m_mu(O) <= d_max^2
 constexpr int PMAXCOL = 2;   // output columns per thread: r' nv nc <= 512
+constexpr int PMAXL = 48;    // orbit size <= |S|
+constexpr int PCH = 2048;    // H elements per chunk (8 per thread)
 
 template <typename T>
 __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__restrict__ H,
@@ -34,56 +38,81 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
                                                  const int32_t *__restrict__ orb_dim,
                                                  const int64_t *__restrict__ ub_off,
                                                  const double *__restrict__ ub, T *__restrict__ Hmu,
-                                                 int64_t ldmu, int maxL) {
+                                                 int64_t ldmu) {
   typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type C2;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ C2 rows[PCH];
+  __shared__ double u1s[PMAXL * PMAXR], u2s[PMAXL * PMAXR];
+  __shared__ int32_t m1s[PMAXL], m2s[PMAXL];
   const int nb = nv * nc;
   const int band = blockIdx.x;        // (v, c) of the output rows
-  const int o2 = blockIdx.y, o1 = blockIdx.z;
+  // orbit ids grow with orbit size on the simple grids, so the largest (longest)
+  // orbit pairs are dispatched first and do not form a tail
+  const int o2 = gridDim.y - 1 - blockIdx.y, o1 = gridDim.z - 1 - blockIdx.z;
   const int r1 = orb_dim[o1], r2 = orb_dim[o2];
   if (r1 == 0 || r2 == 0) return;
   const int L1 = mem_off[o1 + 1] - mem_off[o1], L2 = mem_off[o2 + 1] - mem_off[o2];
-  if (L2 > maxL || r1 > PMAXR || r2 > PMAXR) return;  // outside the LDS sizing
+  // orbits have at most |S| members and bases at most d_mu^2 vectors (the
+  // host checks PMAXL nb <= PCH); anything else is not a valid block
+  if (L1 > PMAXL || L2 > PMAXL || r1 > PMAXR || r2 > PMAXR) return;
   const int32_t *m1 = members + mem_off[o1], *m2 = members + mem_off[o2];
-  const double *U1 = ub + ub_off[o1], *U2 = ub + ub_off[o2];
-  C2 *row = reinterpret_cast<C2 *>(smem);                  // [L2 * nb]
-  double *u2s = reinterpret_cast<double *>(row + L2 * nb);  // [L2 * r2]
-  for (int i = threadIdx.x; i < L2 * r2; i += PNT) u2s[i] = U2[i];
-  const int ncol = r2 * nb;
+  for (int i = threadIdx.x; i < L1 * r1; i += PNT) u1s[i] = ub[ub_off[o1] + i];
+  for (int i = threadIdx.x; i < L2 * r2; i += PNT) u2s[i] = ub[ub_off[o2] + i];
+  if (threadIdx.x < L2) m2s[threadIdx.x] = m2[threadIdx.x];
+  if (threadIdx.x < L1) m1s[threadIdx.x] = m1[threadIdx.x];
+  const int ncol = r2 * nb, per = L2 * nb;
+  const int RU = PCH / per;  // rows per chunk (>= 1)
   double accr[PMAXCOL][PMAXR], acci[PMAXCOL][PMAXR];
 #pragma unroll
   for (int t = 0; t < PMAXCOL; ++t)
 #pragma unroll
     for (int j = 0; j < PMAXR; ++j) accr[t][j] = acci[t][j] = 0.0;
   const int v = band / nc, c = band % nc;
-  for (int i = 0; i < L1; ++i) {
-    const int64_t a = (int64_t(m1[i]) * nv + v) * nc + c;
-    const C2 *hrow = reinterpret_cast<const C2 *>(H) + a * ldh;
-    __syncthreads();
-    for (int e = threadIdx.x; e < L2 * nb; e += PNT) {
-      const int i2 = e / nb, b2 = e % nb;
-      row[e] = hrow[int64_t(m2[i2]) * nb + b2];
+  __syncthreads();  // m1s, m2s
+  // chunk loads go to registers; the next chunk's loads are in flight while
+  // the current one is contracted from LDS
+  C2 x[PCH / PNT];
+  auto fetch = [&](int i0) {
+    const int nr = std::min(RU, L1 - i0);
+#pragma unroll
+    for (int u = 0; u < PCH / PNT; ++u) {
+      const int e = threadIdx.x + PNT * u;
+      x[u] = C2{0, 0};
+      if (e < nr * per) {
+        const int ii = e / per, rem = e - ii * per, i2 = rem / nb, b2 = rem - i2 * nb;
+        const int64_t a = (int64_t(m1s[i0 + ii]) * nv + v) * nc + c;
+        x[u] = reinterpret_cast<const C2 *>(H)[a * ldh + int64_t(m2s[i2]) * nb + b2];
+      }
     }
+  };
+  fetch(0);
+  for (int i0 = 0; i0 < L1; i0 += RU) {
+    const int nr = std::min(RU, L1 - i0);
+    __syncthreads();  // the previous chunk has been consumed
+#pragma unroll
+    for (int u = 0; u < PCH / PNT; ++u) rows[threadIdx.x + PNT * u] = x[u];
     __syncthreads();
+    if (i0 + RU < L1) fetch(i0 + RU);
 #pragma unroll
     for (int t = 0; t < PMAXCOL; ++t) {
       const int col = threadIdx.x + PNT * t;
       if (col >= ncol) break;
       const int j2 = col / nb, b2 = col % nb;
-      double zr = 0, zi = 0;
-      for (int i2 = 0; i2 < L2; ++i2) {
-        const C2 h = row[i2 * nb + b2];
-        const double u = u2s[i2 * r2 + j2];
-        zr += u * double(h.x);
-        zi += u * double(h.y);
-      }
-#pragma unroll
-      for (int j = 0; j < PMAXR; ++j)
-        if (j < r1) {
-          const double u = U1[i * r1 + j];
-          accr[t][j] += u * zr;
-          acci[t][j] += u * zi;
+      for (int ii = 0; ii < nr; ++ii) {
+        double zr = 0, zi = 0;
+        for (int i2 = 0; i2 < L2; ++i2) {
+          const C2 h = rows[ii * per + i2 * nb + b2];
+          const double u = u2s[i2 * r2 + j2];
+          zr += u * double(h.x);
+          zi += u * double(h.y);
         }
+#pragma unroll
+        for (int j = 0; j < PMAXR; ++j)
+          if (j < r1) {
+            const double u = u1s[(i0 + ii) * r1 + j];
+            accr[t][j] += u * zr;
+            acci[t][j] += u * zi;
+          }
+      }
     }
   }
   const int64_t rbase = orb_off[o1] + band, cbase = orb_off[o2];
@@ -139,9 +168,7 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
   const int64_t nk = int64_t(n1) * n2 * n3, nb = int64_t(p->nv) * p->nc, N = nk * nb;
   if (nb > 128 * PMAXCOL * 2) return fail(BSE_EUNSUPPORTED, "nv nc too large for projection");
   hipStream_t s = (hipStream_t)stream;
-  // largest orbit (LDS size) from the host: members are device data, so the
-  // bound |O| <= |S| (48) is used
-  const int maxL = 48;
+  if (int64_t(PMAXL) * nb > PCH) return fail(BSE_EUNSUPPORTED, "nv nc too large for projection");
   for (int ib = 0; ib < nblk; ++ib) {
     const bse_block &b = blk[ib];
     if (b.n < 0 || !b.mem_off || !b.members || !b.orb_off || !b.orb_dim || !b.ub_off || !b.ubasis)
@@ -153,18 +180,15 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
       if (!ldmu || ldmu[ib] < b.n) return fail(BSE_ESHAPE, "ldmu[%d] < n", ib);
       if (9 * nb > PNT * PMAXCOL)
         return fail(BSE_EUNSUPPORTED, "r' nv nc exceeds %d columns", PNT * PMAXCOL);
-      const size_t csz = h_fp64 ? 16 : 8;
-      const size_t lds = size_t(maxL) * nb * csz + size_t(maxL) * PMAXR * 8;
-      if (lds > 160 * 1024) return fail(BSE_EUNSUPPORTED, "projection tile exceeds LDS");
       dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
       if (h_fp64)
-        BSE_LAUNCH("k_project", k_project<double>, g, dim3(PNT), lds, s, p->nv, p->nc,
+        BSE_LAUNCH("k_project", k_project<double>, g, dim3(PNT), 0, s, p->nv, p->nc,
                            (const double *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
-                           b.ub_off, b.ubasis, (double *)Hmu[ib], ldmu[ib], maxL);
+                           b.ub_off, b.ubasis, (double *)Hmu[ib], ldmu[ib]);
       else
-        BSE_LAUNCH("k_project", k_project<float>, g, dim3(PNT), lds, s, p->nv, p->nc,
+        BSE_LAUNCH("k_project", k_project<float>, g, dim3(PNT), 0, s, p->nv, p->nc,
                            (const float *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
-                           b.ub_off, b.ubasis, (float *)Hmu[ib], ldmu[ib], maxL);
+                           b.ub_off, b.ubasis, (float *)Hmu[ib], ldmu[ib]);
       BSE_HIP_CHECK(hipGetLastError());
     }
     if (Bmu && Bmu[ib]) {
