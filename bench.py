@@ -175,9 +175,10 @@ def main():
     s1, s2, ex = build_flops(nk, nv, nc, nmb)
     build_tflops = (s1 + s2 + ex) / (st_ms[0] * 1e-3) / 1e12
     ms_step = wall * 1e3 / args.steps
-    kname = "k_direct_fused" if "k_direct_fused" in prof else "k_direct_t"
+    fused = [k for k in ("k_direct_fused", "k_direct_bf3") if k in prof]
+    kname = fused[0] if fused else "k_direct_t"
     kt_ms, kt_n = prof.get(kname, (float("nan"), 0))
-    kflops = (s1 + s2) if kname == "k_direct_fused" else s1   # flops of the kernel per build
+    kflops = (s1 + s2) if fused else s1   # flops of the kernel per build
     achieved = kflops * args.steps / (kt_ms * 1e-3) / 1e12 if kt_n else None
     res = sv.results()
     pk = PEAK[args.prec]
@@ -206,7 +207,10 @@ def main():
         "lowest_exciton_eV": [round(float(x), 9) for x in res["lowest"][:3]],
         "roofline": {
             "kernel": kname + (" (direct term, both contractions: W(q) Mv and conj(Mc) T, "
-                               "complex MFMA)" if kname == "k_direct_fused" else ""),
+                               "complex MFMA" + (", split BF16: 3 bf16 products per product, "
+                                                 "peak = bf16 dense / 3" if
+                                                 kname == "k_direct_bf3" else "") + ")"
+                               if fused else ""),
             "bound": "mfma",
             "achieved": round(achieved, 3) if achieved else None,
             "peak": pk,

@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "bse_internal.h"
+#include "build_common.h"
 #include "mfma_tile.h"
 
 namespace bse {
@@ -36,16 +37,6 @@ constexpr int NT = 256;
 template <typename T> struct BuildTile;
 template <> struct BuildTile<float> { static constexpr int BM = 128, BN = 128, BK = 32; };
 template <> struct BuildTile<double> { static constexpr int BM = 128, BN = 128, BK = 16; };
-
-__device__ __forceinline__ int kminus(int k, int q, int n1, int n2, int n3) {
-  const int k3 = k % n3, k2 = (k / n3) % n2, k1 = k / (n2 * n3);
-  const int q3 = q % n3, q2 = (q / n3) % n2, q1 = q / (n2 * n3);
-  int a = k1 - q1, b = k2 - q2, c = k3 - q3;
-  a += a < 0 ? n1 : 0;
-  b += b < 0 ? n2 : 0;
-  c += c < 0 ? n3 : 0;
-  return (a * n2 + b) * n3 + c;
-}
 
 // ---------------------------------------------------------------------------
 // exchange + diagonal
@@ -549,9 +540,7 @@ int32_t launch_fused(int MI, dim3 g, hipStream_t s, const bse_problem *p, void *
   return BSE_OK;
 }
 
-bool fused_ok(const bse_problem *p) {
-  return p->nmb % 64 == 0 && p->nmb <= 384 && p->nv * p->nv <= 16 && p->nc * p->nc <= 48;
-}
+bool fused_ok(const bse_problem *p) { return fused_shape(p->nmb, p->nv, p->nc); }
 
 int32_t check_problem(const bse_problem *p, int32_t prec) {
   if (!p) return fail(BSE_EINVAL, "problem is NULL");
@@ -589,13 +578,13 @@ using namespace bse;
 
 extern "C" size_t bse_build_ws_min(const bse_problem *p, int32_t prec) {
   if (check_problem(p, prec)) return 0;
-  if (prec != BSE_BF16X3 && fused_ok(p)) return 256;  // the fused direct term needs no buffer
+  if (fused_ok(p)) return 256;  // the fused direct terms need no buffer
   return per_q_bytes(p, prec);
 }
 
 extern "C" size_t bse_build_ws(const bse_problem *p, int32_t prec) {
   if (check_problem(p, prec)) return 0;
-  if (prec != BSE_BF16X3 && fused_ok(p)) return 256;
+  if (fused_ok(p)) return 256;
   const size_t pq = per_q_bytes(p, prec);
   const size_t nk = size_t(p->grid[0]) * p->grid[1] * p->grid[2];
   const size_t cap = size_t(1) << 30;  // 1 GiB of q-batch buffer is plenty to saturate

@@ -1,10 +1,449 @@
-// Split-BF16 form of the H build (placeholder until the BF16 MFMA kernels land).
+// Split-BF16 ("bf16x3") form of the H build on MFMA 16x16x32 bf16.
+//
+// Same contractions as the FP32 kernels (Eq. (BSE-eigval) with Eq.
+// (w_interaction2): diagonal + (2/N_k) exchange - (1/N_k) direct, q outermost,
+// Sec. III.C.2), with every FP32 operand x split as
+//   hi = bf16(x), lo = bf16(x - hi)        (round to nearest even)
+// and each product x y taken as hi hi' + hi lo' + lo hi' (three MFMAs, FP32
+// accumulation); the dropped lo lo' term is below 2^-16 |x y|, so an element
+// carries about 1e-5 relative error instead of FP32's 1e-7.
+//
+// v_mfma_f32_16x16x32_bf16: lane l supplies 8 consecutive K values of row
+// (l & 15) of A and of column (l & 15) of B for K slot group (l >> 4); the
+// f32 output layout is the one of the 16x16x4 f32 instruction (lane l holds
+// column l & 15, rows 4 (l >> 4) + j).  Any per-lane K assignment is valid as
+// long as A and B use the same one, which the kernels below guarantee.
+//
+//   k_exchange_bf3   every H element: diagonal + exchange, complex GEMM with
+//                    the (I, re/im) interleaved reduction index
+//   k_direct_bf3     fused direct term: stage 1 T^T = W_q Mv^T staged in LDS as
+//                    bf16 hi/lo; stage 2 conj(Mc) T from the stage-1
+//                    accumulators of two adjacent 16-row tiles (8 K values per
+//                    lane), split in registers
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bse_internal.h"
+#include "build_common.h"
+#include "mfma_tile.h"
 
 namespace bse {
-int32_t build_bf16x3(const bse_problem *, void *, int64_t, void *, size_t, bse_stream) {
-  return fail(BSE_EUNSUPPORTED, "split-BF16 build is not implemented yet");
+
+int32_t build_check_problem(const bse_problem *p, int32_t prec);
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ f32x4 mma3(f32x4 acc, bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 bl) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
 }
+
+__device__ __forceinline__ void split1(float x, __bf16 &h, __bf16 &l) {
+  h = (__bf16)x;
+  l = (__bf16)(x - (float)h);
+}
+
+template <int N, typename V>
+__device__ __forceinline__ void splitn(const float *x, V &h, V &l) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    __bf16 a, b;
+    split1(x[i], a, b);
+    h[i] = a;
+    l[i] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exchange + diagonal (tile 128 real rows x 128 columns, K slab 32)
+// ---------------------------------------------------------------------------
+constexpr int XBM = 128, XBN = 128, XBK = 32, XP = XBK + 8;
+
+__global__ __launch_bounds__(NT) void k_exchange_bf3(int nk, int nv, int nc, int nmb,
+                                                     const int32_t *__restrict__ korb,
+                                                     const float *__restrict__ mx,
+                                                     const double *__restrict__ vdiag,
+                                                     const double *__restrict__ ev,
+                                                     const double *__restrict__ ec,
+                                                     float *__restrict__ H, int64_t ldh,
+                                                     double scale) {
+  constexpr int KC = XBK / 2;                       // complex I per slab
+  constexpr int NA = (XBM / 2) * KC / NT, NB = XBN * KC / NT;
+  constexpr int MI = XBM / 32, NI = XBN / 32;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[XBM * XP], Al[XBM * XP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[XBN * XP], Bl[XBN * XP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = nv * nc;
+  const int64_t N = int64_t(nk) * nb;
+  const int64_t a0 = int64_t(blockIdx.y) * (XBM / 2), b0 = int64_t(blockIdx.x) * XBN;
+  const float2 *arow[NA];
+  const float2 *brow[NB];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int64_t a = a0 + (tid + NT * u) / KC;
+    arow[u] = a < N ? reinterpret_cast<const float2 *>(mx) +
+                          (int64_t(korb[a / nb]) * nb + a % nb) * nmb
+                    : nullptr;
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int64_t b = b0 + (tid + NT * u) / KC;
+    brow[u] = b < N ? reinterpret_cast<const float2 *>(mx) +
+                          (int64_t(korb[b / nb]) * nb + b % nb) * nmb
+                    : nullptr;
+  }
+  f32x4 acc[MI][NI];
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f32x4{0, 0, 0, 0};
+  const int wm0 = (wv >> 1) * (XBM / 2), wn0 = (wv & 1) * (XBN / 2);
+  const int r = lane & 15, g = lane >> 4;
+  for (int i0 = 0; i0 < nmb; i0 += KC) {
+    float2 xa[NA], xb[NB];
+    float va[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int I = i0 + (tid + NT * u) % KC;
+      xa[u] = (arow[u] && I < nmb) ? arow[u][I] : float2{0, 0};
+      va[u] = I < nmb ? float(vdiag[I]) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int I = i0 + (tid + NT * u) % KC;
+      xb[u] = (brow[u] && I < nmb) ? brow[u][I] : float2{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int it = tid + NT * u, rr = it / KC, i = it % KC;
+      const float re = xa[u].x * va[u], im = xa[u].y * va[u];
+      const float e0[2] = {re, im}, e1[2] = {im, -re};
+      bf16x2 h0, l0, h1, l1;
+      splitn<2>(e0, h0, l0);
+      splitn<2>(e1, h1, l1);
+      *reinterpret_cast<bf16x2 *>(Ah + (2 * rr) * XP + 2 * i) = h0;
+      *reinterpret_cast<bf16x2 *>(Al + (2 * rr) * XP + 2 * i) = l0;
+      *reinterpret_cast<bf16x2 *>(Ah + (2 * rr + 1) * XP + 2 * i) = h1;
+      *reinterpret_cast<bf16x2 *>(Al + (2 * rr + 1) * XP + 2 * i) = l1;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int it = tid + NT * u, rr = it / KC, i = it % KC;
+      const float e[2] = {xb[u].x, xb[u].y};
+      bf16x2 h, l;
+      splitn<2>(e, h, l);
+      *reinterpret_cast<bf16x2 *>(Bh + rr * XP + 2 * i) = h;
+      *reinterpret_cast<bf16x2 *>(Bl + rr * XP + 2 * i) = l;
+    }
+    __syncthreads();
+    bf16x8 ah[MI], al[MI];
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi) {
+      ah[mi] = *reinterpret_cast<const bf16x8 *>(Ah + (wm0 + 16 * mi + r) * XP + 8 * g);
+      al[mi] = *reinterpret_cast<const bf16x8 *>(Al + (wm0 + 16 * mi + r) * XP + 8 * g);
+    }
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(Bh + (wn0 + 16 * ni + r) * XP + 8 * g);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(Bl + (wn0 + 16 * ni + r) * XP + 8 * g);
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) acc[mi][ni] = mma3(acc[mi][ni], ah[mi], al[mi], bh, bl);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const int64_t b = b0 + wn0 + 16 * ni + r;
+      const int64_t a = a0 + (wm0 + 16 * mi + 4 * g) / 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t aa = a + h;
+        if (aa < N && b < N) {
+          double re = scale * double(acc[mi][ni][2 * h]);
+          const double im = scale * double(acc[mi][ni][2 * h + 1]);
+          if (aa == b) {
+            const int k = int(aa / nb), v = int((aa / nc) % nv), c = int(aa % nc);
+            re += ec[int64_t(k) * nc + c] - ev[int64_t(k) * nv + v];
+          }
+          reinterpret_cast<float2 *>(H)[aa * ldh + b] = float2{float(re), float(im)};
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct term, fused: one workgroup per (q, KC consecutive k), all Nmb rows.
+//   stage 1  T^T[I][(k, t, vv')] = sum_J W_q[I][J] Re/Im(Mv(k, k-q)[vv'][J]);
+//            wave w owns rows I in [w 16 MI, (w+1) 16 MI)
+//   stage 2  D[cc'][vv'] = sum_I conj(Mc(k, k-q)[cc'][I]) T[vv'][I]: lane
+//            (g, c) of tiles mi and mi+1 holds T rows 16 mi + 4 g + j and
+//            16 (mi+1) + 4 g + j (j < 4) at column c, the 8 K values of one
+//            16x16x32 step; the A operand reads Mc at the same I.
+// Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48.
+// ---------------------------------------------------------------------------
+template <int MI, int KC>
+__global__ __launch_bounds__(NT) void k_direct_bf3(int n1, int n2, int n3, int nv, int nc,
+                                                   const int32_t *__restrict__ qorb,
+                                                   const int32_t *__restrict__ pidx,
+                                                   const uint8_t *__restrict__ pconj,
+                                                   const float *__restrict__ mv,
+                                                   const float *__restrict__ mc,
+                                                   const float *__restrict__ w,
+                                                   float *__restrict__ H, int64_t ldh,
+                                                   double scale) {
+  constexpr int BK = 32, P = BK + 8;       // K slab (J) and bf16 row pitch
+  constexpr int NMB = 64 * MI;             // rows I of W
+  constexpr int NI = 2 * KC;               // column blocks: (k, re/im)
+  constexpr int NCOL = 16 * NI;            // B rows in LDS
+  constexpr int NA = NMB * BK / 4 / NT;    // float4 loads of W per thread per slab
+  constexpr int BPR = 2 * BK / 4;          // float4 loads per complex Mv row per slab
+  constexpr int NB = KC * 16 * BPR / NT;   // Mv loads per thread per slab
+  static_assert(NA >= 1 && NB >= 1, "tile too small");
+  constexpr int STAGE = 2 * (NMB + NCOL) * P * 2;  // bytes: hi + lo tiles
+  constexpr int NCB = 3;                   // c c' row blocks of stage 2
+  constexpr int RED = 4 * NCB * 16 * 16 * 8;       // bytes: float2 partial D per wave
+  __shared__ __attribute__((aligned(16))) unsigned char lds[STAGE > RED ? STAGE : RED];
+  __bf16 *Ah = reinterpret_cast<__bf16 *>(lds), *Al = Ah + NMB * P;
+  __bf16 *Bh = Al + NMB * P, *Bl = Bh + NCOL * P;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nk = n1 * n2 * n3, nvv = nv * nv, ncc = nc * nc;
+  const int nmb = NMB;
+  const int q = blockIdx.y;
+  const int k0 = blockIdx.x * KC;
+  const float *wq = w + int64_t(qorb[q]) * nmb * nmb;
+  // B-row sources: row = kk * 16 + vv' (re and im rows of one complex row)
+  const float2 *brow[NB];
+  float bsgn[NB];
+  int boff[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int it = tid + NT * u, row = it / BPR, c = it % BPR, kk = row / 16, vv = row % 16;
+    const int k = k0 + kk;
+    brow[u] = nullptr;
+    bsgn[u] = 1.f;
+    if (k < nk && vv < nvv) {
+      const int kq = kminus(k, q, n1, n2, n3);
+      const int64_t p = int64_t(k) * nk + kq;
+      const bool cj = pconj[p] != 0;
+      const int v = vv / nv, v2 = vv % nv;
+      const int s1 = cj ? v2 : v, s2 = cj ? v : v2;
+      brow[u] = reinterpret_cast<const float2 *>(mv) +
+                ((int64_t(pidx[p]) * nv + s1) * nv + s2) * nmb + 2 * c;
+      bsgn[u] = cj ? -1.f : 1.f;
+    }
+    boff[u] = ((2 * kk) * 16 + vv) * P + 2 * c;
+  }
+  const float *wrow[NA];
+  int aoff[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int it = tid + NT * u, row = it / (BK / 4), c = it % (BK / 4);
+    wrow[u] = wq + int64_t(row) * nmb + c * 4;
+    aoff[u] = row * P + c * 4;
+  }
+  f32x4 acc[MI][NI];
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f32x4{0, 0, 0, 0};
+  const int wm0 = wv * 16 * MI;
+  const int r16 = lane & 15, g = lane >> 4;
+  for (int j0 = 0; j0 < nmb; j0 += BK) {
+    float4 ra[NA], rb[NB];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) ra[u] = *reinterpret_cast<const float4 *>(wrow[u] + j0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      rb[u] = brow[u] ? *reinterpret_cast<const float4 *>(brow[u] + j0) : float4{0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const float e[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
+      bf16x4 h, l;
+      splitn<4>(e, h, l);
+      *reinterpret_cast<bf16x4 *>(Ah + aoff[u]) = h;
+      *reinterpret_cast<bf16x4 *>(Al + aoff[u]) = l;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      // two complex values: re parts to the re row, (signed) im parts to the im row
+      const float er[2] = {rb[u].x, rb[u].z}, ei[2] = {bsgn[u] * rb[u].y, bsgn[u] * rb[u].w};
+      bf16x2 hr, lr, hi, li;
+      splitn<2>(er, hr, lr);
+      splitn<2>(ei, hi, li);
+      *reinterpret_cast<bf16x2 *>(Bh + boff[u]) = hr;
+      *reinterpret_cast<bf16x2 *>(Bl + boff[u]) = lr;
+      *reinterpret_cast<bf16x2 *>(Bh + boff[u] + 16 * P) = hi;
+      *reinterpret_cast<bf16x2 *>(Bl + boff[u] + 16 * P) = li;
+    }
+    __syncthreads();
+    bf16x8 bh[NI], bl[NI];
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      bh[ni] = *reinterpret_cast<const bf16x8 *>(Bh + (16 * ni + r16) * P + 8 * g);
+      bl[ni] = *reinterpret_cast<const bf16x8 *>(Bl + (16 * ni + r16) * P + 8 * g);
+    }
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi) {
+      const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(Ah + (wm0 + 16 * mi + r16) * P + 8 * g);
+      const bf16x8 al = *reinterpret_cast<const bf16x8 *>(Al + (wm0 + 16 * mi + r16) * P + 8 * g);
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = mma3(acc[mi][ni], ah, al, bh[ni], bl[ni]);
+    }
+    __syncthreads();
+  }
+  // ---- stage 2 ----
+  const int ncb = (ncc + 15) / 16;
+  float2 *red = reinterpret_cast<float2 *>(lds);  // [4][NCB*16][16]
+  float2 *Hc = reinterpret_cast<float2 *>(H);
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const int k = k0 + kk;
+    f32x4 dre[NCB], dim[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) dre[cb] = dim[cb] = f32x4{0, 0, 0, 0};
+    int kq = 0;
+    if (k < nk) {
+      kq = kminus(k, q, n1, n2, n3);
+      const int64_t p = int64_t(k) * nk + kq;
+      const bool cj = pconj[p] != 0;
+      const float sg = cj ? -1.f : 1.f;
+      const int cls = pidx[p];
+#pragma unroll
+      for (int mp = 0; mp < MI; mp += 2) {
+        const bool two = mp + 1 < MI;
+        float tre[8], tim[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          tre[j] = acc[mp][2 * kk][j];
+          tim[j] = acc[mp][2 * kk + 1][j];
+          tre[4 + j] = two ? acc[two ? mp + 1 : mp][2 * kk][j] : 0.f;
+          tim[4 + j] = two ? acc[two ? mp + 1 : mp][2 * kk + 1][j] : 0.f;
+        }
+        bf16x8 trh, trl, tih, til;
+        splitn<8>(tre, trh, trl);
+        splitn<8>(tim, tih, til);
+        const int I0 = wm0 + 16 * mp + 4 * g;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          if (cb >= ncb) break;
+          const int cc = 16 * cb + r16;
+          float are[8], aim[8], nim[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) are[j] = aim[j] = 0.f;
+          if (cc < ncc) {
+            const int c = cc / nc, c2 = cc % nc;
+            const int s1 = cj ? c2 : c, s2 = cj ? c : c2;
+            const float4 *src = reinterpret_cast<const float4 *>(
+                reinterpret_cast<const float2 *>(mc) + ((int64_t(cls) * nc + s1) * nc + s2) * nmb);
+            // Mc at I0 .. I0+3 and (second tile) I0+16 .. I0+19
+            const float4 m0 = src[I0 / 2], m1 = src[I0 / 2 + 1];
+            const float4 m2 = two ? src[(I0 + 16) / 2] : float4{0, 0, 0, 0};
+            const float4 m3 = two ? src[(I0 + 16) / 2 + 1] : float4{0, 0, 0, 0};
+            are[0] = m0.x; aim[0] = m0.y; are[1] = m0.z; aim[1] = m0.w;
+            are[2] = m1.x; aim[2] = m1.y; are[3] = m1.z; aim[3] = m1.w;
+            are[4] = m2.x; aim[4] = m2.y; are[5] = m2.z; aim[5] = m2.w;
+            are[6] = m3.x; aim[6] = m3.y; are[7] = m3.z; aim[7] = m3.w;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            aim[j] *= sg;  // Mc = are + i aim
+            nim[j] = -aim[j];
+          }
+          bf16x8 arh, arl, aih, ail, anh, anl;
+          splitn<8>(are, arh, arl);
+          splitn<8>(aim, aih, ail);
+          splitn<8>(nim, anh, anl);
+          // conj(Mc) T = (are tre + aim tim) + i (are tim - aim tre)
+          dre[cb] = mma3(dre[cb], arh, arl, trh, trl);
+          dre[cb] = mma3(dre[cb], aih, ail, tih, til);
+          dim[cb] = mma3(dim[cb], arh, arl, tih, til);
+          dim[cb] = mma3(dim[cb], anh, anl, trh, trl);
+        }
+      }
+    }
+    // partial D of this wave -> LDS, then the sum over waves -> H
+    __syncthreads();  // stage-1 tiles (kk = 0) or the previous reduction are no longer read
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        red[(wv * NCB * 16 + 16 * cb + 4 * g + j) * 16 + r16] = float2{dre[cb][j], dim[cb][j]};
+    __syncthreads();
+    if (k < nk) {
+      for (int e = tid; e < ncc * nvv; e += NT) {
+        const int cc = e / nvv, vv = e % nvv;
+        float2 sum = {0.f, 0.f};
+#pragma unroll
+        for (int w4 = 0; w4 < 4; ++w4) {
+          const float2 x = red[(w4 * NCB * 16 + cc) * 16 + vv];
+          sum.x += x.x;
+          sum.y += x.y;
+        }
+        const int c = cc / nc, c2 = cc % nc, v = vv / nv, v2 = vv % nv;
+        const int64_t a = (int64_t(k) * nv + v) * nc + c;
+        const int64_t b = (int64_t(kq) * nv + v2) * nc + c2;
+        float2 hv = Hc[a * ldh + b];
+        hv.x -= float(scale * double(sum.x));
+        hv.y -= float(scale * double(sum.y));
+        Hc[a * ldh + b] = hv;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_t ws_bytes,
+                     bse_stream stream) {
+  (void)ws;
+  (void)ws_bytes;
+  const int n1 = p->grid[0], n2 = p->grid[1], n3 = p->grid[2];
+  const int nk = n1 * n2 * n3;
+  const int64_t N = int64_t(nk) * p->nv * p->nc;
+  if (!H) return fail(BSE_EINVAL, "H is NULL");
+  if (ldh < N) return fail(BSE_ESHAPE, "ldh %lld < N %lld", (long long)ldh, (long long)N);
+  if (!fused_shape(p->nmb, p->nv, p->nc))
+    return fail(BSE_EUNSUPPORTED,
+                "split-BF16 build needs Nmb = 64 m (m <= 6), nv <= 4 and nc <= 6");
+  hipStream_t s = (hipStream_t)stream;
+  const double inv_nk = 1.0 / nk;
+  dim3 gx((unsigned)((N + XBN - 1) / XBN), (unsigned)((2 * N + XBM - 1) / XBM));
+  if (gx.y > 65535u) return fail(BSE_ESHAPE, "N too large for the exchange grid");
+  BSE_LAUNCH("k_exchange_bf3", k_exchange_bf3, gx, dim3(NT), 0, s, nk, p->nv, p->nc, p->nmb,
+             p->korb, (const float *)p->mx, p->vdiag, p->ev, p->ec, (float *)H, ldh,
+             2.0 * inv_nk);
+  BSE_HIP_CHECK(hipGetLastError());
+  constexpr int KC = 2;
+  dim3 gf((unsigned)((nk + KC - 1) / KC), (unsigned)nk);
+#define BSE_BF3_CASE(M)                                                                       \
+  case M:                                                                                   \
+    BSE_LAUNCH("k_direct_bf3", (k_direct_bf3<M, KC>), gf, dim3(NT), 0, s, n1, n2, n3, p->nv,  \
+               p->nc, p->qorb, p->pidx, p->pconj, (const float *)p->mv, (const float *)p->mc, \
+               (const float *)p->w, (float *)H, ldh, inv_nk);                                \
+    break;
+  switch (p->nmb / 64) {
+    BSE_BF3_CASE(1)
+    BSE_BF3_CASE(2)
+    BSE_BF3_CASE(3)
+    BSE_BF3_CASE(4)
+    BSE_BF3_CASE(5)
+    BSE_BF3_CASE(6)
+    default:
+      return fail(BSE_EUNSUPPORTED, "split-BF16 direct kernel: nmb = 64 m with m <= 6");
+  }
+#undef BSE_BF3_CASE
+  BSE_HIP_CHECK(hipGetLastError());
+  return BSE_OK;
+}
+
 }  // namespace bse
