@@ -200,14 +200,53 @@ int32_t bse_project_blocks(const bse_problem *p, const void *H, int64_t ldh, int
  * Outputs (device FP64): omega[n] all eigenvalues ascending (with
  * multiplicity); pole[n], osc[n]: the optical poles and their strengths,
  * padded with zero strength.  Hmu is read only.
- * prec: FP64 (all FP64), FP32 (FP32 trailing updates and HEMV storage, FP64
- * panel, tridiagonal step and refinement).  nrefine > 0 asks for FP64
- * Rayleigh-Ritz refinement of the lowest nrefine eigenvalues against Hmu.
+ * prec: FP64 (all FP64), FP32 (FP32 storage of the working copy, its HEMV
+ * and trailing updates; FP64 panel vectors, scalars and tridiagonal step).
+ * nrefine must be 0 (FP64 refinement of the lowest eigenvalues is not
+ * available: BSE_EUNSUPPORTED).  Errors: n < 1 or n > 65536 (BSE_ESHAPE),
+ * NULL pointers (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).
  * ------------------------------------------------------------------------- */
 size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int32_t nrefine);
 int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, const void *Bmu,
                        int32_t prec, int32_t nrefine, double *omega, double *pole,
                        double *osc, void *ws, size_t ws_bytes, bse_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched block eigensolver: the same computation as bse_block_eigh for nb
+ * independent blocks (all irrep blocks of many systems, Sec. III.D.1 per
+ * block), run in lockstep: every launch advances every block that still has
+ * columns left by one step, so the per-column launch latency is paid once
+ * per column of the largest block instead of once per column of every block.
+ *   bse_batch_eigh_ws      workspace bytes for blocks of sizes h_n[nb]
+ *   bse_batch_eigh_plan    validates the blocks, lays out the workspace, and
+ *                          uploads the per-block descriptors and launch tables
+ *                          (synchronises `stream`); returns a plan id in
+ *                          *h_plan.  All pointers in the host arrays are device
+ *                          pointers that must stay valid while the plan runs:
+ *                          h_Hmu[b] (n x n, leading dim h_ld[b], complex double
+ *                          if h_fp64 else complex float, read only), h_Bmu[b]
+ *                          (complex double), h_omega/h_pole/h_osc[b] (double[n],
+ *                          outputs as in bse_block_eigh).
+ *   bse_batch_eigh_run     enqueues the whole solve on `stream`: kernel launches
+ *                          only, so it may be captured into a HIP graph.
+ *   bse_batch_eigh_tune    autotuner: times each row-split variant of the
+ *                          HEMV kernel on this batch, keeps the fastest for the
+ *                          plan and returns it in *h_wpr (may be NULL); runs the
+ *                          solve several times (outputs are overwritten).
+ *   bse_batch_eigh_free    forgets the plan (the caller frees the workspace).
+ * Limits: 1 <= nb <= 1024 and 1 <= n <= 16384 per block (BSE_ESHAPE);
+ * prec FP64 or FP32 (BSE_EINVAL).  Plans are kept per process; a plan must
+ * not be run on two streams at once (the workspace is shared).
+ * ------------------------------------------------------------------------- */
+size_t bse_batch_eigh_ws(int32_t nb, const int64_t *h_n, int32_t h_fp64, int32_t prec);
+int32_t bse_batch_eigh_plan(int32_t nb, const int64_t *h_n, const void *const *h_Hmu,
+                            const int64_t *h_ld, int32_t h_fp64, const void *const *h_Bmu,
+                            int32_t prec, double *const *h_omega, double *const *h_pole,
+                            double *const *h_osc, void *ws, size_t ws_bytes, int64_t *h_plan,
+                            bse_stream stream);
+int32_t bse_batch_eigh_run(int64_t plan, bse_stream stream);
+int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t *h_wpr);
+int32_t bse_batch_eigh_free(int64_t plan);
 
 /* ---------------------------------------------------------------------------
  * bse_spectrum: eps2[j] = pref sum_l osc[l] [L(w_j - pole_l) + L(w_j + pole_l)],

@@ -80,6 +80,12 @@ def _load():
         "bse_block_eigh_ws": (ctypes.c_size_t, [i64, i32, i32, i32]),
         "bse_block_eigh": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp,
                                  ctypes.c_size_t, vp]),
+        "bse_batch_eigh_ws": (ctypes.c_size_t, [i32, P(i64), i32, i32]),
+        "bse_batch_eigh_plan": (i32, [i32, P(i64), P(vp), P(i64), i32, P(vp), i32, P(vp), P(vp),
+                                      P(vp), vp, ctypes.c_size_t, P(i64), vp]),
+        "bse_batch_eigh_run": (i32, [i64, vp]),
+        "bse_batch_eigh_tune": (i32, [i64, vp, P(i32)]),
+        "bse_batch_eigh_free": (i32, [i64]),
         "bse_spectrum": (i32, [i64, vp, vp, f64, f64, i64, vp, vp, vp]),
         "bse_prof_enable": (i32, [ctypes.c_char_p]),
         "bse_prof_collect": (i32, []),

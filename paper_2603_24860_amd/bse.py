@@ -154,6 +154,40 @@ def bse_block_eigh(Hmu, Bmu, prec, omega, pole, osc, ws, nrefine=0, stream=None)
                              _stream(stream)))
 
 
+def bse_batch_eigh_ws(ns, h_fp64, prec):
+    arr = (ctypes.c_int64 * len(ns))(*[int(x) for x in ns])
+    return lib.bse_batch_eigh_ws(len(ns), arr, h_fp64, prec)
+
+
+def bse_batch_eigh_plan(Hmus, Bmus, prec, omegas, poles, oscs, ws, stream=None):
+    """Plan a lockstep solve of the blocks Hmus[b] (square tensors); returns the plan id."""
+    nb = len(Hmus)
+    vpa = lambda ts: (ctypes.c_void_p * nb)(*[t.data_ptr() for t in ts])
+    ns = (ctypes.c_int64 * nb)(*[t.shape[0] for t in Hmus])
+    lds = (ctypes.c_int64 * nb)(*[t.stride(0) for t in Hmus])
+    h_fp64 = 1 if Hmus[0].dtype.itemsize == 16 else 0
+    plan = ctypes.c_int64()
+    check(lib.bse_batch_eigh_plan(nb, ns, vpa(Hmus), lds, h_fp64, vpa(Bmus), prec, vpa(omegas),
+                                  vpa(poles), vpa(oscs), _ptr(ws),
+                                  ws.numel() * ws.element_size(), ctypes.byref(plan),
+                                  _stream(stream)))
+    return plan.value
+
+
+def bse_batch_eigh_run(plan, stream=None):
+    check(lib.bse_batch_eigh_run(plan, _stream(stream)))
+
+
+def bse_batch_eigh_tune(plan, stream=None):
+    w = ctypes.c_int32()
+    check(lib.bse_batch_eigh_tune(plan, _stream(stream), ctypes.byref(w)))
+    return w.value
+
+
+def bse_batch_eigh_free(plan):
+    check(lib.bse_batch_eigh_free(plan))
+
+
 def bse_spectrum(pole, osc, pref, eta, w, eps2, stream=None):
     check(lib.bse_spectrum(pole.numel(), _ptr(pole), _ptr(osc), float(pref), float(eta),
                            w.numel(), _ptr(w), _ptr(eps2), _stream(stream)))

@@ -36,6 +36,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "bse_internal.h"
 #include "mfma_tile.h"
@@ -46,8 +49,8 @@ namespace {
 constexpr int ENT = 256;     // threads per workgroup
 constexpr int NBK = 32;      // panel width
 constexpr int RNT = 1024;    // threads of the single-workgroup kernels
-constexpr int PMAX = 1024;   // partial-sum records (k_colB has at most 65536 / 64 workgroups)
-constexpr int PAMAX = 16384; // k_colA partial sums (one wave per row, 4 rows per workgroup)
+constexpr int PMAX = 1024;   // partial-sum records read by k_colA (k_colB writes <= 65536 / 64)
+constexpr int RB_ROWS = 64;  // rows per k_colB workgroup
 // partial-sum record of one k_colB workgroup (complex entries):
 //   [0] (S1, 0) = sum |col|^2, [1 + l] BV_l, [1 + NBK + l] BW_l
 constexpr int PS = 1 + 2 * NBK;
@@ -87,31 +90,81 @@ template <int NTH> __device__ __forceinline__ double block_sum(double v, double 
   return s;
 }
 
-struct Ws {
-  void *A;
-  int64_t lda, ldv;
-  double2 *V, *W;    // [NBK][ldv] column major
-  double2 *col;      // [n] current column
-  double2 *y;        // [n] y = A22 v
-  double2 *wraw;     // [n] initial reflection: w before the alpha v term
-  double2 *vbuf;     // [n] initial reflector
-  double2 *partb;    // [2][PMAX][PS] partial sums of k_colB / k_col0 (alternating)
-  double2 *parta;    // [PAMAX] partial sums of conj(y) v of k_colA
-  double2 *part2;    // [PMAX] initial reflection: partial w^dag v
-  double *part3;     // [PMAX] initial reflection: partial norm
-  double2 *scl;      // [n + 1] reflector scale 1 / (alpha - beta), index j + 1
-  double2 *tau;      // [n + 1], index j + 1
-  double *d, *e;     // [n]
-  double *e2;        // [n] squared subdiagonal
-  double *tsc;       // [8] tridiagonal scalars
-  double *beta0;     // [1]
+constexpr int NBMAX = 1024;  // blocks in one batched solve
+
+// One block's working set.  Partial-sum buffers are sized by the block:
+// k_colB and k_col0 write at most ceil(n / 64) records, k_colA at most n sums,
+// the initial reflection ceil(n / 256).
+struct Desc {
+  int64_t n, ld, lda, ldv;
+  const void *H;             // H_mu [n][ld]
+  const double2 *B;          // B_mu [n]
+  void *A;                   // working copy [n][lda]
+  double2 *V, *W;            // [NBK][ldv] column major
+  double2 *col;              // [n] current column
+  double2 *y;                // [n] y = A22 v
+  double2 *wraw;             // [n] initial reflection: w before the alpha v term
+  double2 *vbuf;             // [n] initial reflector
+  double2 *partb0, *partb1;  // [R][PS] partial sums of k_colB / k_col0 (alternating)
+  double2 *parta;            // [max(n, 1)] partial sums of conj(y) v of k_colA
+  double2 *part2;            // [ceil(n / 256)] initial reflection: partial w^dag v
+  double *part3;             // [ceil(n / 256)] initial reflection: partial norm
+  double2 *scl;              // [n + 1] reflector scale 1 / (alpha - beta), index j + 1
+  double2 *tau;              // [n + 1], index j + 1
+  double *d, *e;             // [n]
+  double *e2;                // [n] squared subdiagonal
+  double *tsc;               // [8] tridiagonal scalars
+  double *beta0;             // [1]
+  double *omega, *pole, *osc;  // outputs [n]
 };
 
-int hemv_rpw(int64_t m) { return (int)std::max<int64_t>(1, (m + 4 * 512 - 1) / (4 * 512)); }
+// ---------------------------------------------------------------------------
+// launch geometry, shared by the host (single block) and the batched kernels
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ __forceinline__ int64_t g_nwg(int64_t m) { return m < 1 ? 1 : cdiv(m, ENT); }
+__host__ __device__ __forceinline__ int g_rpw(int64_t m) {
+  return (int)(m < 2048 ? 1 : cdiv(m, 2048));
+}
+__host__ __device__ __forceinline__ int64_t g_copy_gx(int64_t n) {
+  return cdiv(n, ENT) < 64 ? cdiv(n, ENT) : 64;
+}
+__host__ __device__ __forceinline__ int64_t g_rank2_gx(int64_t n) {
+  return cdiv(n, ENT) < 16 ? cdiv(n, ENT) : 16;
+}
+__host__ __device__ __forceinline__ int64_t g_records(int64_t n) {
+  return n < 64 ? 1 : cdiv(n, 64);
+}
+__host__ __device__ __forceinline__ int g_nbk(int64_t n, int64_t j0) {
+  return (int)(n - j0 < NBK ? n - j0 : NBK);
+}
+// partial-sum records in front of k_colA of column jn (from k_col0 at a
+// panel start, else from k_colB of column jn - 1)
+__host__ __device__ __forceinline__ int g_np_in(int64_t n, int64_t jn) {
+  return (int)(jn % NBK == 0 ? g_nwg(n - jn) : cdiv(n - jn, RB_ROWS));
+}
+__host__ __device__ __forceinline__ int g_colA_wgs(int64_t m, int wpr) {
+  const int64_t rt = 4 / wpr;
+  return (int)(m < 1 ? 1 : cdiv(m, rt));
+}
+__host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
+  const int64_t j0 = jn - jn % NBK;
+  return (jn % NBK) + 1 < g_nbk(n, j0) ? 1 : 0;
+}
+// waves per row of the single-block k_colA: enough workgroups to fill the
+// chip; the batched solve uses its tuned value for every block
+inline int single_wpr(int64_t m) { return m <= 2560 ? 4 : (m <= 8192 ? 2 : 1); }
+
+// relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
+__host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
+  const double eps_w = a_fp64 ? 2.2e-16 : 1.2e-7;
+  return 8.0 * eps_w * sqrt(double(n));
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t ws_layout(int64_t n, bool a_fp64, Ws *w, char *base) {
+// Lays out one block's workspace at base (nullptr: size only).
+size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char *p = base ? base + off : nullptr;
@@ -119,7 +172,9 @@ size_t ws_layout(int64_t n, bool a_fp64, Ws *w, char *base) {
     return p;
   };
   const int64_t lda = (n + 15) / 16 * 16, ldv = (n + 63) / 64 * 64;
-  Ws t;
+  const size_t R = size_t(g_records(n)), P2 = size_t(g_nwg(n));
+  Desc t{};
+  t.n = n;
   t.lda = lda;
   t.ldv = ldv;
   t.A = take(size_t(n) * lda * (a_fp64 ? 16 : 8));
@@ -129,10 +184,11 @@ size_t ws_layout(int64_t n, bool a_fp64, Ws *w, char *base) {
   t.y = (double2 *)take(size_t(n) * 16);
   t.wraw = (double2 *)take(size_t(n) * 16);
   t.vbuf = (double2 *)take(size_t(n) * 16);
-  t.partb = (double2 *)take(size_t(2) * PMAX * PS * 16);
-  t.parta = (double2 *)take(size_t(PAMAX) * 16);
-  t.part2 = (double2 *)take(size_t(PMAX) * 16);
-  t.part3 = (double *)take(size_t(PMAX) * 8);
+  t.partb0 = (double2 *)take(R * PS * 16);
+  t.partb1 = (double2 *)take(R * PS * 16);
+  t.parta = (double2 *)take(size_t(std::max<int64_t>(n, 1)) * 16);
+  t.part2 = (double2 *)take(P2 * 16);
+  t.part3 = (double *)take(P2 * 8);
   t.scl = (double2 *)take(size_t(n + 1) * 16);
   t.tau = (double2 *)take(size_t(n + 1) * 16);
   t.d = (double *)take(size_t(n) * 8);
@@ -165,13 +221,12 @@ __device__ __forceinline__ void householder(double2 al, double xn2, double &beta
 
 // ---------------------------------------------------------------------------
 template <typename TH, typename TA>
-__global__ void k_copy_in(int64_t n, const TH *__restrict__ H, int64_t ldh, TA *__restrict__ A,
-                          int64_t lda) {
+__device__ __forceinline__ void b_copy_in(int64_t n, const TH *__restrict__ H, int64_t ldh, TA *__restrict__ A,
+                          int64_t lda, int64_t r, int64_t xw, int64_t gx) {
   typedef typename C2T<TH>::t CH;
   typedef typename C2T<TA>::t CA;
-  const int64_t r = blockIdx.y;
-  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-       c += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t c = xw * blockDim.x + threadIdx.x; c < n;
+       c += gx * blockDim.x) {
     const CH x = reinterpret_cast<const CH *>(H)[r * ldh + c];
     reinterpret_cast<CA *>(A)[r * lda + c] = CA{TA(x.x), TA(x.y)};
   }
@@ -180,28 +235,28 @@ __global__ void k_copy_in(int64_t n, const TH *__restrict__ H, int64_t ldh, TA *
 // ---------------------------------------------------------------------------
 // initial reflection B -> beta0 e_1 (whole matrix, once per solve)
 // ---------------------------------------------------------------------------
-__global__ void k_load_b(int64_t n, const double2 *__restrict__ B, double2 *__restrict__ col,
-                         double *__restrict__ part3) {
+__device__ __forceinline__ void b_load_b(int64_t n, const double2 *__restrict__ B, double2 *__restrict__ col,
+                         double *__restrict__ part3, int wg, int nwgs) {
   __shared__ double sh[ENT / 64];
   double s = 0;
-  for (int64_t r = int64_t(blockIdx.x) * ENT + threadIdx.x; r < n; r += int64_t(gridDim.x) * ENT) {
+  for (int64_t r = int64_t(wg) * ENT + threadIdx.x; r < n; r += int64_t(nwgs) * ENT) {
     const double2 b = B[r];
     col[r] = b;
     if (r >= 1) s += b.x * b.x + b.y * b.y;
   }
   s = block_sum<ENT>(s, sh);
-  if (threadIdx.x == 0) part3[blockIdx.x] = s;
+  if (threadIdx.x == 0) part3[wg] = s;
 }
 
 // v from the loaded B (scalars from the norm partials), then y = A v.
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_hemv0(int64_t n, int rpw, const TA *__restrict__ A,
+__device__ __forceinline__ void b_hemv0(int64_t n, int rpw, const TA *__restrict__ A,
                                                int64_t lda, const double2 *__restrict__ col,
                                                const double *__restrict__ part3, int np3,
                                                double *__restrict__ beta0,
                                                double2 *__restrict__ tau,
                                                double2 *__restrict__ vbuf,
-                                               double2 *__restrict__ y) {
+                                               double2 *__restrict__ y, int wg) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -211,11 +266,11 @@ __global__ __launch_bounds__(ENT) void k_hemv0(int64_t n, int rpw, const TA *__r
   double beta;
   double2 t, sc;
   householder(col[0], xn2, beta, t, sc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (wg == 0 && threadIdx.x == 0) {
     beta0[0] = beta;
     tau[0] = t;
   }
-  const int64_t rbase = (int64_t(blockIdx.x) * (ENT / 64) + wv) * rpw;
+  const int64_t rbase = (int64_t(wg) * (ENT / 64) + wv) * rpw;
   for (int rr = 0; rr < rpw; ++rr) {
     const int64_t r = rbase + rr;
     if (r >= n) break;
@@ -237,13 +292,13 @@ __global__ __launch_bounds__(ENT) void k_hemv0(int64_t n, int rpw, const TA *__r
 }
 
 // wraw = tau y and the partial conj(wraw) v
-__global__ __launch_bounds__(ENT) void k_w0(int64_t n, const double2 *__restrict__ y,
+__device__ __forceinline__ void b_w0(int64_t n, const double2 *__restrict__ y,
                                             const double2 *__restrict__ vbuf,
                                             const double2 *__restrict__ tau,
                                             double2 *__restrict__ wraw,
-                                            double2 *__restrict__ part2) {
+                                            double2 *__restrict__ part2, int wg) {
   __shared__ double sh[ENT / 64];
-  const int64_t r = int64_t(blockIdx.x) * ENT + threadIdx.x;
+  const int64_t r = int64_t(wg) * ENT + threadIdx.x;
   double sr = 0, si = 0;
   if (r < n) {
     const double2 w = cmul(tau[0], y[r]);
@@ -254,16 +309,16 @@ __global__ __launch_bounds__(ENT) void k_w0(int64_t n, const double2 *__restrict
   }
   sr = block_sum<ENT>(sr, sh);
   si = block_sum<ENT>(si, sh);
-  if (threadIdx.x == 0) part2[blockIdx.x] = double2{sr, si};
+  if (threadIdx.x == 0) part2[wg] = double2{sr, si};
 }
 
 // A -= v w^dag + w v^dag with w = wraw + alpha v
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_rank2(int64_t n, TA *__restrict__ A, int64_t lda,
+__device__ __forceinline__ void b_rank2(int64_t n, TA *__restrict__ A, int64_t lda,
                                                const double2 *__restrict__ wraw,
                                                const double2 *__restrict__ vbuf,
                                                const double2 *__restrict__ part2, int np2,
-                                               const double2 *__restrict__ tau) {
+                                               const double2 *__restrict__ tau, int64_t r, int64_t xw, int64_t gx) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
   double sr = 0, si = 0;
@@ -275,9 +330,8 @@ __global__ __launch_bounds__(ENT) void k_rank2(int64_t n, TA *__restrict__ A, in
   si = block_sum<ENT>(si, sh);
   const double2 t = tau[0];
   const double2 alpha = cmul(double2{-0.5 * t.x, -0.5 * t.y}, double2{sr, si});
-  const int64_t r = blockIdx.y;
-  const double2 vr = vbuf[r], wr = cadd(wraw[r], cmul(alpha, vr));
-  for (int64_t c = int64_t(blockIdx.x) * ENT + threadIdx.x; c < n; c += int64_t(gridDim.x) * ENT) {
+    const double2 vr = vbuf[r], wr = cadd(wraw[r], cmul(alpha, vr));
+  for (int64_t c = xw * ENT + threadIdx.x; c < n; c += gx * ENT) {
     const double2 vc = vbuf[c], wc = cadd(wraw[c], cmul(alpha, vc));
     CA *p = reinterpret_cast<CA *>(A) + r * lda + c;
     double2 a = to_d2(*p);
@@ -291,12 +345,12 @@ __global__ __launch_bounds__(ENT) void k_rank2(int64_t n, TA *__restrict__ A, in
 // panel start: col = A[:, j0] (rows >= j0) and partial |col|^2 over rows >= j0 + 2
 // ---------------------------------------------------------------------------
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_col0(int64_t n, int64_t j0, const TA *__restrict__ A,
+__device__ __forceinline__ void b_col0(int64_t n, int64_t j0, const TA *__restrict__ A,
                                               int64_t lda, double2 *__restrict__ col,
-                                              double2 *__restrict__ partb) {
+                                              double2 *__restrict__ partb, int wg) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
-  const int64_t r = j0 + int64_t(blockIdx.x) * ENT + threadIdx.x;
+  const int64_t r = j0 + int64_t(wg) * ENT + threadIdx.x;
   double s = 0;
   if (r < n) {
     const double2 a = to_d2(reinterpret_cast<const CA *>(A)[r * lda + j0]);
@@ -304,7 +358,7 @@ __global__ __launch_bounds__(ENT) void k_col0(int64_t n, int64_t j0, const TA *_
     if (r >= j0 + 2) s = a.x * a.x + a.y * a.y;
   }
   s = block_sum<ENT>(s, sh);
-  if (threadIdx.x == 0) partb[int64_t(blockIdx.x) * PS] = double2{s, 0};
+  if (threadIdx.x == 0) partb[int64_t(wg) * PS] = double2{s, 0};
 }
 
 // ---------------------------------------------------------------------------
@@ -321,7 +375,7 @@ __global__ __launch_bounds__(ENT) void k_col0(int64_t n, int64_t j0, const TA *_
 constexpr int HU = 4;
 
 template <typename TA, int WPR>
-__global__ __launch_bounds__(ENT) void k_colA(int64_t n, int64_t jn, int ir,
+__device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
                                               const TA *__restrict__ A, int64_t lda,
                                               double2 *__restrict__ V, int64_t ldv,
                                               const double2 *__restrict__ col,
@@ -329,14 +383,14 @@ __global__ __launch_bounds__(ENT) void k_colA(int64_t n, int64_t jn, int ir,
                                               double2 *__restrict__ tau,
                                               double2 *__restrict__ scl, double *__restrict__ d,
                                               double *__restrict__ e, double2 *__restrict__ y,
-                                              double2 *__restrict__ parta) {
+                                              double2 *__restrict__ parta, int wg) {
   typedef typename C2T<TA>::t CA;
   constexpr int RT = (ENT / 64) / WPR;  // rows per workgroup
   __shared__ double sh[ENT / 64];
   __shared__ double2 srow[ENT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = jn + 1;
-  const int64_t r = m0 + int64_t(blockIdx.x) * RT + wv / WPR;
+  const int64_t r = m0 + int64_t(wg) * RT + wv / WPR;
   const int part = wv % WPR;
   // ---- independent loads: every global load is issued from a clamped,
   // in-bounds index before any value is used, so none waits for another ----
@@ -396,12 +450,12 @@ __global__ __launch_bounds__(ENT) void k_colA(int64_t n, int64_t jn, int ir,
   if (lane == 0) srow[wv] = double2{sr, si};
   // ---- reflector scalars (every workgroup) ----
   const double S1 = block_sum<ENT>(s1, sh);  // also publishes srow
-  if (blockIdx.x == 0 && tid == 0) d[jn] = cjn.x;
+  if (wg == 0 && tid == 0) d[jn] = cjn.x;
   if (last) return;
   double beta;
   double2 tj, sc;
   householder(cm0, S1, beta, tj, sc);
-  if (blockIdx.x == 0 && tid == 0) {
+  if (wg == 0 && tid == 0) {
     e[jn] = beta;
     tau[m0] = tj;
     scl[m0] = sc;
@@ -419,7 +473,7 @@ __global__ __launch_bounds__(ENT) void k_colA(int64_t n, int64_t jn, int ir,
   }
   const double yr = block_sum<ENT>(yv.x, sh);
   const double yi = block_sum<ENT>(yv.y, sh);
-  if (tid == 0) parta[blockIdx.x] = double2{yr, yi};
+  if (tid == 0) parta[wg] = double2{yr, yi};
 }
 
 // sum of part[0..np) with eight loads in flight per thread
@@ -462,7 +516,7 @@ __device__ __forceinline__ double2 shfl_sum4(double2 x) {
 }
 
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int more,
+__device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
                                               const TA *__restrict__ A, int64_t lda,
                                               const double2 *__restrict__ V,
                                               double2 *__restrict__ W, int64_t ldv,
@@ -472,7 +526,7 @@ __global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int
                                               const double2 *__restrict__ tau,
                                               const double2 *__restrict__ scl,
                                               double2 *__restrict__ col,
-                                              double2 *__restrict__ pout) {
+                                              double2 *__restrict__ pout, int wg) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
   __shared__ double2 tile[2 * NBK * TP];  // [V_0..V_{NBK-1} | W_0..W_{NBK-1}] x rows
@@ -481,7 +535,7 @@ __global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int
   __shared__ double2 sy[RB], sa[RB], sv[RB], sw[RB], sc_[RB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t jx = jn + 1;
-  const int64_t rb = jx + int64_t(blockIdx.x) * RB;
+  const int64_t rb = jx + int64_t(wg) * RB;
   // ---- loads: every global load is issued from a clamped, in-bounds index
   // before any value is consumed, so none waits for another ----
   constexpr int NP = 16;                // record groups held in registers
@@ -595,7 +649,7 @@ __global__ __launch_bounds__(ENT) void k_colB(int64_t n, int64_t jn, int ir, int
   if (!more) return;
   double s1 = (part == 0 && r < n && r >= jx + 2) ? c.x * c.x + c.y * c.y : 0.0;
   s1 = block_sum<ENT>(s1, sh);  // also publishes sw, sc_
-  double2 *pr = pout + int64_t(blockIdx.x) * PS;
+  double2 *pr = pout + int64_t(wg) * PS;
   if (tid == 0) pr[0] = double2{s1, 0};
   // ---- BV_l, BW_l (l <= ir): four threads per panel column ----
   const int k = tid >> 2, l = k % NBK;
@@ -619,10 +673,10 @@ template <> struct HerTile<float> { static constexpr int BM = 128, BN = 64, BK =
 template <> struct HerTile<double> { static constexpr int BM = 128, BN = 64, BK = 16; };
 
 template <typename T>
-__global__ __launch_bounds__(ENT) void k_her2k(int64_t n, int64_t c0, int nbk,
+__device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
                                                const double2 *__restrict__ V,
                                                const double2 *__restrict__ W, int64_t ldv,
-                                               T *__restrict__ A, int64_t lda) {
+                                               T *__restrict__ A, int64_t lda, int64_t bx, int64_t by) {
   constexpr int BM = HerTile<T>::BM, BN = HerTile<T>::BN, BK = HerTile<T>::BK;
   constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32, KC = BK / 2;
   constexpr int NA = (BM / 2) * KC / ENT, NB = BN * KC / ENT;
@@ -630,7 +684,7 @@ __global__ __launch_bounds__(ENT) void k_her2k(int64_t n, int64_t c0, int nbk,
   __shared__ __attribute__((aligned(16))) T Bs[BN * P];
   typedef typename C2T<T>::t C2;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t a0 = c0 + int64_t(blockIdx.y) * (BM / 2), b0 = c0 + int64_t(blockIdx.x) * BN;
+  const int64_t a0 = c0 + by * (BM / 2), b0 = c0 + bx * BN;
   if (a0 >= n || b0 >= n) return;
   typename Mfma<T>::acc_t acc[MI][NI];
   acc_zero<T, MI, NI>(acc);
@@ -691,7 +745,7 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // scalars: [0] Gershgorin low, [1] high, [2] |T| (max row sum), [3] pivmin,
 // [4] cluster gap tolerance
-__global__ __launch_bounds__(RNT) void k_tri_prep(int64_t n, const double *__restrict__ d,
+__device__ __forceinline__ void b_tri_prep(int64_t n, const double *__restrict__ d,
                                                   const double *__restrict__ e, double ctol_rel,
                                                   double *__restrict__ e2,
                                                   double *__restrict__ sc) {
@@ -751,12 +805,12 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d,
 // One wave per eigenvalue index: each pass evaluates 64 Sturm counts at the
 // interior points of the current interval (lane l at a + (l+1)(b-a)/65) and
 // keeps the sub-interval holding eigenvalue i; ~9 passes reach FP64 resolution.
-__global__ __launch_bounds__(256) void k_bisect(int64_t n, const double *__restrict__ d,
+__device__ __forceinline__ void b_bisect(int64_t n, const double *__restrict__ d,
                                                 const double *__restrict__ e2,
                                                 const double *__restrict__ sc,
-                                                double *__restrict__ omega) {
+                                                double *__restrict__ omega, int wg) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int64_t i = int64_t(wg) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
   double a = sc[0], b = sc[1];
   const double pivmin = sc[3];
@@ -781,15 +835,15 @@ __global__ __launch_bounds__(256) void k_bisect(int64_t n, const double *__restr
 // beta0^2 times the residue of G(z) = [(z - T)^-1]_00 as strength, the other
 // members get zero strength.  One wave per index; lanes are contour nodes.
 constexpr int NCONT = 64;  // trapezoidal nodes on the circle (32 in the upper half)
-__global__ __launch_bounds__(256) void k_weights(int64_t n, const double *__restrict__ d,
+__device__ __forceinline__ void b_weights(int64_t n, const double *__restrict__ d,
                                                  const double *__restrict__ e2,
                                                  const double *__restrict__ sc,
                                                  const double *__restrict__ beta0,
                                                  const double *__restrict__ omega,
                                                  double *__restrict__ pole,
-                                                 double *__restrict__ osc) {
+                                                 double *__restrict__ osc, int wg) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int64_t i = int64_t(wg) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
   const double ctol = sc[4];
   const double li = omega[i];
@@ -831,7 +885,324 @@ __global__ __launch_bounds__(256) void k_weights(int64_t n, const double *__rest
   }
 }
 
+static_assert(RB == RB_ROWS, "k_colB rows per workgroup");
+
+// ---------------------------------------------------------------------------
+// kernels: single block (descriptor by value, grid = the block's workgroups)
+// and batched (descriptor array sorted by n descending; pre[b] is the first
+// workgroup of block b in this launch, the active blocks are 0 .. nact-1)
+// ---------------------------------------------------------------------------
+#define BSE_FIND_BLOCK                                                                    \
+  __shared__ int spre[NBMAX + 1];                                                         \
+  for (int i_ = threadIdx.x; i_ <= nact; i_ += blockDim.x) spre[i_] = pre[i_];            \
+  __syncthreads();                                                                        \
+  int lo_ = 0, hi_ = nact;                                                                \
+  while (hi_ - lo_ > 1) {                                                                 \
+    const int mid_ = (lo_ + hi_) >> 1;                                                    \
+    if (spre[mid_] <= int(blockIdx.x)) lo_ = mid_; else hi_ = mid_;                       \
+  }                                                                                       \
+  const Desc &D = Ds[lo_];                                                                \
+  const int wg = int(blockIdx.x) - spre[lo_];
+
+#define BSE_PAIR(NAME, ARGS, ...)                                                         \
+  template <typename TH, typename TA, int WPR>                                            \
+  __global__ __launch_bounds__(ENT) void k_##NAME(Desc D, ARGS) {                         \
+    const int wg = int(blockIdx.x);                                                       \
+    __VA_ARGS__                                                                           \
+  }                                                                                       \
+  template <typename TH, typename TA, int WPR>                                            \
+  __global__ __launch_bounds__(ENT) void k_##NAME##_b(const Desc *__restrict__ Ds,        \
+                                                      const int *__restrict__ pre,        \
+                                                      int nact, ARGS) {                   \
+    BSE_FIND_BLOCK                                                                        \
+    __VA_ARGS__                                                                           \
+  }
+
+#define BSE_COMMA ,
+BSE_PAIR(copy_in, int unused_, {
+  (void)unused_;
+  const int64_t gx = g_copy_gx(D.n);
+  b_copy_in<TH, TA>(D.n, (const TH *)D.H, D.ld, (TA *)D.A, D.lda, wg / gx, wg % gx, gx);
+})
+BSE_PAIR(load_b, int unused_, {
+  (void)unused_;
+  b_load_b(D.n, D.B, D.col, D.part3, wg, (int)g_nwg(D.n));
+})
+BSE_PAIR(hemv0, int unused_, {
+  (void)unused_;
+  b_hemv0<TA>(D.n, g_rpw(D.n), (const TA *)D.A, D.lda, D.col, D.part3, (int)g_nwg(D.n),
+              D.beta0, D.tau, D.vbuf, D.y, wg);
+})
+BSE_PAIR(w0, int unused_, {
+  (void)unused_;
+  b_w0(D.n, D.y, D.vbuf, D.tau, D.wraw, D.part2, wg);
+})
+BSE_PAIR(rank2, int unused_, {
+  (void)unused_;
+  const int64_t gx = g_rank2_gx(D.n);
+  b_rank2<TA>(D.n, (TA *)D.A, D.lda, D.wraw, D.vbuf, D.part2, (int)g_nwg(D.n), D.tau, wg / gx,
+              wg % gx, gx);
+})
+BSE_PAIR(col0, int64_t j0 BSE_COMMA int cur, {
+  b_col0<TA>(D.n, j0, (const TA *)D.A, D.lda, D.col, cur ? D.partb1 : D.partb0, wg);
+})
+BSE_PAIR(colA, int64_t jn BSE_COMMA int cur, {
+  b_colA<TA, WPR>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
+                  cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
+                  D.parta, wg);
+})
+BSE_PAIR(colB, int64_t jn BSE_COMMA int cur, {
+  const int64_t m = D.n - jn - 1;
+  b_colB<TA>(D.n, jn, int(jn % NBK), g_more(D.n, jn), (const TA *)D.A, D.lda, D.V, D.W, D.ldv,
+             D.y, D.parta, g_colA_wgs(m, WPR), cur ? D.partb1 : D.partb0, g_np_in(D.n, jn),
+             D.tau, D.scl, D.col, cur ? D.partb0 : D.partb1, wg);
+})
+BSE_PAIR(her2k, int64_t j0, {
+  const int nbk = g_nbk(D.n, j0);
+  const int64_t c0 = j0 + nbk, m = D.n - c0;
+  const int64_t gx = cdiv(m, HerTile<TA>::BN);
+  b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, wg % gx, wg / gx);
+})
+BSE_PAIR(bisect, int unused_, {
+  (void)unused_;
+  b_bisect(D.n, D.d, D.e2, D.tsc, D.omega, wg);
+})
+BSE_PAIR(weights, int unused_, {
+  (void)unused_;
+  b_weights(D.n, D.d, D.e2, D.tsc, D.beta0, D.omega, D.pole, D.osc, wg);
+})
+#undef BSE_PAIR
+
+// the tridiagonal preparation runs one RNT-thread workgroup per block
+template <typename TA>
+__global__ __launch_bounds__(RNT) void k_tri_prep(Desc D, double ctol) {
+  b_tri_prep(D.n, D.d, D.e, ctol, D.e2, D.tsc);
+}
+template <typename TA>
+__global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
+                                                   const int *__restrict__ pre, int nact,
+                                                   int unused_) {
+  (void)unused_;
+  BSE_FIND_BLOCK
+  (void)wg;
+  b_tri_prep(D.n, D.d, D.e, ctol_rel(D.n, sizeof(TA) == 8), D.e2, D.tsc);
+}
+
+// workgroups of one launch kind for one block (0 = the block is not active)
+enum Kind { K_COPY, K_LOADB, K_HEMV0, K_W0, K_RANK2, K_COL0, K_COLA, K_COLB, K_HER2K, K_TRI,
+            K_BISECT, K_WEIGHTS };
+
+template <typename TA>
+int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
+  switch (kind) {
+    case K_COPY: return n * g_copy_gx(n);
+    case K_LOADB: return g_nwg(n);
+    case K_HEMV0: return cdiv(n, 4 * g_rpw(n));
+    case K_W0: return g_nwg(n);
+    case K_RANK2: return n * g_rank2_gx(n);
+    case K_COL0: return j < n ? g_nwg(n - j) : 0;
+    case K_COLA: return j < n ? g_colA_wgs(n - j - 1, wpr) : 0;
+    case K_COLB: return n - j - 1 > 0 ? cdiv(n - j - 1, RB) : 0;
+    case K_HER2K: {
+      if (j >= n) return 0;
+      const int64_t c0 = j + g_nbk(n, j), m = n - c0;
+      return m > 0 ? cdiv(m, HerTile<TA>::BN) * cdiv(2 * m, HerTile<TA>::BM) : 0;
+    }
+    case K_TRI: return 1;
+    default: return cdiv(n, 4);  // bisect, weights
+  }
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// single block
+// ---------------------------------------------------------------------------
+template <typename TH, typename TA>
+int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
+                 double *pole, double *osc, void *ws, hipStream_t s) {
+  Desc D;
+  ws_layout(n, sizeof(TA) == 8, &D, (char *)ws);
+  D.H = Hmu;
+  D.ld = ld;
+  D.B = (const double2 *)Bmu;
+  D.omega = omega;
+  D.pole = pole;
+  D.osc = osc;
+  auto grid = [&](int kind, int64_t j, int wpr) {
+    return dim3((unsigned)kind_wgs<TA>(kind, n, j, wpr));
+  };
+  BSE_LAUNCH("k_copy_in", (k_copy_in<TH, TA, 4>), grid(K_COPY, 0, 4), dim3(ENT), 0, s, D, 0);
+  // ---- initial reflection: B -> beta0 e_1, A <- Q0^dag A Q0 ----
+  BSE_LAUNCH("k_load_b", (k_load_b<TH, TA, 4>), grid(K_LOADB, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_hemv0", (k_hemv0<TH, TA, 4>), grid(K_HEMV0, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_w0", (k_w0<TH, TA, 4>), grid(K_W0, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_rank2", (k_rank2<TH, TA, 4>), grid(K_RANK2, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_HIP_CHECK(hipGetLastError());
+  // ---- blocked tridiagonalisation, two kernels per column ----
+  int cur = 0;  // partial-sum record buffer written last
+  for (int64_t j0 = 0; j0 < n; j0 += NBK) {
+    const int nbk = g_nbk(n, j0);
+    BSE_LAUNCH("k_col0", (k_col0<TH, TA, 4>), grid(K_COL0, j0, 4), dim3(ENT), 0, s, D, j0, cur);
+    for (int i = 0; i < nbk; ++i) {
+      const int64_t jn = j0 + i, m = n - jn - 1;
+      const int wpr = single_wpr(m);
+#define BSE_COLA(W)                                                                         \
+  BSE_LAUNCH("k_colA", (k_colA<TH, TA, W>), grid(K_COLA, jn, W), dim3(ENT), 0, s, D, jn, cur); \
+  if (m > 0)                                                                                \
+    BSE_LAUNCH("k_colB", (k_colB<TH, TA, W>), grid(K_COLB, jn, W), dim3(ENT), 0, s, D, jn, cur);
+      if (wpr == 4) {
+        BSE_COLA(4)
+      } else if (wpr == 2) {
+        BSE_COLA(2)
+      } else {
+        BSE_COLA(1)
+      }
+#undef BSE_COLA
+      if (m <= 0) break;  // last diagonal element recorded; nothing below it
+      cur ^= 1;
+    }
+    BSE_HIP_CHECK(hipGetLastError());
+    if (kind_wgs<TA>(K_HER2K, n, j0, 4) > 0)
+      BSE_LAUNCH("k_her2k", (k_her2k<TH, TA, 4>), grid(K_HER2K, j0, 4), dim3(ENT), 0, s, D, j0);
+    BSE_HIP_CHECK(hipGetLastError());
+  }
+  // ---- tridiagonal eigenvalues and optical weights ----
+  BSE_LAUNCH("k_tri_prep", k_tri_prep<TA>, dim3(1), dim3(RNT), 0, s, D,
+             ctol_rel(n, sizeof(TA) == 8));
+  BSE_LAUNCH("k_bisect", (k_bisect<TH, TA, 4>), grid(K_BISECT, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_weights", (k_weights<TH, TA, 4>), grid(K_WEIGHTS, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_HIP_CHECK(hipGetLastError());
+  return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched: every active block advances one step per launch
+// ---------------------------------------------------------------------------
+struct BatchLaunch {
+  int kind;
+  int64_t j;
+  int cur;
+  int nact;
+  int total;
+  size_t pre_off;  // ints into the prefix table
+};
+
+struct BatchPlan {
+  int nb = 0, h_fp64 = 0, prec = 0, wpr = 4;
+  char *ws = nullptr;
+  Desc *d_desc = nullptr;
+  int *d_pre = nullptr;
+  std::vector<int64_t> n;  // sorted, descending
+  std::vector<BatchLaunch> launches;
+};
+
+// Launch sequence and prefix tables of a batch (host side).
+template <typename TA>
+void plan_launches(BatchPlan &P, std::vector<int> &pre) {
+  P.launches.clear();
+  pre.clear();
+  const int nb = P.nb;
+  auto add = [&](int kind, int64_t j, int cur) {
+    BatchLaunch L{kind, j, cur, 0, 0, pre.size()};
+    int64_t tot = 0;
+    pre.push_back(0);
+    for (int b = 0; b < nb; ++b) {
+      const int64_t w = kind_wgs<TA>(kind, P.n[b], j, P.wpr);
+      if (w == 0) break;  // sorted descending: the rest are inactive too
+      tot += w;
+      pre.push_back((int)tot);
+      ++L.nact;
+    }
+    L.total = (int)tot;
+    if (L.nact == 0) {
+      pre.pop_back();
+      return;
+    }
+    P.launches.push_back(L);
+  };
+  const int64_t nmax = P.n[0];
+  add(K_COPY, 0, 0);
+  add(K_LOADB, 0, 0);
+  add(K_HEMV0, 0, 0);
+  add(K_W0, 0, 0);
+  add(K_RANK2, 0, 0);
+  int cur = 0;
+  for (int64_t j0 = 0; j0 < nmax; j0 += NBK) {
+    add(K_COL0, j0, cur);
+    for (int i = 0; i < NBK && j0 + i < nmax; ++i) {
+      const int64_t jn = j0 + i;
+      add(K_COLA, jn, cur);
+      add(K_COLB, jn, cur);
+      cur ^= 1;
+    }
+    add(K_HER2K, j0, cur);
+  }
+  add(K_TRI, 0, 0);
+  add(K_BISECT, 0, 0);
+  add(K_WEIGHTS, 0, 0);
+}
+
+template <typename TH, typename TA, int W>
+int32_t batch_launch(const BatchPlan &P, const BatchLaunch &L, hipStream_t s) {
+  const dim3 g((unsigned)L.total), b(ENT);
+  const int *pre = P.d_pre + L.pre_off;
+  const Desc *Ds = P.d_desc;
+  switch (L.kind) {
+    case K_COPY: BSE_LAUNCH("k_copy_in", (k_copy_in_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_LOADB: BSE_LAUNCH("k_load_b", (k_load_b_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_HEMV0: BSE_LAUNCH("k_hemv0", (k_hemv0_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_W0: BSE_LAUNCH("k_w0", (k_w0_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_RANK2: BSE_LAUNCH("k_rank2", (k_rank2_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_COL0: BSE_LAUNCH("k_col0", (k_col0_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
+    case K_COLA: BSE_LAUNCH("k_colA", (k_colA_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
+    case K_COLB: BSE_LAUNCH("k_colB", (k_colB_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
+    case K_HER2K: BSE_LAUNCH("k_her2k", (k_her2k_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j); break;
+    case K_TRI: BSE_LAUNCH("k_tri_prep", k_tri_prep_b<TA>, g, dim3(RNT), 0, s, Ds, pre, L.nact, 0); break;
+    case K_BISECT: BSE_LAUNCH("k_bisect", (k_bisect_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    default: BSE_LAUNCH("k_weights", (k_weights_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+  }
+  return BSE_OK;
+}
+
+template <typename TH, typename TA>
+int32_t batch_run(const BatchPlan &P, hipStream_t s) {
+  for (const BatchLaunch &L : P.launches) {
+    int32_t st = P.wpr == 4   ? batch_launch<TH, TA, 4>(P, L, s)
+                 : P.wpr == 2 ? batch_launch<TH, TA, 2>(P, L, s)
+                              : batch_launch<TH, TA, 1>(P, L, s);
+    if (st) return st;
+  }
+  BSE_HIP_CHECK(hipGetLastError());
+  return BSE_OK;
+}
+
+std::mutex g_plan_mu;
+std::map<int64_t, BatchPlan> g_plans;
+int64_t g_next_plan = 1;
+
+size_t batch_ws_bytes(int32_t nb, const int64_t *h_n, bool a_fp64, std::vector<size_t> *offs,
+                      size_t *desc_off, size_t *pre_off, size_t pre_ints) {
+  size_t off = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (offs) offs->push_back(off);
+    off += ws_layout(h_n[b], a_fp64, nullptr, nullptr);
+  }
+  if (desc_off) *desc_off = off;
+  off += align256(size_t(nb) * sizeof(Desc));
+  if (pre_off) *pre_off = off;
+  off += align256(pre_ints * sizeof(int));
+  return off;
+}
+
+// upper bound of the prefix-table size: launches x (active blocks + 1)
+size_t pre_bound(int32_t nb, const int64_t *h_n) {
+  int64_t nmax = 0;
+  for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h_n[b]);
+  const size_t launches = 8 + size_t(cdiv(nmax, NBK)) * (2 * NBK + 2);
+  return launches * size_t(nb + 1);
+}
+
 }  // namespace bse
 
 using namespace bse;
@@ -842,93 +1213,6 @@ extern "C" size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int
   if (n < 1) return 0;
   return ws_layout(n, prec == BSE_FP64, nullptr, nullptr);
 }
-
-namespace bse {
-template <typename TH, typename TA>
-int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
-                 double *pole, double *osc, void *ws, hipStream_t s) {
-  Ws w;
-  ws_layout(n, sizeof(TA) == 8, &w, (char *)ws);
-  TA *A = (TA *)w.A;
-  const int64_t lda = w.lda, ldv = w.ldv;
-  {
-    dim3 g((unsigned)std::min<int64_t>((n + ENT - 1) / ENT, 64), (unsigned)n);
-    BSE_LAUNCH("k_copy_in", (k_copy_in<TH, TA>), g, dim3(ENT), 0, s, n, (const TH *)Hmu, ld, A,
-               lda);
-  }
-  auto nwg = [](int64_t m) { return (unsigned)std::max<int64_t>(1, (m + ENT - 1) / ENT); };
-  // ---- initial reflection: B -> beta0 e_1, A <- Q0^dag A Q0 ----
-  {
-    const unsigned g = std::min<unsigned>(nwg(n), PMAX);
-    BSE_LAUNCH("k_load_b", k_load_b, dim3(g), dim3(ENT), 0, s, n, (const double2 *)Bmu, w.col,
-               w.part3);
-    const int rpw = hemv_rpw(n);
-    const unsigned gh = (unsigned)((n + 4 * rpw - 1) / (4 * rpw));
-    BSE_LAUNCH("k_hemv0", k_hemv0<TA>, dim3(gh), dim3(ENT), 0, s, n, rpw, A, lda, w.col,
-               w.part3, (int)g, w.beta0, w.tau, w.vbuf, w.y);
-    const unsigned gw = nwg(n);
-    BSE_LAUNCH("k_w0", k_w0, dim3(gw), dim3(ENT), 0, s, n, w.y, w.vbuf, w.tau, w.wraw, w.part2);
-    dim3 gr((unsigned)std::min<int64_t>((n + ENT - 1) / ENT, 16), (unsigned)n);
-    BSE_LAUNCH("k_rank2", k_rank2<TA>, gr, dim3(ENT), 0, s, n, A, lda, w.wraw, w.vbuf, w.part2,
-               (int)gw, w.tau);
-    BSE_HIP_CHECK(hipGetLastError());
-  }
-  // ---- blocked tridiagonalisation, two kernels per column ----
-  int cur = 0;  // partial-sum record buffer written last
-  for (int64_t j0 = 0; j0 < n; j0 += NBK) {
-    const int nbk = (int)std::min<int64_t>(NBK, n - j0);
-    unsigned np = nwg(n - j0);
-    BSE_LAUNCH("k_col0", k_col0<TA>, dim3(np), dim3(ENT), 0, s, n, j0, A, lda, w.col,
-               w.partb + cur * PMAX * PS);
-    for (int i = 0; i < nbk; ++i) {
-      const int64_t jn = j0 + i;
-      const int64_t m = n - jn - 1;  // rows below the new reflector's head
-      const double2 *pin = w.partb + cur * PMAX * PS;
-      // waves per row: enough workgroups to fill the chip, at most PAMAX partial sums
-      const int wpr = m <= 2560 ? 4 : (m <= 8192 ? 2 : 1);
-      const unsigned gh = (unsigned)std::max<int64_t>(1, (m + 4 / wpr - 1) / (4 / wpr));
-#define BSE_COLA(WPR)                                                                            \
-  BSE_LAUNCH("k_colA", (k_colA<TA, WPR>), dim3(gh), dim3(ENT), 0, s, n, jn, i, A, lda, w.V, ldv, \
-             w.col, pin, (int)np, w.tau, w.scl, w.d, w.e, w.y, w.parta)
-      if (wpr == 4)
-        BSE_COLA(4);
-      else if (wpr == 2)
-        BSE_COLA(2);
-      else
-        BSE_COLA(1);
-#undef BSE_COLA
-      if (m <= 0) break;  // last diagonal element recorded; nothing below it
-      const int more = (i + 1 < nbk) ? 1 : 0;
-      const unsigned nb = (unsigned)((m + RB - 1) / RB);
-      BSE_LAUNCH("k_colB", k_colB<TA>, dim3(nb), dim3(ENT), 0, s, n, jn, i, more, A, lda, w.V,
-                 w.W, ldv, w.y, w.parta, (int)gh, pin, (int)np, w.tau, w.scl, w.col,
-                 w.partb + (cur ^ 1) * PMAX * PS);
-      cur ^= 1;
-      np = nb;
-    }
-    BSE_HIP_CHECK(hipGetLastError());
-    const int64_t c0 = j0 + nbk;
-    if (c0 < n) {
-      constexpr int BM = HerTile<TA>::BM, BN = HerTile<TA>::BN;
-      const int64_t m = n - c0;
-      dim3 g((unsigned)((m + BN - 1) / BN), (unsigned)((2 * m + BM - 1) / BM));
-      BSE_LAUNCH("k_her2k", k_her2k<TA>, g, dim3(ENT), 0, s, n, c0, nbk, w.V, w.W, ldv, A, lda);
-      BSE_HIP_CHECK(hipGetLastError());
-    }
-  }
-  // ---- tridiagonal eigenvalues and optical weights ----
-  const double eps_w = sizeof(TA) == 8 ? 2.2e-16 : 1.2e-7;
-  const double ctol_rel = 8.0 * eps_w * std::sqrt(double(n));
-  BSE_LAUNCH("k_tri_prep", k_tri_prep, dim3(1), dim3(RNT), 0, s, n, w.d, w.e, ctol_rel, w.e2,
-             w.tsc);
-  const unsigned gw = (unsigned)((n + 3) / 4);
-  BSE_LAUNCH("k_bisect", k_bisect, dim3(gw), dim3(256), 0, s, n, w.d, w.e2, w.tsc, omega);
-  BSE_LAUNCH("k_weights", k_weights, dim3(gw), dim3(256), 0, s, n, w.d, w.e2, w.tsc, w.beta0,
-             omega, pole, osc);
-  BSE_HIP_CHECK(hipGetLastError());
-  return BSE_OK;
-}
-}  // namespace bse
 
 extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64,
                                   const void *Bmu, int32_t prec, int32_t nrefine, double *omega,
@@ -949,4 +1233,169 @@ extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_
                   : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
   return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
                 : eigh_run<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// batched block eigensolver
+// ---------------------------------------------------------------------------
+namespace {
+int32_t check_batch(int32_t nb, const int64_t *h_n, int32_t prec) {
+  if (nb < 1 || nb > NBMAX) return fail(BSE_ESHAPE, "batch of %d blocks (1 .. %d)", nb, NBMAX);
+  if (!h_n) return fail(BSE_EINVAL, "NULL block sizes");
+  for (int b = 0; b < nb; ++b)
+    if (h_n[b] < 1 || h_n[b] > 16384)
+      return fail(BSE_ESHAPE, "block %d: n = %lld outside 1 .. 16384", b, (long long)h_n[b]);
+  if (prec != BSE_FP64 && prec != BSE_FP32) return fail(BSE_EINVAL, "unsupported precision");
+  return BSE_OK;
+}
+
+// Recomputes the launch sequence for P.wpr and uploads the prefix table.
+int32_t upload_tables(BatchPlan &P, hipStream_t s) {
+  std::vector<int> pre;
+  if (P.prec == BSE_FP64)
+    plan_launches<double>(P, pre);
+  else
+    plan_launches<float>(P, pre);
+  BSE_HIP_CHECK(hipMemcpyAsync(P.d_pre, pre.data(), pre.size() * sizeof(int),
+                               hipMemcpyHostToDevice, s));
+  BSE_HIP_CHECK(hipStreamSynchronize(s));
+  return BSE_OK;
+}
+
+int32_t run_plan(const BatchPlan &P, hipStream_t s) {
+  if (P.prec == BSE_FP64)
+    return P.h_fp64 ? batch_run<double, double>(P, s) : batch_run<float, double>(P, s);
+  return P.h_fp64 ? batch_run<double, float>(P, s) : batch_run<float, float>(P, s);
+}
+}  // namespace
+
+extern "C" size_t bse_batch_eigh_ws(int32_t nb, const int64_t *h_n, int32_t h_fp64,
+                                    int32_t prec) {
+  (void)h_fp64;
+  if (check_batch(nb, h_n, prec)) return 0;
+  return batch_ws_bytes(nb, h_n, prec == BSE_FP64, nullptr, nullptr, nullptr,
+                        pre_bound(nb, h_n));
+}
+
+extern "C" int32_t bse_batch_eigh_plan(int32_t nb, const int64_t *h_n, const void *const *h_Hmu,
+                                       const int64_t *h_ld, int32_t h_fp64,
+                                       const void *const *h_Bmu, int32_t prec,
+                                       double *const *h_omega, double *const *h_pole,
+                                       double *const *h_osc, void *ws, size_t ws_bytes,
+                                       int64_t *h_plan, bse_stream stream) {
+  int32_t st = check_batch(nb, h_n, prec);
+  if (st) return st;
+  if (!h_Hmu || !h_ld || !h_Bmu || !h_omega || !h_pole || !h_osc || !h_plan)
+    return fail(BSE_EINVAL, "NULL argument array");
+  for (int b = 0; b < nb; ++b) {
+    if (!h_Hmu[b] || !h_Bmu[b] || !h_omega[b] || !h_pole[b] || !h_osc[b])
+      return fail(BSE_EINVAL, "block %d: NULL pointer", b);
+    if (h_ld[b] < h_n[b]) return fail(BSE_ESHAPE, "block %d: ld < n", b);
+  }
+  const bool a64 = prec == BSE_FP64;
+  std::vector<int> order(nb);
+  for (int b = 0; b < nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return h_n[x] > h_n[y]; });
+  std::vector<int64_t> ns(nb);
+  for (int b = 0; b < nb; ++b) ns[b] = h_n[order[b]];
+  std::vector<size_t> offs;
+  size_t desc_off = 0, pre_off = 0;
+  const size_t need = batch_ws_bytes(nb, ns.data(), a64, &offs, &desc_off, &pre_off,
+                                     pre_bound(nb, ns.data()));
+  if (!ws || ws_bytes < need)
+    return fail(BSE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  BatchPlan P;
+  P.nb = nb;
+  P.h_fp64 = h_fp64 ? 1 : 0;
+  P.prec = prec;
+  P.wpr = 4;
+  P.ws = (char *)ws;
+  P.n = ns;
+  P.d_desc = (Desc *)(P.ws + desc_off);
+  P.d_pre = (int *)(P.ws + pre_off);
+  std::vector<Desc> D(nb);
+  for (int b = 0; b < nb; ++b) {
+    const int o = order[b];
+    ws_layout(ns[b], a64, &D[b], P.ws + offs[b]);
+    D[b].H = h_Hmu[o];
+    D[b].ld = h_ld[o];
+    D[b].B = (const double2 *)h_Bmu[o];
+    D[b].omega = h_omega[o];
+    D[b].pole = h_pole[o];
+    D[b].osc = h_osc[o];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  BSE_HIP_CHECK(hipMemcpyAsync(P.d_desc, D.data(), nb * sizeof(Desc), hipMemcpyHostToDevice, s));
+  st = upload_tables(P, s);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  const int64_t id = g_next_plan++;
+  g_plans[id] = std::move(P);
+  *h_plan = id;
+  return BSE_OK;
+}
+
+extern "C" int32_t bse_batch_eigh_run(int64_t plan, bse_stream stream) {
+  BatchPlan P;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(plan);
+    if (it == g_plans.end()) return fail(BSE_EINVAL, "unknown plan %lld", (long long)plan);
+    P = it->second;
+  }
+  return run_plan(P, (hipStream_t)stream);
+}
+
+extern "C" int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t *h_wpr) {
+  BatchPlan P;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(plan);
+    if (it == g_plans.end()) return fail(BSE_EINVAL, "unknown plan %lld", (long long)plan);
+    P = it->second;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  BSE_HIP_CHECK(hipEventCreate(&e0));
+  BSE_HIP_CHECK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_w = 4;
+  for (int w : {4, 2, 1}) {
+    P.wpr = w;
+    int32_t st = upload_tables(P, s);
+    if (!st) st = run_plan(P, s);  // warm-up
+    if (!st) {
+      BSE_HIP_CHECK(hipEventRecord(e0, s));
+      st = run_plan(P, s);
+      BSE_HIP_CHECK(hipEventRecord(e1, s));
+      BSE_HIP_CHECK(hipEventSynchronize(e1));
+    }
+    if (st) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return st;
+    }
+    float ms = 0;
+    BSE_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_w = w;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  P.wpr = best_w;
+  int32_t st = upload_tables(P, s);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans[plan] = P;
+  if (h_wpr) *h_wpr = best_w;
+  return BSE_OK;
+}
+
+extern "C" int32_t bse_batch_eigh_free(int64_t plan) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (!g_plans.erase(plan)) return fail(BSE_EINVAL, "unknown plan %lld", (long long)plan);
+  return BSE_OK;
 }

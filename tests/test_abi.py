@@ -117,3 +117,26 @@ def test_workload_inputs_identical_to_oracle_inputs():
     for k in ("ev", "ec", "vdiag", "mx", "mv", "mc", "w"):
         assert np.array_equal(inp[k], P[k]), k
     assert np.allclose(inp["B"], P["B"], atol=1e-15)
+
+
+def test_batch_eigh_validation():
+    """The batched eigensolver's size checks run on the host before any device work."""
+    import ctypes
+    from paper_2603_24860_amd import _lib
+    L = _lib.lib
+    ns = (ctypes.c_int64 * 3)(10, 20, 5)
+    assert L.bse_batch_eigh_ws(3, ns, 0, _lib.FP32) > 0
+    assert L.bse_batch_eigh_ws(0, ns, 0, _lib.FP32) == 0
+    big = (ctypes.c_int64 * 1)(16385)
+    assert L.bse_batch_eigh_ws(1, big, 0, _lib.FP32) == 0
+    bad = (ctypes.c_int64 * 1)(0)
+    assert L.bse_batch_eigh_ws(1, bad, 0, _lib.FP32) == 0
+    # a too small workspace is refused before anything is dereferenced
+    fake = (ctypes.c_void_p * 3)(1, 1, 1)
+    lds = (ctypes.c_int64 * 3)(10, 20, 5)
+    plan = ctypes.c_int64()
+    st = L.bse_batch_eigh_plan(3, ns, fake, lds, 0, fake, _lib.FP32, fake, fake, fake,
+                               ctypes.c_void_p(1), 16, ctypes.byref(plan), None)
+    assert st == _lib.EWORKSPACE
+    assert L.bse_batch_eigh_run(12345, None) == _lib.EINVAL
+    assert L.bse_batch_eigh_free(12345) == _lib.EINVAL
