@@ -10,6 +10,6 @@ their own tables.
 """
 from .gen import (  # noqa: F401
     splitmix64, keyed_uniform, keyed_normal, keyed_complex,
-    CONFIGS, config, band_energies, coulomb_diag, exchange_vectors,
+    CONFIGS, config, batch_configs, band_energies, coulomb_diag, exchange_vectors,
     pair_vectors, screened_w, dipoles, omega_grid_from_range, ETA, NOMEGA,
 )

@@ -21,6 +21,7 @@ Recipe (all energies in eV):
     s r = k of R_s g, r the orbit representative.  B = e . d.
 """
 import math
+import os
 import numpy as np
 
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -28,7 +29,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 _GOLD = np.uint64(0x9E3779B97F4A7C15)
 
 # tensor tags: fixed small integers so keys never collide across tensors
-TAG = {"ejv": 1, "ejc": 2, "mx": 3, "mv": 4, "mc": 5, "chi": 6, "dip": 7}
+TAG = {"ejv": 1, "ejc": 2, "mx": 3, "mv": 4, "mc": 5, "chi": 6, "dip": 7, "batch": 8}
 
 
 def splitmix64(z):
@@ -86,6 +87,20 @@ ETA = 0.05       # Lorentzian broadening in eV
 NOMEGA = 2000    # points on the frequency grid
 
 
+def batch_configs(seed=4, count=64):
+    """The batched workload: `count` layered hexagonal (D6h) systems.  Seed 4
+    draws each system's shape (n x n x 1 grid with n in 6..24, Nv and Nc in
+    2..4, Nmb in {128, 192, 256, 320}); system s draws its data with seed
+    4000 + s, so systems of equal shape still differ."""
+    out = []
+    for s in range(count):
+        u = [float(keyed_uniform(seed, "batch", s, j)) for j in range(4)]
+        n = 6 + int(u[0] * 19)
+        out.append(dict(lattice="hex", grid=(n, n, 1), nv=2 + int(u[1] * 3), nc=2 + int(u[2] * 3),
+                        nmb=(2 + int(u[3] * 4)) * 64, seed=4000 + s, name=f"cfg4.{s}"))
+    return out
+
+
 def config(name, **over):
     c = dict(CONFIGS[name])
     c.update(over)
@@ -130,12 +145,15 @@ def exchange_vectors(seed, korb_reps, nv, nc, nmb):
     return keyed_complex(seed, "mx", r, v, c, i, var=np.exp(-i / 16.0))
 
 
-def pair_vectors(seed, tag, class_reps, class_selfswap, nb, nmb, chunk=4096):
+def pair_vectors(seed, tag, class_reps, class_selfswap, nb, nmb, chunk=1024, threads=16):
     """M_v or M_c per pair class: [ncls, nb, nb, nmb] complex128.
 
     class_reps[ncls]: linear pair index k*nk+k' of the stored orientation;
     class_selfswap[ncls]: the class's orbit is its own swap partner, so the
     stored matrix must equal its conjugate transpose over the band indices.
+    Chunks of classes are drawn in parallel threads (numpy releases the GIL in
+    its array kernels); every value depends only on its key, so the result does
+    not depend on the chunking or the thread count.
     """
     reps = np.asarray(class_reps, dtype=np.int64)
     ss = np.asarray(class_selfswap, dtype=bool)
@@ -144,7 +162,8 @@ def pair_vectors(seed, tag, class_reps, class_selfswap, nb, nmb, chunk=4096):
     b2 = np.arange(nb)[None, None, :, None]
     i = np.arange(nmb)[None, None, None, :]
     var = np.exp(-i / 16.0)
-    for s in range(0, len(reps), chunk):
+
+    def fill(s):
         r = reps[s:s + chunk][:, None, None, None]
         z = keyed_complex(seed, tag, r, b1, b2, i, var=var)
         sel = ss[s:s + chunk]
@@ -152,6 +171,16 @@ def pair_vectors(seed, tag, class_reps, class_selfswap, nb, nmb, chunk=4096):
             zs = z[sel]
             z[sel] = (zs + np.conj(np.swapaxes(zs, 1, 2))) / math.sqrt(2.0)
         out[s:s + chunk] = z
+
+    starts = range(0, len(reps), chunk)
+    nt = max(1, min(threads, len(starts), os.cpu_count() or 1))
+    if nt == 1:
+        for s in starts:
+            fill(s)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(nt) as ex:
+            list(ex.map(fill, starts))
     return out
 
 

@@ -45,3 +45,13 @@ def device_system(cfg, prec, vector_dipole=True, zero_interaction=False, device=
         inputs["vdiag"] = np.zeros_like(inputs["vdiag"])
         inputs["w"] = np.zeros_like(inputs["w"])
     return DeviceSystem(group, grid, cfg["nv"], cfg["nc"], cfg["nmb"], T, inputs, prec, device)
+
+
+def batch_systems(cfgs, prec, device="cuda", log=None):
+    """DeviceSystem per config of a batch (e.g. synth.batch_configs())."""
+    out = []
+    for i, c in enumerate(cfgs):
+        out.append(device_system(c, prec, device=device))
+        if log:
+            log(f"  system {i + 1}/{len(cfgs)} uploaded")
+    return out
