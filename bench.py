@@ -182,13 +182,124 @@ def bench_batched(args):
     bs.close()
 
 
+def bench_served(args):
+    """Served form: a Poisson stream of BSE solve requests over a mix of
+    resident systems (cubic cfg1 / cfg2 shapes and three layered D6h systems of
+    the batched family), FP32 or split-BF16 builds, continuous batching on four
+    streams with admission by HBM footprint (288 GB)."""
+    import torch
+    import synth
+    import workloads
+    from paper_2603_24860_amd import bse as B
+    from paper_2603_24860_amd.serve import Request, Server
+    rng = np.random.default_rng(5)
+    d6 = synth.batch_configs()
+    pick = {8: None, 13: None, 20: None}
+    for c in d6:
+        if c["grid"][0] in pick and pick[c["grid"][0]] is None:
+            pick[c["grid"][0]] = c
+    cfgs = {"cfg1": synth.config("cfg1"), "cfg2": synth.config("cfg2"),
+            "d6h-8": pick[8], "d6h-13": pick[13], "d6h-20": pick[20]}
+    t0 = time.perf_counter()
+    sysobjs = {}
+    for name, c in cfgs.items():
+        for pname, prec in (("fp32", B.FP32), ("fp64", B.FP64)):
+            sysobjs[f"{name}/{pname}"] = workloads.device_system(c, prec)
+        log(f"  system {name} resident")
+    grids = {}
+    ref = {}
+    for name in cfgs:  # FP64 reference solve of every system, and its frequency grid
+        srv = Server(slots=1)
+        srv.register(f"{name}/fp64", sysobjs[f"{name}/fp64"], np.linspace(-20, 20, 100))
+        r = srv.run([Request(0, f"{name}/fp64", B.FP64, 0.0)])[0].result
+        ref[name] = r["lowest"]
+        grids[name] = synth.omega_grid_from_range(r["omega"].min(), r["omega"].max())
+    log(f"setup {time.perf_counter() - t0:.1f} s")
+    mix = [("cfg1", "fp32", B.FP32, 0.15), ("cfg1", "fp32", B.BF16X3, 0.10),
+           ("cfg2", "fp32", B.FP32, 0.15), ("cfg2", "fp32", B.BF16X3, 0.15),
+           ("d6h-8", "fp32", B.FP32, 0.10), ("d6h-13", "fp32", B.BF16X3, 0.15),
+           ("d6h-20", "fp32", B.FP32, 0.20)]
+    wts = np.array([m[3] for m in mix])
+    wts /= wts.sum()
+
+    def server(slots):
+        srv = Server(slots=slots, hbm_budget=288e9)
+        for key, ds in sysobjs.items():
+            srv.register(key, ds, grids[key.split("/")[0]])
+        return srv
+
+    def draw(count, fp64=False):
+        out = []
+        for i in range(count):
+            name, cls, prec, _ = mix[int(rng.choice(len(mix), p=wts))]
+            out.append(Request(i, f"{name}/fp64" if fp64 else f"{name}/{cls}",
+                               B.FP64 if fp64 else prec, 0.0))
+        return out
+
+    # warm-up of every request type
+    server(4).run(draw(3 * len(mix)))
+    # plain FP64 GPU form over the same mix, one request after the other
+    nplain = 150
+    t1 = time.perf_counter()
+    server(1).run(draw(nplain, fp64=True))
+    plain = nplain / (time.perf_counter() - t1)
+    # saturation throughput of the served form
+    nsat = 400
+    t1 = time.perf_counter()
+    server(4).run(draw(nsat))
+    sat = nsat / (time.perf_counter() - t1)
+    # Poisson arrivals at 0.8 x saturation
+    lam = 0.8 * sat
+    nreq = max(1000, args.steps)
+    reqs = draw(nreq)
+    t = 0.0
+    for r in reqs:
+        t += rng.exponential(1.0 / lam)
+        r.arrival = t
+    srv = server(4)
+    t1 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t1
+    st = Server.latency_stats(done)
+    err = {}
+    for r in done:
+        name = r.system.split("/")[0]
+        key = {B.FP32: "fp32", B.BF16X3: "bf16x3"}[r.prec]
+        err[key] = max(err.get(key, 0.0), float(np.abs(r.result["lowest"] - ref[name]).max()))
+    ok = sum(1 for r in done if np.abs(r.result["lowest"] - ref[r.system.split("/")[0]]).max()
+             <= 1e-4)
+    out = {
+        "metric": "served form: solves/s and p50/p99 latency (Poisson arrivals, continuous "
+                  "batching on 4 streams, admission by HBM footprint <= 288 GB)",
+        "value": round(len(done) / wall, 3), "unit": "solves/s",
+        "n_gpus": 1, "steps": len(done), "warmup": 3 * len(mix),
+        "ms_per_step": round(wall * 1e3 / len(done), 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+bf16x3",
+        "data": "synthetic (seeded; resident cfg1/cfg2 cubic and three D6h systems)",
+        "config": {"workload": "cfg5: Poisson stream over cfg1 (T1u 162), cfg2 (T1u 2160) and "
+                               "D6h 8x8x1 / 13x13x1 / 20x20x1 (E1u) systems, FP32 or split-BF16 "
+                               "builds", "requests": len(done), "arrival_rate_per_s": round(lam, 3)},
+        "latency_ms": {"p50": round(st["p50_ms"], 3), "p99": round(st["p99_ms"], 3),
+                       "mean": round(st["mean_ms"], 3)},
+        "saturation_solves_per_s": round(sat, 3),
+        "plain_fp64_solves_per_s": round(plain, 3),
+        "served_over_plain_fp64": round((len(done) / wall) / plain, 3),
+        "max_lowest100_err_meV_vs_fp64": {k: round(v * 1e3, 6) for k, v in err.items()},
+        "solves_within_0.1meV": ok,
+        "max_hbm_in_flight_GB": round(srv.max_used / 1e9, 3),
+        "rejected": len(srv.rejected),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg2",
-                    help="cfg1 / cfg2 / cfg3: one system; cfg4: the batched form (64 D6h systems)")
+                    help="cfg1 / cfg2 / cfg3: one system; cfg4: the batched form (64 D6h "
+                         "systems); cfg5: the served form (Poisson request stream)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-q", type=int, default=32)
@@ -220,6 +331,8 @@ def main():
     from paper_2603_24860_amd.system import Solver
     if args.workload == "cfg4":
         return bench_batched(args)
+    if args.workload == "cfg5":
+        return bench_served(args)
 
     prec = {"fp32": B.FP32, "fp64": B.FP64, "bf16x3": B.BF16X3}[args.prec]
     cfg = synth.config(args.workload)

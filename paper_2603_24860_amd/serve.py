@@ -1,0 +1,179 @@
+"""Served form: continuous batching of BSE solves on one GPU.
+
+Requests (a resident system, a build precision) arrive over time.  The server
+keeps every registered system's inputs (band energies, orbit-compressed pair
+vectors, W per q orbit, dipoles, block bases) resident in HBM and runs each
+admitted request's whole path -- bse_build, bse_project_blocks (the
+dipole-active block), bse_block_eigh, bse_spectrum, and the copy of the results
+to pinned host memory -- on one of `slots` HIP streams, so requests that are
+admitted while others run overlap on the device.  A request is admitted when a
+slot is free and its HBM footprint (H, H_mu, workspaces, outputs) fits into the
+budget left by the requests in flight; requests larger than the whole budget
+are rejected.  Completion is detected by a non-blocking event query, which
+frees the slot and the budget for the next waiting request (first come, first
+served).  Every request owns its buffers, so its result does not depend on
+what else is in flight.
+"""
+import math
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import bse as B
+from .system import CDT
+
+EL = {B.FP64: 16, B.FP32: 8, B.BF16X3: 8}
+
+
+class Request:
+    __slots__ = ("rid", "system", "prec", "arrival", "start", "done", "result", "ev", "bufs",
+                 "footprint", "status")
+
+    def __init__(self, rid, system, prec, arrival):
+        self.rid, self.system, self.prec, self.arrival = rid, system, prec, arrival
+        self.start = self.done = None
+        self.result = None
+        self.ev = None
+        self.bufs = None
+        self.footprint = 0
+        self.status = "waiting"
+
+
+class ServedSystem:
+    """A registered, resident system: inputs of one precision class and its
+    dipole-active block (FP64 inputs for FP64 requests, FP32 otherwise)."""
+
+    def __init__(self, name, dev_system, wgrid, eta=0.05):
+        self.name = name
+        self.s = dev_system
+        self.irrep, _ = dev_system.active_irrep()
+        self.blk = dev_system.block(self.irrep)
+        self.w = torch.as_tensor(np.asarray(wgrid, dtype=np.float64), device=dev_system.device)
+        self.eta = eta
+
+    def footprint(self, prec):
+        s, n = self.s, self.blk.n
+        el = EL[prec]
+        eig_prec = B.FP32 if prec == B.BF16X3 else prec
+        h64 = 1 if prec == B.FP64 else 0
+        return (s.N * s.N * el + B.bse_build_ws(s.problem, prec) + n * n * el + 16 * n
+                + B.bse_block_eigh_ws(n, h64, eig_prec, 0) + 3 * 8 * n + 8 * self.w.numel())
+
+
+class Server:
+    def __init__(self, slots=4, hbm_budget=288e9, device="cuda"):
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        self.free = list(range(slots))
+        self.budget = float(hbm_budget)
+        self.used = 0.0
+        self.max_used = 0.0
+        self.systems = {}
+        self.waiting = deque()
+        self.running = {}
+        self.finished = []
+        self.rejected = []
+
+    def register(self, name, dev_system, wgrid):
+        self.systems[name] = ServedSystem(name, dev_system, wgrid)
+
+    # -- one request's path on its stream ----------------------------------
+    def _launch(self, req, slot):
+        ss = self.systems[req.system]
+        s = ss.s
+        st = self.streams[slot]
+        prec = req.prec
+        eig_prec = B.FP32 if prec == B.BF16X3 else prec
+        n = ss.blk.n
+        h = st.cuda_stream
+        with torch.cuda.stream(st):
+            H = torch.empty((s.N, s.N), dtype=CDT[prec], device=self.device)
+            bws = torch.empty(max(B.bse_build_ws(s.problem, prec), 256), dtype=torch.uint8,
+                              device=self.device)
+            B.bse_build(s.problem, prec, H, bws, stream=h)
+            Hmu = torch.empty((n, n), dtype=CDT[prec], device=self.device)
+            Bmu = torch.empty(n, dtype=torch.complex128, device=self.device)
+            B.bse_project_blocks(s.problem, H, s.t["B"], [ss.blk.c], [Hmu], [Bmu], stream=h)
+            del H, bws  # freed for later work on this stream only (stream-ordered pool)
+            h64 = 1 if prec == B.FP64 else 0
+            ews = torch.empty(B.bse_block_eigh_ws(n, h64, eig_prec, 0), dtype=torch.uint8,
+                              device=self.device)
+            om = torch.empty(n, dtype=torch.float64, device=self.device)
+            po, osc = torch.empty_like(om), torch.empty_like(om)
+            B.bse_block_eigh(Hmu, Bmu, eig_prec, om, po, osc, ews, stream=h)
+            e2 = torch.empty_like(ss.w)
+            B.bse_spectrum(po, osc, 8 * math.pi / s.nk, ss.eta, ss.w, e2, stream=h)
+            host = {k: torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+                    for k, t in (("omega", om), ("pole", po), ("osc", osc), ("eps2", e2))}
+            for k, t in (("omega", om), ("pole", po), ("osc", osc), ("eps2", e2)):
+                host[k].copy_(t, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        req.bufs = (Hmu, Bmu, ews, om, po, osc, e2, host)
+        req.ev = ev
+
+    # -- scheduling --------------------------------------------------------
+    def _admit(self, now):
+        while self.waiting and self.free:
+            req = self.waiting[0]
+            fp = self.systems[req.system].footprint(req.prec)
+            if fp > self.budget:
+                self.waiting.popleft()
+                req.status = "rejected"
+                self.rejected.append(req)
+                continue
+            if self.used + fp > self.budget:
+                break  # first come, first served: wait for memory
+            self.waiting.popleft()
+            slot = self.free.pop()
+            req.footprint = fp
+            self.used += fp
+            self.max_used = max(self.max_used, self.used)
+            req.start = now
+            req.status = "running"
+            self._launch(req, slot)
+            self.running[req.rid] = (req, slot)
+
+    def _poll(self):
+        done = [rid for rid, (req, _) in self.running.items() if req.ev.query()]
+        now = time.perf_counter()
+        for rid in done:
+            req, slot = self.running.pop(rid)
+            host = req.bufs[-1]
+            n = host["omega"].numel()
+            req.result = {k: v.numpy().copy() for k, v in host.items()}
+            req.result["lowest"] = req.result["omega"][:min(100, n)]
+            req.done = now
+            req.status = "done"
+            req.bufs = None
+            req.ev = None
+            self.used -= req.footprint
+            self.free.append(slot)
+            self.finished.append(req)
+        return len(done)
+
+    def run(self, requests, t0=None):
+        """Serve `requests` (sorted by arrival, seconds relative to t0); returns
+        when all are finished or rejected."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        t0 = time.perf_counter() if t0 is None else t0
+        for r in pending:
+            r.arrival += t0
+        while pending or self.waiting or self.running:
+            now = time.perf_counter()
+            while pending and pending[0].arrival <= now:
+                self.waiting.append(pending.popleft())
+            self._poll()
+            self._admit(time.perf_counter())
+            if not self._poll() and pending and not self.waiting and not self.running:
+                time.sleep(max(0.0, min(0.001, pending[0].arrival - time.perf_counter())))
+        return self.finished
+
+    @staticmethod
+    def latency_stats(reqs):
+        lat = np.array([r.done - r.arrival for r in reqs])
+        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3),
+                    p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    mean_ms=float(lat.mean() * 1e3), count=int(len(lat)))

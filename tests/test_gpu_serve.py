@@ -1,0 +1,123 @@
+"""GPU tests of the served form (continuous batching).
+
+* Each request's result is the same alone and in the mix: a request type is
+  solved alone (one slot, nothing else in flight), then 24 requests of mixed
+  types arrive within a few milliseconds and run overlapped on four slots;
+  every result equals its solo result bitwise (requests own their buffers and
+  run the same kernels).  The solo results also meet the accuracy targets
+  against the oracle (FP64 1e-9 eV, FP32 1e-5 eV, split BF16 1e-4 eV).
+* Admission by HBM footprint: with a budget of 1.5 times the largest request,
+  the memory in flight never exceeds the budget, and a request larger than
+  the whole budget is rejected rather than run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+SYS = {
+    "oh4": dict(lattice="cubic", grid=(4, 4, 4), nv=3, nc=3, nmb=64, seed=51, name="oh4"),
+    "hex6": dict(lattice="hex", grid=(6, 6, 1), nv=2, nc=3, nmb=128, seed=52, name="hex6"),
+}
+
+
+@pytest.fixture(scope="module")
+def env():
+    from paper_2603_24860_amd import bse as B
+    import synth
+    import workloads
+    from oracle import bse as OB
+    assert torch.cuda.is_available()
+    refs, systems = {}, {}
+    for key, c in SYS.items():
+        P = OB.make_problem(c)
+        r = OB.solve_block(P, OB.dipole_active(P)[0])
+        grid = synth.omega_grid_from_range(r["omega"].min(), r["omega"].max())
+        refs[key] = r
+        for pname, prec in (("fp64", B.FP64), ("fp32", B.FP32)):
+            systems[f"{key}/{pname}"] = (workloads.device_system(c, prec), grid)
+    return B, refs, systems
+
+
+def _server(env, slots, budget=288e9):
+    from paper_2603_24860_amd.serve import Server
+    B, refs, systems = env
+    srv = Server(slots=slots, hbm_budget=budget)
+    for name, (ds, grid) in systems.items():
+        srv.register(name, ds, grid)
+    return srv
+
+
+TYPES = [("oh4/fp64", "FP64", 1e-9), ("oh4/fp32", "FP32", 1e-5), ("oh4/fp32", "BF16X3", 1e-4),
+         ("hex6/fp64", "FP64", 1e-9), ("hex6/fp32", "FP32", 1e-5),
+         ("hex6/fp32", "BF16X3", 1e-4)]
+
+
+def _solo(env):
+    from paper_2603_24860_amd.serve import Request
+    B, refs, _ = env
+    out = {}
+    for i, (sysname, pname, tol) in enumerate(TYPES):
+        srv = _server(env, 1)
+        done = srv.run([Request(i, sysname, getattr(B, pname), 0.0)])
+        res = done[0].result
+        ref = refs[sysname.split("/")[0]]
+        err = np.abs(res["lowest"] - ref["lowest"]).max()
+        say("solo", sysname, pname, "lowest-100 err", err)
+        assert err < tol
+        out[(sysname, pname)] = res
+    return out
+
+
+def test_same_alone_and_in_the_mix(env):
+    from paper_2603_24860_amd.serve import Request
+    B = env[0]
+    solo = _solo(env)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(24):
+        sysname, pname, _ = TYPES[int(rng.integers(len(TYPES)))]
+        reqs.append(Request(i, sysname, getattr(B, pname), float(i) * 2.5e-4))
+    srv = _server(env, 4)
+    done = srv.run(reqs)
+    assert len(done) == 24 and not srv.rejected
+    overlap = sum(1 for a in done for b in done
+                  if a.rid < b.rid and a.start < b.done and b.start < a.done)
+    say("mix: 24 requests, overlapping pairs", overlap, "max in flight bytes", srv.max_used)
+    assert overlap > 0
+    for r in done:
+        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec])]
+        for k in ("omega", "pole", "osc", "eps2"):
+            assert np.array_equal(r.result[k], ref[k]), (r.rid, r.system, k)
+
+
+def test_admission_by_footprint(env):
+    from paper_2603_24860_amd.serve import Request
+    B = env[0]
+    solo = _solo(env)
+    srv = _server(env, 4)
+    fps = {(s, p): srv.systems[s].footprint(getattr(B, p)) for s, p, _ in TYPES}
+    budget = 1.5 * max(fps.values())
+    srv = _server(env, 4, budget=budget)
+    reqs = [Request(i, s, getattr(B, p), 0.0) for i, (s, p, _) in enumerate(TYPES * 3)]
+    done = srv.run(reqs)
+    say("budget", budget, "max in flight", srv.max_used, "served", len(done))
+    assert srv.max_used <= budget
+    assert len(done) == len(reqs)
+    for r in done:
+        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec])]
+        assert np.array_equal(r.result["omega"], ref["omega"])
+    # a request larger than the whole budget is rejected
+    small = _server(env, 4, budget=0.5 * min(fps.values()))
+    assert not small.run([Request(0, "oh4/fp32", B.FP32, 0.0)])
+    assert len(small.rejected) == 1
