@@ -202,9 +202,16 @@ int32_t bse_project_blocks(const bse_problem *p, const void *H, int64_t ldh, int
  * padded with zero strength.  Hmu is read only.
  * prec: FP64 (all FP64), FP32 (FP32 storage of the working copy, its HEMV
  * and trailing updates; FP64 panel vectors, scalars and tridiagonal step).
- * nrefine must be 0 (FP64 refinement of the lowest eigenvalues is not
- * available: BSE_EUNSUPPORTED).  Errors: n < 1 or n > 65536 (BSE_ESHAPE),
- * NULL pointers (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).
+ * nrefine = K in 0 .. 256: FP64 refinement of the lowest min(K, n)
+ * eigenvalues against the stored Hmu: inverse iteration on T (members of a
+ * degenerate cluster orthogonalised), back-transformation through the kept
+ * reflectors and the Rayleigh quotient Re(x^dag Hmu x) / |x|^2, which is exact
+ * to O(delta^2 |Hmu|) for an eigenvector error delta; omega[0 .. K) then holds
+ * the refined values (ascending) and the poles of clusters inside that range
+ * are re-centred.  It removes the eigensolver's rounding, not errors already
+ * in Hmu.  The workspace grows by about n^2 16 B (all reflectors) for K > 0.
+ * Errors: n < 1 or n > 65536 (BSE_ESHAPE), NULL pointers or nrefine outside
+ * 0 .. 256 (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).
  * ------------------------------------------------------------------------- */
 size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int32_t nrefine);
 int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, const void *Bmu,

@@ -91,6 +91,8 @@ template <int NTH> __device__ __forceinline__ double block_sum(double v, double 
 }
 
 constexpr int NBMAX = 1024;  // blocks in one batched solve
+constexpr int CMAX = 8;      // cluster members refined per eigenvalue cluster
+constexpr int KMAX = 256;    // eigenvalues refinable per solve
 
 // One block's working set.  Partial-sum buffers are sized by the block:
 // k_colB and k_col0 write at most ceil(n / 64) records, k_colA at most n sums,
@@ -116,6 +118,14 @@ struct Desc {
   double *tsc;               // [8] tridiagonal scalars
   double *beta0;             // [1]
   double *omega, *pole, *osc;  // outputs [n]
+  // refinement of the lowest K eigenvalues (K = 0: none)
+  int64_t K;
+  double2 *Vall;             // [n][ldv] every reflector (column j: reflector of column j)
+  double *Z;                 // [K][n] eigenvectors of T
+  double2 *X;                // [K][n] their back-transforms
+  double *rqp;               // [K][cdiv(n, 4)][2] partial Rayleigh quotients
+  double *scr;               // [K][(4 + CMAX) n] inverse-iteration scratch
+  double *wref;              // [K] refined eigenvalues
 };
 
 // ---------------------------------------------------------------------------
@@ -164,7 +174,7 @@ __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Lays out one block's workspace at base (nullptr: size only).
-size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base) {
+size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char *p = base ? base + off : nullptr;
@@ -196,6 +206,15 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base) {
   t.e2 = (double *)take(size_t(n) * 8);
   t.tsc = (double *)take(8 * 8);
   t.beta0 = (double *)take(8);
+  t.K = K;
+  if (K > 0) {
+    t.Vall = (double2 *)take(size_t(n) * ldv * 16);
+    t.Z = (double *)take(size_t(K) * n * 8);
+    t.X = (double2 *)take(size_t(K) * n * 16);
+    t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, 4)) * 16);
+    t.scr = (double *)take(size_t(K) * (4 + CMAX) * n * 8);
+    t.wref = (double *)take(size_t(K) * 8);
+  }
   if (w) *w = t;
   return off;
 }
@@ -1013,6 +1032,240 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// refinement of the lowest K eigenvalues against the stored H_mu (FP64)
+//   k_invit   eigenvectors z of T by inverse iteration (3 steps) for each of
+//             the lowest K eigenvalues; the members of a cluster of
+//             (numerically) degenerate eigenvalues start from distinct
+//             vectors and are orthogonalised in order, so a cluster gets an
+//             orthonormal basis of its invariant subspace
+//   k_backxf  x = Q0 H(0) H(1) ... H(n-2) z, applying the stored reflectors
+//   k_hx_part partial sums of x^dag H_mu x and |x|^2 (one wave per row)
+//   k_rq_fin  theta = Re(x^dag H_mu x) / |x|^2 replaces omega[l]; the pole of
+//             a cluster inside the refined range becomes the mean of its members
+// The Rayleigh quotient of an approximate eigenvector with error delta is
+// exact to O(delta^2 |H_mu|), so rounding of the eigensolver itself (FP32
+// storage of the working copy) is removed; errors of H_mu are not.
+// ---------------------------------------------------------------------------
+// (T - sigma) x = rhs for symmetric tridiagonal T (diag d, off-diag e) by
+// Gaussian elimination with partial pivoting; serial, scratch 4 n doubles.
+__device__ void tri_solve(int64_t n, const double *__restrict__ d, const double *__restrict__ e,
+                          double sigma, double tiny, double *__restrict__ dd,
+                          double *__restrict__ du, double *__restrict__ du2,
+                          double *__restrict__ dl, double *__restrict__ x) {
+  for (int64_t i = 0; i < n; ++i) dd[i] = d[i] - sigma;
+  for (int64_t i = 0; i + 1 < n; ++i) {
+    du[i] = e[i];
+    dl[i] = e[i];
+  }
+  // factorisation; dl[i] < 0 encodes "rows i and i+1 swapped" through du2 usage
+  for (int64_t i = 0; i + 1 < n; ++i) {
+    if (fabs(dd[i]) >= fabs(dl[i])) {
+      const double piv = fabs(dd[i]) < tiny ? (dd[i] < 0 ? -tiny : tiny) : dd[i];
+      dd[i] = piv;
+      const double f = dl[i] / piv;
+      dl[i] = f;
+      dd[i + 1] -= f * du[i];
+      du2[i] = 0.0;
+      x[i] = 0.0;  // marker: no interchange
+    } else {
+      const double f = dd[i] / dl[i];
+      dd[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = dd[i + 1];
+      dd[i + 1] = t - f * dd[i + 1];
+      if (i + 2 < n) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      } else {
+        du2[i] = 0.0;
+      }
+      x[i] = 1.0;  // marker: rows i, i+1 interchanged
+    }
+  }
+  if (fabs(dd[n - 1]) < tiny) dd[n - 1] = dd[n - 1] < 0 ? -tiny : tiny;
+}
+
+// solves with the factors of tri_solve; b holds the right-hand side on entry
+// and the solution on exit; piv are the interchange markers left in x
+__device__ void tri_apply(int64_t n, const double *__restrict__ dd, const double *__restrict__ du,
+                          const double *__restrict__ du2, const double *__restrict__ dl,
+                          const double *__restrict__ piv, double *__restrict__ b) {
+  for (int64_t i = 0; i + 1 < n; ++i) {
+    if (piv[i] == 0.0) {
+      b[i + 1] -= dl[i] * b[i];
+    } else {
+      const double t = b[i];
+      b[i] = b[i + 1];
+      b[i + 1] = t - dl[i] * b[i];
+    }
+  }
+  b[n - 1] /= dd[n - 1];
+  if (n > 1) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
+  for (int64_t i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+}
+
+__global__ __launch_bounds__(ENT) void k_invit(Desc D) {
+  __shared__ double sh[ENT / 64];
+  const int64_t n = D.n, l = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double ctol = D.tsc[4], tn = D.tsc[2];
+  const double *om = D.omega;
+  int64_t i = l;
+  while (i > 0 && om[i] - om[i - 1] <= ctol) --i;
+  const int64_t m = l - i;  // member index of l in its cluster
+  double *scr = D.scr + size_t(l) * (4 + CMAX) * n;
+  double *dd = scr, *du = scr + n, *du2 = scr + 2 * n, *dl = scr + 3 * n;
+  double *mem = scr + 4 * n;  // [CMAX][n] vectors of the members so far
+  double *z = D.Z + size_t(l) * n;
+  if (m >= CMAX) {  // cluster too large to refine: mark, omega[l] stays
+    for (int64_t k = tid; k < n; k += ENT) z[k] = __builtin_nan("");
+    return;
+  }
+  const double tiny = 2.2e-16 * fmax(1.0, tn);
+  for (int64_t q = 0; q <= m; ++q) {
+    double *v = mem + q * n;
+    const double sigma = om[i + q];
+    for (int64_t k = tid; k < n; k += ENT) v[k] = 1.0 + 0.5 * sin(0.7 * double(k + 1) * double(q + 1));
+    __syncthreads();
+    double *piv = z;  // interchange markers (z is written at the end)
+    if (tid == 0) tri_solve(n, D.d, D.e, sigma, tiny, dd, du, du2, dl, piv);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      if (tid == 0) tri_apply(n, dd, du, du2, dl, piv, v);
+      __syncthreads();
+      // orthogonalise against the earlier members (modified Gram-Schmidt), normalise
+      for (int64_t p = 0; p < q; ++p) {
+        const double *u = mem + p * n;
+        double dot = 0;
+        for (int64_t k = tid; k < n; k += ENT) dot += u[k] * v[k];
+        dot = block_sum<ENT>(dot, sh);
+        for (int64_t k = tid; k < n; k += ENT) v[k] -= dot * u[k];
+        __syncthreads();
+      }
+      double s2 = 0;
+      for (int64_t k = tid; k < n; k += ENT) s2 += v[k] * v[k];
+      s2 = block_sum<ENT>(s2, sh);
+      const double inv = s2 > 0 ? 1.0 / sqrt(s2) : 0.0;
+      for (int64_t k = tid; k < n; k += ENT) v[k] *= inv;
+      __syncthreads();
+    }
+  }
+  const double *v = mem + m * n;
+  for (int64_t k = tid; k < n; k += ENT) z[k] = v[k];
+}
+
+__global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
+  __shared__ double sh[ENT / 64];
+  const int64_t n = D.n, l = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double *z = D.Z + size_t(l) * n;
+  double2 *x = D.X + size_t(l) * n;
+  for (int64_t k = tid; k < n; k += ENT) x[k] = double2{z[k], 0.0};
+  __syncthreads();
+  for (int64_t jn = n - 2; jn >= -1; --jn) {
+    // jn >= 0: reflector of column jn (rows jn+1 ..), jn = -1: the initial reflection
+    const double2 *v = jn >= 0 ? D.Vall + size_t(jn) * D.ldv : D.vbuf;
+    const int64_t r0 = jn + 1;
+    const double2 t = D.tau[jn + 1];
+    double sr = 0, si = 0;
+    for (int64_t r = r0 + tid; r < n; r += ENT) {
+      const double2 c = cmulc(v[r], x[r]);
+      sr += c.x;
+      si += c.y;
+    }
+    sr = block_sum<ENT>(sr, sh);
+    si = block_sum<ENT>(si, sh);
+    const double2 f = cmul(t, double2{sr, si});
+    for (int64_t r = r0 + tid; r < n; r += ENT) x[r] = csub(x[r], cmul(f, v[r]));
+    __syncthreads();
+  }
+}
+
+// partial sums over 4 rows per workgroup (one wave per row): grid (cdiv(n, 4), K)
+template <typename TH>
+__global__ __launch_bounds__(ENT) void k_hx_part(Desc D) {
+  typedef typename C2T<TH>::t CH;
+  __shared__ double sh[ENT / 64];
+  const int64_t n = D.n, l = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t r = int64_t(blockIdx.x) * 4 + wv;
+  const double2 *x = D.X + size_t(l) * n;
+  double num = 0, den = 0;
+  if (r < n) {
+    const CH *h = reinterpret_cast<const CH *>(D.H) + r * D.ld;
+    double yr = 0, yi = 0;
+    for (int64_t c = lane; c < n; c += 64) {
+      const double2 a = to_d2(h[c]), b = x[c];
+      yr += a.x * b.x - a.y * b.y;
+      yi += a.x * b.y + a.y * b.x;
+    }
+    yr = wave_sum(yr);
+    yi = wave_sum(yi);
+    const double2 xr = x[r];
+    num = xr.x * yr + xr.y * yi;  // Re(conj(x_r) y_r)
+    den = xr.x * xr.x + xr.y * xr.y;
+  }
+  if (lane != 0) num = den = 0;
+  num = block_sum<ENT>(num, sh);
+  den = block_sum<ENT>(den, sh);
+  if (tid == 0) {
+    double *p = D.rqp + (size_t(l) * size_t(cdiv(n, 4)) + blockIdx.x) * 2;
+    p[0] = num;
+    p[1] = den;
+  }
+}
+
+// one workgroup: reduce the partial quotients, write the refined values in
+// ascending order and re-centre the poles of refined clusters
+__global__ __launch_bounds__(ENT) void k_rq_fin(Desc D) {
+  __shared__ double sh[ENT / 64];
+  __shared__ double th[KMAX];
+  const int64_t n = D.n, K = D.K, nw = cdiv(n, 4);
+  const int tid = threadIdx.x;
+  for (int64_t l = 0; l < K; ++l) {
+    double num = 0, den = 0;
+    for (int64_t p = tid; p < nw; p += ENT) {
+      num += D.rqp[(size_t(l) * nw + p) * 2];
+      den += D.rqp[(size_t(l) * nw + p) * 2 + 1];
+    }
+    num = block_sum<ENT>(num, sh);
+    den = block_sum<ENT>(den, sh);
+    if (tid == 0) th[l] = (den > 0 && num == num) ? num / den : D.omega[l];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int64_t a = 1; a < K; ++a) {  // insertion sort (K <= KMAX)
+      const double v = th[a];
+      int64_t b = a - 1;
+      while (b >= 0 && th[b] > v) {
+        th[b + 1] = th[b];
+        --b;
+      }
+      th[b + 1] = v;
+    }
+    const double ctol = D.tsc[4];
+    // clusters of the unrefined values: heads carry the pole
+    int64_t i = 0;
+    while (i < K) {
+      int64_t j = i;
+      while (j + 1 < n && D.omega[j + 1] - D.omega[j] <= ctol) ++j;
+      if (j < K) {
+        double s = 0;
+        for (int64_t q = i; q <= j; ++q) s += th[q];
+        D.pole[i] = s / double(j - i + 1);
+        for (int64_t q = i + 1; q <= j; ++q) D.pole[q] = th[q];
+      }
+      i = j + 1;
+    }
+    for (int64_t l = 0; l < K; ++l) {
+      D.wref[l] = th[l];
+      D.omega[l] = th[l];
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1020,9 +1273,9 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
 // ---------------------------------------------------------------------------
 template <typename TH, typename TA>
 int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
-                 double *pole, double *osc, void *ws, hipStream_t s) {
+                 double *pole, double *osc, void *ws, hipStream_t s, int64_t K) {
   Desc D;
-  ws_layout(n, sizeof(TA) == 8, &D, (char *)ws);
+  ws_layout(n, sizeof(TA) == 8, &D, (char *)ws, K);
   D.H = Hmu;
   D.ld = ld;
   D.B = (const double2 *)Bmu;
@@ -1041,8 +1294,10 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
   BSE_HIP_CHECK(hipGetLastError());
   // ---- blocked tridiagonalisation, two kernels per column ----
   int cur = 0;  // partial-sum record buffer written last
+  const Desc D0 = D;
   for (int64_t j0 = 0; j0 < n; j0 += NBK) {
     const int nbk = g_nbk(n, j0);
+    if (K > 0) D.V = D0.Vall + j0 * D0.ldv;  // keep every reflector for the back-transform
     BSE_LAUNCH("k_col0", (k_col0<TH, TA, 4>), grid(K_COL0, j0, 4), dim3(ENT), 0, s, D, j0, cur);
     for (int i = 0; i < nbk; ++i) {
       const int64_t jn = j0 + i, m = n - jn - 1;
@@ -1073,6 +1328,15 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
   BSE_LAUNCH("k_bisect", (k_bisect<TH, TA, 4>), grid(K_BISECT, 0, 4), dim3(ENT), 0, s, D, 0);
   BSE_LAUNCH("k_weights", (k_weights<TH, TA, 4>), grid(K_WEIGHTS, 0, 4), dim3(ENT), 0, s, D, 0);
   BSE_HIP_CHECK(hipGetLastError());
+  if (K > 0) {
+    D = D0;
+    BSE_LAUNCH("k_invit", k_invit, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    BSE_LAUNCH("k_backxf", k_backxf, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, 4), (unsigned)K), dim3(ENT), 0,
+               s, D);
+    BSE_LAUNCH("k_rq_fin", k_rq_fin, dim3(1), dim3(ENT), 0, s, D);
+    BSE_HIP_CHECK(hipGetLastError());
+  }
   return BSE_OK;
 }
 
@@ -1209,9 +1473,8 @@ using namespace bse;
 
 extern "C" size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int32_t nrefine) {
   (void)h_fp64;
-  (void)nrefine;
-  if (n < 1) return 0;
-  return ws_layout(n, prec == BSE_FP64, nullptr, nullptr);
+  if (n < 1 || nrefine < 0 || nrefine > KMAX) return 0;
+  return ws_layout(n, prec == BSE_FP64, nullptr, nullptr, std::min<int64_t>(nrefine, n));
 }
 
 extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64,
@@ -1223,16 +1486,18 @@ extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_
   if (!Hmu || !Bmu || !omega || !pole || !osc) return fail(BSE_EINVAL, "NULL pointer");
   if (ld < n) return fail(BSE_ESHAPE, "ld < n");
   if (prec != BSE_FP64 && prec != BSE_FP32) return fail(BSE_EINVAL, "unsupported precision");
-  if (nrefine != 0) return fail(BSE_EUNSUPPORTED, "refinement is not implemented yet");
-  const size_t need = ws_layout(n, prec == BSE_FP64, nullptr, nullptr);
+  if (nrefine < 0 || nrefine > KMAX)
+    return fail(BSE_EINVAL, "nrefine = %d outside 0 .. %d", nrefine, KMAX);
+  const int64_t K = std::min<int64_t>(nrefine, n);
+  const size_t need = ws_layout(n, prec == BSE_FP64, nullptr, nullptr, K);
   if (!ws || ws_bytes < need)
     return fail(BSE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t s = (hipStream_t)stream;
   if (prec == BSE_FP64)
-    return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
-                  : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
-  return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
-                : eigh_run<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
+    return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
+                  : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
+  return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
+                : eigh_run<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
 }
 
 // ---------------------------------------------------------------------------

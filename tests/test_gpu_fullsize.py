@@ -60,19 +60,22 @@ def _match_cumulative(pole, osc, ce, cw, tol, wtol):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("precname,tol,wtol", [("FP32", 1e-5, 1e-3), ("FP64", 1e-9, 1e-6),
-                                                ("BF16X3", 1e-4, 1e-3)])
-def test_cfg2_end_to_end(lib, precname, tol, wtol):
+@pytest.mark.parametrize("precname,tol,wtol,nref", [("FP32", 1e-5, 1e-3, 0),
+                                                     ("FP64", 1e-9, 1e-6, 0),
+                                                     ("BF16X3", 1e-4, 1e-3, 0),
+                                                     ("FP32", 1e-5, 1e-3, 100),
+                                                     ("BF16X3", 1e-4, 1e-3, 100)])
+def test_cfg2_end_to_end(lib, precname, tol, wtol, nref):
     import workloads
     from paper_2603_24860_amd.system import Solver
     ref = json.load(open(GOLD))
     cfg = synth.config("cfg2")
-    say("cfg2 e2e", precname)
+    say("cfg2 e2e", precname, "nrefine", nref)
     S = workloads.device_system(cfg, getattr(lib, precname))
     act, _ = S.active_irrep()
     assert act == ref["irrep"]
     wgrid = np.linspace(ref["wmin"], ref["wmax"], ref["nw"])
-    sv = Solver(S, act, wgrid=wgrid)
+    sv = Solver(S, act, wgrid=wgrid, nrefine=nref)
     assert sv.blk.n == ref["n"]
     sv.step()
     res = sv.results()

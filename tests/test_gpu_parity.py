@@ -229,6 +229,40 @@ def test_eigh_known_spectrum_fp32(lib, n, mult):
     assert np.abs(om - np.sort(lam)).max() < 2e-5
 
 
+@pytest.mark.parametrize("n,mult,K", [(64, 1, 20), (162, 3, 100), (257, 1, 100),
+                                       (600, 3, 100), (1, 1, 5)])
+def test_eigh_refinement(lib, n, mult, K):
+    """FP32 working storage with FP64 refinement of the lowest K against an
+    FP64 H_mu: the refined values reach FP64 accuracy (the rounding of the
+    FP32 tridiagonalisation is removed), the rest of the spectrum is the
+    unrefined one, and the oscillator strengths are unchanged."""
+    say("eigh-refine", n, mult, K)
+    A, b, lam, Q = _random_hermitian(n, seed=3 * n + mult, mult=mult)
+    Hmu = torch.as_tensor(A, dtype=torch.complex128, device="cuda")
+    Bmu = torch.as_tensor(b, dtype=torch.complex128, device="cuda")
+    outs = []
+    for nref in (0, K):
+        ws = torch.empty(lib.bse_block_eigh_ws(n, 1, lib.FP32, nref), dtype=torch.uint8,
+                         device="cuda")
+        om = torch.empty(n, dtype=torch.float64, device="cuda")
+        po, os_ = torch.empty_like(om), torch.empty_like(om)
+        lib.bse_block_eigh(Hmu, Bmu, lib.FP32, om, po, os_, ws, nrefine=nref)
+        torch.cuda.synchronize()
+        outs.append((om.cpu().numpy(), po.cpu().numpy(), os_.cpu().numpy()))
+    (o0, p0, s0), (o1, p1, s1) = outs
+    k = min(K, n)
+    ex = np.sort(lam)
+    e0 = np.abs(o0[:k] - ex[:k]).max()
+    e1 = np.abs(o1[:k] - ex[:k]).max()
+    say("  lowest", k, "error unrefined", e0, "refined", e1)
+    # Rayleigh quotients are exact to (delta^2 |H|), delta ~ eps32 |H| / gap
+    # (gaps ~ 0.1 here): about 1e-9 |H| at worst, against ~1e-7 |H| unrefined
+    assert e1 < 1e-9 * max(1.0, np.abs(lam).max())
+    assert e1 <= e0 / 100 or e0 < 1e-12
+    assert np.array_equal(o0[k:], o1[k:])
+    assert np.array_equal(s0, s1)
+
+
 def test_eigh_degenerate_inputs(lib):
     say("eigh-degenerate")
     n = 40
