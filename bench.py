@@ -306,6 +306,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit: "
                          "the reference for scaling HBM byte counters")
+    ap.add_argument("--partner", action="store_true",
+                    help="solve the x-partner block of the dipole-active vector irrep (1/d of "
+                         "the isotypic block, the same eps2) instead of the isotypic block")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel (adds event records; breakdown on stderr)")
     args = ap.parse_args()
@@ -339,8 +342,9 @@ def main():
     t0 = time.perf_counter()
     S = workloads.device_system(cfg, prec)
     irrep, weights = S.active_irrep()
-    sv = Solver(S, irrep)
-    log(f"setup {time.perf_counter() - t0:.1f} s; N = {S.N}, block {irrep} n = {sv.blk.n}")
+    sv = Solver(S, irrep, partner=0 if args.partner else None)
+    log(f"setup {time.perf_counter() - t0:.1f} s; N = {S.N}, block {irrep}"
+        f"{' x-partner' if args.partner else ''} n = {sv.blk.n}")
     # frequency grid from the block spectrum (first solve, untimed)
     sv.step()
     torch.cuda.synchronize()
@@ -400,7 +404,9 @@ def main():
         "data": "synthetic (seeded; paper-shaped Oh system, random-phase pair vectors)",
         "config": {"workload": f"{cfg['name']}: Oh {cfg['grid'][0]}x{cfg['grid'][1]}x"
                                f"{cfg['grid'][2]} k grid ({nk} k), Nv={nv}, Nc={nc}, N={S.N}, "
-                               f"Nmb={nmb}, dipole-active {irrep} block n={sv.blk.n}, dense-mode "
+                               f"Nmb={nmb}, dipole-active {irrep}"
+                               f"{' x-partner' if args.partner else ''} block n={sv.blk.n}, "
+                               f"dense-mode "
                                f"build of all {nk * nk} k pairs",
                    "precision": args.prec},
         "block_eigh_s": round(st_ms[2] * 1e-3, 6),

@@ -135,6 +135,23 @@ int32_t bse_block_basis(int32_t group, const int32_t *h_grid3, int32_t irrep, in
                         int64_t *h_orb_off, int32_t *h_orb_dim, int64_t *h_ub_off,
                         double *h_ubasis);
 
+/* Partner-resolved block of a vector irrep (T1u of Oh; E1u and A2u of D6h):
+ * the projector P_pp = d_mu/|S| sum_s Gamma_mu(s)_pp Gamma(s) onto one row p
+ * of the irrep, whose matrices for a vector irrep are the Cartesian rotation
+ * matrices R_s themselves (p = 0, 1, 2 for x, y, z of T1u; 0, 1 for x, y of
+ * E1u; 0 for z of A2u).  The block has 1/d_mu of the isotypic block's
+ * dimension and every eigenvalue of the isotypic block once instead of d_mu
+ * times (partner functions are degenerate); a dipole polarised along
+ * Cartesian axis i lies entirely in the block of the row along i.  Same
+ * output layout as bse_block_basis; other irreps: BSE_EUNSUPPORTED. */
+int32_t bse_partner_block_dims_get(int32_t group, const int32_t *h_grid3, int32_t irrep,
+                                   int32_t partner, int32_t nv, int32_t nc,
+                                   bse_block_dims *h_out);
+int32_t bse_partner_block_basis(int32_t group, const int32_t *h_grid3, int32_t irrep,
+                                int32_t partner, int32_t nv, int32_t nc, int32_t *h_mem_off,
+                                int32_t *h_members, int64_t *h_orb_off, int32_t *h_orb_dim,
+                                int64_t *h_ub_off, double *h_ubasis);
+
 /* ---------------------------------------------------------------------------
  * bse_build: H (N x N, N = nk nv nc) from orbit-compressed inputs.
  * Dense mode: every (k, k') pair is contracted (the kernels never assume that

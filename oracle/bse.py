@@ -194,6 +194,53 @@ def isotypic_basis(P, irrep_name):
                 orb_dim=np.array(dims, dtype=np.int64), basis=basis)
 
 
+# ----------------------------------------------------------------------------
+# partner-resolved blocks of a vector irrep (a step beyond the paper, which uses
+# characters only): for T1u of Oh and E1u, A2u of D6h the irrep matrices are
+# the Cartesian rotation matrices R_s, so the projector onto row p is
+#   P_pp = d/|S| sum_s (R_s)_{ii} Gamma(s),  i = the Cartesian axis of row p
+# ----------------------------------------------------------------------------
+VECTOR_ROWS = {"T1u": (0, 1, 2), "E1u": (0, 1), "A2u": (2,)}
+
+
+def partner_weights(P, irrep_name, p):
+    axis = VECTOR_ROWS[irrep_name][p]
+    return P["group"]["rcart"][:, axis, axis]
+
+
+def partner_basis(P, irrep_name, p):
+    """Per-orbit orthonormal bases of the range of P_pp (same layout as
+    isotypic_basis, orb_dim[O] = m_mu(O))."""
+    d, _ = groups.irrep(P["group"], irrep_name)
+    w = partner_weights(P, irrep_name, p)
+    nb = P["nv"] * P["nc"]
+    offs, dims, basis = [], [], []
+    off = 0
+    for members in orbit_members(P):
+        Pm = orbit_projector(P, w, d, members)
+        u, s, _ = np.linalg.svd(Pm)
+        r = int(np.sum(s > 0.5))
+        offs.append(off)
+        dims.append(r)
+        basis.append((members, u[:, :r]))
+        off += r * nb
+    return dict(irrep=irrep_name, d=d, n=off, orb_off=np.array(offs, dtype=np.int64),
+                orb_dim=np.array(dims, dtype=np.int64), basis=basis)
+
+
+def full_partner_projector(P, irrep_name, p):
+    """Dense P_pp on the whole product space (small systems only)."""
+    d, _ = groups.irrep(P["group"], irrep_name)
+    w = partner_weights(P, irrep_name, p)
+    kp = P["T"]["kperm"]
+    nb = P["nv"] * P["nc"]
+    Pm = np.zeros((P["N"], P["N"]))
+    for s in range(kp.shape[0]):
+        for k in range(P["nk"]):
+            Pm[kp[s, k] * nb + np.arange(nb), k * nb + np.arange(nb)] += w[s]
+    return Pm * (d / kp.shape[0])
+
+
 def basis_matrix(P, blk):
     """Dense U_mu (N x n_mu) with the canonical block layout."""
     nv, nc = P["nv"], P["nc"]

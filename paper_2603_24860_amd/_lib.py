@@ -72,6 +72,8 @@ def _load():
         "bse_tables_build": (i32, [i32, vp, P(Tables)]),
         "bse_block_dims_get": (i32, [i32, vp, i32, i32, i32, P(BlockDims)]),
         "bse_block_basis": (i32, [i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "bse_partner_block_dims_get": (i32, [i32, vp, i32, i32, i32, i32, P(BlockDims)]),
+        "bse_partner_block_basis": (i32, [i32, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "bse_build_ws": (ctypes.c_size_t, [P(Problem), i32]),
         "bse_build_ws_min": (ctypes.c_size_t, [P(Problem), i32]),
         "bse_build": (i32, [P(Problem), i32, vp, i64, vp, ctypes.c_size_t, vp]),

@@ -94,19 +94,28 @@ def bse_tables_build(group, grid):
     return t
 
 
-def bse_block_basis(group, grid, irrep, nv, nc):
+def bse_block_basis(group, grid, irrep, nv, nc, partner=None):
+    """Isotypic block basis of `irrep`, or (partner = p) the partner-resolved
+    basis of row p of a vector irrep."""
     g = _grid(grid)
     gid = _gid(group)
     ir = irrep_index(group, irrep) if isinstance(irrep, str) else int(irrep)
     bd = _lib.BlockDims()
-    check(lib.bse_block_dims_get(gid, _ptr(g), ir, nv, nc, ctypes.byref(bd)))
+    if partner is None:
+        check(lib.bse_block_dims_get(gid, _ptr(g), ir, nv, nc, ctypes.byref(bd)))
+    else:
+        check(lib.bse_partner_block_dims_get(gid, _ptr(g), ir, int(partner), nv, nc,
+                                             ctypes.byref(bd)))
     nkorb = bse_dims_get(group, grid)["nkorb"]
     out = dict(n=bd.n, mem_off=np.zeros(nkorb + 1, np.int32), members=np.zeros(bd.nmem, np.int32),
                orb_off=np.zeros(nkorb, np.int64), orb_dim=np.zeros(nkorb, np.int32),
                ub_off=np.zeros(nkorb + 1, np.int64), ubasis=np.zeros(max(bd.nub, 1), np.float64))
-    check(lib.bse_block_basis(gid, _ptr(g), ir, nv, nc, _ptr(out["mem_off"]), _ptr(out["members"]),
-                              _ptr(out["orb_off"]), _ptr(out["orb_dim"]), _ptr(out["ub_off"]),
-                              _ptr(out["ubasis"])))
+    args = [_ptr(out["mem_off"]), _ptr(out["members"]), _ptr(out["orb_off"]),
+            _ptr(out["orb_dim"]), _ptr(out["ub_off"]), _ptr(out["ubasis"])]
+    if partner is None:
+        check(lib.bse_block_basis(gid, _ptr(g), ir, nv, nc, *args))
+    else:
+        check(lib.bse_partner_block_basis(gid, _ptr(g), ir, int(partner), nv, nc, *args))
     return out
 
 

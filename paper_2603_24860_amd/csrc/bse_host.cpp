@@ -290,10 +290,66 @@ struct BlockBasis {
   std::vector<double> ub;
 };
 
+// Cartesian rows spanned by a vector irrep: its characters are the trace of
+// an invariant sub-block of the rotation matrices (T1u of Oh: x, y, z; E1u of
+// D6h: x, y; A2u of D6h: z).  Returns false for the other irreps.
+static bool vector_rows(const Group *g, int irrep, std::vector<int> &rows) {
+  const Group::Irrep &ir = g->irreps[irrep];
+  const int sets[7][3] = {{0, 1, 2}, {0, 1, -1}, {0, 2, -1}, {1, 2, -1},
+                          {0, -1, -1}, {1, -1, -1}, {2, -1, -1}};
+  for (const auto &st : sets) {
+    std::vector<int> S;
+    for (int i = 0; i < 3; ++i)
+      if (st[i] >= 0) S.push_back(st[i]);
+    if (int(S.size()) != ir.dim) continue;
+    bool ok = true;
+    for (int s = 0; s < g->nops && ok; ++s) {
+      const double *R = &g->rcart[size_t(s) * 9];
+      double tr = 0;
+      for (int i : S) tr += R[i * 3 + i];
+      if (std::fabs(tr - ir.chi[s]) > 1e-12) ok = false;
+      for (int i : S)  // invariance: no coupling to rows outside S
+        for (int j = 0; j < 3 && ok; ++j)
+          if (std::find(S.begin(), S.end(), j) == S.end() && std::fabs(R[i * 3 + j]) > 1e-12)
+            ok = false;
+    }
+    if (ok) {
+      rows = S;
+      return true;
+    }
+  }
+  return false;
+}
+
+// weights w[s] of the projector P = d/|G| sum_s w[s] Gamma(s): the characters
+// (isotypic block, Eq. (projection)) or, for partner row p >= 0 of a vector
+// irrep, the diagonal irrep-matrix element Gamma(s)_pp = (R_s)_ii
+static int32_t projector_weights(const Group *g, int irrep, int partner,
+                                 std::vector<double> &w) {
+  if (irrep < 0 || irrep >= int(g->irreps.size())) return fail(BSE_EINVAL, "irrep out of range");
+  const Group::Irrep &ir = g->irreps[irrep];
+  if (partner < 0) {
+    w = ir.chi;
+    return BSE_OK;
+  }
+  std::vector<int> rows;
+  if (!vector_rows(g, irrep, rows))
+    return fail(BSE_EUNSUPPORTED, "partner blocks need a vector irrep (%s is not one)",
+                ir.name.c_str());
+  if (partner >= ir.dim) return fail(BSE_EINVAL, "partner row %d >= dim %d", partner, ir.dim);
+  const int i = rows[partner];
+  w.resize(g->nops);
+  for (int s = 0; s < g->nops; ++s) w[s] = g->rcart[size_t(s) * 9 + i * 3 + i];
+  return BSE_OK;
+}
+
 static int32_t build_basis(const Group *g, const Grid &gr, int irrep, int nv, int nc,
-                           BlockBasis &bb) {
+                           BlockBasis &bb, int partner = -1) {
   if (irrep < 0 || irrep >= int(g->irreps.size())) return fail(BSE_EINVAL, "irrep out of range");
   if (nv < 1 || nc < 1) return fail(BSE_ESHAPE, "nv, nc must be >= 1");
+  std::vector<double> wts;
+  int32_t st = projector_weights(g, irrep, partner, wts);
+  if (st) return st;
   Tables t;
   build_tables(g, gr, t, false);
   const int64_t nk = t.nk;
@@ -318,12 +374,12 @@ static int32_t build_basis(const Group *g, const Grid &gr, int irrep, int nv, in
   for (int o = 0; o < nkorb; ++o) {
     const int L = bb.mem_off[o + 1] - bb.mem_off[o];
     const int32_t *mem = &bb.members[bb.mem_off[o]];
-    // projector restricted to the orbit: P[i][j] = d/|G| sum_s chi(s) [s m_j = m_i]
+    // projector restricted to the orbit: P[i][j] = d/|G| sum_s w(s) [s m_j = m_i]
     std::vector<double> P(size_t(L) * L, 0.0);
     for (int s = 0; s < g->nops; ++s)
       for (int j = 0; j < L; ++j) {
         int32_t img = t.kperm[size_t(s) * nk + mem[j]];
-        P[size_t(pos[img]) * L + j] += ir.chi[s];
+        P[size_t(pos[img]) * L + j] += wts[s];
       }
     double tr = 0;
     for (int i = 0; i < L; ++i) tr += P[size_t(i) * L + i] * scale;
@@ -460,15 +516,16 @@ extern "C" int32_t bse_tables_build(int32_t group, const int32_t *h_grid3, const
   return BSE_OK;
 }
 
-extern "C" int32_t bse_block_dims_get(int32_t group, const int32_t *h_grid3, int32_t irrep,
-                                      int32_t nv, int32_t nc, bse_block_dims *h_out) {
+namespace {
+int32_t dims_impl(int32_t group, const int32_t *h_grid3, int32_t irrep, int32_t partner,
+                  int32_t nv, int32_t nc, bse_block_dims *h_out) {
   const Group *g = get_group(group);
   Grid gr;
   int32_t st = check_grid(g, h_grid3, gr);
   if (st) return st;
   if (!h_out) return fail(BSE_EINVAL, "out is NULL");
   BlockBasis bb;
-  st = build_basis(g, gr, irrep, nv, nc, bb);
+  st = build_basis(g, gr, irrep, nv, nc, bb, partner);
   if (st) return st;
   h_out->n = bb.n;
   h_out->nmem = int32_t(gr.nk());
@@ -476,16 +533,15 @@ extern "C" int32_t bse_block_dims_get(int32_t group, const int32_t *h_grid3, int
   return BSE_OK;
 }
 
-extern "C" int32_t bse_block_basis(int32_t group, const int32_t *h_grid3, int32_t irrep,
-                                   int32_t nv, int32_t nc, int32_t *h_mem_off, int32_t *h_members,
-                                   int64_t *h_orb_off, int32_t *h_orb_dim, int64_t *h_ub_off,
-                                   double *h_ubasis) {
+int32_t basis_impl(int32_t group, const int32_t *h_grid3, int32_t irrep, int32_t partner,
+                   int32_t nv, int32_t nc, int32_t *h_mem_off, int32_t *h_members,
+                   int64_t *h_orb_off, int32_t *h_orb_dim, int64_t *h_ub_off, double *h_ubasis) {
   const Group *g = get_group(group);
   Grid gr;
   int32_t st = check_grid(g, h_grid3, gr);
   if (st) return st;
   BlockBasis bb;
-  st = build_basis(g, gr, irrep, nv, nc, bb);
+  st = build_basis(g, gr, irrep, nv, nc, bb, partner);
   if (st) return st;
   auto cp = [](void *dst, const void *src, size_t bytes) {
     if (dst) std::memcpy(dst, src, bytes);
@@ -497,4 +553,35 @@ extern "C" int32_t bse_block_basis(int32_t group, const int32_t *h_grid3, int32_
   cp(h_ub_off, bb.ub_off.data(), bb.ub_off.size() * 8);
   cp(h_ubasis, bb.ub.data(), bb.ub.size() * 8);
   return BSE_OK;
+}
+}  // namespace
+
+extern "C" int32_t bse_block_dims_get(int32_t group, const int32_t *h_grid3, int32_t irrep,
+                                      int32_t nv, int32_t nc, bse_block_dims *h_out) {
+  return dims_impl(group, h_grid3, irrep, -1, nv, nc, h_out);
+}
+
+extern "C" int32_t bse_block_basis(int32_t group, const int32_t *h_grid3, int32_t irrep,
+                                   int32_t nv, int32_t nc, int32_t *h_mem_off, int32_t *h_members,
+                                   int64_t *h_orb_off, int32_t *h_orb_dim, int64_t *h_ub_off,
+                                   double *h_ubasis) {
+  return basis_impl(group, h_grid3, irrep, -1, nv, nc, h_mem_off, h_members, h_orb_off,
+                    h_orb_dim, h_ub_off, h_ubasis);
+}
+
+extern "C" int32_t bse_partner_block_dims_get(int32_t group, const int32_t *h_grid3,
+                                              int32_t irrep, int32_t partner, int32_t nv,
+                                              int32_t nc, bse_block_dims *h_out) {
+  if (partner < 0) return fail(BSE_EINVAL, "partner row must be >= 0");
+  return dims_impl(group, h_grid3, irrep, partner, nv, nc, h_out);
+}
+
+extern "C" int32_t bse_partner_block_basis(int32_t group, const int32_t *h_grid3, int32_t irrep,
+                                           int32_t partner, int32_t nv, int32_t nc,
+                                           int32_t *h_mem_off, int32_t *h_members,
+                                           int64_t *h_orb_off, int32_t *h_orb_dim,
+                                           int64_t *h_ub_off, double *h_ubasis) {
+  if (partner < 0) return fail(BSE_EINVAL, "partner row must be >= 0");
+  return basis_impl(group, h_grid3, irrep, partner, nv, nc, h_mem_off, h_members, h_orb_off,
+                    h_orb_dim, h_ub_off, h_ubasis);
 }

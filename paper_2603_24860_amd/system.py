@@ -26,9 +26,10 @@ def _dev(a, dtype=None, device="cuda"):
 
 
 class DeviceBlock:
-    def __init__(self, group, grid, irrep, nv, nc, device="cuda"):
-        b = B.bse_block_basis(group, grid, irrep, nv, nc)
+    def __init__(self, group, grid, irrep, nv, nc, device="cuda", partner=None):
+        b = B.bse_block_basis(group, grid, irrep, nv, nc, partner=partner)
         self.irrep = irrep
+        self.partner = partner
         self.n = int(b["n"])
         self.host = b
         self.t = {k: _dev(v, device=device) for k, v in b.items() if k != "n"}
@@ -83,11 +84,12 @@ class DeviceSystem:
         if self.ws is None or self.ws.numel() < want:
             self.ws = torch.empty(want, dtype=torch.uint8, device=self.device)
 
-    def block(self, irrep):
-        if irrep not in self.blocks:
-            self.blocks[irrep] = DeviceBlock(self.group, self.grid, irrep, self.nv, self.nc,
-                                             self.device)
-        return self.blocks[irrep]
+    def block(self, irrep, partner=None):
+        key = irrep if partner is None else (irrep, partner)
+        if key not in self.blocks:
+            self.blocks[key] = DeviceBlock(self.group, self.grid, irrep, self.nv, self.nc,
+                                           self.device, partner=partner)
+        return self.blocks[key]
 
     # -- pieces of the path ----------------------------------------------
     def build(self):
@@ -119,9 +121,13 @@ class DeviceSystem:
 class Solver:
     """Reusable buffers for repeated solves of one block of one system."""
 
-    def __init__(self, system, irrep, eig_prec=None, nrefine=0, wgrid=None, eta=0.05):
+    def __init__(self, system, irrep, eig_prec=None, nrefine=0, wgrid=None, eta=0.05,
+                 partner=None):
+        """partner = p: solve the partner-resolved block of row p of the vector
+        irrep (1/d of the isotypic block, the same optical spectrum for a
+        dipole along that row's axis)."""
         self.s = system
-        self.blk = system.block(irrep)
+        self.blk = system.block(irrep, partner)
         n = self.blk.n
         dev = system.device
         self.eig_prec = system.prec if eig_prec is None else eig_prec

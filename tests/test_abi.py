@@ -140,3 +140,35 @@ def test_batch_eigh_validation():
     assert st == _lib.EWORKSPACE
     assert L.bse_batch_eigh_run(12345, None) == _lib.EINVAL
     assert L.bse_batch_eigh_free(12345) == _lib.EINVAL
+
+
+@pytest.mark.parametrize("cfg,irrep,rows", [
+    (dict(lattice="cubic", grid=(4, 4, 4), nv=2, nc=1), "T1u", 3),
+    (dict(lattice="cubic", grid=(3, 3, 3), nv=1, nc=2), "T1u", 3),
+    (dict(lattice="hex", grid=(6, 6, 1), nv=1, nc=2), "E1u", 2),
+])
+def test_partner_basis_matches_projector(cfg, irrep, rows):
+    """The library's partner-resolved basis: orthonormal, inside the range of
+    the oracle's P_pp, of the oracle's dimensions; a non-vector irrep is refused."""
+    c = dict(cfg, nmb=4, seed=1, name="t")
+    P = OB.make_problem(c)
+    gname = "Oh" if cfg["lattice"] == "cubic" else "D6h"
+    nb = cfg["nv"] * cfg["nc"]
+    for p in range(rows):
+        b = B.bse_block_basis(gname, cfg["grid"], irrep, cfg["nv"], cfg["nc"], partner=p)
+        ob = OB.partner_basis(P, irrep, p)
+        assert b["n"] == ob["n"]
+        assert np.array_equal(b["orb_dim"], ob["orb_dim"])
+        U = np.zeros((P["N"], b["n"]))
+        for o in range(len(b["orb_dim"])):
+            mem = b["members"][b["mem_off"][o]:b["mem_off"][o + 1]]
+            r = b["orb_dim"][o]
+            Uo = b["ubasis"][b["ub_off"][o]:b["ub_off"][o + 1]].reshape(len(mem), r)
+            for j in range(r):
+                for i, k in enumerate(mem):
+                    U[k * nb + np.arange(nb), b["orb_off"][o] + j * nb + np.arange(nb)] = Uo[i, j]
+        Pm = OB.full_partner_projector(P, irrep, p)
+        assert np.abs(U.T @ U - np.eye(b["n"])).max() < 1e-13
+        assert np.abs(Pm @ U - U).max() < 1e-13
+    with pytest.raises(B.BseError):
+        B.bse_block_basis(gname, cfg["grid"], "A1g", cfg["nv"], cfg["nc"], partner=0)

@@ -93,6 +93,34 @@ def test_cfg2_end_to_end(lib, precname, tol, wtol, nref):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precname,tol", [("FP32", 1e-5), ("BF16X3", 1e-4)])
+def test_cfg2_partner_block(lib, precname, tol):
+    """cfg2 x-partner block of T1u (n = 720): each eigenvalue is one of the
+    oracle's degenerate T1u triples; eps2 equals the whole block's."""
+    import workloads
+    from paper_2603_24860_amd.system import Solver
+    ref = json.load(open(GOLD))
+    cfg = synth.config("cfg2")
+    say("cfg2 partner block", precname)
+    S = workloads.device_system(cfg, getattr(lib, precname))
+    wgrid = np.linspace(ref["wmin"], ref["wmax"], ref["nw"])
+    sv = Solver(S, "T1u", wgrid=wgrid, partner=0)
+    assert sv.blk.n * 3 == ref["n"]
+    sv.step()
+    res = sv.results()
+    om = np.asarray(ref["omega"])
+    assert np.abs(om.reshape(-1, 3).max(axis=1) - om.reshape(-1, 3).min(axis=1)).max() < 1e-9
+    err = np.abs(res["omega"] - om[::3]).max()
+    e2 = np.asarray(ref["eps2"])
+    e2err = np.abs(res["eps2"] - e2).max() / np.abs(e2).max()
+    say("  spectrum max err (eV)", err, "eps2 rel err", e2err)
+    assert err < tol
+    assert e2err <= 1e-4
+    del sv, S
+    torch.cuda.empty_cache()
+
+
 def _sample_pairs(P, rng, nrand):
     """(a, b) element indices: corners, the diagonal, k = k', conjugated
     classes and random pairs."""

@@ -346,6 +346,33 @@ def test_end_to_end_cfg1(lib, precname, tol, vector):
                  1e-6 if prec == lib.FP64 else 1e-3)
 
 
+@pytest.mark.parametrize("precname,tol", [("FP64", 1e-9), ("FP32", 1e-5)])
+def test_partner_block_cfg1(lib, precname, tol):
+    """x-partner block of T1u (a third of the block): its eigenvalues are the
+    oracle's partner-block eigenvalues (the T1u spectrum without the triple
+    degeneracy) and it gives the same eps2 as the whole T1u block."""
+    import workloads
+    from paper_2603_24860_amd.system import Solver
+    cfg = synth.config("cfg1")
+    say("partner-cfg1", precname)
+    P = OB.make_problem(cfg)
+    H = OB.hamiltonian(P)
+    r = OB.solve_block(P, "T1u", H)
+    wx = np.linalg.eigvalsh(OB.project(H, OB.basis_matrix(P, OB.partner_basis(P, "T1u", 0))))
+    S = workloads.device_system(cfg, getattr(lib, precname))
+    wgrid = synth.omega_grid_from_range(r["omega"].min(), r["omega"].max())
+    sv = Solver(S, "T1u", wgrid=wgrid, partner=0)
+    assert sv.blk.n * 3 == r["blk"]["n"]
+    sv.step()
+    res = sv.results()
+    err = np.abs(res["omega"] - wx).max()
+    e2 = OB.eps2(r["cl_e"], r["cl_w"], P["nk"], synth.ETA, wgrid)
+    e2err = np.abs(res["eps2"] - e2).max() / np.abs(e2).max()
+    say("  spectrum err", err, "eps2 rel err vs whole T1u", e2err)
+    assert err < tol
+    assert e2err < 1e-4
+
+
 def test_non_interacting_end_to_end(lib):
     """W = v = 0: the block spectrum is E_c - E_v with the Frobenius multiplicities."""
     import workloads

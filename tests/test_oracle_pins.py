@@ -361,3 +361,34 @@ def test_pair_subset_problem_matches_full():
     Ps = bse.make_problem(cfg, pairs=pairs)
     for a, b in ab:
         assert bse.hamiltonian_element(Ps, a, b) == bse.hamiltonian_element(P, a, b)
+
+
+@pytest.mark.parametrize("cfg,irrep,rows", [
+    (dict(lattice="cubic", grid=(4, 4, 4), nv=2, nc=2, nmb=16, seed=9), "T1u", 3),
+    (dict(lattice="hex", grid=(6, 6, 1), nv=2, nc=2, nmb=16, seed=9), "E1u", 2),
+])
+def test_partner_blocks(cfg, irrep, rows):
+    """Partner-resolved blocks of the vector irrep: projector algebra (P_pp
+    idempotent, mutually orthogonal, summing to the isotypic projector), each
+    partner block carries every isotypic eigenvalue once (the d-fold partner
+    degeneracy removed), and an x-polarised equivariant dipole lies entirely in
+    the x block."""
+    cfg = dict(cfg, name="t")
+    P = bse.make_problem(cfg)
+    H = bse.hamiltonian(P)
+    Pmu = bse.full_projector(P, irrep)
+    Pp = [bse.full_partner_projector(P, irrep, p) for p in range(rows)]
+    for p in range(rows):
+        assert np.abs(Pp[p] @ Pp[p] - Pp[p]).max() < 1e-12
+        for q in range(p):
+            assert np.abs(Pp[p] @ Pp[q]).max() < 1e-12
+    assert np.abs(sum(Pp) - Pmu).max() < 1e-12
+    iso = np.linalg.eigvalsh(bse.project(H, bse.basis_matrix(P, bse.isotypic_basis(P, irrep))))
+    nb2 = np.sum(np.abs(P["B"]) ** 2)
+    for p in range(rows):
+        U = bse.basis_matrix(P, bse.partner_basis(P, irrep, p))
+        wp = np.linalg.eigvalsh(bse.project(H, U))
+        assert len(wp) * rows == len(iso)
+        assert np.abs(iso.reshape(-1, rows) - wp[:, None]).max() < 1e-9
+        w = np.sum(np.abs(U.T @ P["B"]) ** 2) / nb2
+        assert abs(w - (1.0 if p == 0 else 0.0)) < 1e-12
