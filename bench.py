@@ -306,6 +306,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit: "
                          "the reference for scaling HBM byte counters")
+    ap.add_argument("--seed", action="store_true",
+                    help="build H by the seed construction (one contraction per pair orbit); "
+                         "TFLOP/s then counts the contractions performed")
     ap.add_argument("--partner", action="store_true",
                     help="solve the x-partner block of the dipole-active vector irrep (1/d of "
                          "the isotypic block, the same eps2) instead of the isotypic block")
@@ -341,6 +344,8 @@ def main():
     cfg = synth.config(args.workload)
     t0 = time.perf_counter()
     S = workloads.device_system(cfg, prec)
+    if args.seed:
+        S.use_seed()
     irrep, weights = S.active_irrep()
     sv = Solver(S, irrep, partner=0 if args.partner else None)
     log(f"setup {time.perf_counter() - t0:.1f} s; N = {S.N}, block {irrep}"
@@ -380,9 +385,13 @@ def main():
     st_ms = stages.mean(axis=0)
     nk, nv, nc, nmb = S.nk, S.nv, S.nc, S.nmb
     s1, s2, ex = build_flops(nk, nv, nc, nmb)
+    if args.seed:  # contractions performed: one pair per pair orbit, one k per k orbit
+        dims = B.bse_dims_get(S.group, S.grid)
+        s1, s2 = s1 * dims["nporb"] / nk ** 2, s2 * dims["nporb"] / nk ** 2
+        ex = ex * (dims["nkorb"] / nk) ** 2
     build_tflops = (s1 + s2 + ex) / (st_ms[0] * 1e-3) / 1e12
     ms_step = wall * 1e3 / args.steps
-    fused = [k for k in ("k_direct_fused", "k_direct_bf3") if k in prof]
+    fused = [k for k in ("k_direct_seed", "k_direct_fused", "k_direct_bf3") if k in prof]
     kname = fused[0] if fused else "k_direct_t"
     kt_ms, kt_n = prof.get(kname, (float("nan"), 0))
     kflops = (s1 + s2) if fused else s1   # flops of the kernel per build
@@ -406,8 +415,8 @@ def main():
                                f"{cfg['grid'][2]} k grid ({nk} k), Nv={nv}, Nc={nc}, N={S.N}, "
                                f"Nmb={nmb}, dipole-active {irrep}"
                                f"{' x-partner' if args.partner else ''} block n={sv.blk.n}, "
-                               f"dense-mode "
-                               f"build of all {nk * nk} k pairs",
+                               + (f"seed build (one contraction per pair orbit)" if args.seed
+                                  else f"dense-mode build of all {nk * nk} k pairs"),
                    "precision": args.prec},
         "block_eigh_s": round(st_ms[2] * 1e-3, 6),
         "solves_per_s": round(1e3 / ms_step, 3),

@@ -185,6 +185,31 @@ int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_t ldh, void
                   size_t ws_bytes, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Seed (symmetry-accelerated) construction of the same H as bse_build
+ * (Sec. III.C.2, Eq. (Wtrafo): pairs (s k, s k') related by an operation share
+ * their interaction elements, and with band-trivial symmetry operations the
+ * rotation of the bands is the identity).  The direct term is contracted only
+ * for one representative pair per pair orbit and the exchange for one k point
+ * per k orbit; a final pass writes every element of H from these pieces.
+ *   bse_seed_ws     workspace bytes (0 on invalid input or unsupported shape)
+ *   bse_seed_plan   builds the orbit tables of (group, p->grid) on the host,
+ *                   the q-grouped work list, and uploads them into ws
+ *                   (synchronises `stream`); *h_plan receives the plan id.  The
+ *                   problem's device arrays must stay valid while the plan is
+ *                   used (the plan keeps a copy of the struct).
+ *   bse_build_seed  writes H (N x N, leading dimension ldh, complex of the
+ *                   plan's precision) on `stream`; kernel launches only.
+ *   bse_seed_free   forgets the plan.
+ * Precision FP32 or FP64; shapes as the fused direct kernel (Nmb = 64 m with
+ * m <= 6, nv <= 4, nc <= 6), else BSE_EUNSUPPORTED.
+ * ------------------------------------------------------------------------- */
+size_t bse_seed_ws(int32_t group, const bse_problem *p, int32_t prec);
+int32_t bse_seed_plan(int32_t group, const bse_problem *p, int32_t prec, void *ws,
+                      size_t ws_bytes, int64_t *h_plan, bse_stream stream);
+int32_t bse_build_seed(int64_t plan, void *H, int64_t ldh, bse_stream stream);
+int32_t bse_seed_free(int64_t plan);
+
+/* ---------------------------------------------------------------------------
  * bse_project_blocks: H_mu = U_mu^T H U_mu and B_mu = U_mu^T B for nblk blocks
  * (Eq. (transformationU) applied irrep-wise).  Per block, Hmu[i] may be NULL
  * (only B_mu wanted) and Bmu[i] may be NULL.

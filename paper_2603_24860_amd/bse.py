@@ -138,6 +138,25 @@ def bse_build(problem, prec, H, ws, stream=None):
                         _stream(stream)))
 
 
+def bse_seed_ws(group, problem, prec):
+    return lib.bse_seed_ws(_gid(group), ctypes.byref(problem), prec)
+
+
+def bse_seed_plan(group, problem, prec, ws, stream=None):
+    plan = ctypes.c_int64()
+    check(lib.bse_seed_plan(_gid(group), ctypes.byref(problem), prec, _ptr(ws),
+                            ws.numel() * ws.element_size(), ctypes.byref(plan), _stream(stream)))
+    return plan.value
+
+
+def bse_build_seed(plan, H, stream=None):
+    check(lib.bse_build_seed(plan, _ptr(H), H.stride(0), _stream(stream)))
+
+
+def bse_seed_free(plan):
+    check(lib.bse_seed_free(plan))
+
+
 def bse_project_blocks(problem, H, B, blocks, Hmu, Bmu, stream=None):
     """blocks: list of _lib.Block; Hmu / Bmu: lists of tensors or None."""
     nb = len(blocks)

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(NT) void k_exchange(int nk, int nv, int nc, int nmb
                                                  const double *__restrict__ vdiag,
                                                  const double *__restrict__ ev,
                                                  const double *__restrict__ ec, T *__restrict__ H,
-                                                 int64_t ldh, double scale) {
+                                                 int64_t ldh, double scale, int diag) {
   constexpr int BM = BuildTile<T>::BM, BN = BuildTile<T>::BN, BK = BuildTile<T>::BK;
   constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32, KC = BK / 2;
   constexpr int NA = (BM / 2) * KC / NT, NB = BN * KC / NT;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NT) void k_exchange(int nk, int nv, int nc, int nmb
         if (aa < N && b < N) {
           double re = scale * double(acc[mi][ni][2 * h]);
           const double im = scale * double(acc[mi][ni][2 * h + 1]);
-          if (aa == b) {
+          if (diag && aa == b) {
             const int k = int(aa / nb), v = int((aa / nc) % nv), c = int(aa % nc);
             re += ec[int64_t(k) * nc + c] - ev[int64_t(k) * nv + v];
           }
@@ -342,7 +342,10 @@ template <int VEC> __device__ __forceinline__ void split_store(double2 x, double
 //            LDS and subtracted from H.  T never leaves the registers.
 // Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48.
 // ---------------------------------------------------------------------------
-template <typename T, int MI, int KC>
+// SEED: the workgroup takes its q and KC k points from a work list (one k per
+// pair-orbit representative, -1 for padding) and writes the blocks D of the
+// representatives to drep[orbit][cc'][vv'] instead of subtracting them from H.
+template <typename T, int MI, int KC, bool SEED>
 __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int nv, int nc,
                                                      const int32_t *__restrict__ qorb,
                                                      const int32_t *__restrict__ pidx,
@@ -350,7 +353,9 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
                                                      const T *__restrict__ mv,
                                                      const T *__restrict__ mc,
                                                      const T *__restrict__ w, T *__restrict__ H,
-                                                     int64_t ldh, double scale) {
+                                                     int64_t ldh, double scale,
+                                                     const int32_t *__restrict__ items,
+                                                     T *__restrict__ drep) {
   constexpr int BK = 16, P = Pitch<T, BK>::value;  // 16-deep slabs: two workgroups per CU
   constexpr int NMB = 64 * MI;             // rows of W handled by the workgroup
   constexpr int NI = 2 * KC;               // column blocks: (k, re/im)
@@ -371,8 +376,11 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nk = n1 * n2 * n3, nvv = nv * nv, ncc = nc * nc;
   const int nmb = NMB;
-  const int q = blockIdx.y;
+  const int32_t *item = SEED ? items + int64_t(blockIdx.x) * (1 + 2 * KC) : nullptr;
+  const int q = SEED ? item[0] : int(blockIdx.y);
   const int k0 = blockIdx.x * KC;
+  auto kof = [&](int kk) { return SEED ? item[1 + kk] : k0 + kk; };
+  auto kok = [&](int k) { return SEED ? k >= 0 : k < nk; };
   const T *wq = w + int64_t(qorb[q]) * nmb * nmb;
   // B-row sources: row = kk * 16 + vv' (re and im rows of one complex row)
   const C2 *brow[NB];
@@ -380,10 +388,10 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int it = tid + NT * u, row = it / BPR, kk = row / 16, vv = row % 16;
-    const int k = k0 + kk;
+    const int k = kof(kk);
     brow[u] = nullptr;
     bsgn[u] = T(1);
-    if (k < nk && vv < nvv) {
+    if (kok(k) && vv < nvv) {
       const int kq = kminus(k, q, n1, n2, n3);
       const int64_t p = int64_t(k) * nk + kq;
       const bool cj = pconj[p] != 0;
@@ -443,14 +451,14 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   C2 *Hc = reinterpret_cast<C2 *>(H);
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk) {
-    const int k = k0 + kk;
+    const int k = kof(kk);
     acc_t dre[NCB], dim[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) dre[cb][j] = dim[cb][j] = T(0);
     int kq = 0;
-    if (k < nk) {
+    if (kok(k)) {
       kq = kminus(k, q, n1, n2, n3);
       const int64_t p = int64_t(k) * nk + kq;
       const bool cj = pconj[p] != 0;
@@ -492,7 +500,7 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
       for (int j = 0; j < 4; ++j)
         red[(wv * NCB * 16 + 16 * cb + 4 * g + j) * 16 + r16] = C2{dre[cb][j], dim[cb][j]};
     __syncthreads();
-    if (k < nk) {
+    if (kok(k)) {
       for (int e = tid; e < ncc * nvv; e += NT) {
         const int cc = e / nvv, vv = e % nvv;
         C2 sum = {T(0), T(0)};
@@ -501,6 +509,10 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
           const C2 x = red[(w4 * NCB * 16 + cc) * 16 + vv];
           sum.x += x.x;
           sum.y += x.y;
+        }
+        if (SEED) {
+          reinterpret_cast<C2 *>(drep)[int64_t(item[1 + KC + kk]) * ncc * nvv + e] = sum;
+          continue;
         }
         const int c = cc / nc, c2 = cc % nc, v = vv / nv, v2 = vv % nv;
         const int64_t a = (int64_t(k) * nv + v) * nc + c;
@@ -515,15 +527,16 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   }
 }
 
-template <typename T, int KC>
+template <typename T, int KC, bool SEED = false>
 int32_t launch_fused(int MI, dim3 g, hipStream_t s, const bse_problem *p, void *H, int64_t ldh,
-                     double scale) {
+                     double scale, const int32_t *items = nullptr, void *drep = nullptr) {
 #define BSE_FUSED_CASE(M)                                                                     \
   case M:                                                                                   \
-    BSE_LAUNCH("k_direct_fused", (k_direct_fused<T, M, KC>), g, dim3(NT), 0, s,                \
-               p->grid[0],                                                                  \
+    BSE_LAUNCH(SEED ? "k_direct_seed" : "k_direct_fused", (k_direct_fused<T, M, KC, SEED>),   \
+               g, dim3(NT), 0, s, p->grid[0],                                               \
                p->grid[1], p->grid[2], p->nv, p->nc, p->qorb, p->pidx, p->pconj,             \
-               (const T *)p->mv, (const T *)p->mc, (const T *)p->w, (T *)H, ldh, scale);    \
+               (const T *)p->mv, (const T *)p->mc, (const T *)p->w, (T *)H, ldh, scale,     \
+               items, (T *)drep);                                                          \
     break;
   switch (MI) {
     BSE_FUSED_CASE(1)
@@ -538,6 +551,41 @@ int32_t launch_fused(int MI, dim3 g, hipStream_t s, const bse_problem *p, void *
 #undef BSE_FUSED_CASE
   BSE_HIP_CHECK(hipGetLastError());
   return BSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// seed-mode assembly: every H element from the per-orbit pieces
+//   H[(k v c),(k' v' c')] = X[(o(k) v c),(o(k') v' c')] + delta (E_c - E_v)
+//                           - scale D[porb(k,k')][(c c')][(v v')]
+// X: exchange between k-orbit representatives, D: direct blocks of the
+// pair-orbit representatives.  One row per workgroup row, columns coalesced.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_seed_assemble(int nk, int nv, int nc,
+                                                      const int32_t *__restrict__ korb,
+                                                      const int32_t *__restrict__ porb,
+                                                      const double *__restrict__ ev,
+                                                      const double *__restrict__ ec,
+                                                      const T *__restrict__ xs, int64_t ldx,
+                                                      const T *__restrict__ drep,
+                                                      T *__restrict__ H, int64_t ldh,
+                                                      double scale) {
+  typedef typename Cplx<T>::type C2;
+  const int nb = nv * nc, ncc = nc * nc, nvv = nv * nv;
+  const int64_t N = int64_t(nk) * nb;
+  const int64_t nbx = (N + NT - 1) / NT;  // workgroups per row
+  const int64_t a = int64_t(blockIdx.x) / nbx;
+  const int64_t b = (int64_t(blockIdx.x) % nbx) * NT + threadIdx.x;
+  if (b >= N) return;
+  const int k = int(a / nb), ia = int(a % nb), v = ia / nc, c = ia % nc;
+  const int k2 = int(b / nb), ib = int(b % nb), v2 = ib / nc, c2 = ib % nc;
+  const C2 x = reinterpret_cast<const C2 *>(xs)[(int64_t(korb[k]) * nb + ia) * ldx +
+                                                int64_t(korb[k2]) * nb + ib];
+  const int64_t o = porb[int64_t(k) * nk + k2];
+  const C2 d = reinterpret_cast<const C2 *>(drep)[(o * ncc + c * nc + c2) * nvv + v * nv + v2];
+  double re = double(x.x) - scale * double(d.x), im = double(x.y) - scale * double(d.y);
+  if (a == b) re += ec[int64_t(k) * nc + c] - ev[int64_t(k) * nv + v];
+  reinterpret_cast<C2 *>(H)[a * ldh + b] = C2{T(re), T(im)};
 }
 
 bool fused_ok(const bse_problem *p) { return fused_shape(p->nmb, p->nv, p->nc); }
@@ -614,7 +662,7 @@ extern "C" int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_
     dim3 gx((unsigned)((N + BN - 1) / BN), (unsigned)((2 * N + BM - 1) / BM));
     if (gx.y > 65535u) return fail(BSE_ESHAPE, "N too large for the exchange grid");
     BSE_LAUNCH("k_exchange", k_exchange<T>, gx, dim3(NT), 0, s, nk, p->nv, p->nc, p->nmb, p->korb,
-                       (const T *)p->mx, p->vdiag, p->ev, p->ec, (T *)H, ldh, 2.0 * inv_nk);
+                       (const T *)p->mx, p->vdiag, p->ev, p->ec, (T *)H, ldh, 2.0 * inv_nk, 1);
     BSE_HIP_CHECK(hipGetLastError());
     if (fused) {
       constexpr int KC = 2;  // k points per workgroup
@@ -637,4 +685,197 @@ extern "C" int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_
   };
   if (prec == BSE_FP64) return launch(double(0));
   return launch(float(0));
+}
+
+// ===========================================================================
+// seed (symmetry-accelerated) construction: the direct term is contracted for
+// one representative pair per pair orbit (Sec. III.C.2: pairs related by an
+// operation share their interaction elements), the exchange for one k point
+// per k orbit, and H is assembled from these pieces.
+// ===========================================================================
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace bse {
+namespace {
+constexpr int SEED_KC = 2;
+
+struct SeedPlan {
+  bse_problem p{};
+  int32_t prec = 0;
+  int nk = 0, nkorb = 0, nporb = 0, nitems = 0;
+  int32_t *items = nullptr, *porb = nullptr, *ident = nullptr;
+  void *xs = nullptr, *drep = nullptr;
+  int64_t ldx = 0;
+};
+std::mutex g_seed_mu;
+std::map<int64_t, SeedPlan> g_seeds;
+int64_t g_seed_next = 1;
+
+struct SeedLayout {
+  size_t items, porb, ident, xs, drep, total;
+};
+
+SeedLayout seed_layout(const bse_problem *p, int32_t prec, int nkorb, int nporb, int nitems) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t el = prec == BSE_FP64 ? 16 : 8;
+  const size_t nk = size_t(p->grid[0]) * p->grid[1] * p->grid[2];
+  const size_t nb = size_t(p->nv) * p->nc;
+  SeedLayout L;
+  size_t off = 0;
+  L.items = off;
+  off += al(size_t(nitems) * (1 + 2 * SEED_KC) * 4);
+  L.porb = off;
+  off += al(nk * nk * 4);
+  L.ident = off;
+  off += al(size_t(nkorb) * 4);
+  L.xs = off;
+  off += al(size_t(nkorb) * nb * nkorb * nb * el);
+  L.drep = off;
+  off += al(size_t(nporb) * p->nc * p->nc * p->nv * p->nv * el);
+  L.total = off;
+  return L;
+}
+
+// tables of (group, grid) through the library's own host builder
+int32_t seed_tables(int32_t group, const bse_problem *p, std::vector<int32_t> &porb,
+                    std::vector<int32_t> &porb_rep, std::vector<int32_t> &korb, int &nkorb) {
+  bse_dims d;
+  int32_t st = bse_dims_get(group, p->grid, &d);
+  if (st) return st;
+  std::vector<int32_t> kperm(size_t(d.nops) * d.nk), krep(d.nkorb), pidx(size_t(d.nk) * d.nk),
+      crep(d.ncls);
+  std::vector<uint8_t> pconj(size_t(d.nk) * d.nk), css(d.ncls);
+  porb.assign(size_t(d.nk) * d.nk, 0);
+  porb_rep.assign(d.nporb, 0);
+  korb.assign(d.nk, 0);
+  bse_tables t{kperm.data(), korb.data(), krep.data(), porb.data(), porb_rep.data(),
+               pidx.data(), pconj.data(), crep.data(), css.data()};
+  st = bse_tables_build(group, p->grid, &t);
+  nkorb = d.nkorb;
+  return st;
+}
+
+// work list: representatives grouped by q, KC per item
+void seed_items(const bse_problem *p, const std::vector<int32_t> &porb_rep,
+                std::vector<int32_t> &items) {
+  const int n1 = p->grid[0], n2 = p->grid[1], n3 = p->grid[2], nk = n1 * n2 * n3;
+  std::vector<std::vector<int>> byq(nk);
+  for (int o = 0; o < int(porb_rep.size()); ++o) {
+    const int k = porb_rep[o] / nk, k2 = porb_rep[o] % nk;
+    const int a1 = k / (n2 * n3), a2 = (k / n3) % n2, a3 = k % n3;
+    const int b1 = k2 / (n2 * n3), b2 = (k2 / n3) % n2, b3 = k2 % n3;
+    const int q = (((a1 - b1 + n1) % n1) * n2 + (a2 - b2 + n2) % n2) * n3 + (a3 - b3 + n3) % n3;
+    byq[q].push_back(o);
+  }
+  items.clear();
+  for (int q = 0; q < nk; ++q)
+    for (size_t i = 0; i < byq[q].size(); i += SEED_KC) {
+      items.push_back(q);
+      for (int kk = 0; kk < SEED_KC; ++kk)
+        items.push_back(i + kk < byq[q].size() ? porb_rep[byq[q][i + kk]] / nk : -1);
+      for (int kk = 0; kk < SEED_KC; ++kk)
+        items.push_back(i + kk < byq[q].size() ? byq[q][i + kk] : 0);
+    }
+}
+}  // namespace
+}  // namespace bse
+
+extern "C" size_t bse_seed_ws(int32_t group, const bse_problem *p, int32_t prec) {
+  if (check_problem(p, prec) || prec == BSE_BF16X3 || !fused_ok(p)) return 0;
+  std::vector<int32_t> porb, prep, korb;
+  int nkorb = 0;
+  if (seed_tables(group, p, porb, prep, korb, nkorb)) return 0;
+  std::vector<int32_t> items;
+  seed_items(p, prep, items);
+  return seed_layout(p, prec, nkorb, int(prep.size()), int(items.size() / (1 + 2 * SEED_KC)))
+      .total;
+}
+
+extern "C" int32_t bse_seed_plan(int32_t group, const bse_problem *p, int32_t prec, void *ws,
+                                 size_t ws_bytes, int64_t *h_plan, bse_stream stream) {
+  int32_t st = check_problem(p, prec);
+  if (st) return st;
+  if (prec == BSE_BF16X3) return fail(BSE_EUNSUPPORTED, "seed construction: FP32 or FP64");
+  if (!fused_ok(p))
+    return fail(BSE_EUNSUPPORTED, "seed construction needs Nmb = 64 m (m <= 6), nv <= 4, nc <= 6");
+  if (!h_plan) return fail(BSE_EINVAL, "plan is NULL");
+  SeedPlan P;
+  std::vector<int32_t> porb, prep, korb;
+  st = seed_tables(group, p, porb, prep, korb, P.nkorb);
+  if (st) return st;
+  if (P.nkorb != p->nkorb) return fail(BSE_EINVAL, "group does not match the problem's orbits");
+  std::vector<int32_t> items;
+  seed_items(p, prep, items);
+  P.p = *p;
+  P.prec = prec;
+  P.nk = p->grid[0] * p->grid[1] * p->grid[2];
+  P.nporb = int(prep.size());
+  P.nitems = int(items.size() / (1 + 2 * SEED_KC));
+  const SeedLayout L = seed_layout(p, prec, P.nkorb, P.nporb, P.nitems);
+  if (!ws || ws_bytes < L.total)
+    return fail(BSE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  char *base = (char *)ws;
+  P.items = (int32_t *)(base + L.items);
+  P.porb = (int32_t *)(base + L.porb);
+  P.ident = (int32_t *)(base + L.ident);
+  P.xs = base + L.xs;
+  P.drep = base + L.drep;
+  P.ldx = int64_t(P.nkorb) * p->nv * p->nc;
+  std::vector<int32_t> ident(P.nkorb);
+  for (int i = 0; i < P.nkorb; ++i) ident[i] = i;
+  hipStream_t s = (hipStream_t)stream;
+  BSE_HIP_CHECK(hipMemcpyAsync(P.items, items.data(), items.size() * 4, hipMemcpyHostToDevice, s));
+  BSE_HIP_CHECK(hipMemcpyAsync(P.porb, porb.data(), porb.size() * 4, hipMemcpyHostToDevice, s));
+  BSE_HIP_CHECK(hipMemcpyAsync(P.ident, ident.data(), ident.size() * 4, hipMemcpyHostToDevice, s));
+  BSE_HIP_CHECK(hipStreamSynchronize(s));
+  std::lock_guard<std::mutex> lk(g_seed_mu);
+  const int64_t id = g_seed_next++;
+  g_seeds[id] = P;
+  *h_plan = id;
+  return BSE_OK;
+}
+
+extern "C" int32_t bse_build_seed(int64_t plan, void *H, int64_t ldh, bse_stream stream) {
+  SeedPlan P;
+  {
+    std::lock_guard<std::mutex> lk(g_seed_mu);
+    auto it = g_seeds.find(plan);
+    if (it == g_seeds.end()) return fail(BSE_EINVAL, "unknown seed plan %lld", (long long)plan);
+    P = it->second;
+  }
+  const bse_problem *p = &P.p;
+  const int64_t N = int64_t(P.nk) * p->nv * p->nc;
+  if (!H) return fail(BSE_EINVAL, "H is NULL");
+  if (ldh < N) return fail(BSE_ESHAPE, "ldh %lld < N %lld", (long long)ldh, (long long)N);
+  hipStream_t s = (hipStream_t)stream;
+  const double inv_nk = 1.0 / P.nk;
+  auto launch = [&](auto tag) -> int32_t {
+    typedef decltype(tag) T;
+    constexpr int BM = BuildTile<T>::BM, BN = BuildTile<T>::BN;
+    const int64_t Nx = P.ldx;
+    dim3 gx((unsigned)((Nx + BN - 1) / BN), (unsigned)((2 * Nx + BM - 1) / BM));
+    BSE_LAUNCH("k_exchange", k_exchange<T>, gx, dim3(NT), 0, s, P.nkorb, p->nv, p->nc, p->nmb,
+               P.ident, (const T *)p->mx, p->vdiag, p->ev, p->ec, (T *)P.xs, P.ldx,
+               2.0 * inv_nk, 0);
+    BSE_HIP_CHECK(hipGetLastError());
+    int32_t st = launch_fused<T, SEED_KC, true>(p->nmb / 64, dim3((unsigned)P.nitems), s, p,
+                                                nullptr, 0, 0.0, P.items, P.drep);
+    if (st) return st;
+    dim3 ga((unsigned)(N * ((N + NT - 1) / NT)));
+    BSE_LAUNCH("k_seed_assemble", k_seed_assemble<T>, ga, dim3(NT), 0, s, P.nk, p->nv, p->nc,
+               p->korb, P.porb, p->ev, p->ec, (const T *)P.xs, P.ldx, (const T *)P.drep,
+               (T *)H, ldh, inv_nk);
+    BSE_HIP_CHECK(hipGetLastError());
+    return BSE_OK;
+  };
+  if (P.prec == BSE_FP64) return launch(double(0));
+  return launch(float(0));
+}
+
+extern "C" int32_t bse_seed_free(int64_t plan) {
+  std::lock_guard<std::mutex> lk(g_seed_mu);
+  if (!g_seeds.erase(plan)) return fail(BSE_EINVAL, "unknown seed plan %lld", (long long)plan);
+  return BSE_OK;
 }

@@ -92,7 +92,22 @@ class DeviceSystem:
         return self.blocks[key]
 
     # -- pieces of the path ----------------------------------------------
+    def use_seed(self, on=True):
+        """Build H by the seed (symmetry-accelerated) construction from now on."""
+        if on and getattr(self, "seed_plan", None) is None:
+            nbytes = B.bse_seed_ws(self.group, self.problem, self.prec)
+            if nbytes == 0:
+                raise B.BseError(-6, B.lib.bse_last_error().decode())
+            self.seed_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.seed_plan = B.bse_seed_plan(self.group, self.problem, self.prec, self.seed_ws)
+        self.seed = on
+
     def build(self):
+        if getattr(self, "seed", False):
+            if self.H is None:
+                self.H = torch.empty((self.N, self.N), dtype=CDT[self.prec], device=self.device)
+            B.bse_build_seed(self.seed_plan, self.H)
+            return self.H
         self.alloc_build()
         B.bse_build(self.problem, self.prec, self.H, self.ws)
         return self.H

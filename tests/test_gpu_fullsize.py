@@ -192,3 +192,32 @@ def test_cfg3_block_properties(lib):
     assert np.all(np.diff(res["omega"]) >= 0)
     del sv, S
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_cfg2_seed_build(lib):
+    """cfg2 seed construction (7140 pair-orbit contractions instead of 262144):
+    the same H as the dense build, and the same solution."""
+    import workloads
+    from paper_2603_24860_amd.system import Solver
+    ref = json.load(open(GOLD))
+    cfg = synth.config("cfg2")
+    say("cfg2 seed build FP32")
+    S = workloads.device_system(cfg, lib.FP32)
+    Hd = S.build().clone()
+    S.use_seed()
+    Hs = S.build()
+    torch.cuda.synchronize()
+    d = float((Hs - Hd).abs().max()) / float(Hd.abs().max())
+    say("  seed vs dense", d)
+    assert d <= 1e-6
+    del Hd
+    sv = Solver(S, "T1u", wgrid=np.linspace(ref["wmin"], ref["wmax"], ref["nw"]))
+    sv.step()
+    res = sv.results()
+    err = np.abs(res["lowest"] - np.asarray(ref["omega"][:100])).max()
+    say("  lowest-100 max err (eV)", err)
+    assert err < 1e-5
+    lib.bse_seed_free(S.seed_plan)
+    del sv, S
+    torch.cuda.empty_cache()

@@ -386,3 +386,34 @@ def test_non_interacting_end_to_end(lib):
     sv.step()
     res = sv.results()
     assert np.abs(res["omega"] - r["omega"]).max() < 1e-12
+
+
+SEEDCFG = [
+    _cfg(grid=(4, 4, 4), nv=3, nc=3, nmb=64, seed=1),
+    _cfg(grid=(3, 3, 3), nv=2, nc=3, nmb=128),
+    _cfg(lattice="hex", grid=(6, 6, 1), nv=4, nc=6, nmb=192),
+]
+
+
+@pytest.mark.parametrize("cfg", SEEDCFG, ids=_ids)
+@pytest.mark.parametrize("precname", ["FP64", "FP32"])
+def test_seed_build_equals_dense(lib, cfg, precname):
+    """Seed construction (one contraction per pair orbit, one exchange row per
+    k orbit) gives the dense-mode H up to the rounding of the final sum, and
+    the oracle's H within the dense-mode tolerance."""
+    import workloads
+    prec = getattr(lib, precname)
+    say("seed-build", _ids(cfg), precname)
+    S = workloads.device_system(cfg, prec)
+    Hd = S.build().clone()
+    S.use_seed()
+    Hs = S.build()
+    torch.cuda.synchronize()
+    hmax = float(Hd.abs().max())
+    d = float((Hs - Hd).abs().max()) / hmax
+    Ho = OB.hamiltonian(OB.make_problem(cfg))
+    e = np.abs(Hs.cpu().numpy().astype(np.complex128) - Ho).max() / np.abs(Ho).max()
+    say("  seed vs dense", d, "seed vs oracle", e)
+    assert d <= (1e-14 if prec == lib.FP64 else 1e-6)
+    assert e <= (1e-12 if prec == lib.FP64 else 2e-6)
+    lib.bse_seed_free(S.seed_plan)
