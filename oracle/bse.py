@@ -352,3 +352,50 @@ def solve_block(P, irrep_name, H=None, nlow=100):
     e, s, m = oscillator_strengths(w, A, Bm)
     return dict(blk=blk, Hmu=Hm, Bmu=Bm, omega=w, A=A, cl_e=e, cl_w=s, cl_m=m,
                 lowest=w[:nlow])
+
+
+# ----------------------------------------------------------------------------
+# longitudinal excitons, Sec. III.D.2: adding the G = 0 Coulomb term
+# c B B^dag (c = 4 pi / (N_k V), times the spin factor 2 of the exchange, as in
+# eps2) to the block leaves dark directions unchanged and moves each weighted
+# pole to a root of the secular equation, Eq. (secular),
+#     f(x) = 1 - c sum_i w_i / (x - p_i) = 0,
+# one root between consecutive weighted poles and one above the highest.  The
+# eigenvector components of Eq. (eigenvec_xi) give the new strengths
+#     w'_xi = (B^T A')^2 / |A'|^2 = 1 / (c^2 sum_i w_i / (x_xi - p_i)^2).
+# ----------------------------------------------------------------------------
+def secular_roots(poles, weights, c, iters=200):
+    """Roots of Eq. (secular) for the weighted poles (ascending, w > 0) by
+    bisection in every interval at once."""
+    p = np.asarray(poles, dtype=np.float64)
+    w = np.asarray(weights, dtype=np.float64)
+    m = len(p)
+    lo = p.copy()
+    hi = np.append(p[1:], p[-1] + c * w.sum())
+
+    def f(x):
+        return 1.0 - c * np.sum(w[None, :] / (x[:, None] - p[None, :]), axis=1)
+
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        neg = f(mid) < 0
+        lo = np.where(neg, mid, lo)
+        hi = np.where(neg, hi, mid)
+    x = 0.5 * (lo + hi)
+    assert len(x) == m
+    return x
+
+
+def secular_weights(roots, poles, weights, c):
+    """Strengths of the longitudinal excitons from Eq. (eigenvec_xi)."""
+    d = np.asarray(roots)[:, None] - np.asarray(poles)[None, :]
+    return 1.0 / (c * c * np.sum(np.asarray(weights)[None, :] / d ** 2, axis=1))
+
+
+def eels(cl_e, cl_w, nk, rel=1e-14):
+    """Longitudinal poles and strengths from the clustered optical poles."""
+    keep = cl_w > rel * cl_w.sum()
+    p, w = cl_e[keep], cl_w[keep]
+    c = 8.0 * np.pi / nk
+    x = secular_roots(p, w, c)
+    return x, secular_weights(x, p, w, c)

@@ -392,3 +392,31 @@ def test_partner_blocks(cfg, irrep, rows):
         assert np.abs(iso.reshape(-1, rows) - wp[:, None]).max() < 1e-9
         w = np.sum(np.abs(U.T @ P["B"]) ** 2) / nb2
         assert abs(w - (1.0 if p == 0 else 0.0)) < 1e-12
+
+
+def test_secular_equation_pins():
+    """Longitudinal excitons (Eq. (secular)): the roots together with the dark
+    eigenvalues are the spectrum of H_mu + c B B^dag (matrix determinant
+    lemma); roots interlace strictly with the weighted poles, one above the
+    top; the closed-form strengths equal the projections of B on the
+    eigenvectors of the updated matrix and keep the sum rule."""
+    P = bse.make_problem(synth.config("cfg1"))
+    r = bse.solve_block(P, "T1u")
+    c = 8.0 * np.pi / P["nk"]
+    keep = r["cl_w"] > 1e-14 * r["cl_w"].sum()
+    p, w = r["cl_e"][keep], r["cl_w"][keep]
+    x, wx = bse.eels(r["cl_e"], r["cl_w"], P["nk"])
+    assert np.all(x[:-1] > p[:-1]) and np.all(x[:-1] < p[1:]) and x[-1] > p[-1]
+    b = r["Bmu"]
+    Hp = r["Hmu"] + c * np.outer(b, b.conj())
+    ev, V = np.linalg.eigh(Hp)
+    # dark spectrum: every eigenvalue of H_mu, minus one member of each weighted cluster
+    om = list(r["omega"])
+    for e in p:
+        om.pop(int(np.argmin(np.abs(np.asarray(om) - e))))
+    assert np.abs(np.sort(np.concatenate([x, om])) - ev).max() < 1e-9
+    proj = np.abs(V.conj().T @ b) ** 2
+    for xi, wi in zip(x, wx):
+        j = int(np.argmin(np.abs(ev - xi)))
+        assert abs(proj[j] - wi) < 1e-9 * w.sum()
+    assert abs(wx.sum() - w.sum()) < 1e-9 * w.sum()
