@@ -312,6 +312,9 @@ def main():
     ap.add_argument("--partner", action="store_true",
                     help="solve the x-partner block of the dipole-active vector irrep (1/d of "
                          "the isotypic block, the same eps2) instead of the isotypic block")
+    ap.add_argument("--eels", action="store_true",
+                    help="also solve the secular equation for the longitudinal excitons and "
+                         "their loss spectrum in every step (stage 'eels')")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel (adds event records; breakdown on stderr)")
     args = ap.parse_args()
@@ -375,6 +378,8 @@ def main():
         sv.eigh()
         e[3].record()
         sv.spectrum()
+        if args.eels:
+            sv.longitudinal()
         e[4].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -415,13 +420,16 @@ def main():
                                f"{cfg['grid'][2]} k grid ({nk} k), Nv={nv}, Nc={nc}, N={S.N}, "
                                f"Nmb={nmb}, dipole-active {irrep}"
                                f"{' x-partner' if args.partner else ''} block n={sv.blk.n}, "
+                               + ("eps2 and loss spectrum (secular equation), " if args.eels
+                                  else "")
                                + (f"seed build (one contraction per pair orbit)" if args.seed
                                   else f"dense-mode build of all {nk * nk} k pairs"),
                    "precision": args.prec},
         "block_eigh_s": round(st_ms[2] * 1e-3, 6),
         "solves_per_s": round(1e3 / ms_step, 3),
         "stage_ms": {"build": round(st_ms[0], 3), "project": round(st_ms[1], 3),
-                     "block_eigh": round(st_ms[2], 3), "spectrum": round(st_ms[3], 3)},
+                     "block_eigh": round(st_ms[2], 3),
+                     ("spectrum+eels" if args.eels else "spectrum"): round(st_ms[3], 3)},
         "lowest_exciton_eV": [round(float(x), 9) for x in res["lowest"][:3]],
         "roofline": {
             "kernel": kname + (" (direct term, both contractions: W(q) Mv and conj(Mc) T, "
@@ -441,6 +449,10 @@ def main():
             "avg_launch_ms": kt_ms / kt_n if kt_n else None,
         },
     }
+    if args.eels:
+        xo = sv.xosc.cpu().numpy()
+        xp = sv.xpole.cpu().numpy()[xo > 0]
+        out["lowest_longitudinal_eV"] = [round(float(x), 9) for x in xp[:3]]
     if args.profile_all:
         for k, (ms, n) in sorted(prof.items(), key=lambda x: -x[1][0]):
             log(f"  {k:14s} {ms / args.steps:10.3f} ms/step  {n // args.steps:6d} launches/step")

@@ -306,6 +306,30 @@ int32_t bse_spectrum(int64_t n, const double *pole, const double *osc, double pr
                      int64_t nw, const double *w, double *eps2, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * bse_eels: longitudinal excitons of one block from its optical poles
+ * (Sec. III.D.2, Eqs. (secular), (eigenvec_xi)).  Adding the G = 0 Coulomb
+ * term c B B^dag to H_mu leaves dark directions unchanged and moves every
+ * weighted pole p_i (strength w_i) to a root x of
+ *     1 - c sum_i w_i / (x - p_i) = 0,
+ * one in each interval between consecutive weighted poles and one in
+ * (p_m, p_m + c sum w), with strength 1 / (c^2 sum_i w_i / (x - p_i)^2).
+ *   pole, osc   device double[n], the output of bse_block_eigh (ascending
+ *               poles; entries with osc <= 1e-14 sum(osc), i.e. dark clusters
+ *               and non-leading cluster members, are not poles of the sum)
+ *   c           coupling > 0; 8 pi / N_k for the spin-degenerate exchange
+ *               (the same prefactor as the exchange and eps2)
+ *   xpole, xosc device double[n] outputs: the m roots (ascending) and their
+ *               strengths, then n - m entries (0, 0); pass them to bse_spectrum
+ *               for the loss spectrum.  They may not alias pole/osc.
+ *   ws          device workspace of bse_eels_ws(n) bytes (caller owned).
+ * Errors: BSE_ESHAPE (n < 1), BSE_EINVAL (NULL pointer, c <= 0),
+ * BSE_EWORKSPACE.  Asynchronous on `stream`; launches kernels only.
+ * ------------------------------------------------------------------------- */
+size_t bse_eels_ws(int64_t n);
+int32_t bse_eels(int64_t n, const double *pole, const double *osc, double c, double *xpole,
+                 double *xosc, void *ws, size_t ws_bytes, bse_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (host).  bse_prof_enable(prefix) brackets every subsequent
  * launch of a library kernel whose name starts with `prefix` with two HIP
  * events on the launch stream ("" or NULL disables; "k_" times every kernel).

@@ -93,6 +93,8 @@ def _load():
         "bse_batch_eigh_tune": (i32, [i64, vp, P(i32)]),
         "bse_batch_eigh_free": (i32, [i64]),
         "bse_spectrum": (i32, [i64, vp, vp, f64, f64, i64, vp, vp, vp]),
+        "bse_eels_ws": (ctypes.c_size_t, [i64]),
+        "bse_eels": (i32, [i64, vp, vp, f64, vp, vp, vp, ctypes.c_size_t, vp]),
         "bse_prof_enable": (i32, [ctypes.c_char_p]),
         "bse_prof_collect": (i32, []),
         "bse_prof_count": (i32, []),

@@ -221,6 +221,17 @@ def bse_spectrum(pole, osc, pref, eta, w, eps2, stream=None):
                            w.numel(), _ptr(w), _ptr(eps2), _stream(stream)))
 
 
+def bse_eels_ws(n):
+    return int(lib.bse_eels_ws(int(n)))
+
+
+def bse_eels(pole, osc, c, xpole, xosc, ws, stream=None):
+    """Longitudinal poles and strengths (roots of the secular equation) from
+    the optical poles of bse_block_eigh; unused tail entries are (0, 0)."""
+    check(lib.bse_eels(pole.numel(), _ptr(pole), _ptr(osc), float(c), _ptr(xpole), _ptr(xosc),
+                       _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
 # --------------------------------------------------------------------------
 # kernel timing
 # --------------------------------------------------------------------------

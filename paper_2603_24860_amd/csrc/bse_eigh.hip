@@ -1637,8 +1637,8 @@ extern "C" int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t 
       BSE_HIP_CHECK(hipEventSynchronize(e1));
     }
     if (st) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       return st;
     }
     float ms = 0;
@@ -1648,8 +1648,8 @@ extern "C" int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t 
       best_w = w;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   P.wpr = best_w;
   int32_t st = upload_tables(P, s);
   if (st) return st;

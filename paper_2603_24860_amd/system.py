@@ -175,6 +175,31 @@ class Solver:
     def spectrum(self):
         B.bse_spectrum(self.pole, self.osc, 8 * math.pi / self.s.nk, self.eta, self.w, self.eps2)
 
+    def longitudinal(self):
+        """Enqueue the longitudinal excitons of the block (after eigh): roots of
+        the secular equation with coupling 8 pi / N_k, their strengths, and
+        their spectrum on the same grid and broadening as eps2."""
+        n = self.blk.n
+        if getattr(self, "loss", None) is None or self.loss.shape != self.w.shape:
+            dev = self.s.device
+            self.xpole = torch.empty(n, dtype=torch.float64, device=dev)
+            self.xosc = torch.empty_like(self.xpole)
+            self.xws = torch.empty(B.bse_eels_ws(n), dtype=torch.uint8, device=dev)
+            self.loss = torch.empty_like(self.w)
+        pref = 8 * math.pi / self.s.nk
+        B.bse_eels(self.pole, self.osc, pref, self.xpole, self.xosc, self.xws)
+        B.bse_spectrum(self.xpole, self.xosc, pref, self.eta, self.w, self.loss)
+
+    def eels(self):
+        """longitudinal() and its results as host arrays (roots, strengths,
+        spectrum)."""
+        self.longitudinal()
+        torch.cuda.synchronize()
+        xo = self.xosc.cpu().numpy()
+        m = int(np.count_nonzero(xo))
+        return dict(pole=self.xpole.cpu().numpy()[:m], osc=xo[:m],
+                    spectrum=self.loss.cpu().numpy())
+
     def step(self):
         """One pass of the hot path: build, project, block eigh, spectrum."""
         self.s.build()

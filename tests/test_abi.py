@@ -104,6 +104,12 @@ def test_invalid_arguments_rejected_on_host():
                                 None) == _lib.ESHAPE
     assert B.lib.bse_spectrum(4, None, None, 1.0, 0.05, 10, None, None, None) == _lib.EINVAL
     assert B.lib.bse_spectrum(0, None, None, 1.0, 0.05, 0, None, None, None) == _lib.OK
+    assert B.lib.bse_eels(0, None, None, 1.0, None, None, None, 0, None) == _lib.ESHAPE
+    assert B.lib.bse_eels(4, None, None, 1.0, None, None, None, 0, None) == _lib.EINVAL
+    d = ctypes.c_void_p(16)  # never dereferenced: the call fails on the host first
+    assert B.lib.bse_eels(4, d, d, 0.0, d, d, d, 1 << 20, None) == _lib.EINVAL
+    assert B.lib.bse_eels(4, d, d, 1.0, d, d, d, 8, None) == _lib.EWORKSPACE
+    assert B.lib.bse_eels_ws(0) == 0 and B.lib.bse_eels_ws(10) == 8 * 22
     assert "NULL" in B.lib.bse_last_error().decode() or B.lib.bse_last_error() is not None
 
 

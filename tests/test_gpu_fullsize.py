@@ -5,7 +5,9 @@
   tests/golden/cfg2_t1u_oracle.json (written by make_cfg2_reference.py from
   the oracle alone).  Lowest 100 energies within 1e-5 eV (FP32 path) /
   1e-9 eV (FP64 path) / 1e-4 eV (split-BF16 build), eps2 within 1e-4
-  relative, cumulative strengths.
+  relative, cumulative strengths; the longitudinal excitons from the same
+  eigenpairs against the oracle's secular-equation roots of the stored
+  clusters (cumulative strengths, loss spectrum within 1e-4 relative).
 * cfg2 and cfg3 (Oh 12^3, N = 41472): H elements sampled across the matrix
   (corners, conjugated classes, k = k', the diagonal, random pairs) against
   the oracle's element-by-element definition.  FP32 tolerance 2e-6 max|H|.
@@ -40,6 +42,10 @@ def lib():
     from paper_2603_24860_amd import bse as B
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     return B
+
+
+def cfg_nk(cfg):
+    return int(np.prod(cfg["grid"]))
 
 
 def _match_cumulative(pole, osc, ce, cw, tol, wtol):
@@ -89,6 +95,15 @@ def test_cfg2_end_to_end(lib, precname, tol, wtol, nref):
     assert e2err <= 1e-4
     _match_cumulative(res["pole"], res["osc"], np.asarray(ref["cl_e"]), np.asarray(ref["cl_w"]),
                       100 * tol, wtol)
+    if nref == 0:
+        # longitudinal excitons from the same eigenpairs (secular equation)
+        xr, wr = OB.eels(np.asarray(ref["cl_e"]), np.asarray(ref["cl_w"]), cfg_nk(cfg))
+        out = sv.eels()
+        loss = OB.eps2(xr, wr, cfg_nk(cfg), synth.ETA, wgrid)
+        lerr = np.abs(out["spectrum"] - loss).max() / np.abs(loss).max()
+        say("  eels roots", len(out["pole"]), "oracle", len(xr), "loss rel err", lerr)
+        _match_cumulative(out["pole"], out["osc"], xr, wr, 100 * tol, wtol)
+        assert lerr <= 1e-4
     del sv, S
     torch.cuda.empty_cache()
 
