@@ -399,3 +399,55 @@ def eels(cl_e, cl_w, nk, rel=1e-14):
     c = 8.0 * np.pi / nk
     x = secular_roots(p, w, c)
     return x, secular_weights(x, p, w, c)
+
+
+# ----------------------------------------------------------------------------
+# Lanczos-Haydock per block (the alternative to diagonalisation that the
+# block structure also serves, Sec. III.D.1): Lanczos on H_mu started from
+# v_0 = B_mu / |B_mu| gives the tridiagonal coefficients a_j, b_j; the
+# resolvent element v_0^dag (z - H_mu)^-1 v_0 is the continued fraction
+#     G(z) = 1 / (z - a_0 - b_1^2 / (z - a_1 - b_2^2 / (...)))
+# truncated after K levels, and since L_eta(x) = -Im 1/(x + i eta),
+#     eps2(w) = (8 pi / N_k) |B_mu|^2 (-Im G(w + i eta) - Im G(-w + i eta)),
+# the same two terms as in eps2 above.
+# ----------------------------------------------------------------------------
+def haydock_coefficients(Hm, Bm, K):
+    """Plain Lanczos (no reorthogonalisation): a[0..K'), b[0..K'] with
+    b[0] = |B_mu| and b[j] (j >= 1) the norm of the j-th residual; stops early
+    (K' < K) when a residual vanishes (the Krylov space is invariant)."""
+    Hm = np.asarray(Hm, dtype=np.complex128)
+    v = np.asarray(Bm, dtype=np.complex128)
+    bn = np.linalg.norm(v)
+    a, b = [], [bn]
+    v_prev = np.zeros_like(v)
+    v = v / bn
+    beta = 0.0
+    for j in range(K):
+        w = Hm @ v - beta * v_prev
+        alpha = float(np.real(np.vdot(v, w)))
+        w = w - alpha * v
+        beta = float(np.linalg.norm(w))
+        a.append(alpha)
+        b.append(beta)
+        if beta == 0.0:
+            break
+        v_prev, v = v, w / beta
+    return np.array(a), np.array(b)
+
+
+def continued_fraction(a, b, z):
+    """G(z) for the coefficients of haydock_coefficients, evaluated from the
+    deepest level up (the remainder below level K is dropped)."""
+    z = np.asarray(z, dtype=np.complex128)
+    g = np.zeros_like(z)
+    for j in range(len(a) - 1, -1, -1):
+        tail = b[j + 1] ** 2 * g if j + 1 < len(a) else 0.0
+        g = 1.0 / (z - a[j] - tail)
+    return g
+
+
+def haydock_eps2(a, b, nk, eta, wgrid):
+    w = np.asarray(wgrid, dtype=np.float64)
+    g1 = continued_fraction(a, b, w + 1j * eta)
+    g2 = continued_fraction(a, b, -w + 1j * eta)
+    return (8 * np.pi / nk) * b[0] ** 2 * (-g1.imag - g2.imag)

@@ -420,3 +420,81 @@ def test_secular_equation_pins():
         j = int(np.argmin(np.abs(ev - xi)))
         assert abs(proj[j] - wi) < 1e-9 * w.sum()
     assert abs(wx.sum() - w.sum()) < 1e-9 * w.sum()
+
+
+# --------------------------------------------------------------------------
+# Lanczos-Haydock (the diagonalisation-free alternative served by the blocks)
+# --------------------------------------------------------------------------
+def _rand_herm(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    return (X + X.conj().T) / 2, rng.normal(size=n) + 1j * rng.normal(size=n)
+
+
+def test_haydock_gauss_quadrature_moments():
+    """K Lanczos steps are the K-point Gauss quadrature of the spectral
+    measure sum_l |B_l|^2 delta(x - Omega_l): the moments of T_K agree with
+    those of the spectrum for every power below 2K (and not at 2K)."""
+    H, b = _rand_herm(40, 3)
+    lam, Q = np.linalg.eigh(H)
+    wt = np.abs(Q.conj().T @ b) ** 2 / np.linalg.norm(b) ** 2
+    K = 6
+    a, bb = bse.haydock_coefficients(H, b, K)
+    assert len(a) == K and abs(bb[0] - np.linalg.norm(b)) < 1e-12 * bb[0]
+    T = np.diag(a) + np.diag(bb[1:K], 1) + np.diag(bb[1:K], -1)
+    tl, tz = np.linalg.eigh(T)
+    tw = tz[0] ** 2
+    s = np.abs(lam).max()
+    for p in range(2 * K):
+        exact = np.sum(wt * (lam / s) ** p)
+        assert abs(np.sum(tw * (tl / s) ** p) - exact) < 1e-10, p
+    assert abs(np.sum(tw * (tl / s) ** (2 * K)) - np.sum(wt * (lam / s) ** (2 * K))) > 1e-6
+
+
+def test_continued_fraction_is_the_resolvent_element():
+    """G(z) from the fraction equals [(z - T)^-1]_00 for the tridiagonal T."""
+    rng = np.random.default_rng(4)
+    K = 9
+    a = rng.normal(size=K)
+    b = np.concatenate([[1.7], rng.uniform(0.2, 2.0, K)])
+    T = np.diag(a) + np.diag(b[1:K], 1) + np.diag(b[1:K], -1)
+    for z in (0.3 + 0.05j, -2.0 + 0.5j, 4.1 + 1e-3j):
+        g = bse.continued_fraction(a, b, np.array([z]))[0]
+        e0 = np.zeros(K)
+        e0[0] = 1.0
+        ref = np.linalg.solve(z * np.eye(K) - T, e0)[0]
+        assert abs(g - ref) < 1e-12 * abs(ref)
+
+
+def test_haydock_full_krylov_is_exact():
+    """With the whole Krylov space (K = n, distinct eigenvalues) the fraction
+    is the exact resolvent: eps2 equals the eigen-decomposition form."""
+    H, b = _rand_herm(12, 5)
+    lam, Q = np.linalg.eigh(H)
+    wt = np.abs(Q.conj().T @ b) ** 2
+    a, bb = bse.haydock_coefficients(H, b, 12)
+    w = np.linspace(-10, 10, 400)
+    ref = bse.eps2(lam, wt, 64, 0.05, w)
+    got = bse.haydock_eps2(a, bb, 64, 0.05, w)
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+    # an invariant Krylov space ends the recurrence with an exactly zero residual
+    D = np.diag([1.0, 1.0, 2.0, 3.0, 3.0])
+    a2, b2 = bse.haydock_coefficients(D, np.array([1.0, 0, 0, 0, 0]), 5)
+    assert len(a2) == 1 and b2[-1] == 0.0 and a2[0] == 1.0
+
+
+def test_haydock_converges_to_block_eps2():
+    """cfg1 T1u block: the Haydock eps2 approaches the eps2 of the block's
+    eigenpairs as K grows and is exact once the weighted Krylov space (54
+    distinct weighted clusters) is exhausted."""
+    P = bse.make_problem(synth.config("cfg1"))
+    r = bse.solve_block(P, "T1u")
+    w = synth.omega_grid_from_range(r["omega"].min(), r["omega"].max())
+    ref = bse.eps2(r["cl_e"], r["cl_w"], P["nk"], synth.ETA, w)
+    errs = []
+    for K in (20, 40, 60, 80):
+        a, b = bse.haydock_coefficients(r["Hmu"], r["Bmu"], K)
+        e = bse.haydock_eps2(a, b, P["nk"], synth.ETA, w)
+        errs.append(np.abs(e - ref).max() / np.abs(ref).max())
+    assert errs[0] > errs[2] > errs[3] and errs[3] < 1e-10
+    assert int(np.sum(r["cl_w"] > 1e-14 * r["cl_w"].sum())) == 54
