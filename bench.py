@@ -315,6 +315,9 @@ def main():
     ap.add_argument("--eels", action="store_true",
                     help="also solve the secular equation for the longitudinal excitons and "
                          "their loss spectrum in every step (stage 'eels')")
+    ap.add_argument("--haydock", type=int, default=0, metavar="K",
+                    help="replace the block eigensolver and its spectrum by K Lanczos-Haydock "
+                         "steps and the continued-fraction eps2 (no eigenvalues)")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel (adds event records; breakdown on stderr)")
     args = ap.parse_args()
@@ -361,6 +364,11 @@ def main():
     for _ in range(args.warmup):
         sv.step()
     torch.cuda.synchronize()
+    if args.haydock:  # the eigenpair eps2 on the same grid, to compare against
+        eps2_eigh = sv.eps2.clone()
+        for _ in range(max(1, args.warmup)):
+            sv.haydock(args.haydock)
+        torch.cuda.synchronize()
 
     B.bse_prof_enable("k_" if args.profile_all else "k_direct")
     B.bse_prof_reset()
@@ -375,11 +383,16 @@ def main():
         e[1].record()
         sv.project()
         e[2].record()
-        sv.eigh()
-        e[3].record()
-        sv.spectrum()
-        if args.eels:
-            sv.longitudinal()
+        if args.haydock:
+            sv.haydock_steps(args.haydock)
+            e[3].record()
+            sv.haydock_spectrum()
+        else:
+            sv.eigh()
+            e[3].record()
+            sv.spectrum()
+            if args.eels:
+                sv.longitudinal()
         e[4].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -422,13 +435,15 @@ def main():
                                f"{' x-partner' if args.partner else ''} block n={sv.blk.n}, "
                                + ("eps2 and loss spectrum (secular equation), " if args.eels
                                   else "")
+                               + (f"eps2 by {args.haydock} Lanczos-Haydock steps (no eigh), "
+                                  if args.haydock else "")
                                + (f"seed build (one contraction per pair orbit)" if args.seed
                                   else f"dense-mode build of all {nk * nk} k pairs"),
                    "precision": args.prec},
-        "block_eigh_s": round(st_ms[2] * 1e-3, 6),
+        "block_eigh_s": None if args.haydock else round(st_ms[2] * 1e-3, 6),
         "solves_per_s": round(1e3 / ms_step, 3),
         "stage_ms": {"build": round(st_ms[0], 3), "project": round(st_ms[1], 3),
-                     "block_eigh": round(st_ms[2], 3),
+                     ("haydock" if args.haydock else "block_eigh"): round(st_ms[2], 3),
                      ("spectrum+eels" if args.eels else "spectrum"): round(st_ms[3], 3)},
         "lowest_exciton_eV": [round(float(x), 9) for x in res["lowest"][:3]],
         "roofline": {
@@ -449,6 +464,9 @@ def main():
             "avg_launch_ms": kt_ms / kt_n if kt_n else None,
         },
     }
+    if args.haydock:
+        dev = float((sv.hd_eps2 - eps2_eigh).abs().max() / eps2_eigh.abs().max())
+        out["haydock"] = {"K": args.haydock, "eps2_rel_dev_vs_eigh": dev}
     if args.eels:
         xo = sv.xosc.cpu().numpy()
         xp = sv.xpole.cpu().numpy()[xo > 0]

@@ -330,6 +330,39 @@ int32_t bse_eels(int64_t n, const double *pole, const double *osc, double c, dou
                  double *xosc, void *ws, size_t ws_bytes, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * bse_haydock: eps2 of one block without diagonalising it: Lanczos-Haydock,
+ * which profits from the block-diagonal form of H as the eigensolver does
+ * (Sec. III.D.1).  Lanczos on H_mu started from B_mu / |B_mu| (classical
+ * recurrence, no reorthogonalisation):
+ *     w = H v_j - b_j v_{j-1},  a_j = Re v_j^dag w,  w -= a_j v_j,
+ *     b_{j+1} = |w|,  v_{j+1} = w / b_{j+1},
+ * with b_0 = |B_mu| and v_{-1} = 0.
+ *   Hmu    device, n x n, row-major with leading dimension ld >= n, complex
+ *          double if h_fp64 else complex float; the full matrix (both
+ *          triangles, as bse_project_blocks writes it) is read; read only.
+ *   Bmu    device complex double[n].
+ *   K      steps, 1 .. 2^20.
+ *   a, b   device double outputs: a[0..K), b[0..K] (b[0] = |B_mu|, b[K] the
+ *          norm of the last residual).  A residual that vanishes exactly
+ *          (invariant Krylov space) zeroes the later coefficients.
+ *   ws     device workspace of bse_haydock_ws(n) bytes (caller owned).
+ * Cost: K dependent kernels, each reading H_mu once (FP64 arithmetic).
+ * bse_haydock_spectrum: eps2(w_j) = pref b_0^2 (-Im G(w_j + i eta)
+ * - Im G(-w_j + i eta)) with G(z) = 1 / (z - a_0 - b_1^2 / (z - a_1 - ...))
+ * truncated after K levels (the resonant and antiresonant terms of
+ * bse_spectrum; pref = 8 pi / N_k).  Device FP64 arrays.
+ * Errors: BSE_ESHAPE (n < 1, n > 2^20, ld < n, nw < 0), BSE_EINVAL (NULL
+ * pointer, K outside 1 .. 2^20, eta <= 0), BSE_EWORKSPACE.  Asynchronous.
+ * ------------------------------------------------------------------------- */
+size_t bse_haydock_ws(int64_t n);
+int32_t bse_haydock(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, const void *Bmu,
+                    int32_t K, double *a, double *b, void *ws, size_t ws_bytes,
+                    bse_stream stream);
+int32_t bse_haydock_spectrum(int32_t K, const double *a, const double *b, double pref,
+                             double eta, int64_t nw, const double *w, double *eps2,
+                             bse_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (host).  bse_prof_enable(prefix) brackets every subsequent
  * launch of a library kernel whose name starts with `prefix` with two HIP
  * events on the launch stream ("" or NULL disables; "k_" times every kernel).

@@ -95,6 +95,9 @@ def _load():
         "bse_spectrum": (i32, [i64, vp, vp, f64, f64, i64, vp, vp, vp]),
         "bse_eels_ws": (ctypes.c_size_t, [i64]),
         "bse_eels": (i32, [i64, vp, vp, f64, vp, vp, vp, ctypes.c_size_t, vp]),
+        "bse_haydock_ws": (ctypes.c_size_t, [i64]),
+        "bse_haydock": (i32, [i64, vp, i64, i32, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+        "bse_haydock_spectrum": (i32, [i32, vp, vp, f64, f64, i64, vp, vp, vp]),
         "bse_prof_enable": (i32, [ctypes.c_char_p]),
         "bse_prof_collect": (i32, []),
         "bse_prof_count": (i32, []),

@@ -221,6 +221,24 @@ def bse_spectrum(pole, osc, pref, eta, w, eps2, stream=None):
                            w.numel(), _ptr(w), _ptr(eps2), _stream(stream)))
 
 
+def bse_haydock_ws(n):
+    return int(lib.bse_haydock_ws(int(n)))
+
+
+def bse_haydock(Hmu, Bmu, K, a, b, ws, stream=None):
+    """K Lanczos-Haydock steps on the block: a[K], b[K+1] (b[0] = |B_mu|)."""
+    import torch
+    n = Hmu.shape[0]
+    h64 = 1 if Hmu.dtype == torch.complex128 else 0
+    check(lib.bse_haydock(n, _ptr(Hmu), Hmu.stride(0), h64, _ptr(Bmu), int(K), _ptr(a), _ptr(b),
+                          _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def bse_haydock_spectrum(K, a, b, pref, eta, w, eps2, stream=None):
+    check(lib.bse_haydock_spectrum(int(K), _ptr(a), _ptr(b), float(pref), float(eta), w.numel(),
+                                   _ptr(w), _ptr(eps2), _stream(stream)))
+
+
 def bse_eels_ws(n):
     return int(lib.bse_eels_ws(int(n)))
 

@@ -175,6 +175,31 @@ class Solver:
     def spectrum(self):
         B.bse_spectrum(self.pole, self.osc, 8 * math.pi / self.s.nk, self.eta, self.w, self.eps2)
 
+    def haydock_steps(self, K):
+        """Enqueue K Lanczos-Haydock steps on the projected block (coefficients
+        hd_a[K], hd_b[K+1]; no diagonalisation)."""
+        n = self.blk.n
+        dev = self.s.device
+        if getattr(self, "hd_K", None) != K:
+            self.hd_a = torch.empty(K, dtype=torch.float64, device=dev)
+            self.hd_b = torch.empty(K + 1, dtype=torch.float64, device=dev)
+            self.hd_K = K
+        if getattr(self, "hd_ws", None) is None:
+            self.hd_ws = torch.empty(B.bse_haydock_ws(n), dtype=torch.uint8, device=dev)
+        B.bse_haydock(self.Hmu, self.Bmu, K, self.hd_a, self.hd_b, self.hd_ws)
+
+    def haydock_spectrum(self):
+        """Enqueue the continued-fraction eps2 of the last haydock_steps on the grid."""
+        if getattr(self, "hd_eps2", None) is None or self.hd_eps2.shape != self.w.shape:
+            self.hd_eps2 = torch.empty_like(self.w)
+        B.bse_haydock_spectrum(self.hd_K, self.hd_a, self.hd_b, 8 * math.pi / self.s.nk,
+                               self.eta, self.w, self.hd_eps2)
+
+    def haydock(self, K):
+        """haydock_steps(K) then haydock_spectrum()."""
+        self.haydock_steps(K)
+        self.haydock_spectrum()
+
     def longitudinal(self):
         """Enqueue the longitudinal excitons of the block (after eigh): roots of
         the secular equation with coupling 8 pi / N_k, their strengths, and
