@@ -318,6 +318,12 @@ def main():
     ap.add_argument("--haydock", type=int, default=0, metavar="K",
                     help="replace the block eigensolver and its spectrum by K Lanczos-Haydock "
                          "steps and the continued-fraction eps2 (no eigenvalues)")
+    ap.add_argument("--nrefine", type=int, default=0, metavar="K",
+                    help="FP64 refinement of the lowest K block eigenvalues (0..256)")
+    ap.add_argument("--vs-fp64", action="store_true",
+                    help="after the timed steps, time the plain FP64 GPU form of the same "
+                         "workload and report the error of the lowest 100 energies (meV) and "
+                         "of eps2 against it")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel (adds event records; breakdown on stderr)")
     args = ap.parse_args()
@@ -353,7 +359,7 @@ def main():
     if args.seed:
         S.use_seed()
     irrep, weights = S.active_irrep()
-    sv = Solver(S, irrep, partner=0 if args.partner else None)
+    sv = Solver(S, irrep, partner=0 if args.partner else None, nrefine=args.nrefine)
     log(f"setup {time.perf_counter() - t0:.1f} s; N = {S.N}, block {irrep}"
         f"{' x-partner' if args.partner else ''} n = {sv.blk.n}")
     # frequency grid from the block spectrum (first solve, untimed)
@@ -439,7 +445,7 @@ def main():
                                   if args.haydock else "")
                                + (f"seed build (one contraction per pair orbit)" if args.seed
                                   else f"dense-mode build of all {nk * nk} k pairs"),
-                   "precision": args.prec},
+                   "precision": args.prec, "nrefine": args.nrefine},
         "block_eigh_s": None if args.haydock else round(st_ms[2] * 1e-3, 6),
         "solves_per_s": round(1e3 / ms_step, 3),
         "stage_ms": {"build": round(st_ms[0], 3), "project": round(st_ms[1], 3),
@@ -474,9 +480,45 @@ def main():
     if args.profile_all:
         for k, (ms, n) in sorted(prof.items(), key=lambda x: -x[1][0]):
             log(f"  {k:14s} {ms / args.steps:10.3f} ms/step  {n // args.steps:6d} launches/step")
+    if args.vs_fp64:
+        out["vs_fp64"] = vs_fp64(cfg, sv, args, ms_step, log)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_q, log)
     print(json.dumps(out), flush=True)
+
+
+def vs_fp64(cfg, sv, args, ms_step, log_fn):
+    """The plain FP64 GPU form of the same workload (FP64 build, projection,
+    eigensolver and spectrum, no refinement): its time per solve, and the
+    error of the timed form's lowest 100 energies (meV) and eps2 against it."""
+    import torch
+    import workloads
+    from paper_2603_24860_amd import bse as B
+    from paper_2603_24860_amd.system import Solver
+    res = sv.results()
+    w = sv.w.cpu().numpy()
+    irrep, partner = sv.blk.irrep, sv.blk.partner
+    sv.s.H = None  # free the timed form's H and build workspace first
+    sv.s.ws = None
+    torch.cuda.empty_cache()
+    S = workloads.device_system(cfg, B.FP64)
+    s64 = Solver(S, irrep, partner=partner, wgrid=w)
+    s64.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrep = max(1, min(args.steps, 3))
+    for _ in range(nrep):
+        s64.step()
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / nrep
+    r64 = s64.results()
+    err = float(np.abs(res["lowest"] - r64["lowest"]).max()) * 1e3
+    e2 = float(np.abs(res["eps2"] - r64["eps2"]).max() / np.abs(r64["eps2"]).max())
+    log_fn(f"plain FP64 form {ms64:.1f} ms per solve; lowest-100 max err {err:.2e} meV, "
+           f"eps2 rel err {e2:.2e}")
+    return {"fp64_ms_per_solve": round(ms64, 3), "fp64_solves_per_s": round(1e3 / ms64, 3),
+            "speedup_vs_fp64": round(ms64 / ms_step, 3), "max_lowest100_err_meV": err,
+            "eps2_rel_err": e2, "within_0.1meV": bool(err <= 0.1)}
 
 
 if __name__ == "__main__":

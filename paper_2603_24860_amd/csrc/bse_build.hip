@@ -368,8 +368,13 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   constexpr int STAGE = (NMB + NCOL) * P;  // staging elements
   constexpr int NCB = 3;                   // c c' row blocks of stage 2
   constexpr int RED = 4 * NCB * 16 * 16 * 2;
-  __shared__ __attribute__((aligned(16))) T lds[STAGE > RED ? STAGE : RED];
-  T *As = lds, *Bs = lds + NMB * P;
+  constexpr bool SWZ = sizeof(T) == 4;      // swizzled FP32 rows (see below)
+  constexpr int PP = SWZ ? BK : P;          // LDS row pitch
+  constexpr int LDSN = SWZ ? (NMB + NCOL) * PP : STAGE;
+  static_assert(!SWZ || BK == 16, "the FP32 swizzle assumes four chunks per row");
+  auto swz = [](int row, int chunk) { return SWZ ? (chunk ^ ((row >> 1) & 3)) : chunk; };
+  __shared__ __attribute__((aligned(16))) T lds[LDSN > RED ? LDSN : RED];
+  T *As = lds, *Bs = lds + NMB * PP;
   typedef typename Cplx<T>::type C2;
   typedef typename Mfma<T>::acc_t acc_t;
   typedef typename Mfma<T>::frag_t frag_t;
@@ -410,25 +415,39 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   __shared__ __attribute__((aligned(16))) C2 bzero_s[4];  // source of rows without data
   if (tid < 4) bzero_s[tid] = C2{T(0), T(0)};
   __syncthreads();
+  // LDS rows of 16-byte chunks.  FP32: no padding, chunk c of row r stored at
+  // c ^ ((r >> 1) & 3), so the eight lanes of one b128 access (eight rows at
+  // one chunk for the MFMA fragments, two rows at four chunks for the stores)
+  // hit eight distinct bank groups.  FP64: rows padded by one chunk.
   const T *wrow[NA];
   int aoff[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
     const int it = tid + NT * u, row = it / (BK / VEC), c = it % (BK / VEC);
     wrow[u] = wq + int64_t(row) * nmb + c * VEC;
-    aoff[u] = row * P + c * VEC;
+    aoff[u] = row * PP + swz(row, c) * VEC;
   }
   const C2 *bsrc[NB];
-  int bstride[NB], boff[NB];
+  int bstride[NB], boff[NB], boff2[NB];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int it = tid + NT * u, row = it / BPR, c = it % BPR, kk = row / 16, vv = row % 16;
     bsrc[u] = brow[u] ? brow[u] + (VEC == 4 ? 2 * c : c) : bzero_s;
     bstride[u] = brow[u] ? 1 : 0;
-    boff[u] = ((2 * kk) * 16 + vv) * P + (VEC == 4 ? 2 * c : c);
+    const int r0 = (2 * kk) * 16 + vv, r1 = r0 + 16;  // real and imaginary rows
+    if (VEC == 4) {  // two complex = four floats: the re pair and the im pair
+      boff[u] = r0 * PP + swz(r0, c >> 1) * 4 + 2 * (c & 1);
+      boff2[u] = r1 * PP + swz(r1, c >> 1) * 4 + 2 * (c & 1);
+    } else {
+      boff[u] = r0 * PP + c;
+      boff2[u] = r1 * PP + c;
+    }
   }
-  // Two workgroups per CU hide the load latency better than an in-register
-  // prefetch of the next slab, which would cost the second workgroup.
+  // Several workgroups per CU hide the load latency better than an
+  // in-register prefetch of the next slab or a second LDS buffer, which cost
+  // registers and LDS and so workgroups per CU (measured: 0.47-0.50 of peak
+  // against 0.68).
+  const int r = lane & 15, g = lane >> 4;
   for (int j0 = 0; j0 < nmb; j0 += BK) {
     V16 ra[NA], rb[NB];
 #pragma unroll
@@ -438,14 +457,34 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
 #pragma unroll
     for (int u = 0; u < NA; ++u) *reinterpret_cast<V16 *>(As + aoff[u]) = ra[u];
 #pragma unroll
-    for (int u = 0; u < NB; ++u)
-      split_store<VEC>(rb[u], Bs + boff[u], Bs + boff[u] + 16 * P, 0, bsgn[u]);
+    for (int u = 0; u < NB; ++u) split_store<VEC>(rb[u], Bs + boff[u], Bs + boff2[u], 0, bsgn[u]);
     __syncthreads();
-    mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, 0, lane);
+    if (SWZ) {
+      frag_t fa[MI], fb[NI];
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) {
+        const int row = wm0 + 16 * mi + r;
+        fa[mi] = lds_frag<T>(As + row * PP + swz(row, g) * 4);
+      }
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni) {
+        const int row = 16 * ni + r;
+        fb[ni] = lds_frag<T>(Bs + row * PP + swz(row, g) * 4);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NI; ++ni)
+            acc[mi][ni] = Mfma<T>::mma(fa[mi][i], fb[ni][i], acc[mi][ni]);
+    } else {
+      mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, 0, lane);
+    }
     __syncthreads();
   }
   // ---- stage 2 ----
-  const int r16 = lane & 15, g = lane >> 4;
+  const int r16 = r;
   const int ncb = (ncc + 15) / 16;
   C2 *red = reinterpret_cast<C2 *>(lds);  // [4][NCB*16][16]
   C2 *Hc = reinterpret_cast<C2 *>(H);

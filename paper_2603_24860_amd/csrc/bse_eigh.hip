@@ -126,6 +126,7 @@ struct Desc {
   double *rqp;               // [K][cdiv(n, 4)][2] partial Rayleigh quotients
   double *scr;               // [K][(4 + CMAX) n] inverse-iteration scratch
   double *wref;              // [K] refined eigenvalues
+  double2 *Tm;               // [cdiv(n - 1, NBK)][NBK][NBK] block-reflector factors T
 };
 
 // ---------------------------------------------------------------------------
@@ -153,8 +154,10 @@ __host__ __device__ __forceinline__ int g_nbk(int64_t n, int64_t j0) {
 __host__ __device__ __forceinline__ int g_np_in(int64_t n, int64_t jn) {
   return (int)(jn % NBK == 0 ? g_nwg(n - jn) : cdiv(n - jn, RB_ROWS));
 }
+// wpr = 0: the LDS-staged form of k_colA (LDS_RW rows per wave)
+constexpr int LDS_RW = 2;
 __host__ __device__ __forceinline__ int g_colA_wgs(int64_t m, int wpr) {
-  const int64_t rt = 4 / wpr;
+  const int64_t rt = wpr == 0 ? 4 * LDS_RW : 4 / wpr;
   return (int)(m < 1 ? 1 : cdiv(m, rt));
 }
 __host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
@@ -162,8 +165,10 @@ __host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
   return (jn % NBK) + 1 < g_nbk(n, j0) ? 1 : 0;
 }
 // waves per row of the single-block k_colA: enough workgroups to fill the
-// chip; the batched solve uses its tuned value for every block
-inline int single_wpr(int64_t m) { return m <= 2560 ? 4 : (m <= 8192 ? 2 : 1); }
+// chip, and above LDS_M rows the LDS-staged form; the batched solve uses its
+// tuned value for every block
+constexpr int64_t LDS_M = 4096;
+inline int single_wpr(int64_t m) { return m <= 2560 ? 4 : (m <= LDS_M ? 2 : 0); }
 
 // relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
 __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
@@ -214,6 +219,7 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
     t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, 4)) * 16);
     t.scr = (double *)take(size_t(K) * (4 + CMAX) * n * 8);
     t.wref = (double *)take(size_t(K) * 8);
+    t.Tm = (double2 *)take(size_t(std::max<int64_t>(cdiv(n - 1, NBK), 1)) * NBK * NBK * 16);
   }
   if (w) *w = t;
   return off;
@@ -489,6 +495,119 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
     y[r] = yr;
     V[int64_t(ir) * ldv + r] = v;
     yv = cmulc(yr, v);
+  }
+  const double yr = block_sum<ENT>(yv.x, sh);
+  const double yi = block_sum<ENT>(yv.y, sh);
+  if (tid == 0) parta[wg] = double2{yr, yi};
+}
+
+// k_colA for large trailing blocks: LDS_RW rows per wave, 4 LDS_RW rows per
+// workgroup.  The current column is staged in LDS in chunks of CCH entries,
+// so each workgroup reads it from L2 once for all its rows instead of once
+// per row (FP64 column entries are twice the bytes of FP32 A entries); every
+// lane keeps LDS_RW x U row loads in flight.  Same results as b_colA.
+template <typename TA>
+__device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
+                                           const TA *__restrict__ A, int64_t lda,
+                                           double2 *__restrict__ V, int64_t ldv,
+                                           const double2 *__restrict__ col,
+                                           const double2 *__restrict__ partb, int np,
+                                           double2 *__restrict__ tau, double2 *__restrict__ scl,
+                                           double *__restrict__ d, double *__restrict__ e,
+                                           double2 *__restrict__ y, double2 *__restrict__ parta,
+                                           int wg) {
+  typedef typename C2T<TA>::t CA;
+  constexpr int RW = LDS_RW, RWG = (ENT / 64) * RW;
+  constexpr int CCH = 2048;     // column entries per LDS chunk (32 KB)
+  constexpr int U = 16 / RW;    // columns per lane per pass: RW U = 16 loads in flight
+  __shared__ double sh[ENT / 64];
+  __shared__ double2 xs[CCH];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m0 = jn + 1;
+  const bool last = m0 >= n;
+  const int64_t mc = std::min<int64_t>(m0, n - 1);
+  const int64_t rbase = m0 + int64_t(wg) * RWG + int64_t(wv) * RW;
+  double2 px[PMAX / ENT];
+#pragma unroll
+  for (int u = 0; u < PMAX / ENT; ++u) px[u] = partb[int64_t(std::min(tid + ENT * u, np - 1)) * PS];
+  const double2 cjn = col[jn], cm0 = col[mc];
+  const CA *arow[RW];
+  double2 a0[RW], cr[RW];
+  double sr[RW], si[RW];
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    const int64_t rk = std::min<int64_t>(rbase + k, n - 1);
+    arow[k] = reinterpret_cast<const CA *>(A) + rk * lda;
+    a0[k] = to_d2(arow[k][mc]);
+    cr[k] = col[rk];
+    sr[k] = si[k] = 0.0;
+  }
+  for (int64_t c0 = m0 + 1; c0 < n; c0 += CCH) {
+    const int cn = int(std::min<int64_t>(CCH, n - c0));
+    __syncthreads();
+    for (int t = tid; t < cn; t += ENT) xs[t] = col[c0 + t];
+    __syncthreads();
+    int cc = lane;
+    for (; cc + (U - 1) * 64 < cn; cc += U * 64) {
+      CA a[RW][U];
+#pragma unroll
+      for (int k = 0; k < RW; ++k)
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[k][u] = arow[k][c0 + cc + 64 * u];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double2 x = xs[cc + 64 * u];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+          const double2 av = to_d2(a[k][u]);
+          sr[k] += av.x * x.x - av.y * x.y;
+          si[k] += av.x * x.y + av.y * x.x;
+        }
+      }
+    }
+    for (; cc < cn; cc += 64) {
+      const double2 x = xs[cc];
+#pragma unroll
+      for (int k = 0; k < RW; ++k) {
+        const double2 av = to_d2(arow[k][c0 + cc]);
+        sr[k] += av.x * x.x - av.y * x.y;
+        si[k] += av.x * x.y + av.y * x.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    sr[k] = wave_sum(sr[k]);
+    si[k] = wave_sum(si[k]);
+  }
+  double s1 = 0;
+#pragma unroll
+  for (int u = 0; u < PMAX / ENT; ++u)
+    if (tid + ENT * u < np) s1 += px[u].x;
+  const double S1 = block_sum<ENT>(s1, sh);
+  if (wg == 0 && tid == 0) d[jn] = cjn.x;
+  if (last) return;
+  double beta;
+  double2 tj, sc;
+  householder(cm0, S1, beta, tj, sc);
+  if (wg == 0 && tid == 0) {
+    e[jn] = beta;
+    tau[m0] = tj;
+    scl[m0] = sc;
+  }
+  double2 yv = {0, 0};
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      const int64_t r = rbase + k;
+      if (r < n) {
+        const double2 yr = cadd(a0[k], cmul(sc, double2{sr[k], si[k]}));
+        const double2 v = r == m0 ? double2{1, 0} : cmul(sc, cr[k]);
+        y[r] = yr;
+        V[int64_t(ir) * ldv + r] = v;
+        yv = cadd(yv, cmulc(yr, v));
+      }
+    }
   }
   const double yr = block_sum<ENT>(yv.x, sh);
   const double yi = block_sum<ENT>(yv.y, sh);
@@ -966,9 +1085,14 @@ BSE_PAIR(col0, int64_t j0 BSE_COMMA int cur, {
   b_col0<TA>(D.n, j0, (const TA *)D.A, D.lda, D.col, cur ? D.partb1 : D.partb0, wg);
 })
 BSE_PAIR(colA, int64_t jn BSE_COMMA int cur, {
-  b_colA<TA, WPR>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
-                  cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
-                  D.parta, wg);
+  if constexpr (WPR == 0)
+    b_colA_lds<TA>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
+                   cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
+                   D.parta, wg);
+  else
+    b_colA<TA, WPR>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
+                    cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
+                    D.parta, wg);
 })
 BSE_PAIR(colB, int64_t jn BSE_COMMA int cur, {
   const int64_t m = D.n - jn - 1;
@@ -1040,6 +1164,7 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
 //             vectors and are orthogonalised in order, so a cluster gets an
 //             orthonormal basis of its invariant subspace
 //   k_backxf  x = Q0 H(0) H(1) ... H(n-2) z, applying the stored reflectors
+//             a panel at a time (block form below)
 //   k_hx_part partial sums of x^dag H_mu x and |x|^2 (one wave per row)
 //   k_rq_fin  theta = Re(x^dag H_mu x) / |x|^2 replaces omega[l]; the pole of
 //             a cluster inside the refined range becomes the mean of its members
@@ -1048,62 +1173,117 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
 // storage of the working copy) is removed; errors of H_mu are not.
 // ---------------------------------------------------------------------------
 // (T - sigma) x = rhs for symmetric tridiagonal T (diag d, off-diag e) by
-// Gaussian elimination with partial pivoting; serial, scratch 4 n doubles.
+// Gaussian elimination with partial pivoting (rows i and i + 1), one thread.
+// The running diagonal and superdiagonal entries are carried in registers and
+// the read-only inputs are fetched TCH entries ahead of their use, so the
+// serial chain waits on arithmetic rather than on memory.  Stored factors:
+// ddi[i] = 1 / pivot_i, du[i], du2[i] (second superdiagonal from an
+// interchange), dl[i] (multiplier), piv[i] = 1 if rows i, i + 1 were swapped.
+constexpr int TCH = 16;
 __device__ void tri_solve(int64_t n, const double *__restrict__ d, const double *__restrict__ e,
-                          double sigma, double tiny, double *__restrict__ dd,
+                          double sigma, double tiny, double *__restrict__ ddi,
                           double *__restrict__ du, double *__restrict__ du2,
-                          double *__restrict__ dl, double *__restrict__ x) {
-  for (int64_t i = 0; i < n; ++i) dd[i] = d[i] - sigma;
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    du[i] = e[i];
-    dl[i] = e[i];
-  }
-  // factorisation; dl[i] < 0 encodes "rows i and i+1 swapped" through du2 usage
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    if (fabs(dd[i]) >= fabs(dl[i])) {
-      const double piv = fabs(dd[i]) < tiny ? (dd[i] < 0 ? -tiny : tiny) : dd[i];
-      dd[i] = piv;
-      const double f = dl[i] / piv;
-      dl[i] = f;
-      dd[i + 1] -= f * du[i];
-      du2[i] = 0.0;
-      x[i] = 0.0;  // marker: no interchange
-    } else {
-      const double f = dd[i] / dl[i];
-      dd[i] = dl[i];
-      dl[i] = f;
-      const double t = du[i];
-      du[i] = dd[i + 1];
-      dd[i + 1] = t - f * dd[i + 1];
-      if (i + 2 < n) {
-        du2[i] = du[i + 1];
-        du[i + 1] = -f * du[i + 1];
-      } else {
+                          double *__restrict__ dl, double *__restrict__ piv) {
+  double cd = d[0] - sigma;         // current diagonal entry of row i
+  double cu = n > 1 ? e[0] : 0.0;   // current superdiagonal entry of row i
+  for (int64_t i0 = 0; i0 + 1 < n; i0 += TCH) {
+    double dn[TCH], en[TCH], eu[TCH];
+#pragma unroll
+    for (int k = 0; k < TCH; ++k) {
+      const int64_t i = i0 + k;
+      const int64_t i1 = std::min<int64_t>(i + 1, n - 1), i0c = std::min<int64_t>(i, n - 2);
+      const int64_t i2 = std::min<int64_t>(i + 1, n - 2);
+      dn[k] = d[i1] - sigma;
+      en[k] = e[i0c];
+      eu[k] = i + 2 < n ? e[i2] : 0.0;  // select on a loaded value
+    }
+#pragma unroll
+    for (int k = 0; k < TCH; ++k) {
+      const int64_t i = i0 + k;
+      if (i + 1 >= n) break;
+      const double bl = en[k];
+      if (fabs(cd) >= fabs(bl)) {
+        const double pv = fabs(cd) < tiny ? (cd < 0 ? -tiny : tiny) : cd;
+        const double ip = 1.0 / pv, f = bl * ip;
+        ddi[i] = ip;
+        dl[i] = f;
+        du[i] = cu;
         du2[i] = 0.0;
+        piv[i] = 0.0;
+        cd = dn[k] - f * cu;
+        cu = eu[k];
+      } else {
+        const double ib = 1.0 / bl, f = cd * ib;
+        ddi[i] = ib;
+        dl[i] = f;
+        du[i] = dn[k];
+        du2[i] = eu[k];
+        piv[i] = 1.0;
+        cd = cu - f * dn[k];
+        cu = -f * eu[k];
       }
-      x[i] = 1.0;  // marker: rows i, i+1 interchanged
     }
   }
-  if (fabs(dd[n - 1]) < tiny) dd[n - 1] = dd[n - 1] < 0 ? -tiny : tiny;
+  if (fabs(cd) < tiny) cd = cd < 0 ? -tiny : tiny;
+  ddi[n - 1] = 1.0 / cd;
 }
 
 // solves with the factors of tri_solve; b holds the right-hand side on entry
-// and the solution on exit; piv are the interchange markers left in x
-__device__ void tri_apply(int64_t n, const double *__restrict__ dd, const double *__restrict__ du,
-                          const double *__restrict__ du2, const double *__restrict__ dl,
-                          const double *__restrict__ piv, double *__restrict__ b) {
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    if (piv[i] == 0.0) {
-      b[i + 1] -= dl[i] * b[i];
-    } else {
-      const double t = b[i];
-      b[i] = b[i + 1];
-      b[i + 1] = t - dl[i] * b[i];
+// and the solution on exit
+__device__ void tri_apply(int64_t n, const double *__restrict__ ddi,
+                          const double *__restrict__ du, const double *__restrict__ du2,
+                          const double *__restrict__ dl, const double *__restrict__ piv,
+                          double *__restrict__ b) {
+  double cb = b[0];
+  for (int64_t i0 = 0; i0 + 1 < n; i0 += TCH) {
+    double bn[TCH], l[TCH], pv[TCH];
+#pragma unroll
+    for (int k = 0; k < TCH; ++k) {
+      const int64_t i = i0 + k;
+      const int64_t i1 = std::min<int64_t>(i + 1, n - 1), ic = std::min<int64_t>(i, n - 2);
+      bn[k] = b[i1];
+      l[k] = dl[ic];
+      pv[k] = piv[ic];
+    }
+#pragma unroll
+    for (int k = 0; k < TCH; ++k) {
+      const int64_t i = i0 + k;
+      if (i + 1 >= n) break;
+      if (pv[k] == 0.0) {
+        b[i] = cb;
+        cb = bn[k] - l[k] * cb;
+      } else {
+        b[i] = bn[k];
+        cb = cb - l[k] * bn[k];
+      }
     }
   }
-  b[n - 1] /= dd[n - 1];
-  if (n > 1) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
-  for (int64_t i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+  double x1 = cb * ddi[n - 1];  // b[n - 1]
+  b[n - 1] = x1;
+  if (n < 2) return;
+  double x0 = (b[n - 2] - du[n - 2] * x1) * ddi[n - 2];
+  b[n - 2] = x0;
+  for (int64_t i0 = n - 3; i0 >= 0; i0 -= TCH) {
+    double bb[TCH], u1[TCH], u2[TCH], q[TCH];
+#pragma unroll
+    for (int k = 0; k < TCH; ++k) {
+      const int64_t i = i0 - k;
+      const int64_t ic = i >= 0 ? i : 0;
+      bb[k] = b[ic];
+      u1[k] = du[ic];
+      u2[k] = du2[ic];
+      q[k] = ddi[ic];
+    }
+#pragma unroll
+    for (int k = 0; k < TCH; ++k) {
+      const int64_t i = i0 - k;
+      if (i < 0) break;
+      const double xi = (bb[k] - u1[k] * x0 - u2[k] * x1) * q[k];
+      b[i] = xi;
+      x1 = x0;
+      x0 = xi;
+    }
+  }
 }
 
 __global__ __launch_bounds__(ENT) void k_invit(Desc D) {
@@ -1116,7 +1296,7 @@ __global__ __launch_bounds__(ENT) void k_invit(Desc D) {
   while (i > 0 && om[i] - om[i - 1] <= ctol) --i;
   const int64_t m = l - i;  // member index of l in its cluster
   double *scr = D.scr + size_t(l) * (4 + CMAX) * n;
-  double *dd = scr, *du = scr + n, *du2 = scr + 2 * n, *dl = scr + 3 * n;
+  double *ddi = scr, *du = scr + n, *du2 = scr + 2 * n, *dl = scr + 3 * n;
   double *mem = scr + 4 * n;  // [CMAX][n] vectors of the members so far
   double *z = D.Z + size_t(l) * n;
   if (m >= CMAX) {  // cluster too large to refine: mark, omega[l] stays
@@ -1130,10 +1310,10 @@ __global__ __launch_bounds__(ENT) void k_invit(Desc D) {
     for (int64_t k = tid; k < n; k += ENT) v[k] = 1.0 + 0.5 * sin(0.7 * double(k + 1) * double(q + 1));
     __syncthreads();
     double *piv = z;  // interchange markers (z is written at the end)
-    if (tid == 0) tri_solve(n, D.d, D.e, sigma, tiny, dd, du, du2, dl, piv);
+    if (tid == 0) tri_solve(n, D.d, D.e, sigma, tiny, ddi, du, du2, dl, piv);
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
-      if (tid == 0) tri_apply(n, dd, du, du2, dl, piv, v);
+      if (tid == 0) tri_apply(n, ddi, du, du2, dl, piv, v);
       __syncthreads();
       // orthogonalise against the earlier members (modified Gram-Schmidt), normalise
       for (int64_t p = 0; p < q; ++p) {
@@ -1156,21 +1336,161 @@ __global__ __launch_bounds__(ENT) void k_invit(Desc D) {
   for (int64_t k = tid; k < n; k += ENT) z[k] = v[k];
 }
 
+// Block form of the back-transformation.  The reflectors of columns
+// j0 .. j0 + b - 1 (one panel, b <= NBK) multiply as
+//     H(j0) H(j0 + 1) ... H(j0 + b - 1) = I - V T V^dag
+// with T upper triangular: T[i][i] = tau_i and
+//     T[0:i, i] = -tau_i T[0:i, 0:i] (V[:, 0:i]^dag v_i)
+// (the forward, column-wise accumulation of the compact WY form).
+//   k_bx_tmat     one workgroup per panel: the Gram products v_k^dag v_i
+//                 (k < i) over LDS-staged row chunks, then T
+//   k_backxf      one workgroup per vector, panels from the last to the
+//                 first: w = V^dag x (one block reduction per panel), t = T w,
+//                 x -= V t; then the initial reflection.  Each thread owns
+//                 the rows tid + ENT q of x throughout.
+constexpr int BXR = 128;  // rows of a panel staged per chunk in k_bx_tmat
+
+__global__ __launch_bounds__(ENT) void k_bx_tmat(Desc D) {
+  constexpr int NP = NBK * (NBK - 1) / 2;  // pairs k < i
+  __shared__ double2 vs[BXR][NBK];
+  __shared__ double2 gs[NBK][NBK];
+  __shared__ double2 ts[NBK][NBK];
+  __shared__ unsigned char pk[NP], pi[NP];
+  const int64_t n = D.n, ldv = D.ldv;
+  const int tid = threadIdx.x;
+  const int64_t j0 = int64_t(blockIdx.x) * NBK;
+  const int bp = int(std::min<int64_t>(NBK, n - 1 - j0));
+  for (int q = tid; q < NP; q += ENT) {
+    int i = 1;
+    while ((i + 1) * i / 2 <= q) ++i;
+    pi[q] = (unsigned char)i;
+    pk[q] = (unsigned char)(q - i * (i - 1) / 2);
+  }
+  for (int q = tid; q < NBK * NBK; q += ENT) ts[q / NBK][q % NBK] = double2{0, 0};
+  __syncthreads();
+  double2 acc[(NP + ENT - 1) / ENT];
+#pragma unroll
+  for (int u = 0; u < (NP + ENT - 1) / ENT; ++u) acc[u] = double2{0, 0};
+  for (int64_t r0 = j0 + 1; r0 < n; r0 += BXR) {
+    __syncthreads();
+    for (int q = tid; q < BXR * NBK; q += ENT) {
+      const int rr = q % BXR, c = q / BXR;
+      const int64_t row = r0 + rr;
+      vs[rr][c] = (c < bp && row < n && row >= j0 + c + 1) ? D.Vall[(j0 + c) * ldv + row]
+                                                           : double2{0, 0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (NP + ENT - 1) / ENT; ++u) {
+      const int q = tid + ENT * u;
+      if (q < NP) {
+        const int k = pk[q], i = pi[q];
+        double2 a = acc[u];
+        for (int rr = 0; rr < BXR; ++rr) a = cadd(a, cmulc(vs[rr][k], vs[rr][i]));
+        acc[u] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < (NP + ENT - 1) / ENT; ++u) {
+    const int q = tid + ENT * u;
+    if (q < NP) gs[pk[q]][pi[q]] = acc[u];
+  }
+  __syncthreads();
+  for (int i = 0; i < bp; ++i) {
+    const double2 ti = D.tau[j0 + i + 1];
+    if (tid < i) {
+      double2 sacc = {0, 0};
+      for (int m = tid; m < i; ++m) sacc = cadd(sacc, cmul(ts[tid][m], gs[m][i]));
+      ts[tid][i] = cmul(double2{-ti.x, -ti.y}, sacc);
+    }
+    if (tid == i) ts[i][i] = ti;
+    __syncthreads();
+  }
+  double2 *T = D.Tm + size_t(blockIdx.x) * NBK * NBK;
+  for (int q = tid; q < NBK * NBK; q += ENT) T[q] = ts[q / NBK][q % NBK];
+}
+
 __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
   __shared__ double sh[ENT / 64];
-  const int64_t n = D.n, l = blockIdx.x;
-  const int tid = threadIdx.x;
+  __shared__ double2 sw[ENT / 64][NBK];
+  __shared__ double2 st[NBK];
+  const int64_t n = D.n, ldv = D.ldv, l = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double *z = D.Z + size_t(l) * n;
   double2 *x = D.X + size_t(l) * n;
   for (int64_t k = tid; k < n; k += ENT) x[k] = double2{z[k], 0.0};
-  __syncthreads();
-  for (int64_t jn = n - 2; jn >= -1; --jn) {
-    // jn >= 0: reflector of column jn (rows jn+1 ..), jn = -1: the initial reflection
-    const double2 *v = jn >= 0 ? D.Vall + size_t(jn) * D.ldv : D.vbuf;
-    const int64_t r0 = jn + 1;
-    const double2 t = D.tau[jn + 1];
+  const int64_t npan = n >= 2 ? cdiv(n - 1, NBK) : 0;
+  for (int64_t p = npan - 1; p >= 0; --p) {
+    const int64_t j0 = p * NBK;
+    const int bp = int(std::min<int64_t>(NBK, n - 1 - j0));
+    const double2 *V = D.Vall + j0 * ldv;
+    const double2 *T = D.Tm + size_t(p) * NBK * NBK;
+    // w = V^dag x over the panel's rows (v_c is zero above row j0 + c + 1)
+    double2 w[NBK];
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) w[c] = double2{0, 0};
+    // every load is unconditional (column index clamped in bounds) and the
+    // support mask is applied to the value, so the loads of a row overlap
+    for (int64_t r = (j0 + 1) / ENT * ENT + tid; r < n; r += ENT) {
+      if (r < j0 + 1) continue;
+      const double2 xr = x[r];
+      double2 vr[NBK];
+#pragma unroll
+      for (int c = 0; c < NBK; ++c) vr[c] = V[std::min(c, bp - 1) * ldv + r];
+#pragma unroll
+      for (int c = 0; c < NBK; ++c) {
+        const double2 t = cmulc(vr[c], xr);
+        const bool ok = c < bp && r >= j0 + c + 1;
+        w[c].x += ok ? t.x : 0.0;
+        w[c].y += ok ? t.y : 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) {
+      w[c].x = wave_sum(w[c].x);
+      w[c].y = wave_sum(w[c].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < NBK; ++c) sw[wv][c] = w[c];
+    }
+    __syncthreads();
+    if (tid < bp) {  // t = T w (T upper triangular)
+      double2 tc = {0, 0};
+      for (int m = tid; m < bp; ++m) {
+        double2 wm = sw[0][m];
+        for (int q = 1; q < ENT / 64; ++q) wm = cadd(wm, sw[q][m]);
+        tc = cadd(tc, cmul(T[tid * NBK + m], wm));
+      }
+      st[tid] = tc;
+    }
+    __syncthreads();
+    double2 tc[NBK];
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) tc[c] = st[c];
+    for (int64_t r = (j0 + 1) / ENT * ENT + tid; r < n; r += ENT) {
+      if (r < j0 + 1) continue;
+      double2 xr = x[r];
+      double2 vr[NBK];
+#pragma unroll
+      for (int c = 0; c < NBK; ++c) vr[c] = V[std::min(c, bp - 1) * ldv + r];
+#pragma unroll
+      for (int c = 0; c < NBK; ++c) {
+        const double2 t = cmul(vr[c], tc[c]);
+        const bool ok = c < bp && r >= j0 + c + 1;
+        xr.x -= ok ? t.x : 0.0;
+        xr.y -= ok ? t.y : 0.0;
+      }
+      x[r] = xr;
+    }
+    __syncthreads();
+  }
+  {  // the initial reflection (rows 0 ..)
+    const double2 *v = D.vbuf;
+    const double2 t = D.tau[0];
     double sr = 0, si = 0;
-    for (int64_t r = r0 + tid; r < n; r += ENT) {
+    for (int64_t r = tid; r < n; r += ENT) {
       const double2 c = cmulc(v[r], x[r]);
       sr += c.x;
       si += c.y;
@@ -1178,8 +1498,7 @@ __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
     sr = block_sum<ENT>(sr, sh);
     si = block_sum<ENT>(si, sh);
     const double2 f = cmul(t, double2{sr, si});
-    for (int64_t r = r0 + tid; r < n; r += ENT) x[r] = csub(x[r], cmul(f, v[r]));
-    __syncthreads();
+    for (int64_t r = tid; r < n; r += ENT) x[r] = csub(x[r], cmul(f, v[r]));
   }
 }
 
@@ -1310,8 +1629,10 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
         BSE_COLA(4)
       } else if (wpr == 2) {
         BSE_COLA(2)
-      } else {
+      } else if (wpr == 1) {
         BSE_COLA(1)
+      } else {
+        BSE_COLA(0)
       }
 #undef BSE_COLA
       if (m <= 0) break;  // last diagonal element recorded; nothing below it
@@ -1331,6 +1652,8 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
   if (K > 0) {
     D = D0;
     BSE_LAUNCH("k_invit", k_invit, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    if (n >= 2)
+      BSE_LAUNCH("k_bx_tmat", k_bx_tmat, dim3((unsigned)cdiv(n - 1, NBK)), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_backxf", k_backxf, dim3((unsigned)K), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, 4), (unsigned)K), dim3(ENT), 0,
                s, D);

@@ -229,6 +229,50 @@ def test_eigh_known_spectrum_fp32(lib, n, mult):
     assert np.abs(om - np.sort(lam)).max() < 2e-5
 
 
+def _householder_hermitian(n, seed, mult=1, spread=10.0, nref=3):
+    """A = Q diag(lam) Q^dag with Q a product of nref random reflectors: a
+    dense Hermitian matrix of known spectrum and weights |Q^dag b|^2, built in
+    O(n^2)."""
+    rng = np.random.default_rng(seed)
+    nd = (n + mult - 1) // mult
+    lam = np.repeat(np.sort(rng.uniform(-spread, spread, nd)), mult)[:n]
+    A = np.diag(lam).astype(np.complex128)
+    us = []
+    for _ in range(nref):
+        u = rng.normal(size=n) + 1j * rng.normal(size=n)
+        u /= np.linalg.norm(u)
+        us.append(u)
+        Au = A @ u
+        uA = u.conj() @ A
+        A = A - 2 * np.outer(u, uA) - 2 * np.outer(Au, u.conj()) + 4 * (u.conj() @ Au) * np.outer(u, u.conj())
+    A = 0.5 * (A + A.conj().T)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    qb = b.copy()  # A = Q diag(lam) Q^dag with Q = H_nref ... H_1: Q^dag b = H_1 ... H_nref b
+    for u in reversed(us):
+        qb = qb - 2 * u * (u.conj() @ qb)
+    return A, b, lam, qb
+
+
+@pytest.mark.parametrize("precname,mult", [("FP64", 1), ("FP64", 3), ("FP32", 1)])
+def test_eigh_large_blocks(lib, precname, mult):
+    """n = 4500: the first columns of the reduction take the LDS-staged HEMV
+    (trailing blocks above 4096 rows), the rest the row-parallel one."""
+    n = 4500
+    say("eigh-large", precname, mult)
+    A, b, lam, qb = _householder_hermitian(n, seed=45 + mult, mult=mult)
+    h_dtype = torch.complex128 if precname == "FP64" else torch.complex64
+    om, po, os_ = _gpu_eigh(lib, A, b, getattr(lib, precname), h_dtype)
+    err = np.abs(om - np.sort(lam)).max()
+    say("  max eigenvalue error", err)
+    assert err < (1e-11 * np.abs(lam).max() if precname == "FP64" else 1e-4)
+    if precname == "FP64":
+        w = np.abs(qb) ** 2
+        st = OB.clusters(lam, 1e-9)
+        ce = np.array([lam[st[i]] for i in range(len(st) - 1)])
+        cw = np.array([w[st[i]:st[i + 1]].sum() for i in range(len(st) - 1)])
+        _match_poles(po, os_, ce, cw, 1e-9)
+
+
 @pytest.mark.parametrize("n,mult,K", [(64, 1, 20), (162, 3, 100), (257, 1, 100),
                                        (600, 3, 100), (1, 1, 5)])
 def test_eigh_refinement(lib, n, mult, K):
