@@ -164,11 +164,11 @@ __host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
   const int64_t j0 = jn - jn % NBK;
   return (jn % NBK) + 1 < g_nbk(n, j0) ? 1 : 0;
 }
-// waves per row of the single-block k_colA: enough workgroups to fill the
-// chip, and above LDS_M rows the LDS-staged form; the batched solve uses its
-// tuned value for every block
-constexpr int64_t LDS_M = 4096;
-inline int single_wpr(int64_t m) { return m <= 2560 ? 4 : (m <= LDS_M ? 2 : 0); }
+// waves per row of the single-block k_colA: one row per workgroup up to
+// LDS_M trailing rows (latency-bound), the LDS-staged form above (measured
+// best at n = 720, 2160 and 10080); the batched solve uses its tuned value
+constexpr int64_t LDS_M = 1024;
+inline int single_wpr(int64_t m) { return m > LDS_M ? 0 : 4; }
 
 // relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
 __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {

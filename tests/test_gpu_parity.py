@@ -255,8 +255,9 @@ def _householder_hermitian(n, seed, mult=1, spread=10.0, nref=3):
 
 @pytest.mark.parametrize("precname,mult", [("FP64", 1), ("FP64", 3), ("FP32", 1)])
 def test_eigh_large_blocks(lib, precname, mult):
-    """n = 4500: the first columns of the reduction take the LDS-staged HEMV
-    (trailing blocks above 4096 rows), the rest the row-parallel one."""
+    """n = 4500: most columns of the reduction take the LDS-staged HEMV
+    (trailing blocks above 1024 rows, several LDS chunks), the rest the
+    row-parallel one."""
     n = 4500
     say("eigh-large", precname, mult)
     A, b, lam, qb = _householder_hermitian(n, seed=45 + mult, mult=mult)
