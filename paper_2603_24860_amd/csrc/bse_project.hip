@@ -71,18 +71,22 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
   // chunk loads go to registers; the next chunk's loads are in flight while
   // the current one is contracted from LDS
   C2 x[PCH / PNT];
+  // every load is issued unconditionally from a clamped, in-bounds index and
+  // entries past the chunk are zeroed afterwards, so the loads do not wait on
+  // one another
   auto fetch = [&](int i0) {
     const int nr = std::min(RU, L1 - i0);
 #pragma unroll
     for (int u = 0; u < PCH / PNT; ++u) {
-      const int e = threadIdx.x + PNT * u;
-      x[u] = C2{0, 0};
-      if (e < nr * per) {
-        const int ii = e / per, rem = e - ii * per, i2 = rem / nb, b2 = rem - i2 * nb;
-        const int64_t a = (int64_t(m1s[i0 + ii]) * nv + v) * nc + c;
-        x[u] = reinterpret_cast<const C2 *>(H)[a * ldh + int64_t(m2s[i2]) * nb + b2];
-      }
+      const int e0 = threadIdx.x + PNT * u;
+      const int e = std::min(e0, nr * per - 1);
+      const int ii = e / per, rem = e - ii * per, i2 = rem / nb, b2 = rem - i2 * nb;
+      const int64_t a = (int64_t(m1s[i0 + ii]) * nv + v) * nc + c;
+      x[u] = reinterpret_cast<const C2 *>(H)[a * ldh + int64_t(m2s[i2]) * nb + b2];
     }
+#pragma unroll
+    for (int u = 0; u < PCH / PNT; ++u)
+      if (threadIdx.x + PNT * u >= nr * per) x[u] = C2{0, 0};
   };
   fetch(0);
   for (int i0 = 0; i0 < L1; i0 += RU) {
