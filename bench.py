@@ -182,11 +182,12 @@ def bench_batched(args):
     bs.close()
 
 
-def bench_served(args):
+def bench_served(args, large=False):
     """Served form: a Poisson stream of BSE solve requests over a mix of
-    resident systems (cubic cfg1 / cfg2 shapes and three layered D6h systems of
-    the batched family), FP32 or split-BF16 builds, continuous batching on four
-    streams with admission by HBM footprint (288 GB)."""
+    resident systems (cubic cfg1 / cfg2 / cfg3 shapes and three layered D6h
+    systems of the batched family, blocks of 162 to 10080), FP32 builds or
+    split-BF16 builds with FP64 refinement, continuous batching on four streams
+    with admission by HBM footprint (288 GB)."""
     import torch
     import synth
     import workloads
@@ -200,6 +201,8 @@ def bench_served(args):
             pick[c["grid"][0]] = c
     cfgs = {"cfg1": synth.config("cfg1"), "cfg2": synth.config("cfg2"),
             "d6h-8": pick[8], "d6h-13": pick[13], "d6h-20": pick[20]}
+    if large:
+        cfgs["cfg3"] = synth.config("cfg3")
     t0 = time.perf_counter()
     sysobjs = {}
     for name, c in cfgs.items():
@@ -215,10 +218,14 @@ def bench_served(args):
         ref[name] = r["lowest"]
         grids[name] = synth.omega_grid_from_range(r["omega"].min(), r["omega"].max())
     log(f"setup {time.perf_counter() - t0:.1f} s")
-    mix = [("cfg1", "fp32", B.FP32, 0.15), ("cfg1", "fp32", B.BF16X3, 0.10),
-           ("cfg2", "fp32", B.FP32, 0.15), ("cfg2", "fp32", B.BF16X3, 0.15),
-           ("d6h-8", "fp32", B.FP32, 0.10), ("d6h-13", "fp32", B.BF16X3, 0.15),
-           ("d6h-20", "fp32", B.FP32, 0.20)]
+    # (system, input class, build precision, weight, FP64 refinement of the lowest K):
+    # split-BF16 requests are refined
+    mix = [("cfg1", "fp32", B.FP32, 0.15, 0), ("cfg1", "fp32", B.BF16X3, 0.10, 100),
+           ("cfg2", "fp32", B.FP32, 0.15, 0), ("cfg2", "fp32", B.BF16X3, 0.15, 100),
+           ("d6h-8", "fp32", B.FP32, 0.10, 0), ("d6h-13", "fp32", B.BF16X3, 0.15, 100),
+           ("d6h-20", "fp32", B.FP32, 0.20, 0)]
+    if large:  # a small share of cfg3 requests (T1u block 10080)
+        mix += [("cfg3", "fp32", B.FP32, 0.02, 0), ("cfg3", "fp32", B.BF16X3, 0.02, 100)]
     wts = np.array([m[3] for m in mix])
     wts /= wts.sum()
 
@@ -231,26 +238,26 @@ def bench_served(args):
     def draw(count, fp64=False):
         out = []
         for i in range(count):
-            name, cls, prec, _ = mix[int(rng.choice(len(mix), p=wts))]
+            name, cls, prec, _, nref = mix[int(rng.choice(len(mix), p=wts))]
             out.append(Request(i, f"{name}/fp64" if fp64 else f"{name}/{cls}",
-                               B.FP64 if fp64 else prec, 0.0))
+                               B.FP64 if fp64 else prec, 0.0, 0 if fp64 else nref))
         return out
 
     # warm-up of every request type
     server(4).run(draw(3 * len(mix)))
     # plain FP64 GPU form over the same mix, one request after the other
-    nplain = 150
+    nplain = 100 if large else 150
     t1 = time.perf_counter()
     server(1).run(draw(nplain, fp64=True))
     plain = nplain / (time.perf_counter() - t1)
     # saturation throughput of the served form
-    nsat = 400
+    nsat = 200 if large else 400
     t1 = time.perf_counter()
     server(4).run(draw(nsat))
     sat = nsat / (time.perf_counter() - t1)
     # Poisson arrivals at 0.8 x saturation
     lam = 0.8 * sat
-    nreq = max(1000, args.steps)
+    nreq = max(400 if large else 1000, args.steps)
     reqs = draw(nreq)
     t = 0.0
     for r in reqs:
@@ -275,10 +282,17 @@ def bench_served(args):
         "n_gpus": 1, "steps": len(done), "warmup": 3 * len(mix),
         "ms_per_step": round(wall * 1e3 / len(done), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32+bf16x3",
-        "data": "synthetic (seeded; resident cfg1/cfg2 cubic and three D6h systems)",
-        "config": {"workload": "cfg5: Poisson stream over cfg1 (T1u 162), cfg2 (T1u 2160) and "
-                               "D6h 8x8x1 / 13x13x1 / 20x20x1 (E1u) systems, FP32 or split-BF16 "
-                               "builds", "requests": len(done), "arrival_rate_per_s": round(lam, 3)},
+        "data": "synthetic (seeded; resident cubic cfg1/cfg2" + ("/cfg3" if large else "")
+                + " and three D6h systems)",
+        "config": {"workload": ("cfg5l" if large else "cfg5") + ": Poisson stream over cfg1 "
+                               "(T1u 162), cfg2 (T1u 2160), " + ("cfg3 (T1u 10080), " if large
+                                                                  else "")
+                               + "D6h 8x8x1 / 13x13x1 / 20x20x1 (E1u) systems, FP32 builds or "
+                               "split-BF16 builds with FP64 refinement of the lowest 100",
+                   "requests": len(done),
+                   "arrival_rate_per_s": round(lam, 3),
+                   "mix": [{"system": m[0], "precision": {B.FP32: "fp32", B.BF16X3: "bf16x3"}[m[2]],
+                            "weight": m[3], "nrefine": m[4]} for m in mix]},
         "latency_ms": {"p50": round(st["p50_ms"], 3), "p99": round(st["p99_ms"], 3),
                        "mean": round(st["mean_ms"], 3)},
         "saturation_solves_per_s": round(sat, 3),
@@ -299,7 +313,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg2",
                     help="cfg1 / cfg2 / cfg3: one system; cfg4: the batched form (64 D6h "
-                         "systems); cfg5: the served form (Poisson request stream)")
+                         "systems); cfg5: the served form (Poisson request stream); cfg5l: "
+                         "the served form with a share of cfg3 requests")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-q", type=int, default=32)
@@ -349,8 +364,8 @@ def main():
     from paper_2603_24860_amd.system import Solver
     if args.workload == "cfg4":
         return bench_batched(args)
-    if args.workload == "cfg5":
-        return bench_served(args)
+    if args.workload in ("cfg5", "cfg5l"):
+        return bench_served(args, large=args.workload == "cfg5l")
 
     prec = {"fp32": B.FP32, "fp64": B.FP64, "bf16x3": B.BF16X3}[args.prec]
     cfg = synth.config(args.workload)

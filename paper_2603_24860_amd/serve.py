@@ -7,11 +7,12 @@ admitted request's whole path -- bse_build, bse_project_blocks (the
 dipole-active block), bse_block_eigh, bse_spectrum, and the copy of the results
 to pinned host memory -- on one of `slots` HIP streams, so requests that are
 admitted while others run overlap on the device.  A request is admitted when a
-slot is free and its HBM footprint (H, H_mu, workspaces, outputs) fits into the
-budget left by the requests in flight; requests larger than the whole budget
-are rejected.  Completion is detected by a non-blocking event query, which
-frees the slot and the budget for the next waiting request (first come, first
-served).  Every request owns its buffers, so its result does not depend on
+slot is free, its HBM footprint (H, H_mu, workspaces, outputs) fits into the
+budget left by the requests in flight and, for a large request, the quota of
+large requests in flight is not used up; waiting requests are considered in
+arrival order and one that cannot start lets later ones pass.  Requests larger
+than the whole budget are rejected.  Completion is detected by a non-blocking
+event query, which frees the slot and the budget.  Every request owns its buffers, so its result does not depend on
 what else is in flight.
 """
 import math
@@ -28,11 +29,15 @@ EL = {B.FP64: 16, B.FP32: 8, B.BF16X3: 8}
 
 
 class Request:
-    __slots__ = ("rid", "system", "prec", "arrival", "start", "done", "result", "ev", "bufs",
-                 "footprint", "status")
+    """One solve: a registered system, the build precision, the arrival time
+    (seconds relative to the start of Server.run) and the number of lowest
+    eigenvalues to refine in FP64 (0: none)."""
+    __slots__ = ("rid", "system", "prec", "arrival", "nrefine", "start", "done", "result", "ev",
+                 "bufs", "footprint", "status")
 
-    def __init__(self, rid, system, prec, arrival):
+    def __init__(self, rid, system, prec, arrival, nrefine=0):
         self.rid, self.system, self.prec, self.arrival = rid, system, prec, arrival
+        self.nrefine = nrefine
         self.start = self.done = None
         self.result = None
         self.ev = None
@@ -53,21 +58,30 @@ class ServedSystem:
         self.w = torch.as_tensor(np.asarray(wgrid, dtype=np.float64), device=dev_system.device)
         self.eta = eta
 
-    def footprint(self, prec):
+    def footprint(self, prec, nrefine=0):
         s, n = self.s, self.blk.n
         el = EL[prec]
         eig_prec = B.FP32 if prec == B.BF16X3 else prec
         h64 = 1 if prec == B.FP64 else 0
         return (s.N * s.N * el + B.bse_build_ws(s.problem, prec) + n * n * el + 16 * n
-                + B.bse_block_eigh_ws(n, h64, eig_prec, 0) + 3 * 8 * n + 8 * self.w.numel())
+                + B.bse_block_eigh_ws(n, h64, eig_prec, nrefine) + 3 * 8 * n + 8 * self.w.numel())
 
 
 class Server:
-    def __init__(self, slots=4, hbm_budget=288e9, device="cuda"):
+    """slots: HIP streams (requests in flight); hbm_budget: bytes of HBM the
+    requests in flight may hold together; a request whose footprint exceeds
+    big_bytes is large, and at most big_slots large requests are in flight, so
+    small requests are not queued behind long ones."""
+
+    def __init__(self, slots=4, hbm_budget=288e9, device="cuda", big_bytes=4e9, big_slots=1):
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
         self.free = list(range(slots))
         self.budget = float(hbm_budget)
+        self.big_bytes = float(big_bytes)
+        self.big_slots = big_slots
+        self.big_inflight = 0
+        self.max_big = 0
         self.used = 0.0
         self.max_used = 0.0
         self.systems = {}
@@ -98,11 +112,11 @@ class Server:
             B.bse_project_blocks(s.problem, H, s.t["B"], [ss.blk.c], [Hmu], [Bmu], stream=h)
             del H, bws  # freed for later work on this stream only (stream-ordered pool)
             h64 = 1 if prec == B.FP64 else 0
-            ews = torch.empty(B.bse_block_eigh_ws(n, h64, eig_prec, 0), dtype=torch.uint8,
-                              device=self.device)
+            ews = torch.empty(B.bse_block_eigh_ws(n, h64, eig_prec, req.nrefine),
+                              dtype=torch.uint8, device=self.device)
             om = torch.empty(n, dtype=torch.float64, device=self.device)
             po, osc = torch.empty_like(om), torch.empty_like(om)
-            B.bse_block_eigh(Hmu, Bmu, eig_prec, om, po, osc, ews, stream=h)
+            B.bse_block_eigh(Hmu, Bmu, eig_prec, om, po, osc, ews, nrefine=req.nrefine, stream=h)
             e2 = torch.empty_like(ss.w)
             B.bse_spectrum(po, osc, 8 * math.pi / s.nk, ss.eta, ss.w, e2, stream=h)
             host = {k: torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
@@ -116,21 +130,31 @@ class Server:
 
     # -- scheduling --------------------------------------------------------
     def _admit(self, now):
-        while self.waiting and self.free:
-            req = self.waiting[0]
-            fp = self.systems[req.system].footprint(req.prec)
+        """Admit waiting requests in arrival order while a slot is free.  A
+        request that does not fit the HBM left or the large-request quota
+        waits, and later requests that do fit may pass it; a request larger
+        than the whole budget is rejected."""
+        i = 0
+        while self.free and i < len(self.waiting):
+            req = self.waiting[i]
+            fp = self.systems[req.system].footprint(req.prec, req.nrefine)
             if fp > self.budget:
-                self.waiting.popleft()
+                del self.waiting[i]
                 req.status = "rejected"
                 self.rejected.append(req)
                 continue
-            if self.used + fp > self.budget:
-                break  # first come, first served: wait for memory
-            self.waiting.popleft()
+            big = fp > self.big_bytes
+            if self.used + fp > self.budget or (big and self.big_inflight >= self.big_slots):
+                i += 1
+                continue
+            del self.waiting[i]
             slot = self.free.pop()
             req.footprint = fp
             self.used += fp
             self.max_used = max(self.max_used, self.used)
+            if big:
+                self.big_inflight += 1
+                self.max_big = max(self.max_big, self.big_inflight)
             req.start = now
             req.status = "running"
             self._launch(req, slot)
@@ -150,6 +174,8 @@ class Server:
             req.bufs = None
             req.ev = None
             self.used -= req.footprint
+            if req.footprint > self.big_bytes:
+                self.big_inflight -= 1
             self.free.append(slot)
             self.finished.append(req)
         return len(done)

@@ -9,6 +9,8 @@
 * Admission by HBM footprint: with a budget of 1.5 times the largest request,
   the memory in flight never exceeds the budget, and a request larger than
   the whole budget is rejected rather than run.
+* Large-request lane: requests above a footprint threshold run one at a time
+  while the others pass them in the queue; results unchanged.
 """
 import sys
 
@@ -49,33 +51,34 @@ def env():
     return B, refs, systems
 
 
-def _server(env, slots, budget=288e9):
+def _server(env, slots, budget=288e9, **kw):
     from paper_2603_24860_amd.serve import Server
     B, refs, systems = env
-    srv = Server(slots=slots, hbm_budget=budget)
+    srv = Server(slots=slots, hbm_budget=budget, **kw)
     for name, (ds, grid) in systems.items():
         srv.register(name, ds, grid)
     return srv
 
 
-TYPES = [("oh4/fp64", "FP64", 1e-9), ("oh4/fp32", "FP32", 1e-5), ("oh4/fp32", "BF16X3", 1e-4),
-         ("hex6/fp64", "FP64", 1e-9), ("hex6/fp32", "FP32", 1e-5),
-         ("hex6/fp32", "BF16X3", 1e-4)]
+TYPES = [("oh4/fp64", "FP64", 1e-9, 0), ("oh4/fp32", "FP32", 1e-5, 0),
+         ("oh4/fp32", "BF16X3", 1e-4, 0), ("oh4/fp32", "BF16X3", 1e-4, 100),
+         ("hex6/fp64", "FP64", 1e-9, 0), ("hex6/fp32", "FP32", 1e-5, 0),
+         ("hex6/fp32", "BF16X3", 1e-4, 100)]
 
 
 def _solo(env):
     from paper_2603_24860_amd.serve import Request
     B, refs, _ = env
     out = {}
-    for i, (sysname, pname, tol) in enumerate(TYPES):
+    for i, (sysname, pname, tol, nref) in enumerate(TYPES):
         srv = _server(env, 1)
-        done = srv.run([Request(i, sysname, getattr(B, pname), 0.0)])
+        done = srv.run([Request(i, sysname, getattr(B, pname), 0.0, nref)])
         res = done[0].result
         ref = refs[sysname.split("/")[0]]
         err = np.abs(res["lowest"] - ref["lowest"]).max()
-        say("solo", sysname, pname, "lowest-100 err", err)
+        say("solo", sysname, pname, "nrefine", nref, "lowest-100 err", err)
         assert err < tol
-        out[(sysname, pname)] = res
+        out[(sysname, pname, nref)] = res
     return out
 
 
@@ -86,8 +89,8 @@ def test_same_alone_and_in_the_mix(env):
     rng = np.random.default_rng(5)
     reqs = []
     for i in range(24):
-        sysname, pname, _ = TYPES[int(rng.integers(len(TYPES)))]
-        reqs.append(Request(i, sysname, getattr(B, pname), float(i) * 2.5e-4))
+        sysname, pname, _, nref = TYPES[int(rng.integers(len(TYPES)))]
+        reqs.append(Request(i, sysname, getattr(B, pname), float(i) * 2.5e-4, nref))
     srv = _server(env, 4)
     done = srv.run(reqs)
     assert len(done) == 24 and not srv.rejected
@@ -96,7 +99,8 @@ def test_same_alone_and_in_the_mix(env):
     say("mix: 24 requests, overlapping pairs", overlap, "max in flight bytes", srv.max_used)
     assert overlap > 0
     for r in done:
-        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec])]
+        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec],
+                    r.nrefine)]
         for k in ("omega", "pole", "osc", "eps2"):
             assert np.array_equal(r.result[k], ref[k]), (r.rid, r.system, k)
 
@@ -106,18 +110,40 @@ def test_admission_by_footprint(env):
     B = env[0]
     solo = _solo(env)
     srv = _server(env, 4)
-    fps = {(s, p): srv.systems[s].footprint(getattr(B, p)) for s, p, _ in TYPES}
+    fps = {(s, p, k): srv.systems[s].footprint(getattr(B, p), k) for s, p, _, k in TYPES}
     budget = 1.5 * max(fps.values())
     srv = _server(env, 4, budget=budget)
-    reqs = [Request(i, s, getattr(B, p), 0.0) for i, (s, p, _) in enumerate(TYPES * 3)]
+    reqs = [Request(i, s, getattr(B, p), 0.0, k) for i, (s, p, _, k) in enumerate(TYPES * 3)]
     done = srv.run(reqs)
     say("budget", budget, "max in flight", srv.max_used, "served", len(done))
     assert srv.max_used <= budget
     assert len(done) == len(reqs)
     for r in done:
-        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec])]
+        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec],
+                    r.nrefine)]
         assert np.array_equal(r.result["omega"], ref["omega"])
     # a request larger than the whole budget is rejected
     small = _server(env, 4, budget=0.5 * min(fps.values()))
     assert not small.run([Request(0, "oh4/fp32", B.FP32, 0.0)])
     assert len(small.rejected) == 1
+
+
+def test_large_request_lane(env):
+    """Requests above a footprint threshold (here the larger half of the
+    request types) run one at a time while the others pass them in the
+    queue; every result equals its solo result."""
+    from paper_2603_24860_amd.serve import Request
+    B = env[0]
+    solo = _solo(env)
+    srv = _server(env, 4)
+    fps = sorted({srv.systems[s].footprint(getattr(B, p), k) for s, p, _, k in TYPES})
+    mid = len(fps) // 2
+    srv = _server(env, 4, big_bytes=0.5 * (fps[mid - 1] + fps[mid]), big_slots=1)
+    reqs = [Request(i, s, getattr(B, p), 0.0, k) for i, (s, p, _, k) in enumerate(TYPES * 3)]
+    done = srv.run(reqs)
+    say("large lane: max large in flight", srv.max_big, "served", len(done))
+    assert srv.max_big == 1 and len(done) == len(reqs)
+    for r in done:
+        ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec],
+                    r.nrefine)]
+        assert np.array_equal(r.result["omega"], ref["omega"])
