@@ -251,7 +251,8 @@ int32_t bse_project_blocks(const bse_problem *p, const void *H, int64_t ldh, int
  * to O(delta^2 |Hmu|) for an eigenvector error delta; omega[0 .. K) then holds
  * the refined values (ascending) and the poles of clusters inside that range
  * are re-centred.  It removes the eigensolver's rounding, not errors already
- * in Hmu.  The workspace grows by about n^2 16 B (all reflectors) for K > 0.
+ * in Hmu.  The workspace grows by about n^2 16 B (all reflectors) plus
+ * 400 K n B (inverse-iteration scratch) for K > 0.
  * Errors: n < 1 or n > 65536 (BSE_ESHAPE), NULL pointers or nrefine outside
  * 0 .. 256 (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).
  * ------------------------------------------------------------------------- */

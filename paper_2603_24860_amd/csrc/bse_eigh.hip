@@ -124,7 +124,7 @@ struct Desc {
   double *Z;                 // [K][n] eigenvectors of T
   double2 *X;                // [K][n] their back-transforms
   double *rqp;               // [K][cdiv(n, 4)][2] partial Rayleigh quotients
-  double *scr;               // [K][(4 + CMAX) n] inverse-iteration scratch
+  double *scr;               // [K][6 CMAX n] inverse-iteration scratch
   double *wref;              // [K] refined eigenvalues
   double2 *Tm;               // [cdiv(n - 1, NBK)][NBK][NBK] block-reflector factors T
 };
@@ -217,7 +217,7 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
     t.Z = (double *)take(size_t(K) * n * 8);
     t.X = (double2 *)take(size_t(K) * n * 16);
     t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, 4)) * 16);
-    t.scr = (double *)take(size_t(K) * (4 + CMAX) * n * 8);
+    t.scr = (double *)take(size_t(K) * (6 * CMAX) * n * 8);
     t.wref = (double *)take(size_t(K) * 8);
     t.Tm = (double2 *)take(size_t(std::max<int64_t>(cdiv(n - 1, NBK), 1)) * NBK * NBK * 16);
   }
@@ -1286,36 +1286,43 @@ __device__ void tri_apply(int64_t n, const double *__restrict__ ddi,
   }
 }
 
+// The members of a cluster are iterated together: each inverse-iteration
+// step solves every member's system at once (one serial solver per wave,
+// each with its own shift), then orthonormalises the members in order
+// (Gram-Schmidt over the cluster).  Workgroup l returns member m = l - head.
+constexpr int INV_IT = 3;  // inverse-iteration steps
 __global__ __launch_bounds__(ENT) void k_invit(Desc D) {
   __shared__ double sh[ENT / 64];
   const int64_t n = D.n, l = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double ctol = D.tsc[4], tn = D.tsc[2];
   const double *om = D.omega;
   int64_t i = l;
   while (i > 0 && om[i] - om[i - 1] <= ctol) --i;
   const int64_t m = l - i;  // member index of l in its cluster
-  double *scr = D.scr + size_t(l) * (4 + CMAX) * n;
-  double *ddi = scr, *du = scr + n, *du2 = scr + 2 * n, *dl = scr + 3 * n;
-  double *mem = scr + 4 * n;  // [CMAX][n] vectors of the members so far
+  double *scr = D.scr + size_t(l) * (6 * CMAX) * n;
+  double *mem = scr + 5 * CMAX * n;  // [CMAX][n] member vectors
   double *z = D.Z + size_t(l) * n;
   if (m >= CMAX) {  // cluster too large to refine: mark, omega[l] stays
     for (int64_t k = tid; k < n; k += ENT) z[k] = __builtin_nan("");
     return;
   }
   const double tiny = 2.2e-16 * fmax(1.0, tn);
+  auto fac = [&](int64_t q, int f) { return scr + (5 * q + f) * n; };  // ddi du du2 dl piv
+  for (int64_t q = wv; q <= m; q += ENT / 64)
+    if (lane == 0) tri_solve(n, D.d, D.e, om[i + q], tiny, fac(q, 0), fac(q, 1), fac(q, 2), fac(q, 3),
+                             fac(q, 4));
   for (int64_t q = 0; q <= m; ++q) {
     double *v = mem + q * n;
-    const double sigma = om[i + q];
     for (int64_t k = tid; k < n; k += ENT) v[k] = 1.0 + 0.5 * sin(0.7 * double(k + 1) * double(q + 1));
+  }
+  __syncthreads();
+  for (int it = 0; it < INV_IT; ++it) {
+    for (int64_t q = wv; q <= m; q += ENT / 64)
+      if (lane == 0) tri_apply(n, fac(q, 0), fac(q, 1), fac(q, 2), fac(q, 3), fac(q, 4), mem + q * n);
     __syncthreads();
-    double *piv = z;  // interchange markers (z is written at the end)
-    if (tid == 0) tri_solve(n, D.d, D.e, sigma, tiny, ddi, du, du2, dl, piv);
-    __syncthreads();
-    for (int it = 0; it < 3; ++it) {
-      if (tid == 0) tri_apply(n, ddi, du, du2, dl, piv, v);
-      __syncthreads();
-      // orthogonalise against the earlier members (modified Gram-Schmidt), normalise
+    for (int64_t q = 0; q <= m; ++q) {  // modified Gram-Schmidt over the members, in order
+      double *v = mem + q * n;
       for (int64_t p = 0; p < q; ++p) {
         const double *u = mem + p * n;
         double dot = 0;
