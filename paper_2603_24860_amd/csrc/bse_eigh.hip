@@ -90,6 +90,27 @@ template <int NTH> __device__ __forceinline__ double block_sum(double v, double 
   return s;
 }
 
+// Two sums over the workgroup with one pair of barriers; sh holds 2 NTH / 64.
+template <int NTH>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    sh[w] = a;
+    sh[NTH / 64 + w] = b;
+  }
+  __syncthreads();
+  double sa = 0, sb = 0;
+  for (int i = 0; i < NTH / 64; ++i) {
+    sa += sh[i];
+    sb += sh[NTH / 64 + i];
+  }
+  a = sa;
+  b = sb;
+}
+
 constexpr int NBMAX = 1024;  // blocks in one batched solve
 constexpr int CMAX = 8;      // cluster members refined per eigenvalue cluster
 constexpr int KMAX = 256;    // eigenvalues refinable per solve
@@ -412,6 +433,7 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
   typedef typename C2T<TA>::t CA;
   constexpr int RT = (ENT / 64) / WPR;  // rows per workgroup
   __shared__ double sh[ENT / 64];
+  __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 srow[ENT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = jn + 1;
@@ -496,8 +518,8 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
     V[int64_t(ir) * ldv + r] = v;
     yv = cmulc(yr, v);
   }
-  const double yr = block_sum<ENT>(yv.x, sh);
-  const double yi = block_sum<ENT>(yv.y, sh);
+  double yr = yv.x, yi = yv.y;
+  block_sum2<ENT>(yr, yi, sh2);
   if (tid == 0) parta[wg] = double2{yr, yi};
 }
 
@@ -521,6 +543,7 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
   constexpr int CCH = 2048;     // column entries per LDS chunk (32 KB)
   constexpr int U = 16 / RW;    // columns per lane per pass: RW U = 16 loads in flight
   __shared__ double sh[ENT / 64];
+  __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 xs[CCH];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = jn + 1;
@@ -609,8 +632,8 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
       }
     }
   }
-  const double yr = block_sum<ENT>(yv.x, sh);
-  const double yi = block_sum<ENT>(yv.y, sh);
+  double yr = yv.x, yi = yv.y;
+  block_sum2<ENT>(yr, yi, sh2);
   if (tid == 0) parta[wg] = double2{yr, yi};
 }
 
@@ -667,6 +690,7 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
                                               double2 *__restrict__ pout, int wg) {
   typedef typename C2T<TA>::t CA;
   __shared__ double sh[ENT / 64];
+  __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 tile[2 * NBK * TP];  // [V_0..V_{NBK-1} | W_0..W_{NBK-1}] x rows
   __shared__ double2 sred[ENT / 64][2 * NBK];
   __shared__ double2 spq[2 * NBK], shd[2 * NBK];  // p | q, head V_l[jx] | W_l[jx]
@@ -723,8 +747,8 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   for (int u = 0; u < NG; ++u)
     if (tid + ENT * u < npa) ypart = cadd(ypart, gx[u]);
   for (int p = tid + NG * ENT; p < npa; p += ENT) ypart = cadd(ypart, parta[p]);
-  const double yr = block_sum<ENT>(ypart.x, sh);  // also publishes the LDS stores above
-  const double yi = block_sum<ENT>(ypart.y, sh);
+  double yr = ypart.x, yi = ypart.y;
+  block_sum2<ENT>(yr, yi, sh2);  // also publishes the LDS stores above
   // wave 0, lane l < NBK: p_l, q_l, Re(conj(p_l) q_l) and the head term
   // V_l[jx] q_l + W_l[jx] p_l, summed over l in one pass
   __shared__ double ssum[3];
