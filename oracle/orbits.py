@@ -31,6 +31,9 @@ def kperm(grid, kmat):
     out = np.empty((len(kmat), len(k)), dtype=np.int64)
     for s, A in enumerate(kmat):
         out[s] = lin(grid, np.mod(k @ A.T, g))
+    # the group must map the grid onto itself (e.g. Oh needs n1 = n2 = n3)
+    if not all(len(np.unique(row)) == len(k) for row in out):
+        raise ValueError(f"the point group does not act on the {tuple(grid)} grid")
     return out
 
 

@@ -42,7 +42,7 @@ template <> struct BuildTile<double> { static constexpr int BM = 128, BN = 128, 
 // exchange + diagonal
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_exchange(int nk, int nv, int nc, int nmb,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2, 8))) void k_exchange(int nk, int nv, int nc, int nmb,
                                                  const int32_t *__restrict__ korb,
                                                  const T *__restrict__ mx,
                                                  const double *__restrict__ vdiag,
@@ -340,13 +340,14 @@ template <int VEC> __device__ __forceinline__ void split_store(double2 x, double
 //            B operand of a 16x16x4 step whose K slot g is row 4g + j.  Each
 //            wave contracts its own I range; the four partial D are summed in
 //            LDS and subtracted from H.  T never leaves the registers.
-// Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48.
+// Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 16 NCB (NCB <= 3 row blocks of
+// stage 2, a template parameter so that unused accumulators take no registers).
 // ---------------------------------------------------------------------------
 // SEED: the workgroup takes its q and KC k points from a work list (one k per
 // pair-orbit representative, -1 for padding) and writes the blocks D of the
 // representatives to drep[orbit][cc'][vv'] instead of subtracting them from H.
-template <typename T, int MI, int KC, bool SEED>
-__global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int nv, int nc,
+template <typename T, int MI, int KC, bool SEED, int NCB>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : (MI >= 6 ? 1 : 2), 8))) void k_direct_fused(int n1, int n2, int n3, int nv, int nc,
                                                      const int32_t *__restrict__ qorb,
                                                      const int32_t *__restrict__ pidx,
                                                      const uint8_t *__restrict__ pconj,
@@ -366,7 +367,6 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   constexpr int NB = KC * 16 * BPR / NT;   // B loads per thread per slab
   static_assert(NA >= 1 && NB >= 1, "tile too small");
   constexpr int STAGE = (NMB + NCOL) * P;  // staging elements
-  constexpr int NCB = 3;                   // c c' row blocks of stage 2
   constexpr int RED = 4 * NCB * 16 * 16 * 2;
   constexpr bool SWZ = sizeof(T) == 4;      // swizzled FP32 rows (see below)
   constexpr int PP = SWZ ? BK : P;          // LDS row pitch
@@ -419,13 +419,16 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   // c ^ ((r >> 1) & 3), so the eight lanes of one b128 access (eight rows at
   // one chunk for the MFMA fragments, two rows at four chunks for the stores)
   // hit eight distinct bank groups.  FP64: rows padded by one chunk.
-  const T *wrow[NA];
-  int aoff[NA];
-#pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    const int it = tid + NT * u, row = it / (BK / VEC), c = it % (BK / VEC);
-    wrow[u] = wq + int64_t(row) * nmb + c * VEC;
-    aoff[u] = row * PP + swz(row, c) * VEC;
+  // thread slot u covers row tid / 4 + RSTEP u, chunk tid % 4: one base
+  // address plus constant offsets (the swizzle does not change with u)
+  constexpr int RSTEP = NT / (BK / VEC);
+  static_assert(RSTEP % 8 == 0, "the FP32 swizzle must repeat every RSTEP rows");
+  const T *wrow0;
+  int aoff0;
+  {
+    const int row = tid / (BK / VEC), c = tid % (BK / VEC);
+    wrow0 = wq + int64_t(row) * nmb + c * VEC;
+    aoff0 = row * PP + swz(row, c) * VEC;
   }
   const C2 *bsrc[NB];
   int bstride[NB], boff[NB], boff2[NB];
@@ -451,33 +454,34 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
   for (int j0 = 0; j0 < nmb; j0 += BK) {
     V16 ra[NA], rb[NB];
 #pragma unroll
-    for (int u = 0; u < NA; ++u) ra[u] = *reinterpret_cast<const V16 *>(wrow[u] + j0);
+    for (int u = 0; u < NA; ++u)
+      ra[u] = *reinterpret_cast<const V16 *>(wrow0 + int64_t(u) * RSTEP * NMB + j0);
 #pragma unroll
     for (int u = 0; u < NB; ++u) rb[u] = *reinterpret_cast<const V16 *>(bsrc[u] + bstride[u] * j0);
 #pragma unroll
-    for (int u = 0; u < NA; ++u) *reinterpret_cast<V16 *>(As + aoff[u]) = ra[u];
+    for (int u = 0; u < NA; ++u) *reinterpret_cast<V16 *>(As + aoff0 + u * RSTEP * PP) = ra[u];
 #pragma unroll
     for (int u = 0; u < NB; ++u) split_store<VEC>(rb[u], Bs + boff[u], Bs + boff2[u], 0, bsgn[u]);
     __syncthreads();
     if (SWZ) {
-      frag_t fa[MI], fb[NI];
-#pragma unroll
-      for (int mi = 0; mi < MI; ++mi) {
-        const int row = wm0 + 16 * mi + r;
-        fa[mi] = lds_frag<T>(As + row * PP + swz(row, g) * 4);
-      }
+      // B fragments held for the slab, A fragments one row block at a time
+      // (fewer live registers: four waves per SIMD instead of three)
+      frag_t fb[NI];
 #pragma unroll
       for (int ni = 0; ni < NI; ++ni) {
         const int row = 16 * ni + r;
         fb[ni] = lds_frag<T>(Bs + row * PP + swz(row, g) * 4);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int mi = 0; mi < MI; ++mi) {
+        const int row = wm0 + 16 * mi + r;
+        const frag_t fa = lds_frag<T>(As + row * PP + swz(row, g) * 4);
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int ni = 0; ni < NI; ++ni)
-            acc[mi][ni] = Mfma<T>::mma(fa[mi][i], fb[ni][i], acc[mi][ni]);
+            acc[mi][ni] = Mfma<T>::mma(fa[i], fb[ni][i], acc[mi][ni]);
+      }
     } else {
       mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, 0, lane);
     }
@@ -569,13 +573,18 @@ __global__ __launch_bounds__(NT) void k_direct_fused(int n1, int n2, int n3, int
 template <typename T, int KC, bool SEED = false>
 int32_t launch_fused(int MI, dim3 g, hipStream_t s, const bse_problem *p, void *H, int64_t ldh,
                      double scale, const int32_t *items = nullptr, void *drep = nullptr) {
+  const int ncb = (p->nc * p->nc + 15) / 16;
+  if (ncb < 1 || ncb > 3) return fail(BSE_EUNSUPPORTED, "fused direct kernel: nc^2 <= 48");
+#define BSE_FUSED_NCB(M, C)                                                                   \
+  BSE_LAUNCH(SEED ? "k_direct_seed" : "k_direct_fused", (k_direct_fused<T, M, KC, SEED, C>),  \
+             g, dim3(NT), 0, s, p->grid[0], p->grid[1], p->grid[2], p->nv, p->nc, p->qorb,  \
+             p->pidx, p->pconj, (const T *)p->mv, (const T *)p->mc, (const T *)p->w,        \
+             (T *)H, ldh, scale, items, (T *)drep)
 #define BSE_FUSED_CASE(M)                                                                     \
   case M:                                                                                   \
-    BSE_LAUNCH(SEED ? "k_direct_seed" : "k_direct_fused", (k_direct_fused<T, M, KC, SEED>),   \
-               g, dim3(NT), 0, s, p->grid[0],                                               \
-               p->grid[1], p->grid[2], p->nv, p->nc, p->qorb, p->pidx, p->pconj,             \
-               (const T *)p->mv, (const T *)p->mc, (const T *)p->w, (T *)H, ldh, scale,     \
-               items, (T *)drep);                                                          \
+    if (ncb == 1) BSE_FUSED_NCB(M, 1);                                                      \
+    else if (ncb == 2) BSE_FUSED_NCB(M, 2);                                                 \
+    else BSE_FUSED_NCB(M, 3);                                                               \
     break;
   switch (MI) {
     BSE_FUSED_CASE(1)
@@ -588,6 +597,7 @@ int32_t launch_fused(int MI, dim3 g, hipStream_t s, const bse_problem *p, void *
       return fail(BSE_EUNSUPPORTED, "fused direct kernel: nmb = 64 MI with MI <= 6");
   }
 #undef BSE_FUSED_CASE
+#undef BSE_FUSED_NCB
   BSE_HIP_CHECK(hipGetLastError());
   return BSE_OK;
 }

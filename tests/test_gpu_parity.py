@@ -48,6 +48,8 @@ SMALL = [
     _cfg(lattice="hex", grid=(6, 6, 1), nv=2, nc=3, nmb=20),      # D6h
     _cfg(grid=(4, 4, 4), nv=4, nc=6, nmb=24),                     # cfg3 band shape
     _cfg(grid=(1, 1, 1), nv=2, nc=2, nmb=9),                      # N_k = 1
+    _cfg(grid=(2, 2, 2), nv=2, nc=5, nmb=64),                     # fused, two c c' row blocks
+    _cfg(grid=(3, 3, 3), nv=3, nc=6, nmb=128),                    # fused, three row blocks, odd N_k
 ]
 
 
