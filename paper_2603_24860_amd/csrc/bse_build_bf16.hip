@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NT) void k_exchange_bf3(int nk, int nv, int nc, int
 // Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48.
 // ---------------------------------------------------------------------------
 template <int MI, int KC>
-__global__ __launch_bounds__(NT) void k_direct_bf3(int n1, int n2, int n3, int nv, int nc,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 : 2, 8))) void k_direct_bf3(int n1, int n2, int n3, int nv, int nc,
                                                    const int32_t *__restrict__ qorb,
                                                    const int32_t *__restrict__ pidx,
                                                    const uint8_t *__restrict__ pconj,
