@@ -948,7 +948,12 @@ __device__ __forceinline__ void b_tri_prep(int64_t n, const double *__restrict__
   }
 }
 
-// number of eigenvalues of T below x (LDL^T Sturm sequence with pivot guard)
+// number of eigenvalues of T below x (LDL^T Sturm sequence with pivot guard).
+// d and e2 are the same for every lane.  Whole blocks of SU steps read their
+// inputs one block ahead (contiguous uniform loads), so the dependent chain of
+// the recurrence does not wait for a load at every step; the last partial
+// block loads as it goes.
+constexpr int SU = 8;
 __device__ __forceinline__ int sturm_count(const double *__restrict__ d,
                                            const double *__restrict__ e2, int64_t n, double x,
                                            double pivmin) {
@@ -956,11 +961,39 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d,
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0;
-  for (int64_t k = 1; k < n; ++k) {
-    q = d[k] - x - e2[k - 1] * rcp64(q);
+  auto step = [&](double dk, double ek) {
+    q = dk - x - ek * rcp64(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0;
+  };
+  int64_t k = 1;
+  if (k + SU <= n) {
+    double dn[SU], en[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      dn[u] = d[k + u];
+      en[u] = e2[k - 1 + u];
+    }
+    for (; k + SU <= n; k += SU) {
+      double dc[SU], ec[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        dc[u] = dn[u];
+        ec[u] = en[u];
+      }
+      if (k + 2 * SU <= n) {
+        const double *dp = d + k + SU, *ep = e2 + k + SU - 1;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          dn[u] = dp[u];
+          en[u] = ep[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) step(dc[u], ec[u]);
+    }
   }
+  for (; k < n; ++k) step(d[k], e2[k - 1]);
   return cnt;
 }
 
@@ -1030,12 +1063,42 @@ __device__ __forceinline__ void b_weights(int64_t n, const double *__restrict__ 
     const double ct = cos(th), st = sin(th);
     const double zx = c + rad * ct, zy = rad * st;
     // h = z - d_{n-1}; h = z - d_k - e_k^2 / h, k = n-2 .. 0; G = 1 / h
+    // (whole blocks of SU steps read their inputs one block ahead, as in
+    // sturm_count)
     double hx = zx - d[n - 1], hy = zy;
-    for (int64_t k = n - 2; k >= 0; --k) {
-      const double inv = e2[k] * rcp64(hx * hx + hy * hy);
-      hx = zx - d[k] - hx * inv;
+    auto step = [&](double dk, double ek) {
+      const double inv = ek * rcp64(hx * hx + hy * hy);
+      hx = zx - dk - hx * inv;
       hy = zy + hy * inv;
+    };
+    int64_t k = n - 2;
+    if (k - SU + 1 >= 0) {
+      double dn[SU], en[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        dn[u] = d[k - u];
+        en[u] = e2[k - u];
+      }
+      for (; k - SU + 1 >= 0; k -= SU) {
+        double dc[SU], ec[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          dc[u] = dn[u];
+          ec[u] = en[u];
+        }
+        if (k - 2 * SU + 1 >= 0) {
+          const double *dp = d + (k - SU), *ep = e2 + (k - SU);
+#pragma unroll
+          for (int u = 0; u < SU; ++u) {
+            dn[u] = dp[-u];
+            en[u] = ep[-u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) step(dc[u], ec[u]);
+      }
     }
+    for (; k >= 0; --k) step(d[k], e2[k]);
     const double den = rcp64(hx * hx + hy * hy);
     const double gx = hx * den, gy = -hy * den;
     wsum = gx * rad * ct - gy * rad * st;  // Re[G (z - c)]
