@@ -154,6 +154,14 @@ struct Desc {
 // launch geometry, shared by the host (single block) and the batched kernels
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// The last at most MT rows of a block are reduced by one workgroup in LDS
+// (k_tail), starting at the first panel boundary with at most MT rows left.
+constexpr int MT = 96;     // largest trailing block reduced in LDS (147 KB)
+constexpr int TNT = 512;   // threads of k_tail
+static_assert(MT <= TNT, "k_tail: thread j keeps the scalars of column j");
+__host__ __device__ __forceinline__ int64_t g_tail0(int64_t n) {
+  return n <= MT ? 0 : cdiv(n - MT, NBK) * NBK;
+}
 __host__ __device__ __forceinline__ int64_t g_nwg(int64_t m) { return m < 1 ? 1 : cdiv(m, ENT); }
 __host__ __device__ __forceinline__ int g_rpw(int64_t m) {
   return (int)(m < 2048 ? 1 : cdiv(m, 2048));
@@ -1203,6 +1211,152 @@ BSE_PAIR(weights, int unused_, {
 })
 #undef BSE_PAIR
 
+// ---------------------------------------------------------------------------
+// k_tail: the last columns of the reduction in one workgroup.  From a panel
+// boundary j0 with at most MT trailing rows (all earlier updates applied),
+// the trailing block is held in LDS in FP64 and reduced by unblocked
+// Householder steps (LAPACK zhetd2, lower form): reflector of column j from
+// |x|^2, w = tau A22 v, alpha = -tau (w^dag v) / 2, w += alpha v,
+// A22 -= v w^dag + w v^dag.  Same reflector convention and outputs (d, e,
+// tau, scl and, with refinement, every reflector) as the blocked columns, so
+// the result is the same tridiagonal up to rounding; each column costs a few
+// workgroup barriers instead of two dependent kernel launches.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__device__ __forceinline__ void b_tail(const Desc &D, int64_t j0, int keep) {
+  typedef typename C2T<TA>::t CA;
+  constexpr int NWT = TNT / 64;
+  __shared__ double2 As[MT * MT];
+  __shared__ double2 part[NWT * MT];  // partial A22 v of each wave's column chunk
+  __shared__ double2 wv_[MT];         // w of the current step
+  __shared__ double2 dpart[NWT];      // per wave: sum_r conj(partial y_r) v_r
+  __shared__ double npart[NWT];       // per wave: |x|^2 of the next column
+  __shared__ double red[TNT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t n = D.n, lda = D.lda, ldv = D.ldv;
+  const int mt = int(n - j0);  // 1 <= mt <= MT (checked by the host)
+  const CA *A = reinterpret_cast<const CA *>(D.A);
+  for (int q = tid; q < mt * mt; q += TNT) {
+    const int r = q / mt, c = q % mt;
+    As[r * MT + c] = to_d2(A[(j0 + r) * lda + j0 + c]);
+  }
+  __syncthreads();
+  double x2 = 0;  // |x|^2 of the current column below its subdiagonal entry
+  for (int r = 2 + tid; r < mt; r += TNT) {
+    const double2 a = As[r * MT];
+    x2 += a.x * a.x + a.y * a.y;
+  }
+  x2 = block_sum<TNT>(x2, red);
+  // Three barriers per column.  v is never stored: v[c] = 1 at c = j + 1 and
+  // scale A[c][j] below, read from column j, which the later steps leave
+  // unchanged.  Thread j keeps the scalars of column j; nothing goes to
+  // global memory inside the loop (a barrier would wait for such a store).
+  double my_d = 0, my_e = 0;
+  double2 my_tau = {0, 0}, my_sc = {0, 0};
+  for (int j = 0; j < mt; ++j) {
+    if (tid == j) my_d = As[j * MT + j].x;
+    if (j == mt - 1) break;
+    double beta;
+    double2 tj, sc;
+    householder(As[(j + 1) * MT + j], x2, beta, tj, sc);
+    if (tid == j) {
+      my_e = beta;
+      my_tau = tj;
+      my_sc = sc;
+    }
+    auto vof = [&](int c) { return c == j + 1 ? double2{1, 0} : cmul(sc, As[c * MT + j]); };
+    // y = A22 v.  A22 is Hermitian, y[r] = sum_c conj(A[c][r]) v[c]: wave w
+    // sums its chunk of columns c for every row (lane: rows r0 and r0 + 64,
+    // contiguous in LDS; A[c][j] read as a broadcast), and its share of
+    // y^dag v; the partials are added below in a fixed order.
+    {
+      const int cs = (mt - j - 1 + NWT - 1) / NWT;
+      const int cb = j + 1 + wv * cs, ce = std::min(cb + cs, mt);
+      const int r0 = j + 1 + lane, r1 = r0 + 64;
+      double2 p0 = {0, 0}, p1 = {0, 0};
+      for (int c = cb; c < ce; ++c) {
+        const double2 v = vof(c);
+        if (r0 < mt) p0 = cadd(p0, cmulc(As[c * MT + r0], v));
+        if (r1 < mt) p1 = cadd(p1, cmulc(As[c * MT + r1], v));
+      }
+      double dr = 0, di = 0;
+      if (r0 < mt) {
+        part[wv * MT + r0] = p0;
+        const double2 t = cmulc(p0, vof(r0));
+        dr += t.x;
+        di += t.y;
+      }
+      if (r1 < mt) {
+        part[wv * MT + r1] = p1;
+        const double2 t = cmulc(p1, vof(r1));
+        dr += t.x;
+        di += t.y;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      if (lane == 0) dpart[wv] = double2{dr, di};
+    }
+    __syncthreads();
+    // w = tau y + alpha v, alpha = -tau (w_raw^dag v) / 2, w_raw^dag v = conj(tau) y^dag v
+    double2 ydv = {0, 0};
+#pragma unroll
+    for (int q = 0; q < NWT; ++q) ydv = cadd(ydv, dpart[q]);
+    const double2 alpha = cmul(double2{-0.5 * tj.x, -0.5 * tj.y}, cmulc(tj, ydv));
+    for (int r = j + 1 + tid; r < mt; r += TNT) {
+      double2 y = {0, 0};
+#pragma unroll
+      for (int q = 0; q < NWT; ++q) y = cadd(y, part[q * MT + r]);
+      wv_[r] = cadd(cmul(tj, y), cmul(alpha, vof(r)));
+    }
+    __syncthreads();
+    // A22 -= v w^dag + w v^dag: one wave per row, each lane owning columns c0
+    // and c0 + 64; lane 0 owns column j + 1 and sums |x|^2 of the next step
+    const int c0 = j + 1 + lane, c1 = c0 + 64;
+    const double2 vc0 = c0 < mt ? vof(c0) : double2{0, 0};
+    const double2 vc1 = c1 < mt ? vof(c1) : double2{0, 0};
+    const double2 wc0 = c0 < mt ? wv_[c0] : double2{0, 0};
+    const double2 wc1 = c1 < mt ? wv_[c1] : double2{0, 0};
+    double xn = 0;
+    for (int r = j + 1 + wv; r < mt; r += NWT) {
+      const double2 vr = vof(r), wr = wv_[r];
+      if (c0 < mt) {
+        const double2 a =
+            csub(As[r * MT + c0], cadd(cmul(vr, cconj(wc0)), cmul(wr, cconj(vc0))));
+        As[r * MT + c0] = a;
+        if (lane == 0 && r >= j + 3) xn += a.x * a.x + a.y * a.y;
+      }
+      if (c1 < mt)
+        As[r * MT + c1] = csub(As[r * MT + c1], cadd(cmul(vr, cconj(wc1)), cmul(wr, cconj(vc1))));
+    }
+    if (lane == 0) npart[wv] = xn;
+    __syncthreads();
+    x2 = 0;
+#pragma unroll
+    for (int q = 0; q < NWT; ++q) x2 += npart[q];
+  }
+  // outputs of column tid (indices of the whole block)
+  const int64_t jn = j0 + tid;
+  if (tid < mt) D.d[jn] = my_d;
+  if (tid < mt - 1) {
+    D.e[jn] = my_e;
+    D.tau[jn + 1] = my_tau;
+    D.scl[jn + 1] = my_sc;
+    if (keep)
+      for (int r = tid + 1; r < mt; ++r)
+        D.Vall[jn * ldv + j0 + r] = r == tid + 1 ? double2{1, 0} : cmul(my_sc, As[r * MT + tid]);
+  }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(TNT) void k_tail(Desc D, int64_t j0, int keep) {
+  b_tail<TA>(D, j0, keep);
+}
+// batched: one workgroup per block of Ds[b0 ..), all with the same tail start
+template <typename TA>
+__global__ __launch_bounds__(TNT) void k_tail_b(const Desc *__restrict__ Ds, int b0, int64_t j0) {
+  b_tail<TA>(Ds[b0 + int(blockIdx.x)], j0, 0);
+}
+
 // the tridiagonal preparation runs one RNT-thread workgroup per block
 template <typename TA>
 __global__ __launch_bounds__(RNT) void k_tri_prep(Desc D, double ctol) {
@@ -1220,7 +1374,7 @@ __global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
 
 // workgroups of one launch kind for one block (0 = the block is not active)
 enum Kind { K_COPY, K_LOADB, K_HEMV0, K_W0, K_RANK2, K_COL0, K_COLA, K_COLB, K_HER2K, K_TRI,
-            K_BISECT, K_WEIGHTS };
+            K_BISECT, K_WEIGHTS, K_TAIL };
 
 template <typename TA>
 int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
@@ -1230,11 +1384,11 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
     case K_HEMV0: return cdiv(n, 4 * g_rpw(n));
     case K_W0: return g_nwg(n);
     case K_RANK2: return n * g_rank2_gx(n);
-    case K_COL0: return j < n ? g_nwg(n - j) : 0;
-    case K_COLA: return j < n ? g_colA_wgs(n - j - 1, wpr) : 0;
-    case K_COLB: return n - j - 1 > 0 ? cdiv(n - j - 1, RB) : 0;
+    case K_COL0: return j < g_tail0(n) ? g_nwg(n - j) : 0;
+    case K_COLA: return j < g_tail0(n) ? g_colA_wgs(n - j - 1, wpr) : 0;
+    case K_COLB: return j < g_tail0(n) ? cdiv(n - j - 1, RB) : 0;
     case K_HER2K: {
-      if (j >= n) return 0;
+      if (j >= g_tail0(n)) return 0;
       const int64_t c0 = j + g_nbk(n, j), m = n - c0;
       return m > 0 ? cdiv(m, HerTile<TA>::BN) * cdiv(2 * m, HerTile<TA>::BM) : 0;
     }
@@ -1709,6 +1863,10 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
   int cur = 0;  // partial-sum record buffer written last
   const Desc D0 = D;
   for (int64_t j0 = 0; j0 < n; j0 += NBK) {
+    if (j0 == g_tail0(n)) {  // the rest in one workgroup, in LDS
+      BSE_LAUNCH("k_tail", k_tail<TA>, dim3(1), dim3(TNT), 0, s, D0, j0, int(K > 0));
+      break;
+    }
     const int nbk = g_nbk(n, j0);
     if (K > 0) D.V = D0.Vall + j0 * D0.ldv;  // keep every reflector for the back-transform
     BSE_LAUNCH("k_col0", (k_col0<TH, TA, 4>), grid(K_COL0, j0, 4), dim3(ENT), 0, s, D, j0, cur);
@@ -1810,6 +1968,12 @@ void plan_launches(BatchPlan &P, std::vector<int> &pre) {
   add(K_RANK2, 0, 0);
   int cur = 0;
   for (int64_t j0 = 0; j0 < nmax; j0 += NBK) {
+    // blocks whose tail starts here (a contiguous range: n sorted descending)
+    int b0 = 0;
+    while (b0 < nb && g_tail0(P.n[b0]) > j0) ++b0;
+    int b1 = b0;
+    while (b1 < nb && g_tail0(P.n[b1]) == j0) ++b1;
+    if (b1 > b0) P.launches.push_back(BatchLaunch{K_TAIL, j0, b0, b1 - b0, b1 - b0, 0});
     add(K_COL0, j0, cur);
     for (int i = 0; i < NBK && j0 + i < nmax; ++i) {
       const int64_t jn = j0 + i;
@@ -1840,6 +2004,7 @@ int32_t batch_launch(const BatchPlan &P, const BatchLaunch &L, hipStream_t s) {
     case K_COLB: BSE_LAUNCH("k_colB", (k_colB_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
     case K_HER2K: BSE_LAUNCH("k_her2k", (k_her2k_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j); break;
     case K_TRI: BSE_LAUNCH("k_tri_prep", k_tri_prep_b<TA>, g, dim3(RNT), 0, s, Ds, pre, L.nact, 0); break;
+    case K_TAIL: BSE_LAUNCH("k_tail", k_tail_b<TA>, g, dim3(TNT), 0, s, Ds, L.cur, L.j); break;
     case K_BISECT: BSE_LAUNCH("k_bisect", (k_bisect_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
     default: BSE_LAUNCH("k_weights", (k_weights_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
   }
