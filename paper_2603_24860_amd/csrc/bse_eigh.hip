@@ -505,30 +505,39 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
   if (lane == 0) srow[wv] = double2{sr, si};
   // ---- reflector scalars (every workgroup) ----
   const double S1 = block_sum<ENT>(s1, sh);  // also publishes srow
-  if (wg == 0 && tid == 0) d[jn] = cjn.x;
-  if (last) return;
+  if (last) {
+    if (wg == 0 && tid == 0) d[jn] = cjn.x;
+    return;
+  }
   double beta;
   double2 tj, sc;
   householder(cm0, S1, beta, tj, sc);
-  if (wg == 0 && tid == 0) {
-    e[jn] = beta;
-    tau[m0] = tj;
-    scl[m0] = sc;
-  }
-  double2 yv = {0, 0};
+  // the stores follow the reduction: a store whose data registers are
+  // reused by the reduction would have to complete first
+  double2 yv = {0, 0}, yo = {0, 0}, vo = {0, 0};
   if (lead) {
     double2 rs = srow[wv];
 #pragma unroll
     for (int k = 1; k < WPR; ++k) rs = cadd(rs, srow[wv + k]);
-    const double2 yr = cadd(a0, cmul(sc, rs));
-    const double2 v = r == m0 ? double2{1, 0} : cmul(sc, cr);  // lead: r < n, so rc = r
-    y[r] = yr;
-    V[int64_t(ir) * ldv + r] = v;
-    yv = cmulc(yr, v);
+    yo = cadd(a0, cmul(sc, rs));
+    vo = r == m0 ? double2{1, 0} : cmul(sc, cr);  // lead: r < n, so rc = r
+    yv = cmulc(yo, vo);
   }
   double yr = yv.x, yi = yv.y;
   block_sum2<ENT>(yr, yi, sh2);
-  if (tid == 0) parta[wg] = double2{yr, yi};
+  if (lead) {
+    y[r] = yo;
+    V[int64_t(ir) * ldv + r] = vo;
+  }
+  if (tid == 0) {
+    parta[wg] = double2{yr, yi};
+    if (wg == 0) {
+      d[jn] = cjn.x;
+      e[jn] = beta;
+      tau[m0] = tj;
+      scl[m0] = sc;
+    }
+  }
 }
 
 // k_colA for large trailing blocks: LDS_RW rows per wave, 4 LDS_RW rows per
@@ -616,33 +625,42 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
   for (int u = 0; u < PMAX / ENT; ++u)
     if (tid + ENT * u < np) s1 += px[u].x;
   const double S1 = block_sum<ENT>(s1, sh);
-  if (wg == 0 && tid == 0) d[jn] = cjn.x;
-  if (last) return;
+  if (last) {
+    if (wg == 0 && tid == 0) d[jn] = cjn.x;
+    return;
+  }
   double beta;
   double2 tj, sc;
   householder(cm0, S1, beta, tj, sc);
-  if (wg == 0 && tid == 0) {
-    e[jn] = beta;
-    tau[m0] = tj;
-    scl[m0] = sc;
+  double2 yv = {0, 0}, yo[RW], vo[RW];  // stores after the reduction, as in b_colA
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    const int64_t r = rbase + k;
+    yo[k] = cadd(a0[k], cmul(sc, double2{sr[k], si[k]}));
+    vo[k] = r == m0 ? double2{1, 0} : cmul(sc, cr[k]);
+    if (lane == 0 && r < n) yv = cadd(yv, cmulc(yo[k], vo[k]));
   }
-  double2 yv = {0, 0};
+  double yr = yv.x, yi = yv.y;
+  block_sum2<ENT>(yr, yi, sh2);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
       const int64_t r = rbase + k;
       if (r < n) {
-        const double2 yr = cadd(a0[k], cmul(sc, double2{sr[k], si[k]}));
-        const double2 v = r == m0 ? double2{1, 0} : cmul(sc, cr[k]);
-        y[r] = yr;
-        V[int64_t(ir) * ldv + r] = v;
-        yv = cadd(yv, cmulc(yr, v));
+        y[r] = yo[k];
+        V[int64_t(ir) * ldv + r] = vo[k];
       }
     }
   }
-  double yr = yv.x, yi = yv.y;
-  block_sum2<ENT>(yr, yi, sh2);
-  if (tid == 0) parta[wg] = double2{yr, yi};
+  if (tid == 0) {
+    parta[wg] = double2{yr, yi};
+    if (wg == 0) {
+      d[jn] = cjn.x;
+      e[jn] = beta;
+      tau[m0] = tj;
+      scl[m0] = sc;
+    }
+  }
 }
 
 // sum of part[0..np) with eight loads in flight per thread
