@@ -1369,10 +1369,12 @@ template <typename TA>
 __global__ __launch_bounds__(TNT) void k_tail(Desc D, int64_t j0, int keep) {
   b_tail<TA>(D, j0, keep);
 }
-// batched: one workgroup per block of Ds[b0 ..), all with the same tail start
+// batched: one workgroup per block of Ds[b0 ..), each from its own tail start
 template <typename TA>
-__global__ __launch_bounds__(TNT) void k_tail_b(const Desc *__restrict__ Ds, int b0, int64_t j0) {
-  b_tail<TA>(Ds[b0 + int(blockIdx.x)], j0, 0);
+__global__ __launch_bounds__(TNT) void k_tail_b(const Desc *__restrict__ Ds, int b0, int64_t unused_) {
+  (void)unused_;
+  const Desc &D = Ds[b0 + int(blockIdx.x)];
+  b_tail<TA>(D, g_tail0(D.n), 0);
 }
 
 // the tridiagonal preparation runs one RNT-thread workgroup per block
@@ -1986,12 +1988,6 @@ void plan_launches(BatchPlan &P, std::vector<int> &pre) {
   add(K_RANK2, 0, 0);
   int cur = 0;
   for (int64_t j0 = 0; j0 < nmax; j0 += NBK) {
-    // blocks whose tail starts here (a contiguous range: n sorted descending)
-    int b0 = 0;
-    while (b0 < nb && g_tail0(P.n[b0]) > j0) ++b0;
-    int b1 = b0;
-    while (b1 < nb && g_tail0(P.n[b1]) == j0) ++b1;
-    if (b1 > b0) P.launches.push_back(BatchLaunch{K_TAIL, j0, b0, b1 - b0, b1 - b0, 0});
     add(K_COL0, j0, cur);
     for (int i = 0; i < NBK && j0 + i < nmax; ++i) {
       const int64_t jn = j0 + i;
@@ -2001,6 +1997,9 @@ void plan_launches(BatchPlan &P, std::vector<int> &pre) {
     }
     add(K_HER2K, j0, cur);
   }
+  // every block's tail in one launch: a block's working copy is not touched
+  // after its last panel, so the tails need not sit in the lockstep chain
+  P.launches.push_back(BatchLaunch{K_TAIL, 0, 0, nb, nb, 0});
   add(K_TRI, 0, 0);
   add(K_BISECT, 0, 0);
   add(K_WEIGHTS, 0, 0);
