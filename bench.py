@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the block eigensolver keeps each block on one device); use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -47,7 +47,7 @@ enum {
   BSE_EWORKSPACE = -3,   /* workspace smaller than the *_ws query requires   */
   BSE_EDEVICE = -4,      /* a HIP runtime call failed                        */
   BSE_ENOCONV = -5,      /* an iteration did not converge                    */
-  BSE_EUNSUPPORTED = -6  /* valid request this build does not implement      */
+  BSE_EUNSUPPORTED = -6  /* valid request the library does not implement    */
 };
 
 enum { /* arithmetic of the contractions */
