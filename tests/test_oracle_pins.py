@@ -115,6 +115,14 @@ def test_orbit_counts_at_config_sizes():
     assert len({r.tobytes() for r in kp2}) == 6  # non-faithful action at n = 2
 
 
+@pytest.mark.parametrize("grid,name", [((2, 2, 3), "Oh"), ((4, 4, 2), "Oh"), ((6, 4, 1), "D6h")])
+def test_grid_not_preserved_by_group_is_rejected(grid, name):
+    # the operations must map the grid onto itself: Oh permutes the three
+    # coordinates, the hexagonal rotations mix the two in-plane ones
+    with pytest.raises(ValueError):
+        orbits.kperm(grid, groups.group(name)["kmat"])
+
+
 def test_swap_classes():
     oh = groups.group("Oh")
     T = orbits.tables((4, 4, 4), oh["kmat"])
