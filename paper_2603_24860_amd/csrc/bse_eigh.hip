@@ -111,6 +111,34 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
   b = sb;
 }
 
+// The same sums for a buffer that the kernel uses only once: one barrier,
+// after the partial sums are written (it also publishes earlier LDS stores).
+template <int NTH> __device__ __forceinline__ double block_sum_once(double v, double *sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < NTH / 64; ++i) s += sh[i];
+  return s;
+}
+template <int NTH>
+__device__ __forceinline__ void block_sum2_once(double &a, double &b, double *sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = a;
+    sh[NTH / 64 + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  double sa = 0, sb = 0;
+  for (int i = 0; i < NTH / 64; ++i) {
+    sa += sh[i];
+    sb += sh[NTH / 64 + i];
+  }
+  a = sa;
+  b = sb;
+}
+
 constexpr int NBMAX = 1024;  // blocks in one batched solve
 constexpr int CMAX = 8;      // cluster members refined per eigenvalue cluster
 constexpr int KMAX = 256;    // eigenvalues refinable per solve
@@ -504,7 +532,7 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
     if (tid + ENT * u < np) s1 += px[u].x;
   if (lane == 0) srow[wv] = double2{sr, si};
   // ---- reflector scalars (every workgroup) ----
-  const double S1 = block_sum<ENT>(s1, sh);  // also publishes srow
+  const double S1 = block_sum_once<ENT>(s1, sh);  // also publishes srow
   if (last) {
     if (wg == 0 && tid == 0) d[jn] = cjn.x;
     return;
@@ -524,7 +552,7 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
     yv = cmulc(yo, vo);
   }
   double yr = yv.x, yi = yv.y;
-  block_sum2<ENT>(yr, yi, sh2);
+  block_sum2_once<ENT>(yr, yi, sh2);
   if (lead) {
     y[r] = yo;
     V[int64_t(ir) * ldv + r] = vo;
@@ -624,7 +652,7 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
 #pragma unroll
   for (int u = 0; u < PMAX / ENT; ++u)
     if (tid + ENT * u < np) s1 += px[u].x;
-  const double S1 = block_sum<ENT>(s1, sh);
+  const double S1 = block_sum_once<ENT>(s1, sh);
   if (last) {
     if (wg == 0 && tid == 0) d[jn] = cjn.x;
     return;
@@ -641,7 +669,7 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
     if (lane == 0 && r < n) yv = cadd(yv, cmulc(yo[k], vo[k]));
   }
   double yr = yv.x, yi = yv.y;
-  block_sum2<ENT>(yr, yi, sh2);
+  block_sum2_once<ENT>(yr, yi, sh2);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
@@ -719,7 +747,7 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 tile[2 * NBK * TP];  // [V_0..V_{NBK-1} | W_0..W_{NBK-1}] x rows
   __shared__ double2 sred[ENT / 64][2 * NBK];
-  __shared__ double2 spq[2 * NBK], shd[2 * NBK];  // p | q, head V_l[jx] | W_l[jx]
+  __shared__ double2 spq[ENT / 64][2 * NBK], shd[2 * NBK];  // p | q per wave, head V_l[jx] | W_l[jx]
   __shared__ double2 sy[RB], sa[RB], sv[RB], sw[RB], sc_[RB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t jx = jn + 1;
@@ -774,11 +802,12 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
     if (tid + ENT * u < npa) ypart = cadd(ypart, gx[u]);
   for (int p = tid + NG * ENT; p < npa; p += ENT) ypart = cadd(ypart, parta[p]);
   double yr = ypart.x, yi = ypart.y;
-  block_sum2<ENT>(yr, yi, sh2);  // also publishes the LDS stores above
-  // wave 0, lane l < NBK: p_l, q_l, Re(conj(p_l) q_l) and the head term
-  // V_l[jx] q_l + W_l[jx] p_l, summed over l in one pass
-  __shared__ double ssum[3];
-  if (wv == 0) {
+  block_sum2_once<ENT>(yr, yi, sh2);  // also publishes the LDS stores above
+  // every wave, lane l < NBK: p_l, q_l, Re(conj(p_l) q_l) and the head term
+  // V_l[jx] q_l + W_l[jx] p_l, summed over l in one pass; each wave keeps its
+  // own copy of p and q in LDS, so no barrier is needed before the rows
+  double pq_re, hr, hi;
+  {
     double2 pl = {0, 0}, ql = {0, 0}, hl = {0, 0};
     if (lane < ir) {
       const double2 bv = cadd(cadd(sred[0][lane], sred[1][lane]), cadd(sred[2][lane], sred[3][lane]));
@@ -789,24 +818,17 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
       hl = cadd(cmul(shd[lane], ql), cmul(shd[lw], pl));
     }
     if (lane < NBK) {
-      spq[lane] = pl;
-      spq[NBK + lane] = ql;
+      spq[wv][lane] = pl;
+      spq[wv][NBK + lane] = ql;
     }
-    const double pr = wave_sum(pl.x * ql.x + pl.y * ql.y);
-    const double hr = wave_sum(hl.x), hi = wave_sum(hl.y);
-    if (lane == 0) {
-      ssum[0] = pr;
-      ssum[1] = hr;
-      ssum[2] = hi;
-    }
+    pq_re = wave_sum(pl.x * ql.x + pl.y * ql.y);  // Re(p^dag q)
+    hr = wave_sum(hl.x);
+    hi = wave_sum(hl.y);
   }
-  __syncthreads();
-  const double pq_re = ssum[0];  // Re(p^dag q)
   const double2 wdv = cmulc(t, double2{yr - 2.0 * pq_re, yi});
   const double2 alpha = cmul(double2{-0.5 * t.x, -0.5 * t.y}, wdv);
   // head entry W_ir[jx] (v[jx] = 1)
-  const double2 wh = more ? cadd(cmul(t, csub(yjx, double2{ssum[1], ssum[2]})), alpha)
-                          : double2{0, 0};
+  const double2 wh = more ? cadd(cmul(t, csub(yjx, double2{hr, hi})), alpha) : double2{0, 0};
   // ---- rows: four threads per row, panel columns l = part, part + 4, ... ----
   const int row = tid >> 2, part = tid & 3;
   const int64_t r = rb + row;
@@ -816,7 +838,7 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
     const int l = l0 + part;
     if (l < ir) {
       const double2 vl = tile[l * TP + row], wl = tile[(NBK + l) * TP + row];
-      hw = cadd(hw, cadd(cmul(vl, spq[NBK + l]), cmul(wl, spq[l])));
+      hw = cadd(hw, cadd(cmul(vl, spq[wv][NBK + l]), cmul(wl, spq[wv][l])));
       hc = cadd(hc, cadd(cmul(vl, cconj(shd[NBK + l])), cmul(wl, cconj(shd[l]))));
     }
   }
@@ -836,7 +858,7 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   }
   if (!more) return;
   double s1 = (part == 0 && r < n && r >= jx + 2) ? c.x * c.x + c.y * c.y : 0.0;
-  s1 = block_sum<ENT>(s1, sh);  // also publishes sw, sc_
+  s1 = block_sum_once<ENT>(s1, sh);  // also publishes sw, sc_
   double2 *pr = pout + int64_t(wg) * PS;
   if (tid == 0) pr[0] = double2{s1, 0};
   // ---- BV_l, BW_l (l <= ir): four threads per panel column ----
