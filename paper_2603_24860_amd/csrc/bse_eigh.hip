@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <vector>
 
@@ -758,10 +759,21 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   constexpr int NT = 2 * NBK * RB / ENT;  // tile entries per thread
   const int i = tid % RB, k0 = tid / RB;
   const int64_t r0 = rb + i, rcl = std::min<int64_t>(r0, n - 1);
+  // The loads of px and gx come in a few fixed sizes chosen by a uniform
+  // branch on the record count, so that no duplicate (clamped) record is
+  // fetched more than the size class needs.
   double2 px[NP];  // lane = slot of the record, wave = record group
+  auto load_px = [&](auto cnt) {
+    constexpr int C = decltype(cnt)::value;
 #pragma unroll
-  for (int u = 0; u < NP; ++u)
-    px[u] = pin[int64_t(std::min(wv + (ENT / 64) * u, npin - 1)) * PS + 1 + lane];
+    for (int u = 0; u < NP; ++u)
+      px[u] = u < C ? pin[int64_t(std::min(wv + (ENT / 64) * u, npin - 1)) * PS + 1 + lane]
+                    : double2{0, 0};
+  };
+  if (npin <= 2 * (ENT / 64)) load_px(std::integral_constant<int, 2>());
+  else if (npin <= 4 * (ENT / 64)) load_px(std::integral_constant<int, 4>());
+  else if (npin <= 8 * (ENT / 64)) load_px(std::integral_constant<int, 8>());
+  else load_px(std::integral_constant<int, NP>());
   double2 tx[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
@@ -773,8 +785,15 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   const double2 ax = to_d2(reinterpret_cast<const CA *>(A)[rcl * lda + jx]);
   constexpr int NG = 16;  // partial sums of k_colA held in registers per thread
   double2 gx[NG];
+  auto load_gx = [&](auto cnt) {
+    constexpr int C = decltype(cnt)::value;
 #pragma unroll
-  for (int u = 0; u < NG; ++u) gx[u] = parta[std::min(tid + ENT * u, npa - 1)];
+    for (int u = 0; u < NG; ++u) gx[u] = u < C ? parta[std::min(tid + ENT * u, npa - 1)] : double2{0, 0};
+  };
+  if (npa <= ENT) load_gx(std::integral_constant<int, 1>());
+  else if (npa <= 2 * ENT) load_gx(std::integral_constant<int, 2>());
+  else if (npa <= 4 * ENT) load_gx(std::integral_constant<int, 4>());
+  else load_gx(std::integral_constant<int, NG>());
   const double2 t = tau[jx], sc = scl[jx];
   const double2 yjx = y[jx];
   // ---- consume ----
