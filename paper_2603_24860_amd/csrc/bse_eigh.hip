@@ -616,6 +616,57 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
     __syncthreads();
     for (int t = tid; t < cn; t += ENT) xs[t] = col[c0 + t];
     __syncthreads();
+    if constexpr (sizeof(TA) == 4) {
+      // FP32 working copy: two adjacent columns per lane in one 16-byte load
+      // (rows start at multiples of 16 entries, so an even column is aligned)
+      const int first = int(c0 & 1);
+      if (first && lane == 0) {
+        const double2 x = xs[0];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+          const double2 av = to_d2(arow[k][c0]);
+          sr[k] += av.x * x.x - av.y * x.y;
+          si[k] += av.x * x.y + av.y * x.x;
+        }
+      }
+      constexpr int U2 = U / 2;
+      int cc = first + 2 * lane;
+      for (; cc + 1 + (U2 - 1) * 128 < cn; cc += U2 * 128) {
+        float4 a[RW][U2];
+#pragma unroll
+        for (int k = 0; k < RW; ++k)
+#pragma unroll
+          for (int u = 0; u < U2; ++u)
+            a[k][u] = *reinterpret_cast<const float4 *>(arow[k] + c0 + cc + 128 * u);
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+          const double2 x0 = xs[cc + 128 * u], x1 = xs[cc + 1 + 128 * u];
+#pragma unroll
+          for (int k = 0; k < RW; ++k) {
+            const double ar = a[k][u].x, ai = a[k][u].y, br = a[k][u].z, bi = a[k][u].w;
+            sr[k] += ar * x0.x - ai * x0.y;
+            si[k] += ar * x0.y + ai * x0.x;
+            sr[k] += br * x1.x - bi * x1.y;
+            si[k] += br * x1.y + bi * x1.x;
+          }
+        }
+      }
+      for (; cc < cn; cc += 128) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (cc + h < cn) {
+            const double2 x = xs[cc + h];
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+              const double2 av = to_d2(arow[k][c0 + cc + h]);
+              sr[k] += av.x * x.x - av.y * x.y;
+              si[k] += av.x * x.y + av.y * x.x;
+            }
+          }
+        }
+      }
+      continue;
+    }
     int cc = lane;
     for (; cc + (U - 1) * 64 < cn; cc += U * 64) {
       CA a[RW][U];
