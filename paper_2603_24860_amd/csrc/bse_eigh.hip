@@ -854,8 +854,17 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
 #pragma unroll
     for (int u = 0; u < NP; ++u)
       if (wv + (ENT / 64) * u < npin) b = cadd(b, px[u]);
-    for (int p = wv + (ENT / 64) * NP; p < npin; p += ENT / 64)
-      b = cadd(b, pin[int64_t(p) * PS + 1 + lane]);
+    // more than NP record groups (trailing blocks above 64 NP rows): batches
+    // of eight clamped loads issued together
+    for (int p0 = wv + (ENT / 64) * NP; p0 < npin; p0 += 8 * (ENT / 64)) {
+      double2 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        q[u] = pin[int64_t(std::min(p0 + (ENT / 64) * u, npin - 1)) * PS + 1 + lane];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (p0 + (ENT / 64) * u < npin) b = cadd(b, q[u]);
+    }
     sred[wv][lane] = l < ir ? b : double2{0, 0};
   }
   if (tid < 2 * NBK) shd[tid] = tid % NBK < ir ? hx : double2{0, 0};
