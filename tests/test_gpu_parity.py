@@ -211,8 +211,10 @@ def _match_poles(pole, osc, ce, cw, tol, wtol=1e-6):
     assert abs(osc.sum() - tot) <= max(1e-8, wtol) * tot
 
 
-@pytest.mark.parametrize("n,mult", [(1, 1), (2, 1), (3, 3), (33, 1), (64, 1), (100, 1),
-                                    (162, 3), (257, 1), (600, 3)])
+# n = 96: the largest block reduced wholly in LDS; 97 and 128: one blocked
+# panel, then an LDS tail of 65 and 96 rows; 129: two panels, tail of 65
+@pytest.mark.parametrize("n,mult", [(1, 1), (2, 1), (3, 3), (33, 1), (64, 1), (96, 3), (97, 1),
+                                    (100, 1), (128, 1), (129, 3), (162, 3), (257, 1), (600, 3)])
 def test_eigh_known_spectrum_fp64(lib, n, mult):
     say("eigh-fp64", n, mult)
     A, b, lam, Q = _random_hermitian(n, seed=n + 17 * mult, mult=mult)
@@ -222,7 +224,7 @@ def test_eigh_known_spectrum_fp64(lib, n, mult):
     _match_poles(po, os_, ce, cw, 1e-9)
 
 
-@pytest.mark.parametrize("n,mult", [(100, 1), (162, 3), (600, 3)])
+@pytest.mark.parametrize("n,mult", [(96, 1), (100, 1), (128, 1), (162, 3), (600, 3)])
 def test_eigh_known_spectrum_fp32(lib, n, mult):
     say("eigh-fp32", n, mult)
     A, b, lam, Q = _random_hermitian(n, seed=3 * n + mult, mult=mult)
