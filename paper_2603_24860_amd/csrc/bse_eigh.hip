@@ -159,6 +159,7 @@ struct Desc {
   double2 *vbuf;             // [n] initial reflector
   double2 *partb0, *partb1;  // [R][PS] partial sums of k_colB / k_col0 (alternating)
   double2 *parta;            // [max(n, 1)] partial sums of conj(y) v of k_colA
+  double2 *bred;             // [2 NBK] panel dot products of k_colB's records, reduced by k_colA
   double2 *part2;            // [ceil(n / 256)] initial reflection: partial w^dag v
   double *part3;             // [ceil(n / 256)] initial reflection: partial norm
   double2 *scl;              // [n + 1] reflector scale 1 / (alpha - beta), index j + 1
@@ -260,6 +261,7 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
   t.partb0 = (double2 *)take(R * PS * 16);
   t.partb1 = (double2 *)take(R * PS * 16);
   t.parta = (double2 *)take(size_t(std::max<int64_t>(n, 1)) * 16);
+  t.bred = (double2 *)take(2 * NBK * 16);
   t.part2 = (double2 *)take(P2 * 16);
   t.part3 = (double *)take(P2 * 8);
   t.scl = (double2 *)take(size_t(n + 1) * 16);
@@ -457,6 +459,39 @@ __device__ __forceinline__ void b_col0(int64_t n, int64_t j0, const TA *__restri
 // ---------------------------------------------------------------------------
 constexpr int HU = 4;
 
+// Workgroups 0..3 of k_colA also reduce the panel dot products that the
+// previous k_colB left in its np records (slots 1 .. 2 NBK: BV_l, BW_l):
+// workgroup w sums slots 16 w .. 16 w + 15, thread t slot t % 16 over the
+// records t / 16, t / 16 + 16, ...; k_colB then reads 2 NBK sums instead of
+// every record.
+constexpr int BQ = 2;  // record loads per thread issued with the other loads
+__device__ __forceinline__ void bred_load(double2 (&q)[BQ], const double2 *__restrict__ partb,
+                                          int np, int wg, bool on) {
+  const int s = threadIdx.x % 16, g = threadIdx.x / 16;
+#pragma unroll
+  for (int u = 0; u < BQ; ++u)
+    q[u] = on ? partb[int64_t(std::min(g + 16 * u, np - 1)) * PS + 1 + 16 * wg + s]
+              : double2{0, 0};
+}
+__device__ __forceinline__ double2 bred_part(const double2 (&q)[BQ],
+                                             const double2 *__restrict__ partb, int np, int wg) {
+  const int s = threadIdx.x % 16, g = threadIdx.x / 16;
+  double2 acc = {0, 0};
+#pragma unroll
+  for (int u = 0; u < BQ; ++u)
+    if (g + 16 * u < np) acc = cadd(acc, q[u]);
+  for (int p0 = g + 16 * BQ; p0 < np; p0 += 16 * BQ) {  // batches issued together
+    double2 q2[BQ];
+#pragma unroll
+    for (int u = 0; u < BQ; ++u)
+      q2[u] = partb[int64_t(std::min(p0 + 16 * u, np - 1)) * PS + 1 + 16 * wg + s];
+#pragma unroll
+    for (int u = 0; u < BQ; ++u)
+      if (p0 + 16 * u < np) acc = cadd(acc, q2[u]);
+  }
+  return acc;
+}
+
 template <typename TA, int WPR>
 __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
                                               const TA *__restrict__ A, int64_t lda,
@@ -466,12 +501,14 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
                                               double2 *__restrict__ tau,
                                               double2 *__restrict__ scl, double *__restrict__ d,
                                               double *__restrict__ e, double2 *__restrict__ y,
-                                              double2 *__restrict__ parta, int wg) {
+                                              double2 *__restrict__ parta,
+                                              double2 *__restrict__ bred, int wg) {
   typedef typename C2T<TA>::t CA;
   constexpr int RT = (ENT / 64) / WPR;  // rows per workgroup
   __shared__ double sh[ENT / 64];
   __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 srow[ENT / 64];
+  __shared__ double2 bsh[ENT / 16][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = jn + 1;
   const int64_t r = m0 + int64_t(wg) * RT + wv / WPR;
@@ -483,6 +520,9 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
   double2 px[PMAX / ENT];  // np <= PMAX = 4 ENT records
 #pragma unroll
   for (int u = 0; u < PMAX / ENT; ++u) px[u] = partb[int64_t(std::min(tid + ENT * u, np - 1)) * PS];
+  const bool red_on = wg < 4 && ir > 0 && !last;
+  double2 bq[BQ];
+  bred_load(bq, partb, np, wg, red_on);
   const double2 cjn = col[jn], cm0 = col[mc], cr = col[rc];
   const double2 a0 = to_d2(reinterpret_cast<const CA *>(A)[rc * lda + mc]);
   const bool lead = lane == 0 && part == 0 && r < n;
@@ -552,8 +592,15 @@ __device__ __forceinline__ void b_colA(int64_t n, int64_t jn, int ir,
     vo = r == m0 ? double2{1, 0} : cmul(sc, cr);  // lead: r < n, so rc = r
     yv = cmulc(yo, vo);
   }
+  if (red_on) bsh[tid / 16][tid % 16] = bred_part(bq, partb, np, wg);
   double yr = yv.x, yi = yv.y;
-  block_sum2_once<ENT>(yr, yi, sh2);
+  block_sum2_once<ENT>(yr, yi, sh2);  // also publishes bsh
+  if (red_on && tid < 16) {
+    double2 b = bsh[0][tid];
+#pragma unroll
+    for (int g = 1; g < ENT / 16; ++g) b = cadd(b, bsh[g][tid]);
+    bred[16 * wg + tid] = b;
+  }
   if (lead) {
     y[r] = yo;
     V[int64_t(ir) * ldv + r] = vo;
@@ -583,7 +630,7 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
                                            double2 *__restrict__ tau, double2 *__restrict__ scl,
                                            double *__restrict__ d, double *__restrict__ e,
                                            double2 *__restrict__ y, double2 *__restrict__ parta,
-                                           int wg) {
+                                           double2 *__restrict__ bred, int wg) {
   typedef typename C2T<TA>::t CA;
   constexpr int RW = LDS_RW, RWG = (ENT / 64) * RW;
   constexpr int CCH = 2048;     // column entries per LDS chunk (32 KB)
@@ -591,6 +638,7 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
   __shared__ double sh[ENT / 64];
   __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 xs[CCH];
+  __shared__ double2 bsh[ENT / 16][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = jn + 1;
   const bool last = m0 >= n;
@@ -599,6 +647,9 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
   double2 px[PMAX / ENT];
 #pragma unroll
   for (int u = 0; u < PMAX / ENT; ++u) px[u] = partb[int64_t(std::min(tid + ENT * u, np - 1)) * PS];
+  const bool red_on = wg < 4 && ir > 0 && !last;
+  double2 bq[BQ];
+  bred_load(bq, partb, np, wg, red_on);
   const double2 cjn = col[jn], cm0 = col[mc];
   const CA *arow[RW];
   double2 a0[RW], cr[RW];
@@ -720,8 +771,15 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
     vo[k] = r == m0 ? double2{1, 0} : cmul(sc, cr[k]);
     if (lane == 0 && r < n) yv = cadd(yv, cmulc(yo[k], vo[k]));
   }
+  if (red_on) bsh[tid / 16][tid % 16] = bred_part(bq, partb, np, wg);
   double yr = yv.x, yi = yv.y;
-  block_sum2_once<ENT>(yr, yi, sh2);
+  block_sum2_once<ENT>(yr, yi, sh2);  // also publishes bsh
+  if (red_on && tid < 16) {
+    double2 b = bsh[0][tid];
+#pragma unroll
+    for (int g = 1; g < ENT / 16; ++g) b = cadd(b, bsh[g][tid]);
+    bred[16 * wg + tid] = b;
+  }
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
@@ -761,7 +819,8 @@ __device__ __forceinline__ double2 gather_sum(const double2 *__restrict__ part, 
 // k_colB: column jn (panel index ir), rows r >= jx = jn + 1, RB rows per
 // workgroup.  With the panel dot products of the new reflector
 //   p_l = V_l^dag v = conj(V_l[jx]) + scale BV_l,  q_l = W_l^dag v = conj(W_l[jx]) + scale BW_l
-// (l < ir, from the partial sums of the previous column) and
+// (l < ir, from the partial sums BV, BW of the previous column, which k_colA
+// has summed over the records into bred) and
 //   w^dag v = conj(tau) (y^dag v - 2 Re(p^dag q)),  alpha = -tau (w^dag v) / 2:
 //   W_ir[r] = tau (y[r] - sum_{l<ir} (V_l[r] q_l + W_l[r] p_l)) + alpha v[r]
 // and, if column jx is in the panel, its entries with every update
@@ -789,7 +848,7 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
                                               double2 *__restrict__ W, int64_t ldv,
                                               const double2 *__restrict__ y,
                                               const double2 *__restrict__ parta, int npa,
-                                              const double2 *__restrict__ pin, int npin,
+                                              const double2 *__restrict__ bred,
                                               const double2 *__restrict__ tau,
                                               const double2 *__restrict__ scl,
                                               double2 *__restrict__ col,
@@ -798,7 +857,6 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   __shared__ double sh[ENT / 64];
   __shared__ double sh2[2 * (ENT / 64)];
   __shared__ double2 tile[2 * NBK * TP];  // [V_0..V_{NBK-1} | W_0..W_{NBK-1}] x rows
-  __shared__ double2 sred[ENT / 64][2 * NBK];
   __shared__ double2 spq[ENT / 64][2 * NBK], shd[2 * NBK];  // p | q per wave, head V_l[jx] | W_l[jx]
   __shared__ double2 sy[RB], sa[RB], sv[RB], sw[RB], sc_[RB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -806,25 +864,11 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   const int64_t rb = jx + int64_t(wg) * RB;
   // ---- loads: every global load is issued from a clamped, in-bounds index
   // before any value is consumed, so none waits for another ----
-  constexpr int NP = 16;                // record groups held in registers
   constexpr int NT = 2 * NBK * RB / ENT;  // tile entries per thread
   const int i = tid % RB, k0 = tid / RB;
   const int64_t r0 = rb + i, rcl = std::min<int64_t>(r0, n - 1);
-  // The loads of px and gx come in a few fixed sizes chosen by a uniform
-  // branch on the record count, so that no duplicate (clamped) record is
-  // fetched more than the size class needs.
-  double2 px[NP];  // lane = slot of the record, wave = record group
-  auto load_px = [&](auto cnt) {
-    constexpr int C = decltype(cnt)::value;
-#pragma unroll
-    for (int u = 0; u < NP; ++u)
-      px[u] = u < C ? pin[int64_t(std::min(wv + (ENT / 64) * u, npin - 1)) * PS + 1 + lane]
-                    : double2{0, 0};
-  };
-  if (npin <= 2 * (ENT / 64)) load_px(std::integral_constant<int, 2>());
-  else if (npin <= 4 * (ENT / 64)) load_px(std::integral_constant<int, 4>());
-  else if (npin <= 8 * (ENT / 64)) load_px(std::integral_constant<int, 8>());
-  else load_px(std::integral_constant<int, NP>());
+  // panel dot products of the previous column's records, reduced by k_colA
+  const double2 bvx = bred[lane % NBK], bwx = bred[NBK + lane % NBK];
   double2 tx[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
@@ -834,6 +878,9 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   const double2 hx = (tid < NBK ? V : W)[int64_t(tid % NBK) * ldv + jx];
   const double2 yx = y[rcl], vx = V[int64_t(ir) * ldv + rcl];
   const double2 ax = to_d2(reinterpret_cast<const CA *>(A)[rcl * lda + jx]);
+  // The partial sums of k_colA come in a few fixed sizes chosen by a uniform
+  // branch on their count, so that no duplicate (clamped) entry is fetched
+  // more than the size class needs.
   constexpr int NG = 16;  // partial sums of k_colA held in registers per thread
   double2 gx[NG];
   auto load_gx = [&](auto cnt) {
@@ -848,25 +895,6 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   const double2 t = tau[jx], sc = scl[jx];
   const double2 yjx = y[jx];
   // ---- consume ----
-  {
-    const int l = lane % NBK;
-    double2 b = {0, 0};
-#pragma unroll
-    for (int u = 0; u < NP; ++u)
-      if (wv + (ENT / 64) * u < npin) b = cadd(b, px[u]);
-    // more than NP record groups (trailing blocks above 64 NP rows): batches
-    // of eight clamped loads issued together
-    for (int p0 = wv + (ENT / 64) * NP; p0 < npin; p0 += 8 * (ENT / 64)) {
-      double2 q[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        q[u] = pin[int64_t(std::min(p0 + (ENT / 64) * u, npin - 1)) * PS + 1 + lane];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (p0 + (ENT / 64) * u < npin) b = cadd(b, q[u]);
-    }
-    sred[wv][lane] = l < ir ? b : double2{0, 0};
-  }
   if (tid < 2 * NBK) shd[tid] = tid % NBK < ir ? hx : double2{0, 0};
 #pragma unroll
   for (int u = 0; u < NT; ++u) tile[(k0 + (ENT / RB) * u) * TP + i] = r0 < n ? tx[u] : double2{0, 0};
@@ -889,11 +917,9 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   {
     double2 pl = {0, 0}, ql = {0, 0}, hl = {0, 0};
     if (lane < ir) {
-      const double2 bv = cadd(cadd(sred[0][lane], sred[1][lane]), cadd(sred[2][lane], sred[3][lane]));
       const int lw = NBK + lane;
-      const double2 bw = cadd(cadd(sred[0][lw], sred[1][lw]), cadd(sred[2][lw], sred[3][lw]));
-      pl = cadd(cconj(shd[lane]), cmul(sc, bv));
-      ql = cadd(cconj(shd[lw]), cmul(sc, bw));
+      pl = cadd(cconj(shd[lane]), cmul(sc, bvx));
+      ql = cadd(cconj(shd[lw]), cmul(sc, bwx));
       hl = cadd(cmul(shd[lane], ql), cmul(shd[lw], pl));
     }
     if (lane < NBK) {
@@ -1302,17 +1328,17 @@ BSE_PAIR(colA, int64_t jn BSE_COMMA int cur, {
   if constexpr (WPR == 0)
     b_colA_lds<TA>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
                    cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
-                   D.parta, wg);
+                   D.parta, D.bred, wg);
   else
     b_colA<TA, WPR>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
                     cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
-                    D.parta, wg);
+                    D.parta, D.bred, wg);
 })
 BSE_PAIR(colB, int64_t jn BSE_COMMA int cur, {
   const int64_t m = D.n - jn - 1;
   b_colB<TA>(D.n, jn, int(jn % NBK), g_more(D.n, jn), (const TA *)D.A, D.lda, D.V, D.W, D.ldv,
-             D.y, D.parta, g_colA_wgs(m, WPR), cur ? D.partb1 : D.partb0, g_np_in(D.n, jn),
-             D.tau, D.scl, D.col, cur ? D.partb0 : D.partb1, wg);
+             D.y, D.parta, g_colA_wgs(m, WPR), D.bred, D.tau, D.scl, D.col,
+             cur ? D.partb0 : D.partb1, wg);
 })
 BSE_PAIR(her2k, int64_t j0, {
   const int nbk = g_nbk(D.n, j0);
