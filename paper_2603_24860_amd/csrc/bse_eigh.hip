@@ -983,6 +983,12 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
 
 // Trailing update on MFMA: A[r][c] -= sum_l V_l[r] conj(W_l[c]) + W_l[r] conj(V_l[c])
 // for r, c >= c0; real GEMM with K = 4 nbk (x conj(y) interleave, see bse_build).
+// The update is Hermitian: from HER_TRI tile rows on (mirror), only tiles on
+// or below the diagonal are computed (by >= bx) and an off-diagonal tile also
+// subtracts the conjugate transpose of its update from the mirror tile,
+// staged through LDS so that those writes are row-contiguous too.  Smaller
+// trailing blocks keep every tile, for the parallelism.
+constexpr int64_t HER_TRI = 32;
 template <typename T> struct HerTile;
 template <> struct HerTile<float> { static constexpr int BM = 128, BN = 64, BK = 32; };
 template <> struct HerTile<double> { static constexpr int BM = 128, BN = 64, BK = 16; };
@@ -991,13 +997,18 @@ template <typename T>
 __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
                                                const double2 *__restrict__ V,
                                                const double2 *__restrict__ W, int64_t ldv,
-                                               T *__restrict__ A, int64_t lda, int64_t bx, int64_t by) {
+                                               T *__restrict__ A, int64_t lda, int64_t bx, int64_t by,
+                                               bool mirror) {
   constexpr int BM = HerTile<T>::BM, BN = HerTile<T>::BN, BK = HerTile<T>::BK;
   constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32, KC = BK / 2;
   constexpr int NA = (BM / 2) * KC / ENT, NB = BN * KC / ENT;
-  __shared__ __attribute__((aligned(16))) T As[BM * P];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * P];
+  static_assert(BM == 2 * BN, "square tiles in complex entries");
   typedef typename C2T<T>::t C2;
+  constexpr int UP = BN + 1;  // LDS pitch of the staged update
+  constexpr size_t SLAB = sizeof(T) * (BM + BN) * P, STAGE = sizeof(C2) * BN * UP;
+  __shared__ __attribute__((aligned(16))) char smem[SLAB > STAGE ? SLAB : STAGE];
+  T *As = reinterpret_cast<T *>(smem), *Bs = As + BM * P;
+  C2 *Us = reinterpret_cast<C2 *>(smem);  // after the slabs: [a][b] update of the tile
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t a0 = c0 + by * (BM / 2), b0 = c0 + bx * BN;
   if (a0 >= n || b0 >= n) return;
@@ -1044,6 +1055,31 @@ __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
           *p = x;
         }
     }
+  if (!mirror || bx == by) return;  // a diagonal tile holds both triangles itself
+  // mirror tile: A[b][a] -= conj(U[a][b])
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int al = (wm0 + 16 * mi + 4 * g) / 2 + h, bl = wn0 + 16 * ni + r16;
+        Us[al * UP + bl] = C2{acc[mi][ni][2 * h], acc[mi][ni][2 * h + 1]};
+      }
+  __syncthreads();  // (the last slab ended with a barrier: smem is free)
+  const int il = tid % BN;
+#pragma unroll 4
+  for (int jl = tid / BN; jl < BN; jl += ENT / BN) {
+    const int64_t b = b0 + jl, a = a0 + il;
+    if (b < n && a < n) {
+      C2 *p = reinterpret_cast<C2 *>(A) + b * lda + a;
+      const C2 u = Us[il * UP + jl];
+      C2 x = *p;
+      x.x -= u.x;
+      x.y += u.y;
+      *p = x;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1342,9 +1378,16 @@ BSE_PAIR(colB, int64_t jn BSE_COMMA int cur, {
 })
 BSE_PAIR(her2k, int64_t j0, {
   const int nbk = g_nbk(D.n, j0);
-  const int64_t c0 = j0 + nbk, m = D.n - c0;
-  const int64_t gx = cdiv(m, HerTile<TA>::BN);
-  b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, wg % gx, wg / gx);
+  const int64_t c0 = j0 + nbk, t = cdiv(D.n - c0, HerTile<TA>::BN);
+  if (t < HER_TRI) {  // every tile
+    b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, wg % t, wg / t, false);
+  } else {  // tiles on or below the diagonal, row by row: wg = by (by + 1) / 2 + bx
+    int64_t by = int64_t((sqrt(8.0 * double(wg) + 1.0) - 1.0) * 0.5);
+    while (by * (by + 1) / 2 > wg) --by;
+    while ((by + 1) * (by + 2) / 2 <= wg) ++by;
+    const int64_t bx = wg - by * (by + 1) / 2;
+    b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, bx, by, true);
+  }
 })
 BSE_PAIR(bisect, int unused_, {
   (void)unused_;
@@ -1537,7 +1580,8 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
     case K_HER2K: {
       if (j >= g_tail0(n)) return 0;
       const int64_t c0 = j + g_nbk(n, j), m = n - c0;
-      return m > 0 ? cdiv(m, HerTile<TA>::BN) * cdiv(2 * m, HerTile<TA>::BM) : 0;
+      const int64_t t = cdiv(m, HerTile<TA>::BN);  // tile rows (see b_her2k)
+      return m > 0 ? (t < HER_TRI ? t * t : t * (t + 1) / 2) : 0;
     }
     case K_TRI: return 1;
     default: return cdiv(n, 4);  // bisect, weights
