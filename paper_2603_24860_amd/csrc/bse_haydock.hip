@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
+#include <type_traits>
 
 #include "bse_internal.h"
 
@@ -122,12 +124,15 @@ __device__ __forceinline__ double2 ld_h(const TH *p) {
 }
 
 // ws: P[3][n] (ring by j mod 3), Y[2][n], partials[2][3][G] (ring by j mod 2)
-template <typename TH, int RPW>
+// VEC (FP32 H_mu with an even ld and a 16-byte aligned base): each lane
+// reads two adjacent columns in one 16-byte load.
+template <typename TH, int RPW, bool VEC>
 __global__ __launch_bounds__(HNT) void k_hd_step(int64_t n, const TH *__restrict__ H, int64_t ld,
                                                  const double2 *__restrict__ Bv, int j, int G,
                                                  double2 *__restrict__ P, double2 *__restrict__ Y,
                                                  double *__restrict__ part,
                                                  double *__restrict__ a, double *__restrict__ b) {
+  static_assert(!VEC || std::is_same<TH, float2>::value, "16-byte pairs of FP32 entries only");
   __shared__ double2 xs[HCH];
   __shared__ double red[3][HWV];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -161,6 +166,45 @@ __global__ __launch_bounds__(HNT) void k_hd_step(int64_t n, const TH *__restrict
     for (int t = tid; t < cn; t += HNT) xs[t] = hd_x(j, c0 + t, c, Bv, Ym1, Pm1, Pm2);
     __syncthreads();
     constexpr int U = RPW >= 8 ? 2 : 16 / RPW;  // 16 row loads in flight per lane
+    if constexpr (VEC) {
+      constexpr int U2 = U / 2;
+      int cc = 2 * lane;
+      for (; cc + 1 + (U2 - 1) * 128 < cn; cc += U2 * 128) {
+        float4 h[RPW][U2];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int u = 0; u < U2; ++u)
+            h[r][u] = *reinterpret_cast<const float4 *>(hrow[r] + c0 + cc + u * 128);
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+          const double2 x0 = xs[cc + u * 128], x1 = xs[cc + 1 + u * 128];
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            const double hr0 = h[r][u].x, hi0 = h[r][u].y, hr1 = h[r][u].z, hi1 = h[r][u].w;
+            acc[r].x += hr0 * x0.x - hi0 * x0.y;
+            acc[r].y += hr0 * x0.y + hi0 * x0.x;
+            acc[r].x += hr1 * x1.x - hi1 * x1.y;
+            acc[r].y += hr1 * x1.y + hi1 * x1.x;
+          }
+        }
+      }
+      for (; cc < cn; cc += 128) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (cc + e < cn) {
+            const double2 x = xs[cc + e];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+              const double2 h = ld_h(hrow[r] + c0 + cc + e);
+              acc[r].x += h.x * x.x - h.y * x.y;
+              acc[r].y += h.x * x.y + h.y * x.x;
+            }
+          }
+        }
+      }
+      continue;
+    }
     int cc = lane;
     for (; cc + (U - 1) * 64 < cn; cc += U * 64) {
       double2 h[RPW][U];
@@ -188,15 +232,19 @@ __global__ __launch_bounds__(HNT) void k_hd_step(int64_t n, const TH *__restrict
       }
     }
   }
+  // the stores follow the reduction (a pending store whose registers the
+  // reduction reuses would have to complete first)
   double pp = 0, py = 0, pq = 0;
+  double2 xo[RPW], yo[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const double yx = wsum(acc[r].x), yy = wsum(acc[r].y);
     const int64_t i = r0 + r;
+    xo[r] = yo[r] = make_double2(0.0, 0.0);
     if (lane == 0 && i < n) {
       const double2 x = hd_x(j, i, c, Bv, Ym1, Pm1, Pm2);
-      Pj[i] = x;
-      Yj[i] = make_double2(yx, yy);
+      xo[r] = x;
+      yo[r] = make_double2(yx, yy);
       pp += x.x * x.x + x.y * x.y;
       py += x.x * yx + x.y * yy;
       if (j > 0) {
@@ -206,6 +254,16 @@ __global__ __launch_bounds__(HNT) void k_hd_step(int64_t n, const TH *__restrict
     }
   }
   block_sum3(pp, py, pq, red);
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int64_t i = r0 + r;
+      if (i < n) {
+        Pj[i] = xo[r];
+        Yj[i] = yo[r];
+      }
+    }
+  }
   if (tid == 0) {
     pout[blockIdx.x] = pp;
     pout[G + blockIdx.x] = py;
@@ -277,9 +335,17 @@ int hd_groups(int64_t n) {
 template <typename TH, int RPW>
 void launch_steps(int64_t n, const TH *H, int64_t ld, const double2 *Bv, int K, int G,
                   double2 *P, double2 *Y, double *part, double *a, double *b, hipStream_t s) {
+  if constexpr (std::is_same<TH, float2>::value) {
+    if (ld % 2 == 0 && reinterpret_cast<uintptr_t>(H) % 16 == 0) {
+      for (int j = 0; j < K; ++j)
+        BSE_LAUNCH("k_hd_step", (k_hd_step<TH, RPW, true>), dim3(G), dim3(HNT), 0, s, n, H, ld,
+                   Bv, j, G, P, Y, part, a, b);
+      return;
+    }
+  }
   for (int j = 0; j < K; ++j)
-    BSE_LAUNCH("k_hd_step", (k_hd_step<TH, RPW>), dim3(G), dim3(HNT), 0, s, n, H, ld, Bv, j, G,
-               P, Y, part, a, b);
+    BSE_LAUNCH("k_hd_step", (k_hd_step<TH, RPW, false>), dim3(G), dim3(HNT), 0, s, n, H, ld, Bv, j,
+               G, P, Y, part, a, b);
 }
 
 template <typename TH>
