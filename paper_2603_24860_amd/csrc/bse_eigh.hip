@@ -141,6 +141,7 @@ __device__ __forceinline__ void block_sum2_once(double &a, double &b, double *sh
 }
 
 constexpr int NBMAX = 1024;  // blocks in one batched solve
+constexpr int NGRID = 4096;  // grid points of the shared first bisection step (64 x 64)
 constexpr int CMAX = 8;      // cluster members refined per eigenvalue cluster
 constexpr int KMAX = 256;    // eigenvalues refinable per solve
 
@@ -167,6 +168,7 @@ struct Desc {
   double *d, *e;             // [n]
   double *e2;                // [n] squared subdiagonal
   double *tsc;               // [8] tridiagonal scalars
+  int *bgrid;                // [NGRID] Sturm counts on a uniform grid over the Gershgorin interval
   double *beta0;             // [1]
   double *omega, *pole, *osc;  // outputs [n]
   // refinement of the lowest K eigenvalues (K = 0: none)
@@ -270,6 +272,7 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
   t.e = (double *)take(size_t(n) * 8);
   t.e2 = (double *)take(size_t(n) * 8);
   t.tsc = (double *)take(8 * 8);
+  t.bgrid = (int *)take(NGRID * 4);
   t.beta0 = (double *)take(8);
   t.K = K;
   if (K > 0) {
@@ -1186,18 +1189,52 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d,
   return cnt;
 }
 
+// x_g, g = 0 .. NGRID - 1: the interior points of a uniform grid over the
+// Gershgorin interval [sc[0], sc[1]] (the same expression wherever it is used)
+__device__ __forceinline__ double grid_x(const double *__restrict__ sc, int g) {
+  return sc[0] + (sc[1] - sc[0]) * double(g + 1) / double(NGRID + 1);
+}
+
+// Shared first step of the bisection: Sturm counts at the NGRID grid points,
+// one thread per point (NGRID / ENT workgroups).
+__device__ __forceinline__ void b_bisect_grid(int64_t n, const double *__restrict__ d,
+                                              const double *__restrict__ e2,
+                                              const double *__restrict__ sc,
+                                              int *__restrict__ grid, int wg) {
+  const int g = wg * ENT + int(threadIdx.x);
+  grid[g] = sturm_count(d, e2, n, grid_x(sc, g), sc[3]);
+}
+
 // One wave per eigenvalue index: each pass evaluates 64 Sturm counts at the
 // interior points of the current interval (lane l at a + (l+1)(b-a)/65) and
-// keeps the sub-interval holding eigenvalue i; ~9 passes reach FP64 resolution.
+// keeps the sub-interval holding eigenvalue i; ~9 passes reach FP64 resolution
+// from the Gershgorin interval.  With grid (the counts of b_bisect_grid) the
+// start is the grid cell holding eigenvalue i, found in two ballots over
+// 64-entry segments, which saves two passes.
 __device__ __forceinline__ void b_bisect(int64_t n, const double *__restrict__ d,
                                                 const double *__restrict__ e2,
                                                 const double *__restrict__ sc,
+                                                const int *__restrict__ grid,
                                                 double *__restrict__ omega, int wg) {
   const int lane = threadIdx.x & 63;
   const int64_t i = int64_t(wg) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
   double a = sc[0], b = sc[1];
   const double pivmin = sc[3];
+  if (grid) {
+    // count(x) = eigenvalues below x; the first g with count(x_g) > i gives
+    // x_{g-1} <= lambda_i < x_g
+    const unsigned long long m1 = __ballot(grid[64 * lane + 63] > i);
+    if (m1) {
+      const int seg = __builtin_ctzll(m1);
+      const unsigned long long m2 = __ballot(grid[64 * seg + lane] > i);
+      const int g = 64 * seg + __builtin_ctzll(m2);  // m2 != 0: the segment's last entry is > i
+      b = grid_x(sc, g);
+      if (g > 0) a = grid_x(sc, g - 1);
+    } else {
+      a = grid_x(sc, NGRID - 1);
+    }
+  }
   for (int pass = 0; pass < 24; ++pass) {
     if (b - a <= 2.3e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
     const double x = a + (b - a) * double(lane + 1) / 65.0;
@@ -1389,9 +1426,12 @@ BSE_PAIR(her2k, int64_t j0, {
     b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, bx, by, true);
   }
 })
-BSE_PAIR(bisect, int unused_, {
+BSE_PAIR(bisect_grid, int unused_, {
   (void)unused_;
-  b_bisect(D.n, D.d, D.e2, D.tsc, D.omega, wg);
+  b_bisect_grid(D.n, D.d, D.e2, D.tsc, D.bgrid, wg);
+})
+BSE_PAIR(bisect, int use_grid, {
+  b_bisect(D.n, D.d, D.e2, D.tsc, use_grid ? D.bgrid : nullptr, D.omega, wg);
 })
 BSE_PAIR(weights, int unused_, {
   (void)unused_;
@@ -1564,7 +1604,7 @@ __global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
 
 // workgroups of one launch kind for one block (0 = the block is not active)
 enum Kind { K_COPY, K_LOADB, K_HEMV0, K_W0, K_RANK2, K_COL0, K_COLA, K_COLB, K_HER2K, K_TRI,
-            K_BISECT, K_WEIGHTS, K_TAIL };
+            K_BISECT, K_WEIGHTS, K_TAIL, K_BGRID };
 
 template <typename TA>
 int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
@@ -1584,6 +1624,7 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
       return m > 0 ? (t < HER_TRI ? t * t : t * (t + 1) / 2) : 0;
     }
     case K_TRI: return 1;
+    case K_BGRID: return NGRID / ENT;
     default: return cdiv(n, 4);  // bisect, weights
   }
 }
@@ -2089,7 +2130,9 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
   // ---- tridiagonal eigenvalues and optical weights ----
   BSE_LAUNCH("k_tri_prep", k_tri_prep<TA>, dim3(1), dim3(RNT), 0, s, D,
              ctol_rel(n, sizeof(TA) == 8));
-  BSE_LAUNCH("k_bisect", (k_bisect<TH, TA, 4>), grid(K_BISECT, 0, 4), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_bisect_grid", (k_bisect_grid<TH, TA, 4>), dim3(NGRID / ENT), dim3(ENT), 0, s, D,
+             0);
+  BSE_LAUNCH("k_bisect", (k_bisect<TH, TA, 4>), grid(K_BISECT, 0, 4), dim3(ENT), 0, s, D, 1);
   BSE_LAUNCH("k_weights", (k_weights<TH, TA, 4>), grid(K_WEIGHTS, 0, 4), dim3(ENT), 0, s, D, 0);
   BSE_HIP_CHECK(hipGetLastError());
   if (K > 0) {
@@ -2172,6 +2215,7 @@ void plan_launches(BatchPlan &P, std::vector<int> &pre) {
   // after its last panel, so the tails need not sit in the lockstep chain
   P.launches.push_back(BatchLaunch{K_TAIL, 0, 0, nb, nb, 0});
   add(K_TRI, 0, 0);
+  add(K_BGRID, 0, 0);
   add(K_BISECT, 0, 0);
   add(K_WEIGHTS, 0, 0);
 }
@@ -2193,7 +2237,8 @@ int32_t batch_launch(const BatchPlan &P, const BatchLaunch &L, hipStream_t s) {
     case K_HER2K: BSE_LAUNCH("k_her2k", (k_her2k_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j); break;
     case K_TRI: BSE_LAUNCH("k_tri_prep", k_tri_prep_b<TA>, g, dim3(RNT), 0, s, Ds, pre, L.nact, 0); break;
     case K_TAIL: BSE_LAUNCH("k_tail", k_tail_b<TA>, g, dim3(TNT), 0, s, Ds, L.cur, L.j); break;
-    case K_BISECT: BSE_LAUNCH("k_bisect", (k_bisect_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_BGRID: BSE_LAUNCH("k_bisect_grid", (k_bisect_grid_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
+    case K_BISECT: BSE_LAUNCH("k_bisect", (k_bisect_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 1); break;
     default: BSE_LAUNCH("k_weights", (k_weights_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
   }
   return BSE_OK;
@@ -2233,7 +2278,7 @@ size_t batch_ws_bytes(int32_t nb, const int64_t *h_n, bool a_fp64, std::vector<s
 size_t pre_bound(int32_t nb, const int64_t *h_n) {
   int64_t nmax = 0;
   for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h_n[b]);
-  const size_t launches = 8 + size_t(cdiv(nmax, NBK)) * (2 * NBK + 2);
+  const size_t launches = 9 + size_t(cdiv(nmax, NBK)) * (2 * NBK + 2);  // 9 one-off kinds
   return launches * size_t(nb + 1);
 }
 
