@@ -1462,7 +1462,7 @@ __device__ __forceinline__ void b_tail(const Desc &D, int64_t j0, int keep) {
   __shared__ double red[TNT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t n = D.n, lda = D.lda, ldv = D.ldv;
-  const int mt = int(n - j0);  // 1 <= mt <= MT (checked by the host)
+  const int mt = int(n - j0);  // 1 <= mt <= MT: j0 = g_tail0(n)
   const CA *A = reinterpret_cast<const CA *>(D.A);
   for (int q = tid; q < mt * mt; q += TNT) {
     const int r = q / mt, c = q % mt;
