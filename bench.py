@@ -324,6 +324,9 @@ def main():
     ap.add_argument("--seed", action="store_true",
                     help="build H by the seed construction (one contraction per pair orbit); "
                          "TFLOP/s then counts the contractions performed")
+    ap.add_argument("--seed-direct", action="store_true",
+                    help="with --seed: keep only the seed pieces and project the block straight "
+                         "from them (H is never formed)")
     ap.add_argument("--partner", action="store_true",
                     help="solve the x-partner block of the dipole-active vector irrep (1/d of "
                          "the isotypic block, the same eps2) instead of the isotypic block")
@@ -371,8 +374,11 @@ def main():
     cfg = synth.config(args.workload)
     t0 = time.perf_counter()
     S = workloads.device_system(cfg, prec)
+    if args.seed_direct and not args.seed:
+        print("--seed-direct needs --seed", file=sys.stderr)
+        sys.exit(2)
     if args.seed:
-        S.use_seed()
+        S.use_seed(direct=args.seed_direct)
     irrep, weights = S.active_irrep()
     sv = Solver(S, irrep, partner=0 if args.partner else None, nrefine=args.nrefine)
     log(f"setup {time.perf_counter() - t0:.1f} s; N = {S.N}, block {irrep}"
@@ -459,7 +465,9 @@ def main():
                                + (f"eps2 by {args.haydock} Lanczos-Haydock steps (no eigh), "
                                   if args.haydock else "")
                                + (f"seed build (one contraction per pair orbit)" if args.seed
-                                  else f"dense-mode build of all {nk * nk} k pairs"),
+                                  else f"dense-mode build of all {nk * nk} k pairs")
+                               + (", block projected from the seed pieces (no H)"
+                                  if args.seed_direct else ""),
                    "precision": args.prec, "nrefine": args.nrefine},
         "block_eigh_s": None if args.haydock else round(st_ms[2] * 1e-3, 6),
         "solves_per_s": round(1e3 / ms_step, 3),

@@ -199,6 +199,19 @@ int32_t bse_build(const bse_problem *p, int32_t prec, void *H, int64_t ldh, void
  *                   used (the plan keeps a copy of the struct).
  *   bse_build_seed  writes H (N x N, leading dimension ldh, complex of the
  *                   plan's precision) on `stream`; kernel launches only.
+ *                   H = NULL computes the pieces only (for bse_project_seed).
+ *   bse_project_seed  projects blocks straight from the pieces of the last
+ *                   bse_build_seed on the plan, without materialising H: the
+ *                   same bse_block descriptors and H_mu layout as
+ *                   bse_project_blocks (Hmu[i], ldmu[i]; NULL skips a block),
+ *                   element type of the plan's precision.  Every element of H
+ *                   is formed on the fly as the assembly forms it and rounded
+ *                   to that precision, so the result equals bse_project_blocks
+ *                   of the assembled H exactly.  Kernel launches only; stream
+ *                   order with bse_build_seed is the caller's.  B_mu still
+ *                   comes from bse_project_blocks (H = NULL).  Errors:
+ *                   BSE_EINVAL (unknown plan, NULL block arrays), BSE_ESHAPE
+ *                   (ldmu < n), BSE_EUNSUPPORTED (nv nc too large).
  *   bse_seed_free   forgets the plan.
  * Precision FP32 or FP64; shapes as the fused direct kernel (Nmb = 64 m with
  * m <= 6, nv <= 4, nc <= 6), else BSE_EUNSUPPORTED.
@@ -230,6 +243,10 @@ int32_t bse_project_blocks(const bse_problem *p, const void *H, int64_t ldh, int
                            const void *B, int32_t nblk, const bse_block *h_blk,
                            void *const *h_Hmu, const int64_t *h_ldmu, void *const *h_Bmu,
                            bse_stream stream);
+/* bse_project_seed: see the seed construction above (Sec. III.C.2 with
+ * Eq. (transformationU)): blocks projected from a seed plan's pieces. */
+int32_t bse_project_seed(int64_t plan, int32_t nblk, const bse_block *h_blk, void *const *h_Hmu,
+                         const int64_t *h_ldmu, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
  * bse_block_eigh: eigenvalues of the Hermitian block and the oscillator

@@ -80,6 +80,7 @@ def _load():
         "bse_seed_ws": (ctypes.c_size_t, [i32, P(Problem), i32]),
         "bse_seed_plan": (i32, [i32, P(Problem), i32, vp, ctypes.c_size_t, P(i64), vp]),
         "bse_build_seed": (i32, [i64, vp, i64, vp]),
+        "bse_project_seed": (i32, [i64, i32, P(Block), P(vp), P(i64), vp]),
         "bse_seed_free": (i32, [i64]),
         "bse_project_blocks": (i32, [P(Problem), vp, i64, i32, vp, i32, P(Block),
                                      P(vp), P(i64), P(vp), vp]),

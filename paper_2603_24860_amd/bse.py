@@ -150,7 +150,17 @@ def bse_seed_plan(group, problem, prec, ws, stream=None):
 
 
 def bse_build_seed(plan, H, stream=None):
-    check(lib.bse_build_seed(plan, _ptr(H), H.stride(0), _stream(stream)))
+    """H None: the seed pieces only (for bse_project_seed)."""
+    check(lib.bse_build_seed(plan, _ptr(H), H.stride(0) if H is not None else 0, _stream(stream)))
+
+
+def bse_project_seed(plan, blocks, Hmu, stream=None):
+    """H_mu of each block straight from the plan's seed pieces (no H)."""
+    nb = len(blocks)
+    arr = (_lib.Block * max(nb, 1))(*blocks)
+    hp = (ctypes.c_void_p * max(nb, 1))(*[(h.data_ptr() if h is not None else None) for h in Hmu])
+    ld = (ctypes.c_int64 * max(nb, 1))(*[(h.stride(0) if h is not None else 0) for h in Hmu])
+    check(lib.bse_project_seed(plan, nb, arr, hp, ld, _stream(stream)))
 
 
 def bse_seed_free(plan):

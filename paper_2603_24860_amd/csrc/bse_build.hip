@@ -896,8 +896,7 @@ extern "C" int32_t bse_build_seed(int64_t plan, void *H, int64_t ldh, bse_stream
   }
   const bse_problem *p = &P.p;
   const int64_t N = int64_t(P.nk) * p->nv * p->nc;
-  if (!H) return fail(BSE_EINVAL, "H is NULL");
-  if (ldh < N) return fail(BSE_ESHAPE, "ldh %lld < N %lld", (long long)ldh, (long long)N);
+  if (H && ldh < N) return fail(BSE_ESHAPE, "ldh %lld < N %lld", (long long)ldh, (long long)N);
   hipStream_t s = (hipStream_t)stream;
   const double inv_nk = 1.0 / P.nk;
   auto launch = [&](auto tag) -> int32_t {
@@ -912,6 +911,7 @@ extern "C" int32_t bse_build_seed(int64_t plan, void *H, int64_t ldh, bse_stream
     int32_t st = launch_fused<T, SEED_KC, true>(p->nmb / 64, dim3((unsigned)P.nitems), s, p,
                                                 nullptr, 0, 0.0, P.items, P.drep);
     if (st) return st;
+    if (!H) return BSE_OK;  // pieces only (bse_project_seed reads them)
     dim3 ga((unsigned)(N * ((N + NT - 1) / NT)));
     BSE_LAUNCH("k_seed_assemble", k_seed_assemble<T>, ga, dim3(NT), 0, s, P.nk, p->nv, p->nc,
                p->korb, P.porb, p->ev, p->ec, (const T *)P.xs, P.ldx, (const T *)P.drep,
@@ -922,6 +922,23 @@ extern "C" int32_t bse_build_seed(int64_t plan, void *H, int64_t ldh, bse_stream
   if (P.prec == BSE_FP64) return launch(double(0));
   return launch(float(0));
 }
+
+namespace bse {
+int32_t seed_pieces(int64_t plan, SeedPieces *out) {
+  std::lock_guard<std::mutex> lk(g_seed_mu);
+  auto it = g_seeds.find(plan);
+  if (it == g_seeds.end()) return fail(BSE_EINVAL, "unknown seed plan %lld", (long long)plan);
+  const SeedPlan &P = it->second;
+  out->p = P.p;
+  out->prec = P.prec;
+  out->nk = P.nk;
+  out->porb = P.porb;
+  out->xs = P.xs;
+  out->drep = P.drep;
+  out->ldx = P.ldx;
+  return BSE_OK;
+}
+}  // namespace bse
 
 extern "C" int32_t bse_seed_free(int64_t plan) {
   std::lock_guard<std::mutex> lk(g_seed_mu);

@@ -60,6 +60,21 @@ class ProfScope {
 int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_t ws_bytes,
                      bse_stream stream);
 
+// The seed pieces of a plan (bse_seed_plan; filled by bse_build_seed): the
+// exchange between k-orbit representatives xs [nkorb nb][ldx], the direct
+// blocks of the pair-orbit representatives drep [nporb][nc^2][nv^2], the
+// k -> k-orbit and (k, k') -> pair-orbit maps; elements of the plan's
+// precision.  For projecting blocks straight from the pieces.
+struct SeedPieces {
+  bse_problem p;
+  int32_t prec;
+  int nk;
+  const int32_t *porb;
+  const void *xs, *drep;
+  int64_t ldx;
+};
+int32_t seed_pieces(int64_t plan, SeedPieces *out);
+
 }  // namespace bse
 
 #define BSE_HIP_CHECK(expr)                                                        \

@@ -30,7 +30,23 @@ constexpr int PMAXCOL = 2;   // output columns per thread: r' nv nc <= 512
 constexpr int PMAXL = 48;    // orbit size <= |S|
 constexpr int PCH = 2048;    // H elements per chunk (8 per thread)
 
-template <typename T>
+// Source of the H elements when projecting straight from the seed pieces
+// (f1 without materialising H): every element is formed as the seed assembly
+// forms it,
+//   H[(k v c),(k' v' c')] = X[(o(k) v c),(o(k') v' c')] + delta (E_c - E_v)
+//                           - scale D[porb(k,k')][(c c')][(v v')],
+// and rounded to T, so the projected block equals the projection of the
+// assembled H exactly.
+struct SeedSrc {
+  const int32_t *korb, *porb;
+  const double *ev, *ec;
+  const void *xs, *drep;
+  int64_t ldx;
+  int nk;
+  double scale;
+};
+
+template <typename T, bool SEEDSRC>
 __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__restrict__ H,
                                                  int64_t ldh, const int32_t *__restrict__ mem_off,
                                                  const int32_t *__restrict__ members,
@@ -38,11 +54,12 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
                                                  const int32_t *__restrict__ orb_dim,
                                                  const int64_t *__restrict__ ub_off,
                                                  const double *__restrict__ ub, T *__restrict__ Hmu,
-                                                 int64_t ldmu) {
+                                                 int64_t ldmu, SeedSrc sd) {
   typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type C2;
   __shared__ C2 rows[PCH];
   __shared__ double u1s[PMAXL * PMAXR], u2s[PMAXL * PMAXR];
   __shared__ int32_t m1s[PMAXL], m2s[PMAXL];
+  __shared__ int32_t o1s[SEEDSRC ? PMAXL : 1], o2s[SEEDSRC ? PMAXL : 1];  // k orbits of the members
   const int nb = nv * nc;
   const int band = blockIdx.x;        // (v, c) of the output rows
   // orbit ids grow with orbit size on the simple grids, so the largest (longest)
@@ -59,6 +76,10 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
   for (int i = threadIdx.x; i < L2 * r2; i += PNT) u2s[i] = ub[ub_off[o2] + i];
   if (threadIdx.x < L2) m2s[threadIdx.x] = m2[threadIdx.x];
   if (threadIdx.x < L1) m1s[threadIdx.x] = m1[threadIdx.x];
+  if constexpr (SEEDSRC) {
+    if (threadIdx.x < L2) o2s[threadIdx.x] = sd.korb[m2[threadIdx.x]];
+    if (threadIdx.x < L1) o1s[threadIdx.x] = sd.korb[m1[threadIdx.x]];
+  }
   const int ncol = r2 * nb, per = L2 * nb;
   const int RU = PCH / per;  // rows per chunk (>= 1)
   double accr[PMAXCOL][PMAXR], acci[PMAXCOL][PMAXR];
@@ -81,8 +102,21 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
       const int e0 = threadIdx.x + PNT * u;
       const int e = std::min(e0, nr * per - 1);
       const int ii = e / per, rem = e - ii * per, i2 = rem / nb, b2 = rem - i2 * nb;
-      const int64_t a = (int64_t(m1s[i0 + ii]) * nv + v) * nc + c;
-      x[u] = reinterpret_cast<const C2 *>(H)[a * ldh + int64_t(m2s[i2]) * nb + b2];
+      if constexpr (SEEDSRC) {
+        const int k = m1s[i0 + ii], k2 = m2s[i2], ia = v * nc + c;
+        const int v2 = b2 / nc, c2 = b2 % nc;
+        const C2 xe = reinterpret_cast<const C2 *>(sd.xs)[(int64_t(o1s[i0 + ii]) * nb + ia) * sd.ldx +
+                                                          int64_t(o2s[i2]) * nb + b2];
+        const int64_t o = sd.porb[int64_t(k) * sd.nk + k2];
+        const C2 d = reinterpret_cast<const C2 *>(sd.drep)[(o * (nc * nc) + c * nc + c2) * (nv * nv) +
+                                                           v * nv + v2];
+        double re = double(xe.x) - sd.scale * double(d.x), im = double(xe.y) - sd.scale * double(d.y);
+        if (k == k2 && ia == b2) re += sd.ec[int64_t(k) * nc + c] - sd.ev[int64_t(k) * nv + v];
+        x[u] = C2{T(re), T(im)};
+      } else {
+        const int64_t a = (int64_t(m1s[i0 + ii]) * nv + v) * nc + c;
+        x[u] = reinterpret_cast<const C2 *>(H)[a * ldh + int64_t(m2s[i2]) * nb + b2];
+      }
     }
 #pragma unroll
     for (int u = 0; u < PCH / PNT; ++u)
@@ -186,13 +220,13 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
         return fail(BSE_EUNSUPPORTED, "r' nv nc exceeds %d columns", PNT * PMAXCOL);
       dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
       if (h_fp64)
-        BSE_LAUNCH("k_project", k_project<double>, g, dim3(PNT), 0, s, p->nv, p->nc,
+        BSE_LAUNCH("k_project", (k_project<double, false>), g, dim3(PNT), 0, s, p->nv, p->nc,
                            (const double *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
-                           b.ub_off, b.ubasis, (double *)Hmu[ib], ldmu[ib]);
+                           b.ub_off, b.ubasis, (double *)Hmu[ib], ldmu[ib], SeedSrc{});
       else
-        BSE_LAUNCH("k_project", k_project<float>, g, dim3(PNT), 0, s, p->nv, p->nc,
+        BSE_LAUNCH("k_project", (k_project<float, false>), g, dim3(PNT), 0, s, p->nv, p->nc,
                            (const float *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
-                           b.ub_off, b.ubasis, (float *)Hmu[ib], ldmu[ib]);
+                           b.ub_off, b.ubasis, (float *)Hmu[ib], ldmu[ib], SeedSrc{});
       BSE_HIP_CHECK(hipGetLastError());
     }
     if (Bmu && Bmu[ib]) {
@@ -202,6 +236,39 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
                          (const double2 *)B, (double2 *)Bmu[ib]);
       BSE_HIP_CHECK(hipGetLastError());
     }
+  }
+  return BSE_OK;
+}
+
+extern "C" int32_t bse_project_seed(int64_t plan, int32_t nblk, const bse_block *blk,
+                                    void *const *Hmu, const int64_t *ldmu, bse_stream stream) {
+  SeedPieces sp;
+  const int32_t st = seed_pieces(plan, &sp);
+  if (st) return st;
+  const bse_problem *p = &sp.p;
+  if (nblk < 0 || (nblk > 0 && !blk)) return fail(BSE_EINVAL, "bad block list");
+  const int64_t nb = int64_t(p->nv) * p->nc, N = int64_t(sp.nk) * nb;
+  if (int64_t(PMAXL) * nb > PCH || 9 * nb > PNT * PMAXCOL)
+    return fail(BSE_EUNSUPPORTED, "nv nc too large for projection");
+  hipStream_t s = (hipStream_t)stream;
+  const SeedSrc sd{p->korb, sp.porb, p->ev, p->ec, sp.xs, sp.drep, sp.ldx, sp.nk, 1.0 / sp.nk};
+  for (int ib = 0; ib < nblk; ++ib) {
+    if (!Hmu || !Hmu[ib]) continue;
+    const bse_block &b = blk[ib];
+    if (b.n < 0 || !b.mem_off || !b.members || !b.orb_off || !b.orb_dim || !b.ub_off || !b.ubasis)
+      return fail(BSE_EINVAL, "block %d has NULL arrays", ib);
+    if (b.n > N) return fail(BSE_ESHAPE, "block %d larger than N", ib);
+    if (!ldmu || ldmu[ib] < b.n) return fail(BSE_ESHAPE, "ldmu[%d] < n", ib);
+    dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
+    if (sp.prec == BSE_FP64)
+      BSE_LAUNCH("k_project_seed", (k_project<double, true>), g, dim3(PNT), 0, s, p->nv, p->nc,
+                 nullptr, 0, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis,
+                 (double *)Hmu[ib], ldmu[ib], sd);
+    else
+      BSE_LAUNCH("k_project_seed", (k_project<float, true>), g, dim3(PNT), 0, s, p->nv, p->nc,
+                 nullptr, 0, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis,
+                 (float *)Hmu[ib], ldmu[ib], sd);
+    BSE_HIP_CHECK(hipGetLastError());
   }
   return BSE_OK;
 }

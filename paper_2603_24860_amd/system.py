@@ -72,6 +72,7 @@ class DeviceSystem:
             ptr(t["mc"]), ptr(t["w"]), 1 if prec == B.FP64 else 0)
         self.blocks = {}
         self.H = None
+        self.seed_direct = False
         self.ws = None
 
     # -- allocation -------------------------------------------------------
@@ -92,8 +93,10 @@ class DeviceSystem:
         return self.blocks[key]
 
     # -- pieces of the path ----------------------------------------------
-    def use_seed(self, on=True):
-        """Build H by the seed (symmetry-accelerated) construction from now on."""
+    def use_seed(self, on=True, direct=False):
+        """Build H by the seed (symmetry-accelerated) construction from now on.
+        direct: keep only the seed pieces and project blocks straight from them
+        (H is never formed)."""
         if on and getattr(self, "seed_plan", None) is None:
             nbytes = B.bse_seed_ws(self.group, self.problem, self.prec)
             if nbytes == 0:
@@ -101,9 +104,13 @@ class DeviceSystem:
             self.seed_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.seed_plan = B.bse_seed_plan(self.group, self.problem, self.prec, self.seed_ws)
         self.seed = on
+        self.seed_direct = bool(on and direct)
 
     def build(self):
         if getattr(self, "seed", False):
+            if self.seed_direct:
+                B.bse_build_seed(self.seed_plan, None)
+                return None
             if self.H is None:
                 self.H = torch.empty((self.N, self.N), dtype=CDT[self.prec], device=self.device)
             B.bse_build_seed(self.seed_plan, self.H)
@@ -165,6 +172,11 @@ class Solver:
         self.eps2 = torch.empty_like(self.w)
 
     def project(self):
+        if getattr(self.s, "seed_direct", False):
+            B.bse_project_seed(self.s.seed_plan, [self.blk.c], [self.Hmu])
+            B.bse_project_blocks(self.s.problem, None, self.s.t["B"], [self.blk.c], [None],
+                                 [self.Bmu])
+            return
         B.bse_project_blocks(self.s.problem, self.s.H, self.s.t["B"], [self.blk.c], [self.Hmu],
                              [self.Bmu])
 
