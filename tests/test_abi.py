@@ -110,6 +110,9 @@ def test_invalid_arguments_rejected_on_host():
     assert B.lib.bse_eels(4, d, d, 0.0, d, d, d, 1 << 20, None) == _lib.EINVAL
     assert B.lib.bse_eels(4, d, d, 1.0, d, d, d, 8, None) == _lib.EWORKSPACE
     assert B.lib.bse_eels_ws(0) == 0 and B.lib.bse_eels_ws(10) == 8 * 22
+    # projection from seed pieces: an unknown plan is rejected before any launch
+    assert B.lib.bse_project_seed(123456, 0, None, None, None, None) == _lib.EINVAL
+    assert B.lib.bse_build_seed(123456, None, 0, None) == _lib.EINVAL
     assert "NULL" in B.lib.bse_last_error().decode() or B.lib.bse_last_error() is not None
 
 
