@@ -60,6 +60,7 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
   __shared__ double u1s[PMAXL * PMAXR], u2s[PMAXL * PMAXR];
   __shared__ int32_t m1s[PMAXL], m2s[PMAXL];
   __shared__ int32_t o1s[SEEDSRC ? PMAXL : 1], o2s[SEEDSRC ? PMAXL : 1];  // k orbits of the members
+  __shared__ int32_t pps[SEEDSRC ? PMAXL * PMAXL : 1];  // pair orbits of the member pairs
   const int nb = nv * nc;
   const int band = blockIdx.x;        // (v, c) of the output rows
   // orbit ids grow with orbit size on the simple grids, so the largest (longest)
@@ -79,6 +80,8 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
   if constexpr (SEEDSRC) {
     if (threadIdx.x < L2) o2s[threadIdx.x] = sd.korb[m2[threadIdx.x]];
     if (threadIdx.x < L1) o1s[threadIdx.x] = sd.korb[m1[threadIdx.x]];
+    for (int q = threadIdx.x; q < L1 * L2; q += PNT)
+      pps[q] = sd.porb[int64_t(m1[q / L2]) * sd.nk + m2[q % L2]];
   }
   const int ncol = r2 * nb, per = L2 * nb;
   const int RU = PCH / per;  // rows per chunk (>= 1)
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
         const int v2 = b2 / nc, c2 = b2 % nc;
         const C2 xe = reinterpret_cast<const C2 *>(sd.xs)[(int64_t(o1s[i0 + ii]) * nb + ia) * sd.ldx +
                                                           int64_t(o2s[i2]) * nb + b2];
-        const int64_t o = sd.porb[int64_t(k) * sd.nk + k2];
+        const int64_t o = pps[(i0 + ii) * L2 + i2];
         const C2 d = reinterpret_cast<const C2 *>(sd.drep)[(o * (nc * nc) + c * nc + c2) * (nv * nv) +
                                                            v * nv + v2];
         double re = double(xe.x) - sd.scale * double(d.x), im = double(xe.y) - sd.scale * double(d.y);
