@@ -229,8 +229,8 @@ def bench_served(args, large=False):
     wts = np.array([m[3] for m in mix])
     wts /= wts.sum()
 
-    def server(slots):
-        srv = Server(slots=slots, hbm_budget=288e9)
+    def server(slots, seed=args.seed):
+        srv = Server(slots=slots, hbm_budget=288e9, seed=seed)
         for key, ds in sysobjs.items():
             srv.register(key, ds, grids[key.split("/")[0]])
         return srv
@@ -248,7 +248,7 @@ def bench_served(args, large=False):
     # plain FP64 GPU form over the same mix, one request after the other
     nplain = 100 if large else 150
     t1 = time.perf_counter()
-    server(1).run(draw(nplain, fp64=True))
+    server(1, seed=False).run(draw(nplain, fp64=True))
     plain = nplain / (time.perf_counter() - t1)
     # saturation throughput of the served form
     nsat = 200 if large else 400
@@ -288,7 +288,9 @@ def bench_served(args, large=False):
                                "(T1u 162), cfg2 (T1u 2160), " + ("cfg3 (T1u 10080), " if large
                                                                   else "")
                                + "D6h 8x8x1 / 13x13x1 / 20x20x1 (E1u) systems, FP32 builds or "
-                               "split-BF16 builds with FP64 refinement of the lowest 100",
+                               "split-BF16 builds with FP64 refinement of the lowest 100"
+                               + ("; FP32 requests by the seed construction, block projected "
+                                  "from the seed pieces (no H)" if args.seed else ""),
                    "requests": len(done),
                    "arrival_rate_per_s": round(lam, 3),
                    "mix": [{"system": m[0], "precision": {B.FP32: "fp32", B.BF16X3: "bf16x3"}[m[2]],

@@ -17,6 +17,7 @@ what else is in flight.
 """
 import math
 import time
+import weakref
 from collections import deque
 
 import numpy as np
@@ -46,24 +47,54 @@ class Request:
         self.status = "waiting"
 
 
+def _free_plans(cache):
+    for plan, _ in cache:
+        B.bse_seed_free(plan)
+    cache.clear()
+
+
 class ServedSystem:
     """A registered, resident system: inputs of one precision class and its
-    dipole-active block (FP64 inputs for FP64 requests, FP32 otherwise)."""
+    dipole-active block (FP64 inputs for FP64 requests, FP32 otherwise).
+    seed_slots > 0: requests of the inputs' own precision use the seed
+    construction without H (pieces only, block projected straight from them),
+    one seed plan per stream slot so that requests in flight do not share
+    pieces; split-BF16 requests, and shapes the seed construction does not
+    support, keep the dense build."""
 
-    def __init__(self, name, dev_system, wgrid, eta=0.05):
+    def __init__(self, name, dev_system, wgrid, eta=0.05, seed_slots=0):
         self.name = name
         self.s = dev_system
         self.irrep, _ = dev_system.active_irrep()
         self.blk = dev_system.block(self.irrep)
         self.w = torch.as_tensor(np.asarray(wgrid, dtype=np.float64), device=dev_system.device)
         self.eta = eta
+        self.plans = []
+        if seed_slots and B.bse_seed_ws(dev_system.group, dev_system.problem,
+                                        dev_system.prec) > 0:
+            # plans are kept with the resident system and reused by later servers
+            cache = dev_system.__dict__.get("_served_seed_plans")
+            if cache is None:
+                cache = dev_system._served_seed_plans = []
+                weakref.finalize(dev_system, _free_plans, cache)
+            while len(cache) < seed_slots:
+                nbytes = B.bse_seed_ws(dev_system.group, dev_system.problem, dev_system.prec)
+                ws = torch.empty(nbytes, dtype=torch.uint8, device=dev_system.device)
+                cache.append((B.bse_seed_plan(dev_system.group, dev_system.problem,
+                                              dev_system.prec, ws), ws))
+            self.plans = [pl for pl, _ in cache[:seed_slots]]
+            torch.cuda.synchronize(dev_system.device)  # plans are used from the serving streams
+
+    def seeded(self, prec):
+        return bool(self.plans) and prec == self.s.prec
 
     def footprint(self, prec, nrefine=0):
         s, n = self.s, self.blk.n
         el = EL[prec]
         eig_prec = B.FP32 if prec == B.BF16X3 else prec
         h64 = 1 if prec == B.FP64 else 0
-        return (s.N * s.N * el + B.bse_build_ws(s.problem, prec) + n * n * el + 16 * n
+        build = 0 if self.seeded(prec) else s.N * s.N * el + B.bse_build_ws(s.problem, prec)
+        return (build + n * n * el + 16 * n
                 + B.bse_block_eigh_ws(n, h64, eig_prec, nrefine) + 3 * 8 * n + 8 * self.w.numel())
 
 
@@ -73,8 +104,11 @@ class Server:
     big_bytes is large, and at most big_slots large requests are in flight, so
     small requests are not queued behind long ones."""
 
-    def __init__(self, slots=4, hbm_budget=288e9, device="cuda", big_bytes=4e9, big_slots=1):
+    def __init__(self, slots=4, hbm_budget=288e9, device="cuda", big_bytes=4e9, big_slots=1,
+                 seed=False):
         self.device = device
+        self.seed = seed
+        self.nslots = slots
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
         self.free = list(range(slots))
         self.budget = float(hbm_budget)
@@ -91,7 +125,8 @@ class Server:
         self.rejected = []
 
     def register(self, name, dev_system, wgrid):
-        self.systems[name] = ServedSystem(name, dev_system, wgrid)
+        self.systems[name] = ServedSystem(name, dev_system, wgrid,
+                                          seed_slots=self.nslots if self.seed else 0)
 
     # -- one request's path on its stream ----------------------------------
     def _launch(self, req, slot):
@@ -103,14 +138,21 @@ class Server:
         n = ss.blk.n
         h = st.cuda_stream
         with torch.cuda.stream(st):
-            H = torch.empty((s.N, s.N), dtype=CDT[prec], device=self.device)
-            bws = torch.empty(max(B.bse_build_ws(s.problem, prec), 256), dtype=torch.uint8,
-                              device=self.device)
-            B.bse_build(s.problem, prec, H, bws, stream=h)
             Hmu = torch.empty((n, n), dtype=CDT[prec], device=self.device)
             Bmu = torch.empty(n, dtype=torch.complex128, device=self.device)
-            B.bse_project_blocks(s.problem, H, s.t["B"], [ss.blk.c], [Hmu], [Bmu], stream=h)
-            del H, bws  # freed for later work on this stream only (stream-ordered pool)
+            if ss.seeded(prec):  # seed pieces of this slot's plan, no H
+                plan = ss.plans[slot]
+                B.bse_build_seed(plan, None, stream=h)
+                B.bse_project_seed(plan, [ss.blk.c], [Hmu], stream=h)
+                B.bse_project_blocks(s.problem, None, s.t["B"], [ss.blk.c], [None], [Bmu],
+                                     stream=h)
+            else:
+                H = torch.empty((s.N, s.N), dtype=CDT[prec], device=self.device)
+                bws = torch.empty(max(B.bse_build_ws(s.problem, prec), 256), dtype=torch.uint8,
+                                  device=self.device)
+                B.bse_build(s.problem, prec, H, bws, stream=h)
+                B.bse_project_blocks(s.problem, H, s.t["B"], [ss.blk.c], [Hmu], [Bmu], stream=h)
+                del H, bws  # freed for later work on this stream only (stream-ordered pool)
             h64 = 1 if prec == B.FP64 else 0
             ews = torch.empty(B.bse_block_eigh_ws(n, h64, eig_prec, req.nrefine),
                               dtype=torch.uint8, device=self.device)

@@ -147,3 +147,45 @@ def test_large_request_lane(env):
         ref = solo[(r.system, {B.FP64: "FP64", B.FP32: "FP32", B.BF16X3: "BF16X3"}[r.prec],
                     r.nrefine)]
         assert np.array_equal(r.result["omega"], ref["omega"])
+
+
+def test_seeded_served(env):
+    """Served form with the seed construction (seed=True): FP64 and FP32
+    requests build the seed pieces of their slot's plan and project the
+    block straight from them (no H); split-BF16 requests keep the dense
+    build.  Solo results meet the accuracy targets against the oracle, the
+    footprint drops by H and the build workspace, and 24 mixed requests on
+    four slots give their solo results bitwise."""
+    from paper_2603_24860_amd.serve import Request
+    B, refs, systems = env
+    solo = {}
+    for i, (sysname, pname, tol, nref) in enumerate(TYPES):
+        srv = _server(env, 1, seed=True)
+        ss = srv.systems[sysname]
+        prec = getattr(B, pname)
+        dense = _server(env, 1).systems[sysname].footprint(prec, nref)
+        assert ss.seeded(prec) == (prec != B.BF16X3)
+        if ss.seeded(prec):
+            assert ss.footprint(prec, nref) < dense
+        done = srv.run([Request(i, sysname, prec, 0.0, nref)])
+        res = done[0].result
+        err = np.abs(res["lowest"] - refs[sysname.split("/")[0]]["lowest"]).max()
+        say("seeded solo", sysname, pname, "nrefine", nref, "lowest-100 err", err)
+        assert err < tol
+        solo[(sysname, prec, nref)] = res
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(24):
+        sysname, pname, _, nref = TYPES[int(rng.integers(len(TYPES)))]
+        reqs.append(Request(i, sysname, getattr(B, pname), float(i) * 2.5e-4, nref))
+    srv = _server(env, 4, seed=True)
+    done = srv.run(reqs)
+    assert len(done) == 24 and not srv.rejected
+    overlap = sum(1 for a in done for b in done
+                  if a.rid < b.rid and a.start < b.done and b.start < a.done)
+    say("seeded mix: overlapping pairs", overlap)
+    assert overlap > 0
+    for r in done:
+        ref = solo[(r.system, r.prec, r.nrefine)]
+        for k in ("omega", "pole", "osc", "eps2"):
+            assert np.array_equal(r.result[k], ref[k]), (r.rid, r.system, k)
