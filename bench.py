@@ -108,7 +108,7 @@ def bench_batched(args):
     cfgs = synth.batch_configs()
     t0 = time.perf_counter()
     systems = workloads.batch_systems(cfgs, prec, log=log)
-    bs = BatchSolver(systems)
+    bs = BatchSolver(systems, seed=args.seed)
     ns = [b[2].n for b in bs.blocks]
     log(f"setup {time.perf_counter() - t0:.1f} s; {len(systems)} systems, {len(ns)} blocks, "
         f"n in {min(ns)}..{max(ns)}, sum n = {sum(ns)}")
@@ -170,7 +170,9 @@ def bench_batched(args):
         "data": "synthetic (seeded; 64 layered D6h systems)",
         "config": {"workload": f"cfg4: {len(systems)} D6h systems n x n x 1, n in 6..24, "
                                f"Nv, Nc in 2..4, Nmb in 128..320; {len(ns)} irrep blocks, "
-                               f"n {min(ns)}..{max(ns)}, sum n = {sum(ns)}",
+                               f"n {min(ns)}..{max(ns)}, sum n = {sum(ns)}"
+                               + (f"; {len(bs.seeded)} systems by the seed construction, blocks "
+                                  "projected from the seed pieces (no H)" if args.seed else ""),
                    "precision": args.prec},
         "stage_ms": {"builds_and_projections": round(split[0], 3),
                      "batched_block_eigh": round(split[1], 3), "spectra": round(split[2], 3)},

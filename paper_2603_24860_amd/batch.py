@@ -5,7 +5,9 @@ blocks run as usual (one bse_build and one bse_project_blocks call per system).
 All blocks of all systems then go to one batched eigensolver plan
 (bse_batch_eigh_*), which advances every block by one Householder step per
 launch; the dipole-active block of each system gives its eps2.  The whole step
-can be captured once into a HIP graph and replayed.
+can be captured once into a HIP graph and replayed.  With seed=True, systems
+whose shape the seed construction supports build only the seed pieces and
+project every block straight from them (no H); the others stay dense.
 """
 import math
 
@@ -17,9 +19,15 @@ from .system import CDT
 
 
 class BatchSolver:
-    def __init__(self, systems, eig_prec=None, wgrids=None, eta=0.05):
+    def __init__(self, systems, eig_prec=None, wgrids=None, eta=0.05, seed=False):
         self.systems = systems
         self.eta = eta
+        self.seeded = []    # systems switched to the seed construction here (plans freed by close)
+        if seed:
+            for s in systems:
+                if B.bse_seed_ws(s.group, s.problem, s.prec) > 0:
+                    s.use_seed(direct=True)
+                    self.seeded.append(s)
         self.blocks = []    # (system index, irrep, DeviceBlock)
         self.Hmu, self.Bmu, self.om, self.po, self.os = [], [], [], [], []
         self.active = []    # per system: index into self.blocks of its dipole-active block
@@ -65,8 +73,14 @@ class BatchSolver:
         for si, s in enumerate(self.systems):
             s.build()
             idx = self.per_system[si]
-            B.bse_project_blocks(s.problem, s.H, s.t["B"], [self.blocks[i][2].c for i in idx],
-                                 [self.Hmu[i] for i in idx], [self.Bmu[i] for i in idx])
+            blks = [self.blocks[i][2].c for i in idx]
+            if getattr(s, "seed_direct", False):
+                B.bse_project_seed(s.seed_plan, blks, [self.Hmu[i] for i in idx])
+                B.bse_project_blocks(s.problem, None, s.t["B"], blks, [None] * len(idx),
+                                     [self.Bmu[i] for i in idx])
+            else:
+                B.bse_project_blocks(s.problem, s.H, s.t["B"], blks,
+                                     [self.Hmu[i] for i in idx], [self.Bmu[i] for i in idx])
 
     def eigh(self):
         B.bse_batch_eigh_run(self.plan)
@@ -95,7 +109,8 @@ class BatchSolver:
         """Record one whole step (builds, projections, batched eigh, spectra)
         into a HIP graph; later step() calls replay it."""
         for s in self.systems:
-            s.alloc_build()
+            if not getattr(s, "seed_direct", False):
+                s.alloc_build()
         torch.cuda.synchronize()
         side = torch.cuda.Stream()
         g = torch.cuda.CUDAGraph()
@@ -120,3 +135,8 @@ class BatchSolver:
     def close(self):
         self.graph = None
         B.bse_batch_eigh_free(self.plan)
+        for s in self.seeded:
+            B.bse_seed_free(s.seed_plan)
+            s.seed_plan = None
+            s.use_seed(False)
+        self.seeded = []

@@ -144,6 +144,17 @@ def test_batched_form_against_oracle(lib):
     """All irrep blocks of four systems (D6h and Oh) in one batched solve:
     per system, the union of its block spectra is the full spectrum of H, the
     dipole-active block's lowest 100 energies and eps2 match the oracle."""
+    _check_batched(lib, seed=False)
+
+
+def test_batched_form_seed_against_oracle(lib):
+    """The same with seed=True: every system builds only its seed pieces and
+    projects all of its blocks straight from them (H is never formed, also not
+    by the captured graph); same bars against the oracle."""
+    _check_batched(lib, seed=True)
+
+
+def _check_batched(lib, seed):
     import synth
     import workloads
     from oracle import bse as OB
@@ -157,8 +168,9 @@ def test_batched_form_against_oracle(lib):
         refs.append((P, np.linalg.eigvalsh(H), act, r))
         grids.append(synth.omega_grid_from_range(r["omega"].min(), r["omega"].max()))
     systems = workloads.batch_systems(BATCH, lib.FP64)
-    bs = BatchSolver(systems, wgrids=grids)
-    say("batched form:", len(bs.blocks), "blocks from", len(systems), "systems")
+    bs = BatchSolver(systems, wgrids=grids, seed=seed)
+    say("batched form:", len(bs.blocks), "blocks from", len(systems), "systems, seed", seed)
+    assert len(bs.seeded) == (len(systems) if seed else 0)
     bs.step()
     out = bs.results()
     for (P, full, act, r), res, w in zip(refs, out, grids):
@@ -186,4 +198,6 @@ def test_batched_form_against_oracle(lib):
             for nm in a["blocks"]:
                 assert np.array_equal(a["blocks"][nm], b["blocks"][nm]), (rep, nm)
         say("  whole-step graph replay", rep, "matches eager")
+    if seed:
+        assert all(sy.H is None for sy in systems)
     bs.close()
