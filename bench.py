@@ -325,6 +325,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit: "
                          "the reference for scaling HBM byte counters")
+    ap.add_argument("--copy-timed", type=int, default=0, metavar="K",
+                    help="with --copy-mib: then time K more copies and report the achieved "
+                         "read + write bandwidth (the practical HBM ceiling)")
     ap.add_argument("--seed", action="store_true",
                     help="build H by the seed construction (one contraction per pair orbit); "
                          "TFLOP/s then counts the contractions performed")
@@ -363,7 +366,19 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        out = {"copy_bytes": src.numel() * 4, "launches": 3}
+        if args.copy_timed > 0:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.copy_timed):
+                dst.copy_(src)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.copy_timed
+            out.update(launches=3 + args.copy_timed, timed=args.copy_timed,
+                       us_per_copy=round(ms * 1e3, 2),
+                       read_plus_write_TB_s=round(2 * src.numel() * 4 / (ms * 1e-3) / 1e12, 3))
+        print(json.dumps(out), flush=True)
         return
     import synth
     import workloads
