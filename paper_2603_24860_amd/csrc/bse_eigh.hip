@@ -156,6 +156,8 @@ struct Desc {
   double2 *V, *W;            // [NBK][ldv] column major
   double2 *col;              // [n] current column
   double2 *y;                // [n] y = A22 v
+  double2 *ys;               // [slots][ldys] partial sums of y of the tile forms (FP32 A, n > TILE_M + 1)
+  int64_t ldys;
   double2 *wraw;             // [n] initial reflection: w before the alpha v term
   double2 *vbuf;             // [n] initial reflector
   double2 *partb0, *partb1;  // [R][PS] partial sums of k_colB / k_col0 (alternating)
@@ -218,7 +220,7 @@ __host__ __device__ __forceinline__ int g_np_in(int64_t n, int64_t jn) {
 // wpr = 0: the LDS-staged form of k_colA (LDS_RW rows per wave)
 constexpr int LDS_RW = 2;
 __host__ __device__ __forceinline__ int g_colA_wgs(int64_t m, int wpr) {
-  const int64_t rt = wpr == 0 ? 4 * LDS_RW : 4 / wpr;
+  const int64_t rt = wpr <= 0 ? 4 * LDS_RW : 4 / wpr;  // (the tile forms count tiles instead)
   return (int)(m < 1 ? 1 : cdiv(m, rt));
 }
 __host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
@@ -230,6 +232,31 @@ __host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
 // best at n = 720, 2160 and 10080); the batched solve uses its tuned value
 constexpr int64_t LDS_M = 1024;
 inline int single_wpr(int64_t m) { return m > LDS_M ? 0 : 4; }
+
+// Above TILE_M trailing rows an FP32 working copy is multiplied from its lower
+// tiles only (the block is Hermitian): k_colA forms WPR = -1, -2, -3 with
+// square tiles of 64, 128 and 256 entries.  The tile grid of the trailing
+// rows [m0, n) starts at m0 rounded down to 64; tile (i, j), i >= j, adds
+// its row sums to slot j and, below the diagonal, the sums of its columns
+// (conjugated) to slot i of the rows they belong to, so that
+// y[r] = sum over the slots k of ys[k][r].
+constexpr int64_t TILE_M = 2048;
+__host__ __device__ constexpr int tile_of(int wpr) { return 32 << (-wpr); }
+inline int tile_wpr(int64_t m) { return m <= 4096 ? -1 : (m <= 8192 ? -2 : -3); }
+__host__ __device__ __forceinline__ int64_t g_tbase(int64_t m0) { return m0 & ~int64_t(63); }
+__host__ __device__ __forceinline__ int64_t g_tblocks(int64_t n, int64_t m0, int t) {
+  return cdiv(n - g_tbase(m0), t);
+}
+__host__ __device__ __forceinline__ int64_t g_tiles(int64_t n, int64_t m0, int t) {
+  const int64_t b = g_tblocks(n, m0, t);
+  return b * (b + 1) / 2;
+}
+// slots of ys needed by a block of n rows (every tile size it may use)
+__host__ __device__ __forceinline__ int64_t g_yslots(int64_t n) {
+  int64_t s = cdiv(std::min<int64_t>(n, 4096) + 63, 64);
+  s = std::max<int64_t>(s, cdiv(std::min<int64_t>(n, 8192) + 63, 128));
+  return std::max<int64_t>(s, cdiv(n + 63, 256));
+}
 
 // relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
 __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
@@ -258,11 +285,15 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
   t.W = (double2 *)take(size_t(ldv) * NBK * 16);
   t.col = (double2 *)take(size_t(n) * 16);
   t.y = (double2 *)take(size_t(n) * 16);
+  const bool tiles = !a_fp64 && n - 1 > TILE_M;
+  const int64_t slots = tiles ? g_yslots(n) : 0;
+  t.ldys = n;
+  t.ys = tiles ? (double2 *)take(size_t(slots) * size_t(n) * 16) : nullptr;
   t.wraw = (double2 *)take(size_t(n) * 16);
   t.vbuf = (double2 *)take(size_t(n) * 16);
   t.partb0 = (double2 *)take(R * PS * 16);
   t.partb1 = (double2 *)take(R * PS * 16);
-  t.parta = (double2 *)take(size_t(std::max<int64_t>(n, 1)) * 16);
+  t.parta = (double2 *)take(size_t(std::max<int64_t>(std::max<int64_t>(n, 1), slots * (slots + 1) / 2)) * 16);
   t.bred = (double2 *)take(2 * NBK * 16);
   t.part2 = (double2 *)take(P2 * 16);
   t.part3 = (double *)take(P2 * 8);
@@ -804,6 +835,208 @@ __device__ __forceinline__ void b_colA_lds(int64_t n, int64_t jn, int ir,
   }
 }
 
+// Sums of RG values (complex) over the 64 lanes of a wave in one butterfly:
+// each exchange halves the values a lane keeps, so lane l ends with the full
+// sum of value l / (64 / RG) after RG - 1 + 6 - log2(RG) complex shuffles
+// (instead of 6 RG).
+template <int RG, int L>
+__device__ __forceinline__ void wave_fold(double2 (&v)[RG], int lane) {
+  if constexpr (L > 1) {
+    constexpr int o = 32 * L / RG;  // 32 for the first exchange
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < L / 2; ++i) {
+      const double2 keep = hi ? v[i + L / 2] : v[i], send = hi ? v[i] : v[i + L / 2];
+      v[i] = double2{keep.x + __shfl_xor(send.x, o, 64), keep.y + __shfl_xor(send.y, o, 64)};
+    }
+    wave_fold<RG, L / 2>(v, lane);
+  }
+}
+template <int RG>
+__device__ __forceinline__ double2 wave_sums(double2 (&v)[RG], int lane) {
+  wave_fold<RG, RG>(v, lane);
+  double2 x = v[0];
+#pragma unroll
+  for (int o = 32 / RG; o > 0; o >>= 1) {
+    x.x += __shfl_xor(x.x, o, 64);
+    x.y += __shfl_xor(x.y, o, 64);
+  }
+  return x;
+}
+
+// k_colA, tile forms (FP32 working copy, more than TILE_M trailing rows):
+// the same reflector, V column, scalars and panel-product reduction as
+// b_colA_lds, with the HEMV y = A22 v taken from the lower tiles of the
+// trailing block.  Workgroup wg takes tile (bi, bj), bi >= bj, of the grid
+// of T x T tiles starting at g_tbase(m0).  A diagonal tile multiplies its
+// whole square (both triangles); a tile below the diagonal multiplies it
+// from both sides: its row sums go to slot bj of its rows, the sums
+// conj(A[r][c]) v[r] over its rows to slot bi of its columns.  The partial
+// sums of y^dag v come per tile in the same way.  The entries v[m0] = 1 and
+// v[c] = scale col[c] (c > m0) enter as col[c] with the scale applied to the
+// finished sums, the column m0 separately (as in b_colA_lds).
+template <int T>
+__device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
+                                            const float *__restrict__ A, int64_t lda,
+                                            double2 *__restrict__ V, int64_t ldv,
+                                            const double2 *__restrict__ col,
+                                            const double2 *__restrict__ partb, int np,
+                                            double2 *__restrict__ tau, double2 *__restrict__ scl,
+                                            double *__restrict__ d, double *__restrict__ e,
+                                            double2 *__restrict__ ys, int64_t ldys,
+                                            double2 *__restrict__ parta,
+                                            double2 *__restrict__ bred, int wg) {
+  static_assert(T == 64 || T == 128 || T == 256, "tile sizes");
+  constexpr int CPL = T / 64;                            // complex entries per lane and row
+  constexpr int RPW = T / (ENT / 64);                    // rows per wave
+  constexpr int RG = T == 64 ? 16 : (T == 128 ? 8 : 4);  // rows in flight per wave
+  static_assert(RPW % RG == 0, "row groups");
+  __shared__ double sh[ENT / 64];
+  __shared__ double sh2[2 * (ENT / 64)];
+  __shared__ double2 xr[T], xc[T];     // col[] at the tile's rows / columns (0 unless m0 < . < n)
+  __shared__ double2 cpart[ENT / 64][T];
+  __shared__ double2 rpart[T];
+  __shared__ double2 bsh[ENT / 16][16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m0 = jn + 1, base = g_tbase(m0);
+  int bi = int((sqrt(8.0 * double(wg) + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= wg) ++bi;
+  while (bi > 0 && bi * (bi + 1) / 2 > wg) --bi;
+  const int bj = wg - bi * (bi + 1) / 2;
+  const bool diag = bi == bj;
+  const int64_t r0 = base + int64_t(bi) * T, c0 = base + int64_t(bj) * T;
+  // ---- loads that do not depend on the tile's products ----
+  double2 px[PMAX / ENT];
+#pragma unroll
+  for (int u = 0; u < PMAX / ENT; ++u) px[u] = partb[int64_t(std::min(tid + ENT * u, np - 1)) * PS];
+  const bool red_on = wg < 4 && ir > 0;
+  double2 bq[BQ];
+  bred_load(bq, partb, np, wg, red_on);
+  const double2 cjn = col[jn], cm0 = col[m0];
+  // thread t < T: row r0 + t and column c0 + t of the tile
+  const int64_t rt = r0 + tid, ct = c0 + tid;
+  double2 a0 = {0, 0};
+  if (tid < T) {
+    xr[tid] = (rt > m0 && rt < n) ? col[rt] : double2{0, 0};
+    xc[tid] = (ct > m0 && ct < n) ? col[ct] : double2{0, 0};
+    if (bj == 0) a0 = to_d2(reinterpret_cast<const float2 *>(A)[std::min<int64_t>(std::max<int64_t>(rt, m0), n - 1) * lda + m0]);
+  }
+  __syncthreads();
+  // this lane's columns: CPL = 1: c0 + lane; else c0 + 2 lane + 128 u + h (h = 0, 1)
+  double2 xl[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) xl[u] = CPL == 1 ? xc[lane] : xc[2 * lane + 128 * (u / 2) + (u & 1)];
+  double2 cacc[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) cacc[u] = double2{0, 0};
+  const float *arow0 = A;
+  // Columns at or past n: the loads stay inside the row (padding to lda), and
+  // the values are replaced by zero, since the padding holds no data (its x
+  // entries are zero, but 0 times NaN is not).
+  bool cok[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u)
+    cok[u] = (CPL == 1 ? c0 + lane : c0 + 2 * lane + 128 * (u / 2) + (u & 1)) < n;
+  for (int g = 0; g < RPW / RG; ++g) {
+    const int rl0 = wv * RPW + g * RG;
+    double2 acc[RG];
+    if constexpr (CPL == 1) {
+      float2 a[RG];
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const int64_t rr = std::min<int64_t>(std::max<int64_t>(r0 + rl0 + q, m0), n - 1);
+        const int64_t cc = std::min<int64_t>(c0 + lane, lda - 1);
+        a[q] = reinterpret_cast<const float2 *>(arow0)[rr * lda + cc];
+      }
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const double2 av = cok[0] ? to_d2(a[q]) : double2{0, 0};
+        acc[q] = cmul(av, xl[0]);
+        if (!diag) cacc[0] = cadd(cacc[0], cmulc(av, xr[rl0 + q]));
+      }
+    } else {
+      float4 a[RG][CPL / 2];
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const int64_t rr = std::min<int64_t>(std::max<int64_t>(r0 + rl0 + q, m0), n - 1);
+#pragma unroll
+        for (int u = 0; u < CPL / 2; ++u) {
+          const int64_t cc = std::min<int64_t>(c0 + 2 * lane + 128 * u, lda - 2);
+          a[q][u] = *reinterpret_cast<const float4 *>(arow0 + 2 * (rr * lda + cc));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const double2 xq = xr[rl0 + q];
+        double2 sacc = {0, 0};
+#pragma unroll
+        for (int u = 0; u < CPL / 2; ++u) {
+          const double2 av = cok[2 * u] ? double2{double(a[q][u].x), double(a[q][u].y)} : double2{0, 0};
+          const double2 bv = cok[2 * u + 1] ? double2{double(a[q][u].z), double(a[q][u].w)} : double2{0, 0};
+          sacc = cadd(sacc, cadd(cmul(av, xl[2 * u]), cmul(bv, xl[2 * u + 1])));
+          if (!diag) {
+            cacc[2 * u] = cadd(cacc[2 * u], cmulc(av, xq));
+            cacc[2 * u + 1] = cadd(cacc[2 * u + 1], cmulc(bv, xq));
+          }
+        }
+        acc[q] = sacc;
+      }
+    }
+    const double2 rs = wave_sums<RG>(acc, lane);
+    if (lane % (64 / RG) == 0) rpart[rl0 + lane / (64 / RG)] = rs;
+  }
+  if (!diag) {
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      cpart[wv][CPL == 1 ? lane : 2 * lane + 128 * (u / 2) + (u & 1)] = cacc[u];
+  }
+  double s1 = 0;
+#pragma unroll
+  for (int u = 0; u < PMAX / ENT; ++u)
+    if (tid + ENT * u < np) s1 += px[u].x;
+  const double S1 = block_sum_once<ENT>(s1, sh);  // also publishes rpart, cpart
+  double beta;
+  double2 tj, sc;
+  householder(cm0, S1, beta, tj, sc);
+  double2 qf = {0, 0};
+  if (tid < T) {
+    if (rt >= m0 && rt < n) {
+      const double2 yr = cadd(cmul(sc, rpart[tid]), a0);
+      const double2 vr = rt == m0 ? double2{1, 0} : cmul(sc, xr[tid]);
+      qf = cmulc(yr, vr);
+      ys[int64_t(bj) * ldys + rt] = yr;
+      if (diag) V[int64_t(ir) * ldv + rt] = vr;
+    }
+    if (!diag && ct >= m0 && ct < n) {
+      double2 cs = cpart[0][tid];
+#pragma unroll
+      for (int w = 1; w < ENT / 64; ++w) cs = cadd(cs, cpart[w][tid]);
+      const double2 yc = cmul(sc, cs);
+      const double2 vc = ct == m0 ? double2{1, 0} : cmul(sc, xc[tid]);
+      qf = cadd(qf, cmulc(yc, vc));
+      ys[int64_t(bi) * ldys + ct] = yc;
+    }
+  }
+  if (red_on) bsh[tid / 16][tid % 16] = bred_part(bq, partb, np, wg);
+  double qr = qf.x, qi = qf.y;
+  block_sum2_once<ENT>(qr, qi, sh2);  // also publishes bsh
+  if (red_on && tid < 16) {
+    double2 b = bsh[0][tid];
+#pragma unroll
+    for (int gq = 1; gq < ENT / 16; ++gq) b = cadd(b, bsh[gq][tid]);
+    bred[16 * wg + tid] = b;
+  }
+  if (tid == 0) {
+    parta[wg] = double2{qr, qi};
+    if (wg == 0) {
+      d[jn] = cjn.x;
+      e[jn] = beta;
+      tau[m0] = tj;
+      scl[m0] = sc;
+    }
+  }
+}
+
 // sum of part[0..np) with eight loads in flight per thread
 __device__ __forceinline__ double2 gather_sum(const double2 *__restrict__ part, int np, int tid) {
   double2 acc[8];
@@ -850,6 +1083,8 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
                                               const double2 *__restrict__ V,
                                               double2 *__restrict__ W, int64_t ldv,
                                               const double2 *__restrict__ y,
+                                              const double2 *__restrict__ ys, int64_t ldys,
+                                              int nbt,
                                               const double2 *__restrict__ parta, int npa,
                                               const double2 *__restrict__ bred,
                                               const double2 *__restrict__ tau,
@@ -862,6 +1097,7 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   __shared__ double2 tile[2 * NBK * TP];  // [V_0..V_{NBK-1} | W_0..W_{NBK-1}] x rows
   __shared__ double2 spq[ENT / 64][2 * NBK], shd[2 * NBK];  // p | q per wave, head V_l[jx] | W_l[jx]
   __shared__ double2 sy[RB], sa[RB], sv[RB], sw[RB], sc_[RB];
+  __shared__ double2 syj[ENT / 64];  // tile forms: partial sums of y[jx] per wave
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t jx = jn + 1;
   const int64_t rb = jx + int64_t(wg) * RB;
@@ -879,7 +1115,21 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
     tx[u] = l < ir ? (k < NBK ? V : W)[int64_t(l) * ldv + rcl] : double2{0, 0};
   }
   const double2 hx = (tid < NBK ? V : W)[int64_t(tid % NBK) * ldv + jx];
-  const double2 yx = y[rcl], vx = V[int64_t(ir) * ldv + rcl];
+  // y of row rcl, or (tile forms) of row ry: four lanes per row, each summing
+  // the slots kk, kk + 4, ... of it, and y[jx] from slots tid, tid + ENT, ...
+  static_assert(RB == 16 * (ENT / 64), "tile forms: 16 rows per wave");
+  const int ryl = wv * 16 + (lane >> 2), kk = lane & 3;
+  const int64_t ry = rb + ryl;
+  double2 yx = {0, 0}, yj = {0, 0};
+  if (nbt == 0) {
+    yx = y[rcl];
+  } else {
+    const int64_t ryc = std::min<int64_t>(ry, n - 1);
+#pragma unroll 8
+    for (int k = kk; k < nbt; k += 4) yx = cadd(yx, ys[int64_t(k) * ldys + ryc]);
+    for (int k = tid; k < nbt; k += ENT) yj = cadd(yj, ys[int64_t(k) * ldys + jx]);
+  }
+  const double2 vx = V[int64_t(ir) * ldv + rcl];
   const double2 ax = to_d2(reinterpret_cast<const CA *>(A)[rcl * lda + jx]);
   // The partial sums of k_colA come in a few fixed sizes chosen by a uniform
   // branch on their count, so that no duplicate (clamped) entry is fetched
@@ -896,13 +1146,23 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   else if (npa <= 4 * ENT) load_gx(std::integral_constant<int, 4>());
   else load_gx(std::integral_constant<int, NG>());
   const double2 t = tau[jx], sc = scl[jx];
-  const double2 yjx = y[jx];
+  double2 yjx = nbt == 0 ? y[jx] : double2{0, 0};
   // ---- consume ----
   if (tid < 2 * NBK) shd[tid] = tid % NBK < ir ? hx : double2{0, 0};
 #pragma unroll
   for (int u = 0; u < NT; ++u) tile[(k0 + (ENT / RB) * u) * TP + i] = r0 < n ? tx[u] : double2{0, 0};
+  if (nbt > 0) {
+    yx.x += __shfl_xor(yx.x, 1, 64);
+    yx.y += __shfl_xor(yx.y, 1, 64);
+    yx.x += __shfl_xor(yx.x, 2, 64);
+    yx.y += __shfl_xor(yx.y, 2, 64);
+    if (kk == 0) sy[ryl] = ry < n ? yx : double2{0, 0};
+    yj.x = wave_sum(yj.x);
+    yj.y = wave_sum(yj.y);
+    if (lane == 0) syj[wv] = yj;
+  }
   if (tid < RB) {
-    sy[i] = r0 < n ? yx : double2{0, 0};
+    if (nbt == 0) sy[i] = r0 < n ? yx : double2{0, 0};
     sv[i] = r0 < n ? vx : double2{0, 0};
     sa[i] = (more && r0 < n) ? ax : double2{0, 0};
   }
@@ -913,6 +1173,11 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
   for (int p = tid + NG * ENT; p < npa; p += ENT) ypart = cadd(ypart, parta[p]);
   double yr = ypart.x, yi = ypart.y;
   block_sum2_once<ENT>(yr, yi, sh2);  // also publishes the LDS stores above
+  if (nbt > 0) {
+    yjx = syj[0];
+#pragma unroll
+    for (int w = 1; w < ENT / 64; ++w) yjx = cadd(yjx, syj[w]);
+  }
   // every wave, lane l < NBK: p_l, q_l, Re(conj(p_l) q_l) and the head term
   // V_l[jx] q_l + W_l[jx] p_l, summed over l in one pass; each wave keeps its
   // own copy of p and q in LDS, so no barrier is needed before the rows
@@ -1398,7 +1663,12 @@ BSE_PAIR(col0, int64_t j0 BSE_COMMA int cur, {
   b_col0<TA>(D.n, j0, (const TA *)D.A, D.lda, D.col, cur ? D.partb1 : D.partb0, wg);
 })
 BSE_PAIR(colA, int64_t jn BSE_COMMA int cur, {
-  if constexpr (WPR == 0)
+  if constexpr (WPR < 0) {
+    if constexpr (sizeof(TA) == 4)
+      b_colA_tile<tile_of(WPR)>(D.n, jn, int(jn % NBK), (const float *)D.A, D.lda, D.V, D.ldv,
+                                D.col, cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl,
+                                D.d, D.e, D.ys, D.ldys, D.parta, D.bred, wg);
+  } else if constexpr (WPR == 0)
     b_colA_lds<TA>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv, D.col,
                    cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl, D.d, D.e, D.y,
                    D.parta, D.bred, wg);
@@ -1409,8 +1679,15 @@ BSE_PAIR(colA, int64_t jn BSE_COMMA int cur, {
 })
 BSE_PAIR(colB, int64_t jn BSE_COMMA int cur, {
   const int64_t m = D.n - jn - 1;
+  int npa, nbt = 0;  // partial sums of y^dag v; slots of y (tile forms)
+  if constexpr (WPR < 0) {
+    npa = (int)g_tiles(D.n, jn + 1, tile_of(WPR));
+    nbt = (int)g_tblocks(D.n, jn + 1, tile_of(WPR));
+  } else {
+    npa = g_colA_wgs(m, WPR);
+  }
   b_colB<TA>(D.n, jn, int(jn % NBK), g_more(D.n, jn), (const TA *)D.A, D.lda, D.V, D.W, D.ldv,
-             D.y, D.parta, g_colA_wgs(m, WPR), D.bred, D.tau, D.scl, D.col,
+             D.y, D.ys, D.ldys, nbt, D.parta, npa, D.bred, D.tau, D.scl, D.col,
              cur ? D.partb0 : D.partb1, wg);
 })
 BSE_PAIR(her2k, int64_t j0, {
@@ -1615,7 +1892,9 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
     case K_W0: return g_nwg(n);
     case K_RANK2: return n * g_rank2_gx(n);
     case K_COL0: return j < g_tail0(n) ? g_nwg(n - j) : 0;
-    case K_COLA: return j < g_tail0(n) ? g_colA_wgs(n - j - 1, wpr) : 0;
+    case K_COLA:
+      if (j >= g_tail0(n)) return 0;
+      return wpr < 0 ? g_tiles(n, j + 1, tile_of(wpr)) : g_colA_wgs(n - j - 1, wpr);
     case K_COLB: return j < g_tail0(n) ? cdiv(n - j - 1, RB) : 0;
     case K_HER2K: {
       if (j >= g_tail0(n)) return 0;
@@ -2116,7 +2395,23 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
       } else if (wpr == 1) {
         BSE_COLA(1)
       } else {
-        BSE_COLA(0)
+        bool tiled = false;
+        if constexpr (sizeof(TA) == 4) {
+          if (m > TILE_M) {  // lower tiles of the FP32 working copy
+            tiled = true;
+            const int tw = tile_wpr(m);
+            if (tw == -1) {
+              BSE_COLA(-1)
+            } else if (tw == -2) {
+              BSE_COLA(-2)
+            } else {
+              BSE_COLA(-3)
+            }
+          }
+        }
+        if (!tiled) {
+          BSE_COLA(0)
+        }
       }
 #undef BSE_COLA
       if (m <= 0) break;  // last diagonal element recorded; nothing below it
