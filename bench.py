@@ -75,12 +75,13 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_24860_amd", "csrc", f)
                   for f in ("bse_build.hip", "mfma_tile.h")]
 
 
-def measured_traffic(workload, prec):
+def measured_traffic(workload, prec, seed=False):
     """HBM bytes per launch of k_direct_fused from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (copy-calibrated), or None when the kernel
-    sources changed since the counters were taken or the workload differs."""
+    sources changed since the counters were taken, the workload differs or the
+    build is the seed construction (another kernel)."""
     import hashlib
-    if (workload, prec) != ("cfg2", "fp32") or not os.path.exists(TRAFFIC_FILE):
+    if (workload, prec) != ("cfg2", "fp32") or seed or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     for line in open(TRAFFIC_FILE):
@@ -505,7 +506,7 @@ def main():
             "peak": pk,
             "unit": "TFLOP/s",
             "frac": round(achieved / pk, 4) if achieved else None,
-            "traffic": measured_traffic(args.workload, args.prec),
+            "traffic": measured_traffic(args.workload, args.prec, args.seed),
             "traffic_unit": "B/launch (HBM fetch + write, rocprofv3 FETCH_SIZE/WRITE_SIZE, "
                             "copy-calibrated)",
             "flops_per_launch": kflops / max(1, kt_n // args.steps),

@@ -235,14 +235,16 @@ inline int single_wpr(int64_t m) { return m > LDS_M ? 0 : 4; }
 
 // Above TILE_M trailing rows an FP32 working copy is multiplied from its lower
 // tiles only (the block is Hermitian): k_colA forms WPR = -1, -2, -3 with
-// square tiles of 64, 128 and 256 entries.  The tile grid of the trailing
+// square tiles of 64, 128 and 256 entries (up to 2560, up to 6144 and above
+// 6144 trailing rows, the best of a sweep of these switch points and of the
+// form switch over 1024 to 2048 rows).  The tile grid of the trailing
 // rows [m0, n) starts at m0 rounded down to 64; tile (i, j), i >= j, adds
 // its row sums to slot j and, below the diagonal, the sums of its columns
 // (conjugated) to slot i of the rows they belong to, so that
 // y[r] = sum over the slots k of ys[k][r].
 constexpr int64_t TILE_M = 2048;
 __host__ __device__ constexpr int tile_of(int wpr) { return 32 << (-wpr); }
-inline int tile_wpr(int64_t m) { return m <= 4096 ? -1 : (m <= 8192 ? -2 : -3); }
+inline int tile_wpr(int64_t m) { return m <= 2560 ? -1 : (m <= 6144 ? -2 : -3); }
 __host__ __device__ __forceinline__ int64_t g_tbase(int64_t m0) { return m0 & ~int64_t(63); }
 __host__ __device__ __forceinline__ int64_t g_tblocks(int64_t n, int64_t m0, int t) {
   return cdiv(n - g_tbase(m0), t);
@@ -253,8 +255,8 @@ __host__ __device__ __forceinline__ int64_t g_tiles(int64_t n, int64_t m0, int t
 }
 // slots of ys needed by a block of n rows (every tile size it may use)
 __host__ __device__ __forceinline__ int64_t g_yslots(int64_t n) {
-  int64_t s = cdiv(std::min<int64_t>(n, 4096) + 63, 64);
-  s = std::max<int64_t>(s, cdiv(std::min<int64_t>(n, 8192) + 63, 128));
+  int64_t s = cdiv(std::min<int64_t>(n, 2560) + 63, 64);
+  s = std::max<int64_t>(s, cdiv(std::min<int64_t>(n, 6144) + 63, 128));
   return std::max<int64_t>(s, cdiv(n + 63, 256));
 }
 

@@ -266,9 +266,9 @@ def test_eigh_large_blocks(lib, n, precname, mult):
     """n = 4500: most columns of the reduction take the LDS-staged HEMV
     (trailing blocks above 1024 rows, several LDS chunks), the rest the
     row-parallel one; with FP32 working storage the HEMV of trailing blocks
-    above 2048 rows reads lower tiles of 64 (up to 4096 rows) and 128 entries
+    above 2048 rows reads lower tiles of 64 (up to 2560 rows) and 128 entries
     instead; n = 4501 ends rows on an odd column inside the row padding.
-    n = 8400 (FP32) adds tiles of 256 (above 8192 rows).  FP32
+    n = 8400 (FP32) adds tiles of 256 (above 6144 rows).  FP32
     storage moves the eigenvalues by ~eps32 |A| sqrt(n): the bar is 1e-4 at
     n = 4500, scaled by sqrt(n / 4500)."""
     say("eigh-large", n, precname, mult)
