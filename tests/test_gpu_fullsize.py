@@ -207,6 +207,20 @@ def test_cfg3_block_properties(lib):
     assert np.all(np.diff(res["omega"]) >= 0)
     del sv, S
     torch.cuda.empty_cache()
+    # the FP32 path (lower-tile HEMV above 2048 trailing rows, 256-entry tiles
+    # above 6144) against the FP64 path (full-row HEMV) on the same block:
+    # lowest 100 within the FP32 bar of 1e-5 eV, eps2 within 1e-4 relative
+    say("  FP64 solve of the same block")
+    S64 = workloads.device_system(cfg, lib.FP64)
+    sv64 = Solver(S64, act, wgrid=np.linspace(-20, 20, 200))
+    sv64.step()
+    r64 = sv64.results()
+    err = np.abs(res["lowest"] - r64["lowest"]).max()
+    e2 = np.abs(res["eps2"] - r64["eps2"]).max() / np.abs(r64["eps2"]).max()
+    say("  FP32 vs FP64: lowest-100 err", err, "eps2 rel err", e2)
+    assert err < 1e-5 and e2 < 1e-4
+    del sv64, S64
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.timeout(900)
