@@ -871,9 +871,9 @@ __device__ __forceinline__ double2 wave_sums(double2 (&v)[RG], int lane) {
 // b_colA_lds, with the HEMV y = A22 v taken from the lower tiles of the
 // trailing block.  Workgroup wg takes tile (bi, bj), bi >= bj, of the grid
 // of T x T tiles starting at g_tbase(m0).  A diagonal tile multiplies its
-// whole square (both triangles); a tile below the diagonal multiplies it
-// from both sides: its row sums go to slot bj of its rows, the sums
-// conj(A[r][c]) v[r] over its rows to slot bi of its columns.  The partial
+// whole square (both triangles); a tile below the diagonal also stands for
+// its mirror above the diagonal: its row sums go to slot bj of its rows, the
+// sums conj(A[r][c]) v[r] over its rows to slot bi of its columns.  The partial
 // sums of y^dag v come per tile in the same way.  The entries v[m0] = 1 and
 // v[c] = scale col[c] (c > m0) enter as col[c] with the scale applied to the
 // finished sums, the column m0 separately (as in b_colA_lds).
