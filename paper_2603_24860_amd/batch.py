@@ -138,5 +138,6 @@ class BatchSolver:
         for s in self.seeded:
             B.bse_seed_free(s.seed_plan)
             s.seed_plan = None
+            s.seed_ws = None
             s.use_seed(False)
         self.seeded = []
