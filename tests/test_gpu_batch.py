@@ -9,6 +9,8 @@
 * The whole batched solve captured in a HIP graph and replayed three times,
   with eager work and synchronisations between replays, reproduces the eager
   results bitwise on every replay.
+* cfg4 at full size (64 systems, 384 blocks up to 2304): the autotuned
+  lockstep solve against single-block solves of sampled blocks.
 """
 import sys
 
@@ -201,3 +203,47 @@ def _check_batched(lib, seed):
     if seed:
         assert all(sy.H is None for sy in systems)
     bs.close()
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_full_size_lockstep_against_single(lib):
+    """cfg4 at full size (64 D6h systems, 384 blocks up to n = 2304, FP32),
+    the autotuned lockstep solve as the bench times it: for the four largest
+    blocks and four others, the batched eigenvalues agree with a single-block
+    solve of the same H_mu (other HEMV forms, FP32 storage: within 2e-5 of
+    the spectral radius) and the strengths sum to |B_mu|^2 (1e-6)."""
+    import synth
+    import workloads
+    from paper_2603_24860_amd.batch import BatchSolver
+    say("cfg4 full size: generating 64 systems")
+    systems = workloads.batch_systems(synth.batch_configs(), lib.FP32)
+    bs = BatchSolver(systems)
+    ns = [b[2].n for b in bs.blocks]
+    say("  blocks", len(ns), "n max", max(ns), "sum n", sum(ns))
+    assert len(systems) == 64 and max(ns) > 2048
+    bs.tune()
+    bs.step()
+    torch.cuda.synchronize()
+    order = np.argsort(ns)[::-1]
+    pick = list(order[:4]) + list(np.random.default_rng(7).choice(order[4:], 4, replace=False))
+    for i in pick:
+        i = int(i)
+        n = ns[i]
+        om_b = bs.om[i].cpu().numpy()
+        os_b = bs.os[i].cpu().numpy()
+        h, b = bs.Hmu[i], bs.Bmu[i]
+        ws = torch.empty(lib.bse_block_eigh_ws(n, 0, lib.FP32), dtype=torch.uint8, device="cuda")
+        om = torch.empty(n, dtype=torch.float64, device="cuda")
+        po, os_ = torch.empty_like(om), torch.empty_like(om)
+        lib.bse_block_eigh(h, b, lib.FP32, om, po, os_, ws)
+        torch.cuda.synchronize()
+        om_s = om.cpu().numpy()
+        scale = max(1.0, np.abs(om_s).max())
+        err = np.abs(om_b - om_s).max() / scale
+        b2 = float((b.abs() ** 2).sum())
+        say("  block", i, "n", n, "batched vs single", err, "osc sum / |B|^2 - 1", os_b.sum() / b2 - 1)
+        assert err < 2e-5
+        assert abs(os_b.sum() - b2) <= 1e-6 * b2
+    bs.close()
+    del bs, systems
+    torch.cuda.empty_cache()
