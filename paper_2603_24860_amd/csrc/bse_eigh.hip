@@ -1127,9 +1127,17 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
     yx = y[rcl];
   } else {
     const int64_t ryc = std::min<int64_t>(ry, n - 1);
-#pragma unroll 8
-    for (int k = kk; k < nbt; k += 4) yx = cadd(yx, ys[int64_t(k) * ldys + ryc]);
+    // the first 16 slots of each lane in flight together (clamped, masked),
+    // any further ones in a loop
+    constexpr int YQ = 16;
+    double2 yq[YQ];
+#pragma unroll
+    for (int u = 0; u < YQ; ++u) yq[u] = ys[int64_t(std::min(kk + 4 * u, nbt - 1)) * ldys + ryc];
     for (int k = tid; k < nbt; k += ENT) yj = cadd(yj, ys[int64_t(k) * ldys + jx]);
+#pragma unroll
+    for (int u = 0; u < YQ; ++u)
+      if (kk + 4 * u < nbt) yx = cadd(yx, yq[u]);
+    for (int k = kk + 4 * YQ; k < nbt; k += 4) yx = cadd(yx, ys[int64_t(k) * ldys + ryc]);
   }
   const double2 vx = V[int64_t(ir) * ldv + rcl];
   const double2 ax = to_d2(reinterpret_cast<const CA *>(A)[rcl * lda + jx]);
