@@ -261,9 +261,9 @@ int32_t bse_project_seed(int64_t plan, int32_t nblk, const bse_block *h_blk, voi
  * padded with zero strength.  Hmu is read only.
  * prec: FP64 (all FP64), FP32 (FP32 storage of the working copy, its HEMV
  * and trailing updates; FP64 panel vectors, scalars and tridiagonal step).
- * With FP32 storage the HEMV of trailing blocks above 2048 rows reads only
- * their lower half; its partial sums take up to max(49, (n + 63) / 256) x n
- * x 16 B more workspace (n > 2049).
+ * The HEMV of trailing blocks above 2048 rows reads only their lower half;
+ * its partial sums take up to max(49, (n + 63) / 256) x n x 16 B more
+ * workspace (n > 2049).
  * nrefine = K in 0 .. 256: FP64 refinement of the lowest min(K, n)
  * eigenvalues against the stored Hmu: inverse iteration on T (members of a
  * degenerate cluster orthogonalised), back-transformation through the kept

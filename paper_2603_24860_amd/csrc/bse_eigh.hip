@@ -156,7 +156,7 @@ struct Desc {
   double2 *V, *W;            // [NBK][ldv] column major
   double2 *col;              // [n] current column
   double2 *y;                // [n] y = A22 v
-  double2 *ys;               // [slots][ldys] partial sums of y of the tile forms (FP32 A, n > TILE_M + 1)
+  double2 *ys;               // [slots][ldys] partial sums of y of the tile forms (n > TILE_M + 1)
   int64_t ldys;
   double2 *wraw;             // [n] initial reflection: w before the alpha v term
   double2 *vbuf;             // [n] initial reflector
@@ -233,7 +233,7 @@ __host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
 constexpr int64_t LDS_M = 1024;
 inline int single_wpr(int64_t m) { return m > LDS_M ? 0 : 4; }
 
-// Above TILE_M trailing rows an FP32 working copy is multiplied from its lower
+// Above TILE_M trailing rows the working copy is multiplied from its lower
 // tiles only (the block is Hermitian): k_colA forms WPR = -1, -2, -3 with
 // square tiles of 64, 128 and 256 entries (up to 2560, up to 6144 and above
 // 6144 trailing rows, the best of a sweep of these switch points and of the
@@ -287,7 +287,7 @@ size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
   t.W = (double2 *)take(size_t(ldv) * NBK * 16);
   t.col = (double2 *)take(size_t(n) * 16);
   t.y = (double2 *)take(size_t(n) * 16);
-  const bool tiles = !a_fp64 && n - 1 > TILE_M;
+  const bool tiles = n - 1 > TILE_M;
   const int64_t slots = tiles ? g_yslots(n) : 0;
   t.ldys = n;
   t.ys = tiles ? (double2 *)take(size_t(slots) * size_t(n) * 16) : nullptr;
@@ -866,7 +866,7 @@ __device__ __forceinline__ double2 wave_sums(double2 (&v)[RG], int lane) {
   return x;
 }
 
-// k_colA, tile forms (FP32 working copy, more than TILE_M trailing rows):
+// k_colA, tile forms (more than TILE_M trailing rows):
 // the same reflector, V column, scalars and panel-product reduction as
 // b_colA_lds, with the HEMV y = A22 v taken from the lower tiles of the
 // trailing block.  Workgroup wg takes tile (bi, bj), bi >= bj, of the grid
@@ -877,9 +877,9 @@ __device__ __forceinline__ double2 wave_sums(double2 (&v)[RG], int lane) {
 // sums of y^dag v come per tile in the same way.  The entries v[m0] = 1 and
 // v[c] = scale col[c] (c > m0) enter as col[c] with the scale applied to the
 // finished sums, the column m0 separately (as in b_colA_lds).
-template <int T>
+template <typename TA, int T>
 __device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
-                                            const float *__restrict__ A, int64_t lda,
+                                            const TA *__restrict__ A, int64_t lda,
                                             double2 *__restrict__ V, int64_t ldv,
                                             const double2 *__restrict__ col,
                                             const double2 *__restrict__ partb, int np,
@@ -889,9 +889,12 @@ __device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
                                             double2 *__restrict__ parta,
                                             double2 *__restrict__ bred, int wg) {
   static_assert(T == 64 || T == 128 || T == 256, "tile sizes");
+  typedef typename C2T<TA>::t CA;
+  constexpr bool F32 = sizeof(TA) == 4;
   constexpr int CPL = T / 64;                            // complex entries per lane and row
   constexpr int RPW = T / (ENT / 64);                    // rows per wave
-  constexpr int RG = T == 64 ? 16 : (T == 128 ? 8 : 4);  // rows in flight per wave
+  // rows in flight per wave (16-byte loads: 16 per lane for FP32, 8 for FP64)
+  constexpr int RG = F32 ? (T == 64 ? 16 : (T == 128 ? 8 : 4)) : (T == 64 ? 8 : 4);
   static_assert(RPW % RG == 0, "row groups");
   __shared__ double sh[ENT / 64];
   __shared__ double sh2[2 * (ENT / 64)];
@@ -921,28 +924,29 @@ __device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
   if (tid < T) {
     xr[tid] = (rt > m0 && rt < n) ? col[rt] : double2{0, 0};
     xc[tid] = (ct > m0 && ct < n) ? col[ct] : double2{0, 0};
-    if (bj == 0) a0 = to_d2(reinterpret_cast<const float2 *>(A)[std::min<int64_t>(std::max<int64_t>(rt, m0), n - 1) * lda + m0]);
+    if (bj == 0) a0 = to_d2(reinterpret_cast<const CA *>(A)[std::min<int64_t>(std::max<int64_t>(rt, m0), n - 1) * lda + m0]);
   }
   __syncthreads();
-  // this lane's columns: CPL = 1: c0 + lane; else c0 + 2 lane + 128 u + h (h = 0, 1)
+  // this lane's columns: FP32 with CPL > 1: c0 + 2 lane + 128 (u / 2) + (u & 1)
+  // (pairs of columns in one 16-byte load); otherwise c0 + lane + 64 u
+  auto lcol = [&](int u) { return (F32 && CPL > 1) ? 2 * lane + 128 * (u / 2) + (u & 1) : lane + 64 * u; };
   double2 xl[CPL];
 #pragma unroll
-  for (int u = 0; u < CPL; ++u) xl[u] = CPL == 1 ? xc[lane] : xc[2 * lane + 128 * (u / 2) + (u & 1)];
+  for (int u = 0; u < CPL; ++u) xl[u] = xc[lcol(u)];
   double2 cacc[CPL];
 #pragma unroll
   for (int u = 0; u < CPL; ++u) cacc[u] = double2{0, 0};
-  const float *arow0 = A;
+  const TA *arow0 = A;
   // Columns at or past n: the loads stay inside the row (padding to lda), and
   // the values are replaced by zero, since the padding holds no data (its x
   // entries are zero, but 0 times NaN is not).
   bool cok[CPL];
 #pragma unroll
-  for (int u = 0; u < CPL; ++u)
-    cok[u] = (CPL == 1 ? c0 + lane : c0 + 2 * lane + 128 * (u / 2) + (u & 1)) < n;
+  for (int u = 0; u < CPL; ++u) cok[u] = c0 + lcol(u) < n;
   for (int g = 0; g < RPW / RG; ++g) {
     const int rl0 = wv * RPW + g * RG;
     double2 acc[RG];
-    if constexpr (CPL == 1) {
+    if constexpr (F32 && CPL == 1) {
       float2 a[RG];
 #pragma unroll
       for (int q = 0; q < RG; ++q) {
@@ -956,6 +960,29 @@ __device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
         acc[q] = cmul(av, xl[0]);
         if (!diag) cacc[0] = cadd(cacc[0], cmulc(av, xr[rl0 + q]));
       }
+    } else if constexpr (!F32) {
+      CA a[RG][CPL];
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const int64_t rr = std::min<int64_t>(std::max<int64_t>(r0 + rl0 + q, m0), n - 1);
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          const int64_t cc = std::min<int64_t>(c0 + lane + 64 * u, lda - 1);
+          a[q][u] = reinterpret_cast<const CA *>(arow0)[rr * lda + cc];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const double2 xq = xr[rl0 + q];
+        double2 sacc = {0, 0};
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          const double2 av = cok[u] ? to_d2(a[q][u]) : double2{0, 0};
+          sacc = cadd(sacc, cmul(av, xl[u]));
+          if (!diag) cacc[u] = cadd(cacc[u], cmulc(av, xq));
+        }
+        acc[q] = sacc;
+      }
     } else {
       float4 a[RG][CPL / 2];
 #pragma unroll
@@ -964,7 +991,7 @@ __device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
 #pragma unroll
         for (int u = 0; u < CPL / 2; ++u) {
           const int64_t cc = std::min<int64_t>(c0 + 2 * lane + 128 * u, lda - 2);
-          a[q][u] = *reinterpret_cast<const float4 *>(arow0 + 2 * (rr * lda + cc));
+          a[q][u] = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(arow0) + 2 * (rr * lda + cc));
         }
       }
 #pragma unroll
@@ -989,8 +1016,7 @@ __device__ __forceinline__ void b_colA_tile(int64_t n, int64_t jn, int ir,
   }
   if (!diag) {
 #pragma unroll
-    for (int u = 0; u < CPL; ++u)
-      cpart[wv][CPL == 1 ? lane : 2 * lane + 128 * (u / 2) + (u & 1)] = cacc[u];
+    for (int u = 0; u < CPL; ++u) cpart[wv][lcol(u)] = cacc[u];
   }
   double s1 = 0;
 #pragma unroll
@@ -1674,8 +1700,7 @@ BSE_PAIR(col0, int64_t j0 BSE_COMMA int cur, {
 })
 BSE_PAIR(colA, int64_t jn BSE_COMMA int cur, {
   if constexpr (WPR < 0) {
-    if constexpr (sizeof(TA) == 4)
-      b_colA_tile<tile_of(WPR)>(D.n, jn, int(jn % NBK), (const float *)D.A, D.lda, D.V, D.ldv,
+      b_colA_tile<TA, tile_of(WPR)>(D.n, jn, int(jn % NBK), (const TA *)D.A, D.lda, D.V, D.ldv,
                                 D.col, cur ? D.partb1 : D.partb0, g_np_in(D.n, jn), D.tau, D.scl,
                                 D.d, D.e, D.ys, D.ldys, D.parta, D.bred, wg);
   } else if constexpr (WPR == 0)
@@ -2405,21 +2430,16 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
       } else if (wpr == 1) {
         BSE_COLA(1)
       } else {
-        bool tiled = false;
-        if constexpr (sizeof(TA) == 4) {
-          if (m > TILE_M) {  // lower tiles of the FP32 working copy
-            tiled = true;
-            const int tw = tile_wpr(m);
-            if (tw == -1) {
-              BSE_COLA(-1)
-            } else if (tw == -2) {
-              BSE_COLA(-2)
-            } else {
-              BSE_COLA(-3)
-            }
+        if (m > TILE_M) {  // lower tiles of the working copy
+          const int tw = tile_wpr(m);
+          if (tw == -1) {
+            BSE_COLA(-1)
+          } else if (tw == -2) {
+            BSE_COLA(-2)
+          } else {
+            BSE_COLA(-3)
           }
-        }
-        if (!tiled) {
+        } else {
           BSE_COLA(0)
         }
       }

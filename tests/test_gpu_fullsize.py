@@ -207,8 +207,8 @@ def test_cfg3_block_properties(lib):
     assert np.all(np.diff(res["omega"]) >= 0)
     del sv, S
     torch.cuda.empty_cache()
-    # the FP32 path (lower-tile HEMV above 2048 trailing rows, 256-entry tiles
-    # above 6144) against the FP64 path (full-row HEMV) on the same block:
+    # the FP32 path (FP32 working copy and build) against the FP64 path on the
+    # same block (both with the lower-tile HEMV above 2048 trailing rows):
     # lowest 100 within the FP32 bar of 1e-5 eV, eps2 within 1e-4 relative
     say("  FP64 solve of the same block")
     S64 = workloads.device_system(cfg, lib.FP64)

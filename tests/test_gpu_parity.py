@@ -261,14 +261,14 @@ def _householder_hermitian(n, seed, mult=1, spread=10.0, nref=3):
 
 @pytest.mark.parametrize("n,precname,mult", [(4500, "FP64", 1), (4500, "FP64", 3),
                                              (4500, "FP32", 1), (4501, "FP32", 1),
-                                             (8400, "FP32", 3)])
+                                             (8400, "FP32", 3), (8400, "FP64", 1)])
 def test_eigh_large_blocks(lib, n, precname, mult):
     """n = 4500: most columns of the reduction take the LDS-staged HEMV
     (trailing blocks above 1024 rows, several LDS chunks), the rest the
-    row-parallel one; with FP32 working storage the HEMV of trailing blocks
-    above 2048 rows reads lower tiles of 64 (up to 2560 rows) and 128 entries
-    instead; n = 4501 ends rows on an odd column inside the row padding.
-    n = 8400 (FP32) adds tiles of 256 (above 6144 rows).  FP32
+    row-parallel one; the HEMV of trailing blocks above 2048 rows reads lower
+    tiles of 64 (up to 2560 rows) and 128 entries instead (FP32: two columns
+    per 16-byte load; FP64: one); n = 4501 ends rows on an odd column inside
+    the row padding.  n = 8400 adds tiles of 256 (above 6144 rows).  FP32
     storage moves the eigenvalues by ~eps32 |A| sqrt(n): the bar is 1e-4 at
     n = 4500, scaled by sqrt(n / 4500)."""
     say("eigh-large", n, precname, mult)
