@@ -289,6 +289,91 @@ def project(H, U):
     return U.T @ H @ U
 
 
+# ----------------------------------------------------------------------------
+# the same H_mu without holding H: rows of H one k orbit at a time, each slab
+# contracted with the per-orbit bases.  U_mu is block diagonal over k orbits
+# (its columns for orbit O are U_O (x) I_bands on the rows of O, Eq.
+# (transformationU)), so the rows of O meet only the block columns of O:
+#   H_mu[O, O'] = (U_O (x) I)^T H[rows of O, rows of O'] (U_O' (x) I).
+# For systems whose full H does not fit in host memory (N = 41472: 27.5 GB).
+# ----------------------------------------------------------------------------
+def _times_real(M, R):
+    """M @ R for complex M (..., K) and real R (K x L): one real product over
+    the real and imaginary parts of M, stacked as rows."""
+    parts = np.ascontiguousarray(np.stack([M.real, M.imag], axis=-2))
+    Y = (parts.reshape(-1, M.shape[-1]) @ R).reshape(M.shape[:-1] + (2, R.shape[1]))
+    return Y[..., 0, :] + 1j * Y[..., 1, :]
+
+
+def hamiltonian_rows(P, k, mx_all=None):
+    """Rows a = (k, v, c) of H for one k against every column b (nb x N): the
+    terms of hamiltonian() -- diagonal, exchange, direct -- for this slab."""
+    nk, nv, nc, nmb, N = P["nk"], P["nv"], P["nc"], P["nmb"], P["N"]
+    nb = nv * nc
+    T = P["T"]
+    if mx_all is None:
+        mx_all = P["mx"][T["korb"]].reshape(N, nmb)
+    # exchange: 2/N_k sum_I Mx[k,v,c,I] v_I conj(Mx[k',v',c',I])
+    Hs = (2.0 / nk) * (mx_all[k * nb:(k + 1) * nb] * P["vdiag"][None, :]) @ mx_all.conj().T
+    # direct: 1/N_k sum_IJ conj(Mc[k,k'][c,c',I]) W_IJ(k-k') Mv[k,k'][v,v',J]
+    kk = np.full(nk, k)
+    kq = np.arange(nk)
+    Mv = pair_block(P, "mv", kk, kq)                   # [nk', nv, nv, nmb]
+    Mc = pair_block(P, "mc", kk, kq)                   # [nk', nc, nc, nmb]
+    qo = T["qorb"][T["qidx"][k * nk + kq]]             # q orbit of k - k'
+    Tq = np.empty_like(Mv)
+    for o in np.unique(qo):                            # one W(q) per q orbit
+        sel = np.nonzero(qo == o)[0]
+        Tq[sel] = _times_real(Mv[sel], P["w"][o].T)   # sum_J W_IJ Mv[..., J]
+    D = np.matmul(Mc.conj().reshape(nk, nc * nc, nmb),
+                  np.swapaxes(Tq.reshape(nk, nv * nv, nmb), 1, 2))  # [k', (c,c'), (v,v')]
+    D = D.reshape(nk, nc, nc, nv, nv).transpose(3, 1, 0, 4, 2)    # [v, c, k', v', c']
+    Hs -= D.reshape(nb, N) / nk
+    Hs[np.arange(nb), k * nb + np.arange(nb)] += (P["ec"][k][None, :]
+                                                  - P["ev"][k][:, None]).reshape(-1)
+    return Hs
+
+
+def project_streamed(P, blk, log=None):
+    """H_mu = U_mu^T H U_mu (Eq. (transformationU)) for the block of
+    isotypic_basis / partner_basis, forming H one k orbit of rows at a time."""
+    nb = P["nv"] * P["nc"]
+    nk, N = P["nk"], P["N"]
+    mx_all = P["mx"][P["T"]["korb"]].reshape(N, P["nmb"])
+    Hm = np.zeros((blk["n"], blk["n"]), dtype=np.complex128)
+    for o, (members, Uo) in enumerate(blk["basis"]):
+        r = Uo.shape[1]
+        if r == 0:
+            continue
+        slab = np.stack([hamiltonian_rows(P, int(k), mx_all) for k in members])  # [|O|, nb, N]
+        slab = slab.reshape(len(members), nb, nk, nb)
+        i0 = blk["orb_off"][o]
+        for o2, (members2, Uo2) in enumerate(blk["basis"]):
+            r2 = Uo2.shape[1]
+            if r2 == 0:
+                continue
+            Hb = slab[:, :, members2, :]                               # [|O|, nb, |O'|, nb]
+            Hb = np.einsum("ij,iakb,kl->jalb", Uo, Hb, Uo2, optimize=True)
+            j0 = blk["orb_off"][o2]
+            Hm[i0:i0 + r * nb, j0:j0 + r2 * nb] = Hb.reshape(r * nb, r2 * nb)
+        if log:
+            log(o)
+    return Hm
+
+
+def project_vector(P, blk, B):
+    """B_mu = U_mu^T B orbit by orbit (the same per-orbit bases)."""
+    nb = P["nv"] * P["nc"]
+    Bk = np.asarray(B).reshape(P["nk"], nb)
+    out = np.zeros(blk["n"], dtype=np.result_type(B, np.float64))
+    for o, (members, Uo) in enumerate(blk["basis"]):
+        r = Uo.shape[1]
+        if r:
+            i0 = blk["orb_off"][o]
+            out[i0:i0 + r * nb] = (Uo.T @ Bk[members]).reshape(-1)
+    return out
+
+
 def dipole_active(P, tol=1e-12):
     """Irreps whose projected dipole carries weight (Sec. III.D.1)."""
     nb2 = np.sum(np.abs(P["B"]) ** 2)

@@ -357,6 +357,29 @@ def test_paper_table_ratios():
         prev = ratio
 
 
+@pytest.mark.parametrize("cfg,irreps", [
+    (dict(lattice="cubic", grid=(4, 4, 4), nv=3, nc=3, nmb=64, seed=1, name="cfg1"),
+     ("T1u", "A1g", "Eg")),
+    (dict(lattice="hex", grid=(6, 6, 1), nv=2, nc=3, nmb=32, seed=9, name="hex6"),
+     ("E1u", "A1g")),
+])
+def test_streamed_projection_matches_dense(cfg, irreps):
+    """The row-slab route used for systems whose H does not fit in host
+    memory (Eq. (transformationU) with U block diagonal over k orbits) gives the
+    rows of H and U^T H U of the dense route, on the cubic and hexagonal grids."""
+    P = bse.make_problem(cfg)
+    H = bse.hamiltonian(P)
+    nb = P["nv"] * P["nc"]
+    for k in (0, 7, P["nk"] - 1):
+        assert np.abs(bse.hamiltonian_rows(P, k) - H[k * nb:(k + 1) * nb]).max() < 1e-13
+    for irr in irreps:
+        blk = bse.isotypic_basis(P, irr)
+        U = bse.basis_matrix(P, blk)
+        ref = bse.project(H, U)
+        assert np.abs(bse.project_streamed(P, blk) - ref).max() <= 1e-14 * np.abs(ref).max() * 4
+        assert np.abs(bse.project_vector(P, blk, P["B"]) - U.T @ P["B"]).max() < 1e-14
+
+
 def test_pair_subset_problem_matches_full():
     """Elements from a problem holding M only for the sampled pairs' classes
     equal those of the full problem (the generator keys draws by class rep)."""
