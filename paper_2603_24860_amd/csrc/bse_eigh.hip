@@ -42,19 +42,12 @@
 #include <vector>
 
 #include "bse_internal.h"
+#include "eigh_geometry.h"
 #include "mfma_tile.h"
 
 namespace bse {
 namespace {
 
-constexpr int ENT = 256;     // threads per workgroup
-constexpr int NBK = 32;      // panel width
-constexpr int RNT = 1024;    // threads of the single-workgroup kernels
-constexpr int PMAX = 1024;   // partial-sum records read by k_colA (k_colB writes <= 65536 / 64)
-constexpr int RB_ROWS = 64;  // rows per k_colB workgroup
-// partial-sum record of one k_colB workgroup (complex entries):
-//   [0] (S1, 0) = sum |col|^2, [1 + l] BV_l, [1 + NBK + l] BW_l
-constexpr int PS = 1 + 2 * NBK;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -140,186 +133,7 @@ __device__ __forceinline__ void block_sum2_once(double &a, double &b, double *sh
   b = sb;
 }
 
-constexpr int NBMAX = 1024;  // blocks in one batched solve
-constexpr int NGRID = 4096;  // grid points of the shared first bisection step (64 x 64)
-constexpr int CMAX = 8;      // cluster members refined per eigenvalue cluster
-constexpr int KMAX = 256;    // eigenvalues refinable per solve
 
-// One block's working set.  Partial-sum buffers are sized by the block:
-// k_colB and k_col0 write at most ceil(n / 64) records, k_colA at most n sums,
-// the initial reflection ceil(n / 256).
-struct Desc {
-  int64_t n, ld, lda, ldv;
-  const void *H;             // H_mu [n][ld]
-  const double2 *B;          // B_mu [n]
-  void *A;                   // working copy [n][lda]
-  double2 *V, *W;            // [NBK][ldv] column major
-  double2 *col;              // [n] current column
-  double2 *y;                // [n] y = A22 v
-  double2 *ys;               // [slots][ldys] partial sums of y of the tile forms (n > TILE_M + 1)
-  int64_t ldys;
-  double2 *wraw;             // [n] initial reflection: w before the alpha v term
-  double2 *vbuf;             // [n] initial reflector
-  double2 *partb0, *partb1;  // [R][PS] partial sums of k_colB / k_col0 (alternating)
-  double2 *parta;            // [max(n, 1)] partial sums of conj(y) v of k_colA
-  double2 *bred;             // [2 NBK] panel dot products of k_colB's records, reduced by k_colA
-  double2 *part2;            // [ceil(n / 256)] initial reflection: partial w^dag v
-  double *part3;             // [ceil(n / 256)] initial reflection: partial norm
-  double2 *scl;              // [n + 1] reflector scale 1 / (alpha - beta), index j + 1
-  double2 *tau;              // [n + 1], index j + 1
-  double *d, *e;             // [n]
-  double *e2;                // [n] squared subdiagonal
-  double *tsc;               // [8] tridiagonal scalars
-  int *bgrid;                // [NGRID] Sturm counts on a uniform grid over the Gershgorin interval
-  double *beta0;             // [1]
-  double *omega, *pole, *osc;  // outputs [n]
-  // refinement of the lowest K eigenvalues (K = 0: none)
-  int64_t K;
-  double2 *Vall;             // [n][ldv] every reflector (column j: reflector of column j)
-  double *Z;                 // [K][n] eigenvectors of T
-  double2 *X;                // [K][n] their back-transforms
-  double *rqp;               // [K][cdiv(n, 4)][2] partial Rayleigh quotients
-  double *scr;               // [K][6 CMAX n] inverse-iteration scratch
-  double *wref;              // [K] refined eigenvalues
-  double2 *Tm;               // [cdiv(n - 1, NBK)][NBK][NBK] block-reflector factors T
-};
-
-// ---------------------------------------------------------------------------
-// launch geometry, shared by the host (single block) and the batched kernels
-// ---------------------------------------------------------------------------
-__host__ __device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-// The last at most MT rows of a block are reduced by one workgroup in LDS
-// (k_tail), starting at the first panel boundary with at most MT rows left.
-constexpr int MT = 96;     // largest trailing block reduced in LDS (147 KB)
-constexpr int TNT = 512;   // threads of k_tail
-static_assert(MT <= TNT, "k_tail: thread j keeps the scalars of column j");
-__host__ __device__ __forceinline__ int64_t g_tail0(int64_t n) {
-  return n <= MT ? 0 : cdiv(n - MT, NBK) * NBK;
-}
-__host__ __device__ __forceinline__ int64_t g_nwg(int64_t m) { return m < 1 ? 1 : cdiv(m, ENT); }
-__host__ __device__ __forceinline__ int g_rpw(int64_t m) {
-  return (int)(m < 2048 ? 1 : cdiv(m, 2048));
-}
-__host__ __device__ __forceinline__ int64_t g_copy_gx(int64_t n) {
-  return cdiv(n, ENT) < 64 ? cdiv(n, ENT) : 64;
-}
-__host__ __device__ __forceinline__ int64_t g_rank2_gx(int64_t n) {
-  return cdiv(n, ENT) < 16 ? cdiv(n, ENT) : 16;
-}
-__host__ __device__ __forceinline__ int64_t g_records(int64_t n) {
-  return n < 64 ? 1 : cdiv(n, 64);
-}
-__host__ __device__ __forceinline__ int g_nbk(int64_t n, int64_t j0) {
-  return (int)(n - j0 < NBK ? n - j0 : NBK);
-}
-// partial-sum records in front of k_colA of column jn (from k_col0 at a
-// panel start, else from k_colB of column jn - 1)
-__host__ __device__ __forceinline__ int g_np_in(int64_t n, int64_t jn) {
-  return (int)(jn % NBK == 0 ? g_nwg(n - jn) : cdiv(n - jn, RB_ROWS));
-}
-// wpr = 0: the LDS-staged form of k_colA (LDS_RW rows per wave)
-constexpr int LDS_RW = 2;
-__host__ __device__ __forceinline__ int g_colA_wgs(int64_t m, int wpr) {
-  const int64_t rt = wpr <= 0 ? 4 * LDS_RW : 4 / wpr;  // (the tile forms count tiles instead)
-  return (int)(m < 1 ? 1 : cdiv(m, rt));
-}
-__host__ __device__ __forceinline__ int g_more(int64_t n, int64_t jn) {
-  const int64_t j0 = jn - jn % NBK;
-  return (jn % NBK) + 1 < g_nbk(n, j0) ? 1 : 0;
-}
-// waves per row of the single-block k_colA: one row per workgroup up to
-// LDS_M trailing rows (latency-bound), the LDS-staged form above (measured
-// best at n = 720, 2160 and 10080); the batched solve uses its tuned value
-constexpr int64_t LDS_M = 1024;
-inline int single_wpr(int64_t m) { return m > LDS_M ? 0 : 4; }
-
-// Above TILE_M trailing rows the working copy is multiplied from its lower
-// tiles only (the block is Hermitian): k_colA forms WPR = -1, -2, -3 with
-// square tiles of 64, 128 and 256 entries (up to 2560, up to 6144 and above
-// 6144 trailing rows, the best of a sweep of these switch points and of the
-// form switch over 1024 to 2048 rows).  The tile grid of the trailing
-// rows [m0, n) starts at m0 rounded down to 64; tile (i, j), i >= j, adds
-// its row sums to slot j and, below the diagonal, the sums of its columns
-// (conjugated) to slot i of the rows they belong to, so that
-// y[r] = sum over the slots k of ys[k][r].
-constexpr int64_t TILE_M = 2048;
-__host__ __device__ constexpr int tile_of(int wpr) { return 32 << (-wpr); }
-inline int tile_wpr(int64_t m) { return m <= 2560 ? -1 : (m <= 6144 ? -2 : -3); }
-__host__ __device__ __forceinline__ int64_t g_tbase(int64_t m0) { return m0 & ~int64_t(63); }
-__host__ __device__ __forceinline__ int64_t g_tblocks(int64_t n, int64_t m0, int t) {
-  return cdiv(n - g_tbase(m0), t);
-}
-__host__ __device__ __forceinline__ int64_t g_tiles(int64_t n, int64_t m0, int t) {
-  const int64_t b = g_tblocks(n, m0, t);
-  return b * (b + 1) / 2;
-}
-// slots of ys needed by a block of n rows (every tile size it may use)
-__host__ __device__ __forceinline__ int64_t g_yslots(int64_t n) {
-  int64_t s = cdiv(std::min<int64_t>(n, 2560) + 63, 64);
-  s = std::max<int64_t>(s, cdiv(std::min<int64_t>(n, 6144) + 63, 128));
-  return std::max<int64_t>(s, cdiv(n + 63, 256));
-}
-
-// relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
-__host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
-  const double eps_w = a_fp64 ? 2.2e-16 : 1.2e-7;
-  return 8.0 * eps_w * sqrt(double(n));
-}
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// Lays out one block's workspace at base (nullptr: size only).
-size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    char *p = base ? base + off : nullptr;
-    off += align256(bytes);
-    return p;
-  };
-  const int64_t lda = (n + 15) / 16 * 16, ldv = (n + 63) / 64 * 64;
-  const size_t R = size_t(g_records(n)), P2 = size_t(g_nwg(n));
-  Desc t{};
-  t.n = n;
-  t.lda = lda;
-  t.ldv = ldv;
-  t.A = take(size_t(n) * lda * (a_fp64 ? 16 : 8));
-  t.V = (double2 *)take(size_t(ldv) * NBK * 16);
-  t.W = (double2 *)take(size_t(ldv) * NBK * 16);
-  t.col = (double2 *)take(size_t(n) * 16);
-  t.y = (double2 *)take(size_t(n) * 16);
-  const bool tiles = n - 1 > TILE_M;
-  const int64_t slots = tiles ? g_yslots(n) : 0;
-  t.ldys = n;
-  t.ys = tiles ? (double2 *)take(size_t(slots) * size_t(n) * 16) : nullptr;
-  t.wraw = (double2 *)take(size_t(n) * 16);
-  t.vbuf = (double2 *)take(size_t(n) * 16);
-  t.partb0 = (double2 *)take(R * PS * 16);
-  t.partb1 = (double2 *)take(R * PS * 16);
-  t.parta = (double2 *)take(size_t(std::max<int64_t>(std::max<int64_t>(n, 1), slots * (slots + 1) / 2)) * 16);
-  t.bred = (double2 *)take(2 * NBK * 16);
-  t.part2 = (double2 *)take(P2 * 16);
-  t.part3 = (double *)take(P2 * 8);
-  t.scl = (double2 *)take(size_t(n + 1) * 16);
-  t.tau = (double2 *)take(size_t(n + 1) * 16);
-  t.d = (double *)take(size_t(n) * 8);
-  t.e = (double *)take(size_t(n) * 8);
-  t.e2 = (double *)take(size_t(n) * 8);
-  t.tsc = (double *)take(8 * 8);
-  t.bgrid = (int *)take(NGRID * 4);
-  t.beta0 = (double *)take(8);
-  t.K = K;
-  if (K > 0) {
-    t.Vall = (double2 *)take(size_t(n) * ldv * 16);
-    t.Z = (double *)take(size_t(K) * n * 8);
-    t.X = (double2 *)take(size_t(K) * n * 16);
-    t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, 4)) * 16);
-    t.scr = (double *)take(size_t(K) * (6 * CMAX) * n * 8);
-    t.wref = (double *)take(size_t(K) * 8);
-    t.Tm = (double2 *)take(size_t(std::max<int64_t>(cdiv(n - 1, NBK), 1)) * NBK * NBK * 16);
-  }
-  if (w) *w = t;
-  return off;
-}
 
 // Reflector scalars with LAPACK zlarfg semantics:
 // (I - tau v v^dag)^dag (alpha, x) = (beta, 0), v = (1, x / (alpha - beta)),
@@ -1094,8 +908,6 @@ __device__ __forceinline__ double2 gather_sum(const double2 *__restrict__ part, 
 // The workgroup's rows of V_0..V_ir, W_0..W_ir are staged in LDS once; four
 // threads share a row (sums over l) or a column (sums over rows).
 // ---------------------------------------------------------------------------
-constexpr int RB = 64;        // rows per k_colB workgroup
-constexpr int TP = RB + 1;    // LDS pitch of one panel column
 
 __device__ __forceinline__ double2 shfl_sum4(double2 x) {
   x.x += __shfl_xor(x.x, 1, 64);
@@ -1287,15 +1099,6 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
 
 // Trailing update on MFMA: A[r][c] -= sum_l V_l[r] conj(W_l[c]) + W_l[r] conj(V_l[c])
 // for r, c >= c0; real GEMM with K = 4 nbk (x conj(y) interleave, see bse_build).
-// The update is Hermitian: from HER_TRI tile rows on (mirror), only tiles on
-// or below the diagonal are computed (by >= bx) and an off-diagonal tile also
-// subtracts the conjugate transpose of its update from the mirror tile,
-// staged through LDS so that those writes are row-contiguous too.  Smaller
-// trailing blocks keep every tile, for the parallelism.
-constexpr int64_t HER_TRI = 32;
-template <typename T> struct HerTile;
-template <> struct HerTile<float> { static constexpr int BM = 128, BN = 64, BK = 32; };
-template <> struct HerTile<double> { static constexpr int BM = 128, BN = 64, BK = 16; };
 
 template <typename T>
 __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
@@ -1914,34 +1717,6 @@ __global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
   b_tri_prep(D.n, D.d, D.e, ctol_rel(D.n, sizeof(TA) == 8), D.e2, D.tsc);
 }
 
-// workgroups of one launch kind for one block (0 = the block is not active)
-enum Kind { K_COPY, K_LOADB, K_HEMV0, K_W0, K_RANK2, K_COL0, K_COLA, K_COLB, K_HER2K, K_TRI,
-            K_BISECT, K_WEIGHTS, K_TAIL, K_BGRID };
-
-template <typename TA>
-int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
-  switch (kind) {
-    case K_COPY: return n * g_copy_gx(n);
-    case K_LOADB: return g_nwg(n);
-    case K_HEMV0: return cdiv(n, 4 * g_rpw(n));
-    case K_W0: return g_nwg(n);
-    case K_RANK2: return n * g_rank2_gx(n);
-    case K_COL0: return j < g_tail0(n) ? g_nwg(n - j) : 0;
-    case K_COLA:
-      if (j >= g_tail0(n)) return 0;
-      return wpr < 0 ? g_tiles(n, j + 1, tile_of(wpr)) : g_colA_wgs(n - j - 1, wpr);
-    case K_COLB: return j < g_tail0(n) ? cdiv(n - j - 1, RB) : 0;
-    case K_HER2K: {
-      if (j >= g_tail0(n)) return 0;
-      const int64_t c0 = j + g_nbk(n, j), m = n - c0;
-      const int64_t t = cdiv(m, HerTile<TA>::BN);  // tile rows (see b_her2k)
-      return m > 0 ? (t < HER_TRI ? t * t : t * (t + 1) / 2) : 0;
-    }
-    case K_TRI: return 1;
-    case K_BGRID: return NGRID / ENT;
-    default: return cdiv(n, 4);  // bisect, weights
-  }
-}
 
 // ---------------------------------------------------------------------------
 // refinement of the lowest K eigenvalues against the stored H_mu (FP64)
