@@ -282,6 +282,34 @@ int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, c
                        double *osc, void *ws, size_t ws_bytes, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * bse_block_eigh_noalloc: bse_block_eigh for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, computation, kernels and results
+ * as bse_block_eigh, without ws / ws_bytes: the workspace is a static device
+ * array of bse_block_eigh_noalloc_max() bytes (128 MiB) in the library, one
+ * per GPU, held from the first call on that GPU until the process ends.  No
+ * hipMalloc, hipFree or allocating library call is made.  That fits, for
+ * example, FP32 blocks up to n = 3900 without refinement and up to n = 1500
+ * with nrefine = 100 (the limit is bse_block_eigh_ws(n, ...) <= the maximum).
+ * No part of the array needs to start at zero: every word a kernel reads was
+ * written earlier in the same call.
+ * The first call on a device looks up the array's device address (the
+ * device must be current and `stream` must belong to it).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from different host threads) race and give undefined results;
+ * serialise them.  The outputs stay valid after later calls (they are the
+ * caller's buffers, not the scratch).
+ * Errors: those of bse_block_eigh; BSE_EWORKSPACE when the block needs more
+ * workspace than the array holds; BSE_EINVAL when `stream` belongs to
+ * another device than the current one; BSE_EDEVICE when the address lookup
+ * fails.
+ * ------------------------------------------------------------------------- */
+size_t bse_block_eigh_noalloc_max(void);
+int32_t bse_block_eigh_noalloc(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64,
+                               const void *Bmu, int32_t prec, int32_t nrefine, double *omega,
+                               double *pole, double *osc, bse_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Batched block eigensolver: the same computation as bse_block_eigh for nb
  * independent blocks (all irrep blocks of many systems, Sec. III.D.1 per
  * block), run in lockstep: every launch advances every block that still has

@@ -87,6 +87,8 @@ def _load():
         "bse_block_eigh_ws": (ctypes.c_size_t, [i64, i32, i32, i32]),
         "bse_block_eigh": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp,
                                  ctypes.c_size_t, vp]),
+        "bse_block_eigh_noalloc_max": (ctypes.c_size_t, []),
+        "bse_block_eigh_noalloc": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp]),
         "bse_batch_eigh_ws": (ctypes.c_size_t, [i32, P(i64), i32, i32]),
         "bse_batch_eigh_plan": (i32, [i32, P(i64), P(vp), P(i64), i32, P(vp), i32, P(vp), P(vp),
                                       P(vp), vp, ctypes.c_size_t, P(i64), vp]),

@@ -192,6 +192,19 @@ def bse_block_eigh(Hmu, Bmu, prec, omega, pole, osc, ws, nrefine=0, stream=None)
                              _stream(stream)))
 
 
+def bse_block_eigh_noalloc_max():
+    return lib.bse_block_eigh_noalloc_max()
+
+
+def bse_block_eigh_noalloc(Hmu, Bmu, prec, omega, pole, osc, nrefine=0, stream=None):
+    """bse_block_eigh with the library's static device workspace (no allocation)."""
+    n = Hmu.shape[0]
+    h_fp64 = 1 if Hmu.dtype.itemsize == 16 else 0
+    check(lib.bse_block_eigh_noalloc(n, _ptr(Hmu), Hmu.stride(0), h_fp64, _ptr(Bmu), prec,
+                                     nrefine, _ptr(omega), _ptr(pole), _ptr(osc),
+                                     _stream(stream)))
+
+
 def bse_batch_eigh_ws(ns, h_fp64, prec):
     arr = (ctypes.c_int64 * len(ns))(*[int(x) for x in ns])
     return lib.bse_batch_eigh_ws(len(ns), arr, h_fp64, prec)

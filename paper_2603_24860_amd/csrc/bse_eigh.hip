@@ -2416,6 +2416,74 @@ extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free single block: the workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+// Every GPU the library runs on holds one copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, not the device array: its
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and only that address is passed to kernels.
+constexpr size_t SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+int32_t scratch_of(hipStream_t s, void **out) {
+  int dev = -1;
+  BSE_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV) return fail(BSE_EDEVICE, "device %d out of range", dev);
+  if (s) {
+    int sdev = -1;
+    BSE_HIP_CHECK(hipStreamGetDevice(s, &sdev));
+    if (sdev != dev)
+      return fail(BSE_EINVAL, "stream of device %d, but device %d is current", sdev, dev);
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    BSE_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(BSE_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BSE_OK;
+}
+}  // namespace
+
+extern "C" size_t bse_block_eigh_noalloc_max(void) { return SCRATCH_BYTES; }
+
+extern "C" int32_t bse_block_eigh_noalloc(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64,
+                                          const void *Bmu, int32_t prec, int32_t nrefine,
+                                          double *omega, double *pole, double *osc,
+                                          bse_stream stream) {
+  if (n < 1) return fail(BSE_ESHAPE, "n must be >= 1");
+  if (n > 64 * 1024) return fail(BSE_ESHAPE, "n too large");
+  if (!Hmu || !Bmu || !omega || !pole || !osc) return fail(BSE_EINVAL, "NULL pointer");
+  if (ld < n) return fail(BSE_ESHAPE, "ld < n");
+  if (prec != BSE_FP64 && prec != BSE_FP32) return fail(BSE_EINVAL, "unsupported precision");
+  if (nrefine < 0 || nrefine > KMAX)
+    return fail(BSE_EINVAL, "nrefine = %d outside 0 .. %d", nrefine, KMAX);
+  const int64_t K = std::min<int64_t>(nrefine, n);
+  const size_t need = ws_layout(n, prec == BSE_FP64, nullptr, nullptr, K);
+  if (need > SCRATCH_BYTES)
+    return fail(BSE_EWORKSPACE,
+                "n = %lld needs %zu bytes of workspace; the static scratch holds %zu",
+                (long long)n, need, SCRATCH_BYTES);
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  const int32_t st = scratch_of(s, &ws);
+  if (st != BSE_OK) return st;
+  if (prec == BSE_FP64)
+    return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
+                  : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
+  return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
+                : eigh_run<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
+}
+
+// ---------------------------------------------------------------------------
 // batched block eigensolver
 // ---------------------------------------------------------------------------
 namespace {
