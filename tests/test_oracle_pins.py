@@ -226,14 +226,65 @@ def test_signs_binding_and_repulsion():
     assert np.linalg.eigvalsh(bse.hamiltonian(Px))[0] >= gap - 1e-12
 
 
-def test_nk1_matches_lapack():
-    """N_k = 1: H is the N_v N_c matrix dE + 2X - D; spectrum by plain LAPACK."""
+def test_nk1_brute_force():
+    """N_k = 1: H is the Nv Nc matrix dE + 2X - D of Eq. (BSE-eigval), written
+    out here element by element with explicit loops over the band and
+    mixed-basis indices (Eq. (w_interaction2) with 1/N_k = 1):
+      X[(v c),(v' c')] = sum_I Mx[v,c,I] v_I conj(Mx[v',c',I])
+      D[(v c),(v' c')] = sum_IJ conj(Mc[c,c',I]) W_IJ Mv[v,v',J]
+    Pins the conjugations, the operand order of both contractions, the factor 2
+    and the signs; the spectrum then follows from plain LAPACK."""
     P = bse.make_problem(_small(grid=(1, 1, 1), nv=3, nc=2, nmb=5))
     H = bse.hamiltonian(P)
-    assert H.shape == (6, 6)
-    assert np.allclose(np.linalg.eigvalsh(H), np.linalg.eigvalsh(0.5 * (H + H.conj().T)))
+    nv, nc, nmb = P["nv"], P["nc"], P["nmb"]
+    mx, mv, mc, W, vd = P["mx"][0], P["mv"][0], P["mc"][0], P["w"][0], P["vdiag"]
+    ref = np.zeros((nv * nc, nv * nc), dtype=complex)
+    for v in range(nv):
+        for c in range(nc):
+            for v2 in range(nv):
+                for c2 in range(nc):
+                    x = sum(mx[v, c, i] * vd[i] * np.conj(mx[v2, c2, i]) for i in range(nmb))
+                    dd = sum(np.conj(mc[c, c2, i]) * W[i, j] * mv[v, v2, j]
+                             for i in range(nmb) for j in range(nmb))
+                    val = 2 * x - dd
+                    if (v, c) == (v2, c2):
+                        val += P["ec"][0, c] - P["ev"][0, v]
+                    ref[v * nc + c, v2 * nc + c2] = val
+    assert np.abs(H - ref).max() < 1e-13 * np.abs(ref).max()
+    assert np.allclose(np.linalg.eigvalsh(H), np.linalg.eigvalsh(ref), atol=1e-13)
     # the Gamma point is its own orbit, its pair data is band-Hermitian
     assert P["T"]["class_selfswap"].all()
+
+
+def test_direct_term_woodbury_route():
+    """W = v^1/2 (1 + G G^T)^-1 v^1/2 (rank-8 chi, Eq. (w_interaction2) with the
+    synthetic screening) equals diag(v) - F F^T with F = v^1/2 G (1 + G^T G)^-1/2
+    (Woodbury identity), so the direct term also follows from two thin
+    contractions: D = conj(Mc) v Mv - (conj(Mc) F)(F^T Mv).  The oracle's dense
+    route must agree with it to 1e-12 relative on every (k, k') pair."""
+    cfg = _small(grid=(3, 3, 3), nv=2, nc=3, nmb=24)
+    P = bse.make_problem(cfg)
+    nk, nv, nc, nmb = P["nk"], P["nv"], P["nc"], P["nmb"]
+    Hd = bse.direct(P).reshape(nk, nv, nc, nk, nv, nc) * nk  # without the 1/N_k
+    sv = np.sqrt(P["vdiag"])
+    T = P["T"]
+    worst = 0.0
+    for k in range(nk):
+        for k2 in range(nk):
+            q = T["qidx"][k * nk + k2]
+            qrep = T["korb_reps"][T["qorb"][q]]
+            G = synth.keyed_normal(cfg["seed"], "chi", qrep, np.arange(nmb)[:, None],
+                                   np.arange(8)[None, :], std=1.0 / math.sqrt(nmb))
+            lam, Q = np.linalg.eigh(np.eye(8) + G.T @ G)
+            F = (sv[:, None] * G) @ (Q / np.sqrt(lam)) @ Q.T
+            mv = bse.pair_block(P, "mv", np.array([k]), np.array([k2]))[0]
+            mc = bse.pair_block(P, "mc", np.array([k]), np.array([k2]))[0]
+            thin = (np.einsum("cdi,i,vwi->vcwd", mc.conj(), P["vdiag"], mv)
+                    - np.einsum("cdr,vwr->vcwd", np.einsum("cdi,ir->cdr", mc.conj(), F),
+                                np.einsum("vwj,jr->vwr", mv, F)))
+            worst = max(worst, np.abs(Hd[k, :, :, k2, :, :] - thin).max()
+                        / np.abs(thin).max())
+    assert worst < 1e-12, worst
 
 
 # --------------------------------------------------------------------------
