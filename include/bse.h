@@ -249,6 +249,25 @@ int32_t bse_project_seed(int64_t plan, int32_t nblk, const bse_block *h_blk, voi
                          const int64_t *h_ldmu, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * bse_dipole_weights: which irrep blocks the light couples to (Sec. III.D.1:
+ * only blocks with a non-zero projected dipole contribute to eps2; Eq.
+ * (oscillatorA) with B_mu = U_mu^T B).  For each of the nblk blocks (the
+ * bse_block descriptors of bse_project_blocks) it computes
+ *     weights[i] = |U_mu^T B|^2 = sum_l |B_l|^2 over that block's states,
+ * and active[0] = the index of the block with the largest weight, provided
+ * that weight exceeds 1e-12 of the sum over the listed blocks (the first such
+ * block on ties), else -1.  Summed in a fixed order (bitwise reproducible).
+ *   B        device complex double[N], N = nk nv nc.
+ *   weights  device double[nblk] output;  active  device int32[1] output.
+ * Errors: BSE_EINVAL (NULL pointers, nblk < 1, NULL block arrays),
+ * BSE_ESHAPE (bad problem sizes, block larger than N).  Kernel launches
+ * only, on `stream`.
+ * ------------------------------------------------------------------------- */
+int32_t bse_dipole_weights(const bse_problem *p, const void *B, int32_t nblk,
+                           const bse_block *h_blk, double *weights, int32_t *active,
+                           bse_stream stream);
+
+/* ---------------------------------------------------------------------------
  * bse_block_eigh: eigenvalues of the Hermitian block and the oscillator
  * strengths |B_l|^2 = |A_l^dag B_mu|^2 (Eq. (oscillatorA)).
  * Method: a Householder reflection maps B_mu onto |B_mu| e_1; a blocked

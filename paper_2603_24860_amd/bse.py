@@ -179,6 +179,15 @@ def bse_project_blocks(problem, H, B, blocks, Hmu, Bmu, stream=None):
                                  h_fp64, _ptr(B), nb, arr, hp, ld, bp, _stream(stream)))
 
 
+def bse_dipole_weights(problem, B, blocks, weights, active, stream=None):
+    """|U_mu^T B|^2 of every block into weights (device double[nblk]) and the
+    index of the dipole-active block into active (device int32[1], -1: none)."""
+    nb = len(blocks)
+    arr = (_lib.Block * nb)(*blocks)
+    check(lib.bse_dipole_weights(ctypes.byref(problem), _ptr(B), nb, arr, _ptr(weights),
+                                 _ptr(active), _stream(stream)))
+
+
 def bse_block_eigh_ws(n, h_fp64, prec, nrefine=0):
     return lib.bse_block_eigh_ws(n, h_fp64, prec, nrefine)
 

@@ -192,10 +192,88 @@ __global__ void k_project_vec(int nkorb, int nb, const int32_t *__restrict__ mem
   }
 }
 
+// |B_mu|^2 = sum over the block's orbits and basis vectors of |sum_{k in O}
+// U_O[k,j] B[(k,b)]|^2, one workgroup per block (fixed summation order).
+constexpr int DNT = 256;
+__global__ __launch_bounds__(DNT) void k_dipole_norm(int nkorb, int nb,
+                                                     const int32_t *__restrict__ mem_off,
+                                                     const int32_t *__restrict__ members,
+                                                     const int32_t *__restrict__ orb_dim,
+                                                     const int64_t *__restrict__ ub_off,
+                                                     const double *__restrict__ ub,
+                                                     const double2 *__restrict__ B,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[DNT];
+  double acc = 0;
+  for (int o = 0; o < nkorb; ++o) {
+    const int r = orb_dim[o], L = mem_off[o + 1] - mem_off[o];
+    const int32_t *m = members + mem_off[o];
+    const double *U = ub + ub_off[o];
+    for (int e = threadIdx.x; e < r * nb; e += DNT) {
+      const int j = e / nb, b = e % nb;
+      double sr = 0, si = 0;
+      for (int i = 0; i < L; ++i) {
+        const double2 x = B[int64_t(m[i]) * nb + b];
+        sr += U[i * r + j] * x.x;
+        si += U[i * r + j] * x.y;
+      }
+      acc += sr * sr + si * si;
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = DNT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// The dipole-active block: the largest weight, if it exceeds rel times the
+// total (the first such block on ties); -1 when no block carries weight.
+__global__ void k_dipole_select(int nblk, const double *__restrict__ w, double rel,
+                                int32_t *__restrict__ active) {
+  if (threadIdx.x != 0) return;
+  double tot = 0;
+  for (int i = 0; i < nblk; ++i) tot += w[i];
+  int best = -1;
+  for (int i = 0; i < nblk; ++i)
+    if (w[i] > rel * tot && (best < 0 || w[i] > w[best])) best = i;
+  *active = best;
+}
+
 }  // namespace
 }  // namespace bse
 
 using namespace bse;
+
+extern "C" int32_t bse_dipole_weights(const bse_problem *p, const void *B, int32_t nblk,
+                                      const bse_block *blk, double *weights, int32_t *active,
+                                      bse_stream stream) {
+  if (!p || !B || !weights || !active) return fail(BSE_EINVAL, "NULL pointer");
+  if (nblk < 1 || !blk) return fail(BSE_EINVAL, "bad block list");
+  const int n1 = p->grid[0], n2 = p->grid[1], n3 = p->grid[2];
+  if (n1 < 1 || n2 < 1 || n3 < 1 || p->nv < 1 || p->nc < 1 || p->nkorb < 1)
+    return fail(BSE_ESHAPE, "bad problem sizes");
+  const int64_t nb = int64_t(p->nv) * p->nc, N = int64_t(n1) * n2 * n3 * nb;
+  hipStream_t s = (hipStream_t)stream;
+  for (int ib = 0; ib < nblk; ++ib) {
+    const bse_block &b = blk[ib];
+    if (b.n < 0 || !b.mem_off || !b.members || !b.orb_off || !b.orb_dim || !b.ub_off || !b.ubasis)
+      return fail(BSE_EINVAL, "block %d has NULL arrays", ib);
+    if (b.n > N) return fail(BSE_ESHAPE, "block %d larger than N", ib);
+  }
+  for (int ib = 0; ib < nblk; ++ib) {
+    const bse_block &b = blk[ib];
+    BSE_LAUNCH("k_dipole_norm", k_dipole_norm, dim3(1), dim3(DNT), 0, s, p->nkorb, (int)nb,
+               b.mem_off, b.members, b.orb_dim, b.ub_off, b.ubasis, (const double2 *)B,
+               weights + ib);
+  }
+  BSE_LAUNCH("k_dipole_select", k_dipole_select, dim3(1), dim3(64), 0, s, nblk,
+             (const double *)weights, 1e-12, active);
+  BSE_HIP_CHECK(hipGetLastError());
+  return BSE_OK;
+}
 
 extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64_t ldh,
                                       int32_t h_fp64, const void *B, int32_t nblk,

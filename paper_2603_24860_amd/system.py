@@ -120,24 +120,22 @@ class DeviceSystem:
         return self.H
 
     def dipole_weights(self):
-        """|U_mu^T B|^2 for every irrep with a non-empty block (one host sync)."""
+        """|U_mu^T B|^2 for every irrep with a non-empty block and the
+        dipole-active irrep (bse_dipole_weights; one host sync)."""
         names = [nm for nm, _, _ in B.bse_group_irreps(self.group)]
-        blks, outs, keep = [], [], []
-        for nm in names:
-            b = self.block(nm)
-            if b.n == 0:
-                continue
-            keep.append(nm)
-            blks.append(b.c)
-            outs.append(torch.empty(b.n, dtype=torch.complex128, device=self.device))
-        B.bse_project_blocks(self.problem, None, self.t["B"], blks, [None] * len(blks), outs)
-        return {nm: float((o.abs() ** 2).sum()) for nm, o in zip(keep, outs)}
+        keep = [nm for nm in names if self.block(nm).n > 0]
+        w = torch.empty(len(keep), dtype=torch.float64, device=self.device)
+        act = torch.empty(1, dtype=torch.int32, device=self.device)
+        B.bse_dipole_weights(self.problem, self.t["B"], [self.block(nm).c for nm in keep], w, act)
+        wh = w.cpu().numpy()
+        a = int(act.cpu()[0])
+        return dict(zip(keep, map(float, wh))), (keep[a] if a >= 0 else None)
 
     def active_irrep(self):
-        w = self.dipole_weights()
-        tot = sum(w.values())
-        act = [nm for nm, x in w.items() if x > 1e-12 * tot]
-        return max(act, key=lambda nm: w[nm]), w
+        w, act = self.dipole_weights()
+        if act is None:
+            raise ValueError("no irrep block carries dipole weight")
+        return act, w
 
 
 class Solver:

@@ -155,6 +155,31 @@ def test_projection_block_spectrum(lib, cfg):
         assert abs(np.linalg.norm(Bmu.cpu().numpy()) - np.linalg.norm(U.T @ P["B"])) < 1e-12
 
 
+@pytest.mark.parametrize("cfg,vector", [(SMALL[0], True), (SMALL[0], False), (SMALL[3], True),
+                                        (SMALL[4], True)], ids=lambda x: _ids(x) if isinstance(x, dict) else ("vector" if x else "scalar"))
+def test_dipole_weights_and_active_block(lib, cfg, vector):
+    """bse_dipole_weights: |U_mu^T B|^2 of every non-empty block against the
+    oracle's projected dipole (1e-12 relative), and the dipole-active block
+    (index) equal to the oracle's."""
+    import workloads
+    say("dipole weights", _ids(cfg), "vector" if vector else "scalar")
+    S = workloads.device_system(cfg, lib.FP64, vector_dipole=vector)
+    P = OB.make_problem(cfg, vector_dipole=vector)
+    w, act = S.dipole_weights()
+    tot = float(np.sum(np.abs(P["B"]) ** 2))
+    ow = {}
+    for nm, d, chi in P["group"]["irreps"]:
+        ob = OB.isotypic_basis(P, nm)
+        if ob["n"]:
+            ow[nm] = float(np.sum(np.abs(OB.project_vector(P, ob, P["B"])) ** 2))
+    assert set(w) == set(ow)
+    for nm in ow:
+        assert abs(w[nm] - ow[nm]) <= 1e-12 * tot, nm
+    oact = OB.dipole_active(P)
+    assert act == max(oact, key=lambda nm: ow[nm])
+    assert abs(sum(w.values()) - tot) <= 1e-12 * tot
+
+
 def _random_hermitian(n, seed, mult=1, spread=10.0):
     rng = np.random.default_rng(seed)
     nd = (n + mult - 1) // mult
