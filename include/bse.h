@@ -293,12 +293,36 @@ int32_t bse_dipole_weights(const bse_problem *p, const void *B, int32_t nblk,
  * in Hmu.  The workspace grows by about n^2 16 B (all reflectors) plus
  * 400 K n B (inverse-iteration scratch) for K > 0.
  * Errors: n < 1 or n > 65536 (BSE_ESHAPE), NULL pointers or nrefine outside
- * 0 .. 256 (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).
+ * 0 .. 256 (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).  The
+ * call only enqueues kernels; eigenvalues it could not refine (clusters of
+ * more than 8 members) or non-finite results are reported afterwards by
+ * bse_block_eigh_status (BSE_ENOCONV).
  * ------------------------------------------------------------------------- */
 size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int32_t nrefine);
 int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, const void *Bmu,
                        int32_t prec, int32_t nrefine, double *omega, double *pole,
                        double *osc, void *ws, size_t ws_bytes, bse_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * bse_block_eigh_status: what the last solve on a workspace could not do.
+ * Synchronises `stream` and reads four counters that every solve rewrites:
+ *   h_status[0]  eigenvalues among the lowest min(nrefine, n) left unrefined
+ *                (their omega is the unrefined FP64 bisection value): members
+ *                of a degenerate cluster beyond its first 8, whose inverse
+ *                iteration is not run, or a Rayleigh quotient that is not finite;
+ *   h_status[1]  eigenvalues that are not finite (the tridiagonal step met a
+ *                non-finite matrix; outputs undefined);
+ *   h_status[2]  clusters that straddle the refinement bound K (their members
+ *                below K are refined, their pole stays the unrefined centre);
+ *   h_status[3]  0 (reserved).
+ * Arguments n, prec, nrefine as in the solve; ws its workspace, or NULL for
+ * the static workspace of bse_block_eigh_noalloc on the current device.
+ * Returns BSE_ENOCONV when h_status[0] or h_status[1] is non-zero, else
+ * BSE_OK; BSE_ESHAPE / BSE_EINVAL for bad arguments, BSE_EDEVICE when the copy
+ * fails.  Not for use under graph capture (it copies to the host).
+ * ------------------------------------------------------------------------- */
+int32_t bse_block_eigh_status(int64_t n, int32_t prec, int32_t nrefine, const void *ws,
+                              int32_t *h_status, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
  * bse_block_eigh_noalloc: bse_block_eigh for callers that cannot allocate

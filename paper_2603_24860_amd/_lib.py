@@ -88,6 +88,7 @@ def _load():
         "bse_block_eigh_ws": (ctypes.c_size_t, [i64, i32, i32, i32]),
         "bse_block_eigh": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp,
                                  ctypes.c_size_t, vp]),
+        "bse_block_eigh_status": (i32, [i64, i32, i32, vp, P(i32), vp]),
         "bse_block_eigh_noalloc_max": (ctypes.c_size_t, []),
         "bse_block_eigh_noalloc": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp]),
         "bse_batch_eigh_ws": (ctypes.c_size_t, [i32, P(i64), i32, i32]),

@@ -201,6 +201,19 @@ def bse_block_eigh(Hmu, Bmu, prec, omega, pole, osc, ws, nrefine=0, stream=None)
                              _stream(stream)))
 
 
+def bse_block_eigh_status(n, prec, nrefine, ws, stream=None, raise_on_noconv=True):
+    """Counters of the last solve on ws (None: the static workspace of the
+    allocation-free solver): [unrefined, non-finite, straddling clusters, 0].
+    Raises BseError (BSE_ENOCONV) when eigenvalues were left unrefined or are
+    not finite, unless raise_on_noconv is False."""
+    st = (ctypes.c_int32 * 4)()
+    rc = lib.bse_block_eigh_status(n, prec, nrefine, None if ws is None else _ptr(ws), st,
+                                   _stream(stream))
+    if rc != _lib.ENOCONV or raise_on_noconv:
+        check(rc)
+    return list(st)
+
+
 def bse_block_eigh_noalloc_max():
     return lib.bse_block_eigh_noalloc_max()
 

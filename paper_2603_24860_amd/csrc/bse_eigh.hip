@@ -1206,7 +1206,9 @@ __device__ __forceinline__ double rcp64(double x) {
 __device__ __forceinline__ void b_tri_prep(int64_t n, const double *__restrict__ d,
                                                   const double *__restrict__ e, double ctol_rel,
                                                   double *__restrict__ e2,
-                                                  double *__restrict__ sc) {
+                                                  double *__restrict__ sc,
+                                                  int32_t *__restrict__ status) {
+  if (threadIdx.x < 4) status[threadIdx.x] = 0;  // counters of this solve
   __shared__ double s_lo[RNT / 64], s_hi[RNT / 64], s_tn[RNT / 64];
   double lo = 1e300, hi = -1e300, tn = 0;
   for (int64_t k = threadIdx.x; k < n; k += RNT) {
@@ -1319,7 +1321,8 @@ __device__ __forceinline__ void b_bisect(int64_t n, const double *__restrict__ d
                                                 const double *__restrict__ e2,
                                                 const double *__restrict__ sc,
                                                 const int *__restrict__ grid,
-                                                double *__restrict__ omega, int wg) {
+                                                double *__restrict__ omega,
+                                                int32_t *__restrict__ status, int wg) {
   const int lane = threadIdx.x & 63;
   const int64_t i = int64_t(wg) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
@@ -1352,7 +1355,11 @@ __device__ __forceinline__ void b_bisect(int64_t n, const double *__restrict__ d
     a = na;
     b = nb;
   }
-  if (lane == 0) omega[i] = 0.5 * (a + b);
+  const double x = 0.5 * (a + b);
+  if (lane == 0) {
+    omega[i] = x;
+    if (!isfinite(x)) atomicAdd(status + 1, 1);  // no finite eigenvalue (non-finite T)
+  }
 }
 
 // Weights: a cluster is a maximal run of eigenvalues whose consecutive gaps
@@ -1546,7 +1553,7 @@ BSE_PAIR(bisect_grid, int unused_, {
   b_bisect_grid(D.n, D.d, D.e2, D.tsc, D.bgrid, wg);
 })
 BSE_PAIR(bisect, int use_grid, {
-  b_bisect(D.n, D.d, D.e2, D.tsc, use_grid ? D.bgrid : nullptr, D.omega, wg);
+  b_bisect(D.n, D.d, D.e2, D.tsc, use_grid ? D.bgrid : nullptr, D.omega, D.status, wg);
 })
 BSE_PAIR(weights, int unused_, {
   (void)unused_;
@@ -1705,7 +1712,7 @@ __global__ __launch_bounds__(TNT) void k_tail_b(const Desc *__restrict__ Ds, int
 // the tridiagonal preparation runs one RNT-thread workgroup per block
 template <typename TA>
 __global__ __launch_bounds__(RNT) void k_tri_prep(Desc D, double ctol) {
-  b_tri_prep(D.n, D.d, D.e, ctol, D.e2, D.tsc);
+  b_tri_prep(D.n, D.d, D.e, ctol, D.e2, D.tsc, D.status);
 }
 template <typename TA>
 __global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
@@ -1714,7 +1721,7 @@ __global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
   (void)unused_;
   BSE_FIND_BLOCK
   (void)wg;
-  b_tri_prep(D.n, D.d, D.e, ctol_rel(D.n, sizeof(TA) == 8), D.e2, D.tsc);
+  b_tri_prep(D.n, D.d, D.e, ctol_rel(D.n, sizeof(TA) == 8), D.e2, D.tsc, D.status);
 }
 
 
@@ -2120,7 +2127,11 @@ __global__ __launch_bounds__(ENT) void k_rq_fin(Desc D) {
     }
     num = block_sum<ENT>(num, sh);
     den = block_sum<ENT>(den, sh);
-    if (tid == 0) th[l] = (den > 0 && num == num) ? num / den : D.omega[l];
+    if (tid == 0) {
+      const bool ok = den > 0 && num == num;
+      th[l] = ok ? num / den : D.omega[l];
+      if (!ok) D.status[0] += 1;  // left unrefined (cluster beyond CMAX members)
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -2144,6 +2155,8 @@ __global__ __launch_bounds__(ENT) void k_rq_fin(Desc D) {
         for (int64_t q = i; q <= j; ++q) s += th[q];
         D.pole[i] = s / double(j - i + 1);
         for (int64_t q = i + 1; q <= j; ++q) D.pole[q] = th[q];
+      } else {
+        D.status[2] += 1;  // cluster straddling K: its pole stays unrefined
       }
       i = j + 1;
     }
@@ -2481,6 +2494,33 @@ extern "C" int32_t bse_block_eigh_noalloc(int64_t n, const void *Hmu, int64_t ld
                   : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
   return h_fp64 ? eigh_run<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
                 : eigh_run<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
+}
+
+extern "C" int32_t bse_block_eigh_status(int64_t n, int32_t prec, int32_t nrefine,
+                                         const void *ws, int32_t *h_status, bse_stream stream) {
+  if (n < 1 || n > 64 * 1024) return fail(BSE_ESHAPE, "n outside 1 .. 65536");
+  if (!h_status) return fail(BSE_EINVAL, "NULL pointer");
+  if (prec != BSE_FP64 && prec != BSE_FP32) return fail(BSE_EINVAL, "unsupported precision");
+  if (nrefine < 0 || nrefine > KMAX)
+    return fail(BSE_EINVAL, "nrefine = %d outside 0 .. %d", nrefine, KMAX);
+  hipStream_t s = (hipStream_t)stream;
+  const void *base = ws;
+  if (!base) {  // the static workspace of bse_block_eigh_noalloc on this device
+    void *p = nullptr;
+    const int32_t st = scratch_of(s, &p);
+    if (st != BSE_OK) return st;
+    base = p;
+  }
+  Desc D;
+  ws_layout(n, prec == BSE_FP64, &D, (char *)base, std::min<int64_t>(nrefine, n));
+  int32_t h[4] = {0, 0, 0, 0};
+  BSE_HIP_CHECK(hipMemcpyAsync(h, D.status, sizeof(h), hipMemcpyDeviceToHost, s));
+  BSE_HIP_CHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < 4; ++i) h_status[i] = h[i];
+  if (h[0] > 0 || h[1] > 0)
+    return fail(BSE_ENOCONV, "%d of the lowest %d eigenvalues left unrefined, %d non-finite",
+                h[0], nrefine, h[1]);
+  return BSE_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -74,6 +74,7 @@ struct Desc {
   double *tsc;               // [8] tridiagonal scalars
   int *bgrid;                // [NGRID] Sturm counts on a uniform grid over the Gershgorin interval
   double *beta0;             // [1]
+  int32_t *status;           // [4] solve status, see bse_block_eigh_status
   double *omega, *pole, *osc;  // outputs [n]
   // refinement of the lowest K eigenvalues (K = 0: none)
   int64_t K;
@@ -209,6 +210,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
   t.tsc = (double *)take(8 * 8);
   t.bgrid = (int *)take(NGRID * 4);
   t.beta0 = (double *)take(8);
+  t.status = (int32_t *)take(4 * 4);
   t.K = K;
   if (K > 0) {
     t.Vall = (double2 *)take(size_t(n) * ldv * 16);

@@ -242,6 +242,12 @@ class Solver:
         self.eigh()
         self.spectrum()
 
+    def status(self):
+        """Counters of the last eigensolve (bse_block_eigh_status); raises
+        BseError with BSE_ENOCONV when some of the lowest nrefine eigenvalues
+        were left unrefined or the results are not finite."""
+        return B.bse_block_eigh_status(self.blk.n, self.eig_prec, self.nrefine, self.ws)
+
     def results(self, nlow=100):
         torch.cuda.synchronize()
         return dict(omega=self.omega.cpu().numpy(), pole=self.pole.cpu().numpy(),

@@ -137,6 +137,7 @@ int run(int64_t n, bool a64, int64_t K) {
   C.add("tsc", D.tsc, 8, 8);
   C.add("bgrid", D.bgrid, 4, NGRID);
   C.add("beta0", D.beta0, 8, 1);
+  C.add("status", D.status, 4, 4);
   if (K > 0) {
     C.add("Vall", D.Vall, 16, n * D.ldv);
     C.add("Z", D.Z, 8, K * n);
@@ -290,6 +291,7 @@ int run(int64_t n, bool a64, int64_t K) {
   C.range("d", 0, n, "k_tri_prep");
   C.range("e2", 0, n, "k_tri_prep");
   C.range("tsc", 0, 8, "k_tri_prep");
+  C.range("status", 0, 4, "k_tri_prep");
   C.range("bgrid", 0, NGRID, "k_bisect_grid");
   if (K > 0) {
     C.range("Z", 0, K * n, "k_invit");

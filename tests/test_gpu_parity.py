@@ -345,6 +345,46 @@ def test_eigh_refinement(lib, n, mult, K):
     assert np.array_equal(s0, s1)
 
 
+def test_eigh_refinement_status(lib):
+    """Refinement of a cluster larger than the 8 members the inverse iteration
+    handles: the status query reports the members left unrefined and returns
+    BSE_ENOCONV; a spectrum without such a cluster reports none (BSE_OK), also
+    through the allocation-free solver's static workspace (ws = None)."""
+    from paper_2603_24860_amd._lib import ENOCONV
+    n, K = 200, 20
+    rng = np.random.default_rng(77)
+    lam = np.sort(rng.uniform(-10, 10, n))
+    lam[:10] = lam[0]                      # a 10-fold eigenvalue at the bottom
+    X = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    Q, _ = np.linalg.qr(X)
+    A = (Q * lam) @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    for degenerate in (True, False):
+        say("eigh-refine-status", "10-fold cluster" if degenerate else "no large cluster")
+        M = A if degenerate else (Q * np.sort(rng.uniform(-10, 10, n))) @ Q.conj().T
+        M = 0.5 * (M + M.conj().T)
+        Hmu = torch.as_tensor(M, dtype=torch.complex128, device="cuda")
+        Bmu = torch.as_tensor(b, dtype=torch.complex128, device="cuda")
+        ws = torch.empty(lib.bse_block_eigh_ws(n, 1, lib.FP32, K), dtype=torch.uint8,
+                         device="cuda")
+        om = torch.empty(n, dtype=torch.float64, device="cuda")
+        po, os_ = torch.empty_like(om), torch.empty_like(om)
+        lib.bse_block_eigh(Hmu, Bmu, lib.FP32, om, po, os_, ws, nrefine=K)
+        st = lib.bse_block_eigh_status(n, lib.FP32, K, ws, raise_on_noconv=False)
+        say("  status", st)
+        if degenerate:
+            assert st[0] == 2 and st[1] == 0  # members 9 and 10 of the cluster
+            with pytest.raises(lib.BseError) as e:
+                lib.bse_block_eigh_status(n, lib.FP32, K, ws)
+            assert e.value.status == ENOCONV
+        else:
+            assert st[:2] == [0, 0]
+            lib.bse_block_eigh_noalloc(Hmu, Bmu, lib.FP32, om, po, os_, nrefine=K)
+            assert lib.bse_block_eigh_status(n, lib.FP32, K, None)[:2] == [0, 0]
+        assert np.isfinite(om.cpu().numpy()).all()
+
+
 def test_eigh_degenerate_inputs(lib):
     say("eigh-degenerate")
     n = 40
