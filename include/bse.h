@@ -373,7 +373,11 @@ int32_t bse_block_eigh_noalloc(int64_t n, const void *Hmu, int64_t ld, int32_t h
  *   bse_batch_eigh_tune    autotuner: times each row-split variant of the
  *                          HEMV kernel on this batch, keeps the fastest for the
  *                          plan and returns it in *h_wpr (may be NULL); runs the
- *                          solve several times (outputs are overwritten).
+ *                          solve several times (outputs are overwritten).  It
+ *                          rewrites the plan's device launch tables: a graph
+ *                          captured from bse_batch_eigh_run before a tune keeps
+ *                          the old grid sizes and must not be replayed after
+ *                          it (tune first, then capture).
  *   bse_batch_eigh_free    forgets the plan (the caller frees the workspace).
  * Limits: 1 <= nb <= 1024 and 1 <= n <= 16384 per block (BSE_ESHAPE);
  * prec FP64 or FP32 (BSE_EINVAL).  Plans are kept per process; a plan must

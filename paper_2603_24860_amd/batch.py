@@ -100,7 +100,12 @@ class BatchSolver:
         self.spectra()
 
     def tune(self):
-        """Autotune the batched eigensolver on this batch (runs it a few times)."""
+        """Autotune the batched eigensolver on this batch (runs it a few times).
+        Tuning rewrites the plan's launch tables, which a captured graph reads
+        with the grid sizes of its capture, so it must come before capture()."""
+        if self.graph is not None:
+            raise RuntimeError("tune() after capture(): the captured graph keeps the grid sizes "
+                               "of the old tables; tune first, then capture")
         self.build_and_project()
         self.wpr = B.bse_batch_eigh_tune(self.plan)
         return self.wpr
