@@ -334,28 +334,41 @@ def hamiltonian_rows(P, k, mx_all=None):
     return Hs
 
 
+def orbit_slab(P, members, mx_all=None):
+    """Rows of H for every k of one orbit: [|O|, nb, N]."""
+    return np.stack([hamiltonian_rows(P, int(k), mx_all) for k in members])
+
+
+def project_slab(P, blk, o, slab):
+    """Row block of orbit o of H_mu from the orbit's H rows (orbit_slab):
+    (U_O (x) I)^T H[rows of O, rows of O'] (U_O' (x) I) for every orbit O'."""
+    nb = P["nv"] * P["nc"]
+    members, Uo = blk["basis"][o]
+    r = Uo.shape[1]
+    out = np.zeros((r * nb, blk["n"]), dtype=np.complex128)
+    slab = slab.reshape(len(members), nb, P["nk"], nb)
+    for o2, (members2, Uo2) in enumerate(blk["basis"]):
+        r2 = Uo2.shape[1]
+        if r2 == 0:
+            continue
+        Hb = slab[:, :, members2, :]                               # [|O|, nb, |O'|, nb]
+        Hb = np.einsum("ij,iakb,kl->jalb", Uo, Hb, Uo2, optimize=True)
+        j0 = blk["orb_off"][o2]
+        out[:, j0:j0 + r2 * nb] = Hb.reshape(r * nb, r2 * nb)
+    return out
+
+
 def project_streamed(P, blk, log=None):
     """H_mu = U_mu^T H U_mu (Eq. (transformationU)) for the block of
     isotypic_basis / partner_basis, forming H one k orbit of rows at a time."""
     nb = P["nv"] * P["nc"]
-    nk, N = P["nk"], P["N"]
-    mx_all = P["mx"][P["T"]["korb"]].reshape(N, P["nmb"])
+    mx_all = P["mx"][P["T"]["korb"]].reshape(P["N"], P["nmb"])
     Hm = np.zeros((blk["n"], blk["n"]), dtype=np.complex128)
     for o, (members, Uo) in enumerate(blk["basis"]):
         r = Uo.shape[1]
-        if r == 0:
-            continue
-        slab = np.stack([hamiltonian_rows(P, int(k), mx_all) for k in members])  # [|O|, nb, N]
-        slab = slab.reshape(len(members), nb, nk, nb)
-        i0 = blk["orb_off"][o]
-        for o2, (members2, Uo2) in enumerate(blk["basis"]):
-            r2 = Uo2.shape[1]
-            if r2 == 0:
-                continue
-            Hb = slab[:, :, members2, :]                               # [|O|, nb, |O'|, nb]
-            Hb = np.einsum("ij,iakb,kl->jalb", Uo, Hb, Uo2, optimize=True)
-            j0 = blk["orb_off"][o2]
-            Hm[i0:i0 + r * nb, j0:j0 + r2 * nb] = Hb.reshape(r * nb, r2 * nb)
+        if r:
+            i0 = blk["orb_off"][o]
+            Hm[i0:i0 + r * nb] = project_slab(P, blk, o, orbit_slab(P, members, mx_all))
         if log:
             log(o)
     return Hm

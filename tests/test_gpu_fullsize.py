@@ -11,9 +11,15 @@
 * cfg2 and cfg3 (Oh 12^3, N = 41472): H elements sampled across the matrix
   (corners, conjugated classes, k = k', the diagonal, random pairs) against
   the oracle's element-by-element definition.  FP32 tolerance 2e-6 max|H|.
-* cfg3: properties that hold at any size: the T1u block has the closed-form
-  dimension 10080, and its oscillator strengths sum to |B|^2 (all dipole
-  weight lies in T1u), with |B|^2 from the oracle's own dipoles.
+* cfg3 (Oh 12^3, Nv = 4, Nc = 6, Nmb = 384, T1u n = 10080): the whole path
+  against the FP64 oracle's solution in tests/golden/cfg3_t1u_oracle.json
+  (written by make_cfg3_reference.py from the oracle alone, H_mu formed row
+  slab by row slab): lowest 100 energies within 1e-9 eV (FP64 path), 1e-5 eV
+  (FP32 path, with and without FP64 refinement), 1e-4 eV (split-BF16 build
+  with FP64 refinement of the lowest 100); eps2 within 1e-4 relative;
+  cumulative strengths.  Properties that hold at any size: the T1u block has
+  the closed-form dimension 10080, and its oscillator strengths sum to |B|^2
+  (all dipole weight lies in T1u), with |B|^2 from the oracle's own dipoles.
 """
 import json
 import os
@@ -30,6 +36,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_t1u_oracle.json")
+GOLD3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_t1u_oracle.json")
 
 
 def say(*a):
@@ -207,19 +214,46 @@ def test_cfg3_block_properties(lib):
     assert np.all(np.diff(res["omega"]) >= 0)
     del sv, S
     torch.cuda.empty_cache()
-    # the FP32 path (FP32 working copy and build) against the FP64 path on the
-    # same block (both with the lower-tile HEMV above 2048 trailing rows):
-    # lowest 100 within the FP32 bar of 1e-5 eV, eps2 within 1e-4 relative
-    say("  FP64 solve of the same block")
-    S64 = workloads.device_system(cfg, lib.FP64)
-    sv64 = Solver(S64, act, wgrid=np.linspace(-20, 20, 200))
-    sv64.step()
-    r64 = sv64.results()
-    err = np.abs(res["lowest"] - r64["lowest"]).max()
-    e2 = np.abs(res["eps2"] - r64["eps2"]).max() / np.abs(r64["eps2"]).max()
-    say("  FP32 vs FP64: lowest-100 err", err, "eps2 rel err", e2)
-    assert err < 1e-5 and e2 < 1e-4
-    del sv64, S64
+
+
+@pytest.fixture(scope="module")
+def cfg3_host():
+    import workloads
+    say("cfg3: generating inputs on the host")
+    return workloads.host_inputs(synth.config("cfg3"))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precname,nref,tol,wtol", [("FP64", 0, 1e-9, 1e-6),
+                                                    ("FP32", 0, 1e-5, 1e-3),
+                                                    ("FP32", 100, 1e-5, 1e-3),
+                                                    ("BF16X3", 100, 1e-4, 1e-3)])
+def test_cfg3_end_to_end(lib, cfg3_host, precname, nref, tol, wtol):
+    """cfg3 against the oracle's stored solution: the precision configuration
+    (FP64, FP32, refined split-BF16) at full size."""
+    from paper_2603_24860_amd.system import DeviceSystem, Solver
+    ref = json.load(open(GOLD3))
+    cfg = synth.config("cfg3")
+    group, grid, T, inputs = cfg3_host
+    say("cfg3 e2e", precname, "nrefine", nref)
+    S = DeviceSystem(group, grid, cfg["nv"], cfg["nc"], cfg["nmb"], T, inputs,
+                     getattr(lib, precname))
+    act, _ = S.active_irrep()
+    assert act == ref["irrep"]
+    wgrid = np.linspace(ref["wmin"], ref["wmax"], ref["nw"])
+    sv = Solver(S, act, wgrid=wgrid, nrefine=nref)
+    assert sv.blk.n == ref["n"] == 10080
+    sv.step()
+    res = sv.results()
+    err = np.abs(res["lowest"] - np.asarray(ref["omega"][:100])).max()
+    e2 = np.asarray(ref["eps2"])
+    e2err = np.abs(res["eps2"] - e2).max() / np.abs(e2).max()
+    say("  lowest-100 max err (eV)", err, "eps2 rel err", e2err)
+    assert err < tol
+    assert e2err <= 1e-4
+    _match_cumulative(res["pole"], res["osc"], np.asarray(ref["cl_e"]), np.asarray(ref["cl_w"]),
+                      100 * tol, wtol)
+    del sv, S
     torch.cuda.empty_cache()
 
 
