@@ -6,8 +6,11 @@ bse_build (H = dE + 2 exchange - direct, complex MFMA) -> bse_project_blocks
 (dipole-active T1u block) -> bse_block_eigh (all block eigenvalues and the
 optical poles) -> bse_spectrum (eps2 on 2000 frequencies).
 
-Default workload: Oh 8x8x8 k grid (512 k), Nv = Nc = 4 (N = 8192), Nmb = 256,
-complex FP32 contractions, T1u block of 2160.  Prints one JSON line.
+Default workload (the largest single-GPU configuration): Oh 12x12x12 k grid
+(1728 k), Nv = 4, Nc = 6 (N = 41472), Nmb = 384, complex FP32 contractions,
+T1u block of 10080; its results are checked against the FP64 oracle's stored
+solution, and the refined split-BF16 form is timed against the plain FP64 GPU
+form (solves/s at 0.1 meV).  Prints one JSON line.
 """
 import argparse
 import json
@@ -43,48 +46,105 @@ def build_flops(nk, nv, nc, nmb):
     return s1, s2, ex
 
 
-def cpu_baseline(cfg, nq, log_fn):
-    """The oracle's H build (direct term over a q sample plus the exchange),
-    timed on the host; returns TFLOP/s over the counted contractions."""
-    import synth  # noqa: F401
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, n_block, log_fn, eigh_n=2520):
+    """The FP64 oracle timed stage by stage on the host's cores over a bounded
+    sample of the workload, each stage scaled to the whole solve:
+      * build: the H rows of every k of one k orbit of at most 16 points (all
+        columns), scaled by N_k / |O|;
+      * projection: those rows contracted into their rows of H_mu, scaled the
+        same way;
+      * block eigh: numpy.linalg.eigh (LAPACK zheevd, eigenvectors) of a
+        Hermitian matrix of eigh_n rows, scaled by (n / eigh_n)^3;
+      * spectrum: eps2 of n poles on the 2000-point grid (whole).
+    Returns the oracle's build TFLOP/s (the metric's unit) with the per-stage
+    seconds and the solves/s they add up to."""
+    import synth
     from oracle import bse as OB
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count()
-    P = OB.make_problem(cfg)
-    nk, nv, nc, nmb = P["nk"], P["nv"], P["nc"], P["nmb"]
-    qs = list(range(0, nk, max(1, nk // nq)))[:nq]
+        threads = os.cpu_count()
+    nk = int(np.prod(cfg["grid"]))
+    # one k orbit of at most 16 points (the rows of every k cost the same),
+    # its rows against every column
+    P0 = OB.make_problem(cfg, pairs=[0])
+    korb = P0["T"]["korb"]
+    sizes = np.bincount(korb)
+    o = int(np.argmax(np.where(sizes <= 16, sizes, 0)))
+    members = np.nonzero(korb == o)[0]
+    P = OB.make_problem(cfg, pairs=[int(k) * nk + kq for k in members for kq in range(nk)])
+    blk = OB.isotypic_basis(P, "T1u")
     t0 = time.perf_counter()
-    OB.direct(P, qs=qs)
+    slab = OB.orbit_slab(P, members)
     t1 = time.perf_counter()
-    OB.exchange(P)
+    OB.project_slab(P, blk, o, slab)
     t2 = time.perf_counter()
-    s1, s2, ex = build_flops(nk, nv, nc, nmb)
-    fl = (s1 + s2) * len(qs) / nk + ex
-    log_fn(f"cpu baseline: direct {len(qs)} q in {t1 - t0:.2f} s, exchange {t2 - t1:.2f} s")
-    return {"value": fl / (t2 - t0) / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle H build: direct term for {len(qs)} of {nk} q values "
-                      f"(all k each) plus the full exchange, {cfg['name']} shapes; "
-                      f"{t2 - t0:.1f} s"}
+    del slab
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(eigh_n, eigh_n)) + 1j * rng.normal(size=(eigh_n, eigh_n))
+    A = X + X.conj().T
+    del X
+    t3 = time.perf_counter()
+    OB.eigh(A)
+    t4 = time.perf_counter()
+    del A
+    poles = np.sort(rng.uniform(-5, 15, n_block))
+    wts = rng.uniform(0, 1, n_block)
+    wgrid = synth.omega_grid_from_range(poles[0], poles[-1])
+    t5 = time.perf_counter()
+    OB.eps2(poles, wts, nk, synth.ETA, wgrid)
+    t6 = time.perf_counter()
+    scale = nk / len(members)
+    stage = {"build": (t1 - t0) * scale, "projection": (t2 - t1) * scale,
+             "block_eigh": (t4 - t3) * (n_block / eigh_n) ** 3, "spectrum": t6 - t5}
+    s1, s2, ex = build_flops(nk, cfg["nv"], cfg["nc"], cfg["nmb"])
+    total = sum(stage.values())
+    log_fn("cpu baseline: " + ", ".join(f"{k} {v:.1f} s" for k, v in stage.items())
+           + f" (sampled in {t2 - t0 + t4 - t3 + t6 - t5:.1f} s)")
+    return {"value": round((s1 + s2 + ex) / stage["build"] / 1e12, 4), "unit": "TFLOP/s",
+            "cores": threads, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
+            "kind": "oracle",
+            "stage_s": {k: round(v, 2) for k, v in stage.items()},
+            "solve_s": round(total, 2), "solves_per_s": round(1.0 / total, 6),
+            "sample": f"{cfg['name']}: H rows of the {len(members)} k of one k orbit against "
+                      f"all {nk * cfg['nv'] * cfg['nc']} columns (build, {t1 - t0:.1f} s) and "
+                      f"their T1u rows (projection, {t2 - t1:.1f} s), both x {scale:g}; "
+                      f"numpy eigh of a {eigh_n}-row Hermitian matrix ({t4 - t3:.1f} s) "
+                      f"x (n/{eigh_n})^3 for the n = {n_block} block; eps2 of {n_block} poles "
+                      f"on 2000 points ({t6 - t5:.2f} s)"}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_direct_fused_cfg2_fp32.md")
+def traffic_file(workload, prec):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_k_direct_fused_{workload}_{prec}.md")
+
+
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_24860_amd", "csrc", f)
                   for f in ("bse_build.hip", "mfma_tile.h")]
 
 
 def measured_traffic(workload, prec, seed=False):
     """HBM bytes per launch of k_direct_fused from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes (copy-calibrated), or None when the kernel
-    sources changed since the counters were taken, the workload differs or the
-    build is the seed construction (another kernel)."""
+    FETCH_SIZE / WRITE_SIZE passes (copy-calibrated) for this workload and
+    precision, or None when there are none, the kernel sources changed since
+    the counters were taken, or the build is the seed construction (another
+    kernel)."""
     import hashlib
-    if (workload, prec) != ("cfg2", "fp32") or seed or not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(workload, prec)
+    if seed or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         k, _, v = line.strip().partition(": ")
         if k in ("traffic_bytes_per_launch", "source_sha256"):
             vals[k] = v
@@ -94,6 +154,31 @@ def measured_traffic(workload, prec, seed=False):
     if vals.get("source_sha256") != h.hexdigest():
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+GOLDEN = {name: os.path.join(ROOT, "tests", "golden", f"{name}_t1u_oracle.json")
+          for name in ("cfg2", "cfg3")}
+
+
+def oracle_reference(workload):
+    """The FP64 oracle's stored solution of the workload's T1u block (written
+    by tests/golden/make_cfg*_reference.py from the oracle alone), or None."""
+    path = GOLDEN.get(workload)
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+BARS = {"fp64": 1e-9, "fp32": 1e-5, "bf16x3": 1e-4}   # lowest-100 energies, eV
+EPS2_BAR = 1e-4                                       # eps2, relative to its maximum
+
+
+def accuracy(res, ref):
+    """Lowest-100 error (eV) and relative eps2 error against the oracle."""
+    err = float(np.abs(res["lowest"] - np.asarray(ref["omega"][:len(res["lowest"])])).max())
+    e2 = np.asarray(ref["eps2"])
+    return err, float(np.abs(res["eps2"] - e2).max() / np.abs(e2).max())
 
 
 def bench_batched(args):
@@ -316,13 +401,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2",
+    ap.add_argument("--workload", default="cfg3",
                     help="cfg1 / cfg2 / cfg3: one system; cfg4: the batched form (64 D6h "
                          "systems); cfg5: the served form (Poisson request stream); cfg5l: "
                          "the served form with a share of cfg3 requests")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample-q", type=int, default=32)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit: "
                          "the reference for scaling HBM byte counters")
@@ -346,10 +430,10 @@ def main():
                          "steps and the continued-fraction eps2 (no eigenvalues)")
     ap.add_argument("--nrefine", type=int, default=0, metavar="K",
                     help="FP64 refinement of the lowest K block eigenvalues (0..256)")
-    ap.add_argument("--vs-fp64", action="store_true",
-                    help="after the timed steps, time the plain FP64 GPU form of the same "
-                         "workload and report the error of the lowest 100 energies (meV) and "
-                         "of eps2 against it")
+    ap.add_argument("--forms", type=int, default=-1, metavar="K",
+                    help="after the timed steps, time K solves each of the refined split-BF16 "
+                         "form and of the plain FP64 form, every solve checked against the "
+                         "oracle's stored solution (default: 3 for cfg3, else 0)")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel (adds event records; breakdown on stderr)")
     args = ap.parse_args()
@@ -392,22 +476,31 @@ def main():
 
     prec = {"fp32": B.FP32, "fp64": B.FP64, "bf16x3": B.BF16X3}[args.prec]
     cfg = synth.config(args.workload)
+    ref = None if args.partner else oracle_reference(args.workload)
     t0 = time.perf_counter()
-    S = workloads.device_system(cfg, prec)
+    host = workloads.host_inputs(cfg)
+    log(f"inputs drawn in {time.perf_counter() - t0:.1f} s")
+    S = make_system(cfg, host, prec)
     if args.seed_direct and not args.seed:
         print("--seed-direct needs --seed", file=sys.stderr)
         sys.exit(2)
     if args.seed:
         S.use_seed(direct=args.seed_direct)
     irrep, weights = S.active_irrep()
+    if ref is not None and ref["irrep"] != irrep:
+        ref = None
     sv = Solver(S, irrep, partner=0 if args.partner else None, nrefine=args.nrefine)
+    n_block = sv.blk.n
     log(f"setup {time.perf_counter() - t0:.1f} s; N = {S.N}, block {irrep}"
         f"{' x-partner' if args.partner else ''} n = {sv.blk.n}")
-    # frequency grid from the block spectrum (first solve, untimed)
-    sv.step()
-    torch.cuda.synchronize()
-    om = sv.omega.cpu().numpy()
-    sv.set_grid(synth.omega_grid_from_range(om.min(), om.max()))
+    if ref is not None:  # the oracle's frequency grid
+        sv.set_grid(np.linspace(ref["wmin"], ref["wmax"], ref["nw"]))
+        sv.step()
+    else:  # frequency grid from the block spectrum (first solve, untimed)
+        sv.step()
+        torch.cuda.synchronize()
+        om = sv.omega.cpu().numpy()
+        sv.set_grid(synth.omega_grid_from_range(om.min(), om.max()))
     for _ in range(args.warmup):
         sv.step()
     torch.cuda.synchronize()
@@ -513,6 +606,14 @@ def main():
             "avg_launch_ms": kt_ms / kt_n if kt_n else None,
         },
     }
+    if ref is not None and not args.haydock:
+        err, e2err = accuracy(res, ref)
+        bar = BARS["fp64" if args.prec == "fp64" else
+                   ("bf16x3" if args.prec == "bf16x3" and args.nrefine > 0 else "fp32")]
+        out["accuracy_vs_oracle"] = {"lowest100_max_err_eV": err, "eps2_rel_err": e2err,
+                                     "bar_eV": bar, "meets_bars": bool(err < bar and
+                                                                       e2err <= EPS2_BAR)}
+        log(f"against the oracle: lowest-100 max err {err:.2e} eV, eps2 rel err {e2err:.2e}")
     if args.haydock:
         dev = float((sv.hd_eps2 - eps2_eigh).abs().max() / eps2_eigh.abs().max())
         out["haydock"] = {"K": args.haydock, "eps2_rel_dev_vs_eigh": dev}
@@ -523,45 +624,67 @@ def main():
     if args.profile_all:
         for k, (ms, n) in sorted(prof.items(), key=lambda x: -x[1][0]):
             log(f"  {k:14s} {ms / args.steps:10.3f} ms/step  {n // args.steps:6d} launches/step")
-    if args.vs_fp64:
-        out["vs_fp64"] = vs_fp64(cfg, sv, args, ms_step, log)
+    nforms = args.forms if args.forms >= 0 else (3 if args.workload == "cfg3" else 0)
+    if nforms and ref is not None and not (args.partner or args.seed or args.haydock):
+        sv.s.H = None  # free the timed form's H and build workspace first
+        sv.s.ws = None
+        del sv, S
+        torch.cuda.empty_cache()
+        out["precision_forms"] = precision_forms(cfg, host, irrep, nforms, ref, log)
     if args.cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_q, log)
+        out["cpu_baseline"] = cpu_baseline(cfg, n_block, log)
     print(json.dumps(out), flush=True)
 
 
-def vs_fp64(cfg, sv, args, ms_step, log_fn):
-    """The plain FP64 GPU form of the same workload (FP64 build, projection,
-    eigensolver and spectrum, no refinement): its time per solve, and the
-    error of the timed form's lowest 100 energies (meV) and eps2 against it."""
+def make_system(cfg, host, prec):
+    from paper_2603_24860_amd.system import DeviceSystem
+    group, grid, T, inputs = host
+    return DeviceSystem(group, grid, cfg["nv"], cfg["nc"], cfg["nmb"], T, inputs, prec)
+
+
+def precision_forms(cfg, host, irrep, nsolve, ref, log_fn):
+    """The refined split-BF16 form (split-BF16 build, FP32 eigensolver, FP64
+    refinement of the lowest 100) against the plain FP64 GPU form (FP64 build,
+    projection, eigensolver and spectrum): each timed over nsolve whole solves
+    (inputs resident in HBM, lowest 100 energies and eps2 copied to the host),
+    every solve checked against the oracle's stored solution.  solves/s at
+    0.1 meV counts only the solves within 0.1 meV (lowest 100) and 1e-4 (eps2)."""
     import torch
-    import workloads
     from paper_2603_24860_amd import bse as B
     from paper_2603_24860_amd.system import Solver
-    res = sv.results()
-    w = sv.w.cpu().numpy()
-    irrep, partner = sv.blk.irrep, sv.blk.partner
-    sv.s.H = None  # free the timed form's H and build workspace first
-    sv.s.ws = None
-    torch.cuda.empty_cache()
-    S = workloads.device_system(cfg, B.FP64)
-    s64 = Solver(S, irrep, partner=partner, wgrid=w)
-    s64.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nrep = max(1, min(args.steps, 3))
-    for _ in range(nrep):
-        s64.step()
-    torch.cuda.synchronize()
-    ms64 = (time.perf_counter() - t0) * 1e3 / nrep
-    r64 = s64.results()
-    err = float(np.abs(res["lowest"] - r64["lowest"]).max()) * 1e3
-    e2 = float(np.abs(res["eps2"] - r64["eps2"]).max() / np.abs(r64["eps2"]).max())
-    log_fn(f"plain FP64 form {ms64:.1f} ms per solve; lowest-100 max err {err:.2e} meV, "
-           f"eps2 rel err {e2:.2e}")
-    return {"fp64_ms_per_solve": round(ms64, 3), "fp64_solves_per_s": round(1e3 / ms64, 3),
-            "speedup_vs_fp64": round(ms64 / ms_step, 3), "max_lowest100_err_meV": err,
-            "eps2_rel_err": e2, "within_0.1meV": bool(err <= 0.1)}
+    wgrid = np.linspace(ref["wmin"], ref["wmax"], ref["nw"])
+    out = {}
+    for name, prec, nref in (("refined_bf16x3", B.BF16X3, 100), ("plain_fp64", B.FP64, 0)):
+        S = make_system(cfg, host, prec)
+        sv = Solver(S, irrep, nrefine=nref, wgrid=wgrid)
+        sv.step()
+        sv.results()
+        errs, e2s, ok = [], [], 0
+        t0 = time.perf_counter()
+        for _ in range(nsolve):
+            sv.step()
+            res = sv.results()
+            err, e2 = accuracy(res, ref)
+            errs.append(err)
+            e2s.append(e2)
+            ok += int(err <= 1e-4 and e2 <= EPS2_BAR)
+        wall = time.perf_counter() - t0
+        out[name] = {"solves": nsolve, "ms_per_solve": round(wall * 1e3 / nsolve, 3),
+                     "solves_per_s": round(nsolve / wall, 4),
+                     "solves_within_0.1meV": ok,
+                     "solves_per_s_at_0.1meV": round(ok / wall, 4),
+                     "max_lowest100_err_meV": max(errs) * 1e3, "max_eps2_rel_err": max(e2s),
+                     "nrefine": nref}
+        log_fn(f"{name}: {wall * 1e3 / nsolve:.1f} ms per solve, lowest-100 max err "
+               f"{max(errs) * 1e3:.2e} meV, eps2 {max(e2s):.2e}, {ok}/{nsolve} within the bars")
+        S.H = None
+        S.ws = None
+        del sv, S
+        torch.cuda.empty_cache()
+    f = out["plain_fp64"]["solves_per_s_at_0.1meV"]
+    out["refined_bf16x3_over_plain_fp64_at_0.1meV"] = (
+        round(out["refined_bf16x3"]["solves_per_s_at_0.1meV"] / f, 3) if f > 0 else None)
+    return out
 
 
 if __name__ == "__main__":

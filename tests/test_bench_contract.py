@@ -1,9 +1,9 @@
 """Host-side checks of bench.py and of the committed bench lines (no GPU).
 
 * `--gpus N` with N > 1 exits with status 2 and a message (one GPU only).
-* The HBM traffic of the build kernel is reported only for the workload and
-  build the counters were taken on (cfg2, FP32, dense build), never for the
-  seed construction or another workload.
+* The HBM traffic of the build kernel is reported only for a workload and
+  build whose counters are committed (profiles/hbm_traffic_k_direct_fused_*),
+  never for the seed construction or a workload without counters.
 * Every committed bench line under profiles/ carries the command that made it
   and the keys of the bench line; the default line also the roofline and the
   CPU oracle baseline.
@@ -32,11 +32,12 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_only_for_its_own_workload():
     import bench
-    v = bench.measured_traffic("cfg2", "fp32")
-    assert v is None or v > 0  # None once the kernel sources changed since the counters
-    assert bench.measured_traffic("cfg2", "fp32", seed=True) is None
-    assert bench.measured_traffic("cfg3", "fp32") is None
-    assert bench.measured_traffic("cfg2", "bf16x3") is None
+    for w in ("cfg2", "cfg3"):
+        v = bench.measured_traffic(w, "fp32")
+        assert v is None or v > 0  # None once the kernel sources changed since the counters
+        assert bench.measured_traffic(w, "fp32", seed=True) is None
+        assert bench.measured_traffic(w, "bf16x3") is None
+    assert bench.measured_traffic("cfg1", "fp32") is None
 
 
 @pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(ROOT, "profiles", "bench_*.json"))),
