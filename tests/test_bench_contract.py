@@ -5,8 +5,9 @@
   build whose counters are committed (profiles/hbm_traffic_k_direct_fused_*),
   never for the seed construction or a workload without counters.
 * Every committed bench line under profiles/ carries the command that made it
-  and the keys of the bench line; the default line also the roofline and the
-  CPU oracle baseline.
+  and the keys of the bench line; the default line (cfg3) also the roofline,
+  the per-stage CPU oracle baseline, its accuracy against the oracle's stored
+  solution and the refined split-BF16 against plain FP64 comparison.
 """
 import glob
 import json
@@ -48,9 +49,18 @@ def test_committed_bench_lines(path):
     for k in KEYS:
         assert k in d, k
     assert d["n_gpus"] == 1 and d["value"] > 0 and "workload" in d["config"]
-    if os.path.basename(path) == "bench_cfg2_fp32.json":
+    if os.path.basename(path) == "bench_cfg3_fp32.json":  # the default line
+        assert d["command"] == "python bench.py"
         r = d["roofline"]
         assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
         assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
         c = d["cpu_baseline"]
         assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+        assert c["host_cpus"] >= 1 and c["cpu_model"]
+        assert set(c["stage_s"]) == {"build", "projection", "block_eigh", "spectrum"}
+        a = d["accuracy_vs_oracle"]
+        assert a["meets_bars"] and a["lowest100_max_err_eV"] < 1e-5 and a["eps2_rel_err"] <= 1e-4
+        f = d["precision_forms"]
+        for form in ("refined_bf16x3", "plain_fp64"):
+            assert f[form]["solves_within_0.1meV"] == f[form]["solves"]
+        assert f["refined_bf16x3_over_plain_fp64_at_0.1meV"] > 1
