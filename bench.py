@@ -198,8 +198,8 @@ def bench_batched(args):
     ns = [b[2].n for b in bs.blocks]
     log(f"setup {time.perf_counter() - t0:.1f} s; {len(systems)} systems, {len(ns)} blocks, "
         f"n in {min(ns)}..{max(ns)}, sum n = {sum(ns)}")
-    wpr = bs.tune()
-    log(f"autotuner: {wpr} waves per row")
+    wpr, tile = bs.tune()
+    log(f"autotuner: {wpr} waves per row, trailing-update tiles of {tile}")
     bs.step()
     torch.cuda.synchronize()
     for si, r in enumerate(bs.results()):
@@ -265,6 +265,7 @@ def bench_batched(args):
         "block_eigh_one_call_per_block_ms": round(seq_ms, 3),
         "lockstep_gain": round(seq_ms / split[1], 2),
         "autotuned_waves_per_row": wpr,
+        "autotuned_her2k_tile": tile,
     }
     print(json.dumps(out), flush=True)
     bs.close()
@@ -410,6 +411,10 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit: "
                          "the reference for scaling HBM byte counters")
+    ap.add_argument("--sync-probe", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS dependent steps of 256..1024 workgroups, one kernel "
+                         "launch per step against one cooperative launch with grid barriers, "
+                         "and exit (the design input of the batched form)")
     ap.add_argument("--copy-timed", type=int, default=0, metavar="K",
                     help="with --copy-mib: then time K more copies and report the achieved "
                          "read + write bandwidth (the practical HBM ceiling)")
@@ -445,6 +450,20 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.sync_probe:
+        from paper_2603_24860_amd import bse as B
+        props = torch.cuda.get_device_properties(0)
+        out = {"device": props.name, "compute_units": props.multi_processor_count,
+               "steps": args.sync_probe, "us_per_step": {}}
+        buf = torch.zeros(2 * 4096, dtype=torch.int32, device="cuda")
+        for wgs in (256, 512, 1024):
+            row = {}
+            for mode, name in ((0, "launch_per_step"), (1, "grid_barrier")):
+                B.bse_sync_probe(mode, wgs, 100, buf)  # warm-up
+                row[name] = round(B.bse_sync_probe(mode, wgs, args.sync_probe, buf), 3)
+            out["us_per_step"][str(wgs)] = row
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_mib:
         src = torch.ones(args.copy_mib * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -370,14 +370,20 @@ int32_t bse_block_eigh_noalloc(int64_t n, const void *Hmu, int64_t ld, int32_t h
  *                          outputs as in bse_block_eigh).
  *   bse_batch_eigh_run     enqueues the whole solve on `stream`: kernel launches
  *                          only, so it may be captured into a HIP graph.
- *   bse_batch_eigh_tune    autotuner: times each row-split variant of the
- *                          HEMV kernel on this batch, keeps the fastest for the
- *                          plan and returns it in *h_wpr (may be NULL); runs the
- *                          solve several times (outputs are overwritten).  It
+ *   bse_batch_eigh_tune    autotuner: times every combination of the HEMV
+ *                          kernel's row split (1, 2 or 4 waves per row) and the
+ *                          trailing update's tile (64 x 64 or 32 x 32 complex
+ *                          entries) on this batch, keeps the fastest for the
+ *                          plan and returns it in *h_wpr and *h_tile (tile edge
+ *                          in entries; either may be NULL); runs the solve
+ *                          several times (outputs are overwritten).  It
  *                          rewrites the plan's device launch tables: a graph
  *                          captured from bse_batch_eigh_run before a tune keeps
  *                          the old grid sizes and must not be replayed after
  *                          it (tune first, then capture).
+ *   bse_batch_eigh_config  sets the row split (1, 2, 4) and tile edge (64, 32)
+ *                          explicitly, as the tuner would (same caveat for
+ *                          captured graphs; synchronises `stream`).
  *   bse_batch_eigh_free    forgets the plan (the caller frees the workspace).
  * Limits: 1 <= nb <= 1024 and 1 <= n <= 16384 per block (BSE_ESHAPE);
  * prec FP64 or FP32 (BSE_EINVAL).  Plans are kept per process; a plan must
@@ -390,7 +396,9 @@ int32_t bse_batch_eigh_plan(int32_t nb, const int64_t *h_n, const void *const *h
                             double *const *h_osc, void *ws, size_t ws_bytes, int64_t *h_plan,
                             bse_stream stream);
 int32_t bse_batch_eigh_run(int64_t plan, bse_stream stream);
-int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t *h_wpr);
+int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t *h_wpr,
+                            int32_t *h_tile);
+int32_t bse_batch_eigh_config(int64_t plan, int32_t wpr, int32_t tile, bse_stream stream);
 int32_t bse_batch_eigh_free(int64_t plan);
 
 /* ---------------------------------------------------------------------------
@@ -457,6 +465,24 @@ int32_t bse_haydock(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, cons
 int32_t bse_haydock_spectrum(int32_t K, const double *a, const double *b, double pref,
                              double eta, int64_t nw, const double *w, double *eps2,
                              bse_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * bse_sync_probe: cost of one global dependency between two steps of a
+ * lockstep solve on this device, the design input of the batched form (which
+ * pays one per Householder step).  Times `steps` steps of `wgs` workgroups
+ * in which every workgroup reads a value another one wrote in the previous
+ * step:
+ *   mode 0  one kernel launch per step, back to back on `stream`;
+ *   mode 1  one cooperative (persistent) launch with a grid-wide barrier
+ *           between steps (all workgroups must fit on the device at once).
+ *   buf     device int32[2 wgs] scratch (caller owned, overwritten).
+ * *h_us_per_step receives the mean time per step in microseconds.
+ * Synchronises `stream`.  Errors: BSE_EINVAL (mode, NULL), BSE_ESHAPE (wgs
+ * outside 1 .. 4096 or not co-resident for mode 1, steps outside 1 .. 10^6),
+ * BSE_EUNSUPPORTED (no cooperative launch), BSE_EDEVICE.
+ * ------------------------------------------------------------------------- */
+int32_t bse_sync_probe(int32_t mode, int32_t wgs, int32_t steps, int32_t *buf,
+                       double *h_us_per_step, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (host).  bse_prof_enable(prefix) brackets every subsequent

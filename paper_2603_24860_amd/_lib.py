@@ -95,7 +95,8 @@ def _load():
         "bse_batch_eigh_plan": (i32, [i32, P(i64), P(vp), P(i64), i32, P(vp), i32, P(vp), P(vp),
                                       P(vp), vp, ctypes.c_size_t, P(i64), vp]),
         "bse_batch_eigh_run": (i32, [i64, vp]),
-        "bse_batch_eigh_tune": (i32, [i64, vp, P(i32)]),
+        "bse_batch_eigh_tune": (i32, [i64, vp, P(i32), P(i32)]),
+        "bse_batch_eigh_config": (i32, [i64, i32, i32, vp]),
         "bse_batch_eigh_free": (i32, [i64]),
         "bse_spectrum": (i32, [i64, vp, vp, f64, f64, i64, vp, vp, vp]),
         "bse_eels_ws": (ctypes.c_size_t, [i64]),
@@ -103,6 +104,7 @@ def _load():
         "bse_haydock_ws": (ctypes.c_size_t, [i64]),
         "bse_haydock": (i32, [i64, vp, i64, i32, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
         "bse_haydock_spectrum": (i32, [i32, vp, vp, f64, f64, i64, vp, vp, vp]),
+        "bse_sync_probe": (i32, [i32, i32, i32, vp, P(f64), vp]),
         "bse_prof_enable": (i32, [ctypes.c_char_p]),
         "bse_prof_collect": (i32, []),
         "bse_prof_count": (i32, []),

@@ -61,7 +61,7 @@ class BatchSolver:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=systems[0].device)
         self.plan = B.bse_batch_eigh_plan(self.Hmu, self.Bmu, self.eig_prec, self.om, self.po,
                                           self.os, self.ws)
-        self.wpr = 4
+        self.wpr, self.htile = 4, 64
         self.w, self.eps2 = [], []
         for si, s in enumerate(systems):
             wg = wgrids[si] if wgrids is not None else np.linspace(-10, 20, 2000)
@@ -107,8 +107,8 @@ class BatchSolver:
             raise RuntimeError("tune() after capture(): the captured graph keeps the grid sizes "
                                "of the old tables; tune first, then capture")
         self.build_and_project()
-        self.wpr = B.bse_batch_eigh_tune(self.plan)
-        return self.wpr
+        self.wpr, self.htile = B.bse_batch_eigh_tune(self.plan)
+        return self.wpr, self.htile
 
     def capture(self):
         """Record one whole step (builds, projections, batched eigh, spectra)

@@ -214,6 +214,14 @@ def bse_block_eigh_status(n, prec, nrefine, ws, stream=None, raise_on_noconv=Tru
     return list(st)
 
 
+def bse_sync_probe(mode, wgs, steps, buf, stream=None):
+    """Microseconds per step of a lockstep chain: mode 0 one launch per step,
+    mode 1 one cooperative launch with grid barriers (buf: int32[2 wgs])."""
+    us = ctypes.c_double()
+    check(lib.bse_sync_probe(mode, wgs, steps, _ptr(buf), ctypes.byref(us), _stream(stream)))
+    return us.value
+
+
 def bse_block_eigh_noalloc_max():
     return lib.bse_block_eigh_noalloc_max()
 
@@ -252,9 +260,14 @@ def bse_batch_eigh_run(plan, stream=None):
 
 
 def bse_batch_eigh_tune(plan, stream=None):
-    w = ctypes.c_int32()
-    check(lib.bse_batch_eigh_tune(plan, _stream(stream), ctypes.byref(w)))
-    return w.value
+    """Autotune the plan; returns (waves per HEMV row, trailing-update tile edge)."""
+    w, t = ctypes.c_int32(), ctypes.c_int32()
+    check(lib.bse_batch_eigh_tune(plan, _stream(stream), ctypes.byref(w), ctypes.byref(t)))
+    return w.value, t.value
+
+
+def bse_batch_eigh_config(plan, wpr, tile, stream=None):
+    check(lib.bse_batch_eigh_config(plan, wpr, tile, _stream(stream)))
 
 
 def bse_batch_eigh_free(plan):

@@ -1100,13 +1100,13 @@ __device__ __forceinline__ void b_colB(int64_t n, int64_t jn, int ir, int more,
 // Trailing update on MFMA: A[r][c] -= sum_l V_l[r] conj(W_l[c]) + W_l[r] conj(V_l[c])
 // for r, c >= c0; real GEMM with K = 4 nbk (x conj(y) interleave, see bse_build).
 
-template <typename T>
+template <typename T, int S>
 __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
                                                const double2 *__restrict__ V,
                                                const double2 *__restrict__ W, int64_t ldv,
                                                T *__restrict__ A, int64_t lda, int64_t bx, int64_t by,
                                                bool mirror) {
-  constexpr int BM = HerTile<T>::BM, BN = HerTile<T>::BN, BK = HerTile<T>::BK;
+  constexpr int BM = HerTile<T, S>::BM, BN = HerTile<T, S>::BN, BK = HerTile<T, S>::BK;
   constexpr int P = Pitch<T, BK>::value, MI = BM / 32, NI = BN / 32, KC = BK / 2;
   constexpr int NA = (BM / 2) * KC / ENT, NB = BN * KC / ENT;
   static_assert(BM == 2 * BN, "square tiles in complex entries");
@@ -1535,19 +1535,34 @@ BSE_PAIR(colB, int64_t jn BSE_COMMA int cur, {
              D.y, D.ys, D.ldys, nbt, D.parta, npa, D.bred, D.tau, D.scl, D.col,
              cur ? D.partb0 : D.partb1, wg);
 })
-BSE_PAIR(her2k, int64_t j0, {
+// trailing update of one workgroup: tile S; every tile below HER_TRI_M
+// trailing rows, else the lower ones row by row: wg = by (by + 1) / 2 + bx
+template <typename TA, int S>
+__device__ __forceinline__ void her2k_wg(const Desc &D, int64_t j0, int wg) {
+  constexpr int BN = HerTile<TA, S>::BN;
   const int nbk = g_nbk(D.n, j0);
-  const int64_t c0 = j0 + nbk, t = cdiv(D.n - c0, HerTile<TA>::BN);
-  if (t < HER_TRI) {  // every tile
-    b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, wg % t, wg / t, false);
-  } else {  // tiles on or below the diagonal, row by row: wg = by (by + 1) / 2 + bx
+  const int64_t c0 = j0 + nbk, t = cdiv(D.n - c0, BN);
+  if (!her_tri(t, BN)) {
+    b_her2k<TA, S>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, wg % t, wg / t, false);
+  } else {
     int64_t by = int64_t((sqrt(8.0 * double(wg) + 1.0) - 1.0) * 0.5);
     while (by * (by + 1) / 2 > wg) --by;
     while ((by + 1) * (by + 2) / 2 <= wg) ++by;
     const int64_t bx = wg - by * (by + 1) / 2;
-    b_her2k<TA>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, bx, by, true);
+    b_her2k<TA, S>(D.n, c0, nbk, D.V, D.W, D.ldv, (TA *)D.A, D.lda, bx, by, true);
   }
-})
+}
+template <typename TH, typename TA, int S>
+__global__ __launch_bounds__(ENT) void k_her2k(Desc D, int64_t j0) {
+  her2k_wg<TA, S>(D, j0, int(blockIdx.x));
+}
+template <typename TH, typename TA, int S>
+__global__ __launch_bounds__(ENT) void k_her2k_b(const Desc *__restrict__ Ds,
+                                                 const int *__restrict__ pre, int nact,
+                                                 int64_t j0) {
+  BSE_FIND_BLOCK
+  her2k_wg<TA, S>(D, j0, wg);
+}
 BSE_PAIR(bisect_grid, int unused_, {
   (void)unused_;
   b_bisect_grid(D.n, D.d, D.e2, D.tsc, D.bgrid, wg);
@@ -2237,7 +2252,7 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
     }
     BSE_HIP_CHECK(hipGetLastError());
     if (kind_wgs<TA>(K_HER2K, n, j0, 4) > 0)
-      BSE_LAUNCH("k_her2k", (k_her2k<TH, TA, 4>), grid(K_HER2K, j0, 4), dim3(ENT), 0, s, D, j0);
+      BSE_LAUNCH("k_her2k", (k_her2k<TH, TA, 0>), grid(K_HER2K, j0, 4), dim3(ENT), 0, s, D, j0);
     BSE_HIP_CHECK(hipGetLastError());
   }
   // ---- tridiagonal eigenvalues and optical weights ----
@@ -2275,7 +2290,7 @@ struct BatchLaunch {
 };
 
 struct BatchPlan {
-  int nb = 0, h_fp64 = 0, prec = 0, wpr = 4;
+  int nb = 0, h_fp64 = 0, prec = 0, wpr = 4, htile = 0;
   char *ws = nullptr;
   Desc *d_desc = nullptr;
   int *d_pre = nullptr;
@@ -2294,7 +2309,7 @@ void plan_launches(BatchPlan &P, std::vector<int> &pre) {
     int64_t tot = 0;
     pre.push_back(0);
     for (int b = 0; b < nb; ++b) {
-      const int64_t w = kind_wgs<TA>(kind, P.n[b], j, P.wpr);
+      const int64_t w = kind_wgs<TA>(kind, P.n[b], j, P.wpr, P.htile);
       if (w == 0) break;  // sorted descending: the rest are inactive too
       tot += w;
       pre.push_back((int)tot);
@@ -2347,7 +2362,12 @@ int32_t batch_launch(const BatchPlan &P, const BatchLaunch &L, hipStream_t s) {
     case K_COL0: BSE_LAUNCH("k_col0", (k_col0_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
     case K_COLA: BSE_LAUNCH("k_colA", (k_colA_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
     case K_COLB: BSE_LAUNCH("k_colB", (k_colB_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j, L.cur); break;
-    case K_HER2K: BSE_LAUNCH("k_her2k", (k_her2k_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, L.j); break;
+    case K_HER2K:
+      if (P.htile)
+        BSE_LAUNCH("k_her2k", (k_her2k_b<TH, TA, 1>), g, b, 0, s, Ds, pre, L.nact, L.j);
+      else
+        BSE_LAUNCH("k_her2k", (k_her2k_b<TH, TA, 0>), g, b, 0, s, Ds, pre, L.nact, L.j);
+      break;
     case K_TRI: BSE_LAUNCH("k_tri_prep", k_tri_prep_b<TA>, g, dim3(RNT), 0, s, Ds, pre, L.nact, 0); break;
     case K_TAIL: BSE_LAUNCH("k_tail", k_tail_b<TA>, g, dim3(TNT), 0, s, Ds, L.cur, L.j); break;
     case K_BGRID: BSE_LAUNCH("k_bisect_grid", (k_bisect_grid_b<TH, TA, W>), g, b, 0, s, Ds, pre, L.nact, 0); break;
@@ -2635,7 +2655,8 @@ extern "C" int32_t bse_batch_eigh_run(int64_t plan, bse_stream stream) {
   return run_plan(P, (hipStream_t)stream);
 }
 
-extern "C" int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t *h_wpr) {
+extern "C" int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t *h_wpr,
+                                       int32_t *h_tile) {
   BatchPlan P;
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -2648,37 +2669,65 @@ extern "C" int32_t bse_batch_eigh_tune(int64_t plan, bse_stream stream, int32_t 
   BSE_HIP_CHECK(hipEventCreate(&e0));
   BSE_HIP_CHECK(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_w = 4;
-  for (int w : {4, 2, 1}) {
-    P.wpr = w;
-    int32_t st = upload_tables(P, s);
-    if (!st) st = run_plan(P, s);  // warm-up
-    if (!st) {
-      BSE_HIP_CHECK(hipEventRecord(e0, s));
-      st = run_plan(P, s);
-      BSE_HIP_CHECK(hipEventRecord(e1, s));
-      BSE_HIP_CHECK(hipEventSynchronize(e1));
+  int best_w = 4, best_t = 0;
+  // every row split of the HEMV kernel with either trailing-update tile
+  for (int t : {0, 1})
+    for (int w : {4, 2, 1}) {
+      P.wpr = w;
+      P.htile = t;
+      int32_t st = upload_tables(P, s);
+      if (!st) st = run_plan(P, s);  // warm-up
+      if (!st) {
+        BSE_HIP_CHECK(hipEventRecord(e0, s));
+        st = run_plan(P, s);
+        BSE_HIP_CHECK(hipEventRecord(e1, s));
+        BSE_HIP_CHECK(hipEventSynchronize(e1));
+      }
+      if (st) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+      }
+      float ms = 0;
+      BSE_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_w = w;
+        best_t = t;
+      }
     }
-    if (st) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      return st;
-    }
-    float ms = 0;
-    BSE_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_w = w;
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   P.wpr = best_w;
+  P.htile = best_t;
   int32_t st = upload_tables(P, s);
   if (st) return st;
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plans[plan] = P;
   if (h_wpr) *h_wpr = best_w;
+  if (h_tile) *h_tile = best_t ? HerTile<float, 1>::BN : HerTile<float, 0>::BN;
+  return BSE_OK;
+}
+
+extern "C" int32_t bse_batch_eigh_config(int64_t plan, int32_t wpr, int32_t tile,
+                                         bse_stream stream) {
+  if (wpr != 1 && wpr != 2 && wpr != 4) return fail(BSE_EINVAL, "waves per row %d (1, 2, 4)", wpr);
+  if (tile != HerTile<float, 0>::BN && tile != HerTile<float, 1>::BN)
+    return fail(BSE_EINVAL, "tile %d (%d or %d)", tile, HerTile<float, 0>::BN,
+                HerTile<float, 1>::BN);
+  BatchPlan P;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(plan);
+    if (it == g_plans.end()) return fail(BSE_EINVAL, "unknown plan %lld", (long long)plan);
+    P = it->second;
+  }
+  P.wpr = wpr;
+  P.htile = tile == HerTile<float, 1>::BN ? 1 : 0;
+  const int32_t st = upload_tables(P, (hipStream_t)stream);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans[plan] = P;
   return BSE_OK;
 }
 

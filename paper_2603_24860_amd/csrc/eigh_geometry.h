@@ -42,10 +42,17 @@ constexpr int TP = RB + 1;    // LDS pitch of one panel column
 // subtracts the conjugate transpose of its update from the mirror tile,
 // staged through LDS so that those writes are row-contiguous too.  Smaller
 // trailing blocks keep every tile, for the parallelism.
-constexpr int64_t HER_TRI = 32;
-template <typename T> struct HerTile;
-template <> struct HerTile<float> { static constexpr int BM = 128, BN = 64, BK = 32; };
-template <> struct HerTile<double> { static constexpr int BM = 128, BN = 64, BK = 16; };
+// Tiles of the trailing update: S = 0 is 64 x 64 complex entries (BM = 128
+// real rows, BN = 64 complex columns), S = 1 is 32 x 32 (more workgroups for
+// small blocks; the batched solver's autotuner chooses).  From HER_TRI_M
+// trailing rows on, only the tiles on or below the diagonal are computed.
+constexpr int64_t HER_TRI_M = 2048;
+template <typename T, int S = 0> struct HerTile;
+template <> struct HerTile<float, 0> { static constexpr int BM = 128, BN = 64, BK = 32; };
+template <> struct HerTile<double, 0> { static constexpr int BM = 128, BN = 64, BK = 16; };
+template <> struct HerTile<float, 1> { static constexpr int BM = 64, BN = 32, BK = 32; };
+template <> struct HerTile<double, 1> { static constexpr int BM = 64, BN = 32, BK = 16; };
+__host__ __device__ __forceinline__ bool her_tri(int64_t t, int bn) { return t * bn >= HER_TRI_M; }
 
 // One block's working set.  Partial-sum buffers are sized by the block:
 // k_colB and k_col0 write at most ceil(n / 64) records, k_colA at most n sums,
@@ -230,7 +237,7 @@ enum Kind { K_COPY, K_LOADB, K_HEMV0, K_W0, K_RANK2, K_COL0, K_COLA, K_COLB, K_H
             K_BISECT, K_WEIGHTS, K_TAIL, K_BGRID };
 
 template <typename TA>
-int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
+int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr, int htile = 0) {
   switch (kind) {
     case K_COPY: return n * g_copy_gx(n);
     case K_LOADB: return g_nwg(n);
@@ -245,8 +252,9 @@ int64_t kind_wgs(int kind, int64_t n, int64_t j, int wpr) {
     case K_HER2K: {
       if (j >= g_tail0(n)) return 0;
       const int64_t c0 = j + g_nbk(n, j), m = n - c0;
-      const int64_t t = cdiv(m, HerTile<TA>::BN);  // tile rows (see b_her2k)
-      return m > 0 ? (t < HER_TRI ? t * t : t * (t + 1) / 2) : 0;
+      const int bn = htile ? HerTile<TA, 1>::BN : HerTile<TA, 0>::BN;
+      const int64_t t = cdiv(m, bn);  // tile rows (see b_her2k)
+      return m > 0 ? (her_tri(t, bn) ? t * (t + 1) / 2 : t * t) : 0;
     }
     case K_TRI: return 1;
     case K_BGRID: return NGRID / ENT;

@@ -262,23 +262,27 @@ int run(int64_t n, bool a64, int64_t K) {
       }
       cur ^= 1;
     }
-    // k_her2k: tiles of BM/2 x BN complex entries from c0
+    // k_her2k: tiles of BM/2 x BN complex entries from c0, both tile shapes
     const int64_t c0 = j0 + nbk;
-    const int64_t gh = a64 ? kind_wgs<double>(K_HER2K, n, j0, 4) : kind_wgs<float>(K_HER2K, n, j0, 4);
-    if (gh > 0) {
-      const int64_t t = cdiv(n - c0, int64_t(HerTile<float>::BN));
+    for (int ht = 0; ht < 2; ++ht) {
+      const int64_t gh = a64 ? kind_wgs<double>(K_HER2K, n, j0, 4, ht)
+                             : kind_wgs<float>(K_HER2K, n, j0, 4, ht);
+      if (gh <= 0) continue;
+      const int BN = ht ? HerTile<float, 1>::BN : HerTile<float, 0>::BN;
+      const int BM = ht ? HerTile<float, 1>::BM : HerTile<float, 0>::BM;
+      const int64_t t = cdiv(n - c0, int64_t(BN));
       for (int64_t wg = 0; wg < gh; ++wg) {
         int64_t bx, by;
-        if (t < HER_TRI) {
+        if (!her_tri(t, BN)) {
           bx = wg % t;
           by = wg / t;
         } else {
           tri_of(wg, by, bx);
         }
-        const int64_t a0 = c0 + by * (HerTile<float>::BM / 2), b0 = c0 + bx * HerTile<float>::BN;
+        const int64_t a0 = c0 + by * (BM / 2), b0 = c0 + bx * BN;
         if (a0 >= n || b0 >= n) continue;
-        const int64_t a1 = std::min<int64_t>(a0 + HerTile<float>::BM / 2, n) - 1;
-        const int64_t b1 = std::min<int64_t>(b0 + HerTile<float>::BN, n) - 1;
+        const int64_t a1 = std::min<int64_t>(a0 + BM / 2, n) - 1;
+        const int64_t b1 = std::min<int64_t>(b0 + BN, n) - 1;
         C.at("A", a0 * D.lda + b0, "k_her2k");
         C.at("A", a1 * D.lda + b1, "k_her2k");
         C.at("A", b1 * D.lda + a1, "k_her2k mirror");

@@ -9,19 +9,32 @@
 * The whole batched solve captured in a HIP graph and replayed three times,
   with eager work and synchronisations between replays, reproduces the eager
   results bitwise on every replay.
+* Every row split and trailing-update tile the autotuner may choose gives
+  the known spectra.
 * cfg4 at full size (64 systems, 384 blocks up to 2304): the autotuned
-  lockstep solve against single-block solves of sampled blocks.
+  lockstep solve against single-block solves of sampled blocks, and its
+  largest system (24x24x1, N = 6912) against the FP64 oracle's stored
+  solution (tests/golden/cfg4_largest_oracle.json, written by
+  make_cfg4_reference.py from the oracle alone): the union of its six block
+  spectra equals the spectrum of the full H, the E1u block's lowest 100
+  energies within 1e-5 eV and eps2 within 1e-4.
 """
+import json
+import os
 import sys
 
 import numpy as np
 import pytest
 
-from test_gpu_parity import _cluster_weights, _match_poles, _random_hermitian
+from test_gpu_parity import (_cluster_weights, _householder_hermitian, _match_poles,
+                             _random_hermitian)
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+GOLD4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                     "cfg4_largest_oracle.json")
 
 SIZES = [(600, 3), (257, 1), (1, 1), (162, 3), (33, 1), (2, 1), (600, 1), (100, 1), (3, 3),
          (64, 1), (5, 1)]
@@ -99,14 +112,34 @@ def test_batch_equals_single(lib, precname, h_dtype):
 def test_batch_tuned(lib):
     probs = _problems()
     bt = _Batch(lib, probs, lib.FP64, torch.complex128)
-    w = lib.bse_batch_eigh_tune(bt.plan)
-    say("autotuned waves per row", w)
-    assert w in (1, 2, 4)
+    w, t = lib.bse_batch_eigh_tune(bt.plan)
+    say("autotuned waves per row", w, "tile", t)
+    assert w in (1, 2, 4) and t in (32, 64)
     lib.bse_batch_eigh_run(bt.plan)
     for (A, b, lam, Q), (om, po, os_) in zip(probs, bt.host()):
         assert np.abs(om - np.sort(lam)).max() < 1e-11 * max(1, np.abs(lam).max())
         ce, cw = _cluster_weights(lam, Q, b)
         _match_poles(po, os_, ce, cw, 1e-9)
+    lib.bse_batch_eigh_free(bt.plan)
+
+
+@pytest.mark.parametrize("tile", [64, 32])
+@pytest.mark.parametrize("wpr", [4, 2, 1])
+def test_batch_every_config(lib, wpr, tile):
+    """Every row split and trailing-update tile the autotuner may pick gives
+    the known spectra, including a block above the 2048 trailing rows from
+    which the update runs on the lower tiles only (n = 2200, FP32 storage)."""
+    probs = _problems() + [_householder_hermitian(2200, 19)]
+    bt = _Batch(lib, probs, lib.FP32, torch.complex64)
+    lib.bse_batch_eigh_config(bt.plan, wpr, tile)
+    say("batch config", wpr, tile)
+    lib.bse_batch_eigh_run(bt.plan)
+    for (A, b, lam, _), (om, po, os_) in zip(probs, bt.host()):
+        # FP32 storage moves the eigenvalues by ~eps32 |A| sqrt(n) (|A| = 10)
+        err = np.abs(om - np.sort(lam)).max()
+        assert err < 2e-5 * max(1.0, np.sqrt(len(lam) / 600)), (len(lam), err)
+        b2 = float(np.sum(np.abs(b) ** 2))
+        assert abs(os_.sum() - b2) <= 1e-6 * b2
     lib.bse_batch_eigh_free(bt.plan)
 
 
@@ -208,7 +241,9 @@ def _check_batched(lib, seed):
 @pytest.mark.timeout(900)
 def test_cfg4_full_size_lockstep_against_single(lib):
     """cfg4 at full size (64 D6h systems, 384 blocks up to n = 2304, FP32),
-    the autotuned lockstep solve as the bench times it: for the four largest
+    the autotuned lockstep solve as the bench times it: the largest system
+    against the oracle (union of block spectra = full spectrum, E1u lowest 100
+    and eps2); for the four largest
     blocks and four others, the batched eigenvalues agree with a single-block
     solve of the same H_mu (other HEMV forms, FP32 storage: within 2e-5 of
     the spectral radius) and the strengths sum to |B_mu|^2 (1e-6)."""
@@ -221,9 +256,28 @@ def test_cfg4_full_size_lockstep_against_single(lib):
     ns = [b[2].n for b in bs.blocks]
     say("  blocks", len(ns), "n max", max(ns), "sum n", sum(ns))
     assert len(systems) == 64 and max(ns) > 2048
-    bs.tune()
+    # the largest system against the oracle's stored solution (its grid for eps2)
+    ref = json.load(open(GOLD4))
+    si = ref["index"]
+    assert systems[si].N == ref["N"]
+    bs.w[si] = torch.as_tensor(np.linspace(ref["wmin"], ref["wmax"], ref["nw"]), device="cuda")
+    bs.eps2[si] = torch.empty_like(bs.w[si])
+    wpr, tile = bs.tune()
+    say("  autotuned", wpr, "waves per row, tiles of", tile)
     bs.step()
     torch.cuda.synchronize()
+    r = bs.results()[si]
+    union = np.sort(np.concatenate(list(r["blocks"].values())))
+    full = np.asarray(ref["full_spectrum"])
+    uerr = np.abs(union - full).max()
+    lerr = np.abs(r["lowest"] - np.asarray(ref["omega"][:100])).max()
+    e2 = np.asarray(ref["eps2"])
+    e2err = np.abs(r["eps2"] - e2).max() / np.abs(e2).max()
+    say("  largest system", ref["config"], "N", ref["N"], "union of block spectra vs oracle H",
+        uerr, "E1u lowest-100", lerr, "eps2", e2err)
+    assert r["active"] == ref["irrep"]
+    assert len(union) == len(full) and uerr < 2e-5 * max(1.0, np.abs(full).max())
+    assert lerr < 1e-5 and e2err <= 1e-4
     order = np.argsort(ns)[::-1]
     pick = list(order[:4]) + list(np.random.default_rng(7).choice(order[4:], 4, replace=False))
     for i in pick:
