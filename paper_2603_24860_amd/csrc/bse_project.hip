@@ -46,8 +46,8 @@ struct SeedSrc {
   double scale;
 };
 
-template <typename T, bool SEEDSRC>
-__global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__restrict__ H,
+template <typename T, bool SEEDSRC, int NCT>
+__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(NCT == 1 && !SEEDSRC && sizeof(T) == 4 ? 6 : 1, 8))) void k_project(int nv, int nc, const T *__restrict__ H,
                                                  int64_t ldh, const int32_t *__restrict__ mem_off,
                                                  const int32_t *__restrict__ members,
                                                  const int64_t *__restrict__ orb_off,
@@ -85,9 +85,9 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
   }
   const int ncol = r2 * nb, per = L2 * nb;
   const int RU = PCH / per;  // rows per chunk (>= 1)
-  double accr[PMAXCOL][PMAXR], acci[PMAXCOL][PMAXR];
+  double accr[NCT][PMAXR], acci[NCT][PMAXR];  // NCT output columns per thread
 #pragma unroll
-  for (int t = 0; t < PMAXCOL; ++t)
+  for (int t = 0; t < NCT; ++t)
 #pragma unroll
     for (int j = 0; j < PMAXR; ++j) accr[t][j] = acci[t][j] = 0.0;
   const int v = band / nc, c = band % nc;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
     __syncthreads();
     if (i0 + RU < L1) fetch(i0 + RU);
 #pragma unroll
-    for (int t = 0; t < PMAXCOL; ++t) {
+    for (int t = 0; t < NCT; ++t) {
       const int col = threadIdx.x + PNT * t;
       if (col >= ncol) break;
       const int j2 = col / nb, b2 = col % nb;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(PNT) void k_project(int nv, int nc, const T *__rest
   }
   const int64_t rbase = orb_off[o1] + band, cbase = orb_off[o2];
 #pragma unroll
-  for (int t = 0; t < PMAXCOL; ++t) {
+  for (int t = 0; t < NCT; ++t) {
     const int col = threadIdx.x + PNT * t;
     if (col >= ncol) break;
 #pragma unroll
@@ -300,14 +300,17 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
       if (9 * nb > PNT * PMAXCOL)
         return fail(BSE_EUNSUPPORTED, "r' nv nc exceeds %d columns", PNT * PMAXCOL);
       dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
-      if (h_fp64)
-        BSE_LAUNCH("k_project", (k_project<double, false>), g, dim3(PNT), 0, s, p->nv, p->nc,
-                           (const double *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
-                           b.ub_off, b.ubasis, (double *)Hmu[ib], ldmu[ib], SeedSrc{});
-      else
-        BSE_LAUNCH("k_project", (k_project<float, false>), g, dim3(PNT), 0, s, p->nv, p->nc,
-                           (const float *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim,
-                           b.ub_off, b.ubasis, (float *)Hmu[ib], ldmu[ib], SeedSrc{});
+      const bool one = 9 * nb <= PNT;  // every output column of a block row in one thread
+#define BSE_PROJ(T, NCT)                                                                      \
+  BSE_LAUNCH("k_project", (k_project<T, false, NCT>), g, dim3(PNT), 0, s, p->nv, p->nc,       \
+             (const T *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis, \
+             (T *)Hmu[ib], ldmu[ib], SeedSrc{})
+      if (h_fp64) {
+        if (one) BSE_PROJ(double, 1); else BSE_PROJ(double, 2);
+      } else {
+        if (one) BSE_PROJ(float, 1); else BSE_PROJ(float, 2);
+      }
+#undef BSE_PROJ
       BSE_HIP_CHECK(hipGetLastError());
     }
     if (Bmu && Bmu[ib]) {
@@ -341,14 +344,17 @@ extern "C" int32_t bse_project_seed(int64_t plan, int32_t nblk, const bse_block 
     if (b.n > N) return fail(BSE_ESHAPE, "block %d larger than N", ib);
     if (!ldmu || ldmu[ib] < b.n) return fail(BSE_ESHAPE, "ldmu[%d] < n", ib);
     dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
-    if (sp.prec == BSE_FP64)
-      BSE_LAUNCH("k_project_seed", (k_project<double, true>), g, dim3(PNT), 0, s, p->nv, p->nc,
-                 nullptr, 0, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis,
-                 (double *)Hmu[ib], ldmu[ib], sd);
-    else
-      BSE_LAUNCH("k_project_seed", (k_project<float, true>), g, dim3(PNT), 0, s, p->nv, p->nc,
-                 nullptr, 0, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis,
-                 (float *)Hmu[ib], ldmu[ib], sd);
+    const bool one = 9 * nb <= PNT;
+#define BSE_PROJS(T, NCT)                                                                     \
+  BSE_LAUNCH("k_project_seed", (k_project<T, true, NCT>), g, dim3(PNT), 0, s, p->nv, p->nc,   \
+             nullptr, 0, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis,       \
+             (T *)Hmu[ib], ldmu[ib], sd)
+    if (sp.prec == BSE_FP64) {
+      if (one) BSE_PROJS(double, 1); else BSE_PROJS(double, 2);
+    } else {
+      if (one) BSE_PROJS(float, 1); else BSE_PROJS(float, 2);
+    }
+#undef BSE_PROJS
     BSE_HIP_CHECK(hipGetLastError());
   }
   return BSE_OK;
