@@ -461,11 +461,15 @@ def test_end_to_end_cfg1(lib, precname, nrefine, tol, vector):
     say("  eps2 rel err", e2err)
     assert err < tol
     if prec == lib.BF16X3 and not vector:
-        # measured 1.6e-4: the split-BF16 build keeps ~16 bits of each operand,
-        # so the 232 eV exchange of the A1g block moves its unrefined poles by
-        # ~1e-5 eV against eta = 0.05 eV; the energies above meet their target
-        pytest.skip("split-BF16 build, scalar dipoles (A1g, |H_mu| = 232 eV): eps2 misses "
-                    "the 1e-4 bar (1.6e-4 measured); lowest-100 energies checked")
+        # Split BF16 keeps ~17 bits of each operand of the direct term, so the
+        # poles of this exchange-dominated block (A1g, |H_mu| = 232 eV) sit
+        # ~2e-5 eV off the oracle's (the energy target above is 1e-4 eV); a
+        # Lorentzian of width eta moves by at most 0.65 dE / eta of its peak,
+        # i.e. <= 2.6e-4 here.  Measured 1.5e-4 (1.6e-4 with the exchange in
+        # split BF16, 1.5e-4 with it in FP32): above the 1e-4 target.
+        assert e2err <= 2.6e-4
+        pytest.xfail("split-BF16 build, scalar dipoles (A1g): eps2 1.5e-4 misses the 1e-4 "
+                     "target; lowest-100 energies and the 0.65 dE/eta bound checked")
     assert e2err <= 1e-4
     _match_poles(res["pole"], res["osc"], r["cl_e"], r["cl_w"], 100 * tol,
                  1e-6 if prec == lib.FP64 else 1e-3)
