@@ -304,6 +304,27 @@ int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, c
                        double *osc, void *ws, size_t ws_bytes, bse_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Two-stage reduction of large blocks (the same outputs as bse_block_eigh).
+ * Solves with nrefine = 0 and n >= the switch point reduce H_mu in two
+ * stages that both leave e_1 fixed: first to a lower band of half-width 32
+ * (panels of 32 columns: a QR of the panel below the band with one reduction
+ * per column, then the two-sided update A22 - V W^dag - W V^dag of the
+ * trailing block with X = A22 V T formed on the matrix cores), then from the
+ * band to the real tridiagonal by chasing each column's bulge down the band
+ * (one task of one wave per step; launch t runs every step k of sweep i with
+ * 2 i + k = t).  The tridiagonal step is the one above.  FP32 storage keeps
+ * the working copy in FP32 (its products summed in FP64 every 128 terms);
+ * the panel, the band and the chase are FP64.  The workspace grows by about
+ * 6.5 KB per row of the block (66 MB at n = 10080).
+ * bse_block_eigh_set_two_stage(nmin) sets the switch point to nmin (>= 2;
+ * default 4096) and returns the previous one; nmin < 0 only returns it.  It
+ * is process-wide: query bse_block_eigh_ws after setting it, and do not
+ * change it while solves sized under the old value are pending.  The
+ * allocation-free and batched solvers keep the one-stage reduction.
+ * ------------------------------------------------------------------------- */
+int64_t bse_block_eigh_set_two_stage(int64_t nmin);
+
+/* ---------------------------------------------------------------------------
  * bse_block_eigh_status: what the last solve on a workspace could not do.
  * Synchronises `stream` and reads four counters that every solve rewrites:
  *   h_status[0]  eigenvalues among the lowest min(nrefine, n) left unrefined
@@ -333,7 +354,8 @@ int32_t bse_block_eigh_status(int64_t n, int32_t prec, int32_t nrefine, const vo
  * per GPU, held from the first call on that GPU until the process ends.  No
  * hipMalloc, hipFree or allocating library call is made.  That fits, for
  * example, FP32 blocks up to n = 3900 without refinement and up to n = 1500
- * with nrefine = 100 (the limit is bse_block_eigh_ws(n, ...) <= the maximum).
+ * with nrefine = 100 (the limit is the one-stage bse_block_eigh_ws(n, ...) <=
+the maximum: this solver always takes the one-stage reduction).
  * No part of the array needs to start at zero: every word a kernel reads was
  * written earlier in the same call.
  * The first call on a device looks up the array's device address (the

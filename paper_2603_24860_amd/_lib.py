@@ -86,6 +86,7 @@ def _load():
                                      P(vp), P(i64), P(vp), vp]),
         "bse_dipole_weights": (i32, [P(Problem), vp, i32, P(Block), vp, vp, vp]),
         "bse_block_eigh_ws": (ctypes.c_size_t, [i64, i32, i32, i32]),
+        "bse_block_eigh_set_two_stage": (i64, [i64]),
         "bse_block_eigh": (i32, [i64, vp, i64, i32, vp, i32, i32, vp, vp, vp, vp,
                                  ctypes.c_size_t, vp]),
         "bse_block_eigh_status": (i32, [i64, i32, i32, vp, P(i32), vp]),

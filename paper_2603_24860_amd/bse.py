@@ -192,6 +192,11 @@ def bse_block_eigh_ws(n, h_fp64, prec, nrefine=0):
     return lib.bse_block_eigh_ws(n, h_fp64, prec, nrefine)
 
 
+def bse_block_eigh_set_two_stage(nmin):
+    """Switch point of the two-stage reduction (nmin < 0: query); returns the previous."""
+    return lib.bse_block_eigh_set_two_stage(nmin)
+
+
 def bse_block_eigh(Hmu, Bmu, prec, omega, pole, osc, ws, nrefine=0, stream=None):
     n = Hmu.shape[0]
     h_fp64 = 1 if Hmu.dtype.itemsize == 16 else 0

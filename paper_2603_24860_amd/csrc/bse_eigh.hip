@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <type_traits>
@@ -1189,6 +1190,8 @@ __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
   }
 }
 
+#include "eigh_band.h"
+
 // ---------------------------------------------------------------------------
 // tridiagonal eigenvalues (multisection) and cluster weights
 // ---------------------------------------------------------------------------
@@ -2278,6 +2281,74 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
 }
 
 // ---------------------------------------------------------------------------
+// single block, two-stage reduction (no refinement)
+// ---------------------------------------------------------------------------
+template <typename TH, typename TA>
+int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
+                    double *pole, double *osc, void *ws, hipStream_t s) {
+  Desc D;
+  ws_layout(n, sizeof(TA) == 8, &D, (char *)ws, 0, true);
+  D.H = Hmu;
+  D.ld = ld;
+  D.B = (const double2 *)Bmu;
+  D.omega = omega;
+  D.pole = pole;
+  D.osc = osc;
+  auto grid = [&](int kind) { return dim3((unsigned)kind_wgs<TA>(kind, n, 0, 4)); };
+  BSE_LAUNCH("k_copy_in", (k_copy_in<TH, TA, 4>), grid(K_COPY), dim3(ENT), 0, s, D, 0);
+  // ---- initial reflection: B -> beta0 e_1, A <- Q0^dag A Q0 ----
+  BSE_LAUNCH("k_load_b", (k_load_b<TH, TA, 4>), grid(K_LOADB), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_hemv0", (k_hemv0<TH, TA, 4>), grid(K_HEMV0), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_w0", (k_w0<TH, TA, 4>), grid(K_W0), dim3(ENT), 0, s, D, 0);
+  BSE_LAUNCH("k_rank2", (k_rank2<TH, TA, 4>), grid(K_RANK2), dim3(ENT), 0, s, D, 0);
+  BSE_HIP_CHECK(hipGetLastError());
+  // ---- stage 1: full -> band, one panel of SBW columns at a time ----
+  int64_t j0 = 0;
+  for (; j0 + SBW < n; j0 += SBW) {
+    const int64_t p0 = j0 + SBW, m = n - p0;
+    const int nw = (int)g_sb_nw(m), nref = (int)std::min<int64_t>(SBW, m);
+    const dim3 rows((unsigned)cdiv(m, 64));  // k_sb_u, k_sb_w: 64 panel rows per workgroup
+    BSE_LAUNCH("k_sb_pstart", k_sb_pstart<TA>, dim3(nw), dim3(ENT), 0, s, D, j0);
+    for (int c = 0; c < nref; ++c)
+      BSE_LAUNCH("k_sb_pcol", k_sb_pcol, dim3(nw), dim3(PCT), 0, s, D, j0, c, nw);
+    BSE_LAUNCH("k_sb_tmat", k_sb_tmat<TA>, dim3(1), dim3(ENT), 0, s, D, j0, nw);
+    BSE_LAUNCH("k_sb_u", k_sb_u<TA>, rows, dim3(ENT), 0, s, D, j0);
+    BSE_LAUNCH("k_sb_hemm", k_sb_hemm<TA>, dim3((unsigned)g_sb_hemm_wgs(m)), dim3(ENT), 0, s, D,
+               j0);
+    BSE_LAUNCH("k_sb_xred", k_sb_xred, dim3(nw), dim3(ENT), 0, s, D, j0);
+    BSE_LAUNCH("k_sb_z", k_sb_z, dim3(1), dim3(ENT), 0, s, D, nw);
+    BSE_LAUNCH("k_sb_w", k_sb_w, rows, dim3(ENT), 0, s, D, j0);
+    BSE_LAUNCH("k_her2k", k_sb_her2k<TA>, dim3((unsigned)sb_her2k_wgs<TA>(n, p0)), dim3(ENT), 0,
+               s, D, p0);
+    BSE_HIP_CHECK(hipGetLastError());
+  }
+  BSE_LAUNCH("k_sb_bandtail", k_sb_bandtail<TA>, dim3(1), dim3(ENT), 0, s, D, j0);
+  // ---- stage 2: band -> tridiagonal, launch t runs the tasks 2 i + k = t ----
+  for (int64_t t = 0; t <= g_bc_tmax(n); ++t) {
+    const int64_t lo = g_bc_ilo(n, t), hi = g_bc_ihi(n, t);
+    if (lo > hi) continue;
+    BSE_LAUNCH("k_sb_chase", k_sb_chase, dim3((unsigned)(hi - lo + 1)), dim3(BCT), 0, s, D, t,
+               hi);
+  }
+  BSE_LAUNCH("k_sb_diag", k_sb_diag, dim3((unsigned)cdiv(n, ENT)), dim3(ENT), 0, s, D);
+  BSE_HIP_CHECK(hipGetLastError());
+  // ---- tridiagonal eigenvalues and optical weights ----
+  BSE_LAUNCH("k_tri_prep", k_tri_prep<TA>, dim3(1), dim3(RNT), 0, s, D,
+             ctol_rel(n, sizeof(TA) == 8));
+  BSE_LAUNCH("k_bisect_grid", (k_bisect_grid<TH, TA, 4>), dim3(NGRID / ENT), dim3(ENT), 0, s, D,
+             0);
+  BSE_LAUNCH("k_bisect", (k_bisect<TH, TA, 4>), grid(K_BISECT), dim3(ENT), 0, s, D, 1);
+  BSE_LAUNCH("k_weights", (k_weights<TH, TA, 4>), grid(K_WEIGHTS), dim3(ENT), 0, s, D, 0);
+  BSE_HIP_CHECK(hipGetLastError());
+  return BSE_OK;
+}
+
+// Smallest block that takes the two-stage reduction (solves without
+// refinement only); process-wide, set by bse_block_eigh_set_two_stage.
+std::atomic<int64_t> g_two_stage_min{4096};
+inline bool takes_two_stage(int64_t n, int64_t K) { return K == 0 && n >= g_two_stage_min.load(); }
+
+// ---------------------------------------------------------------------------
 // batched: every active block advances one step per launch
 // ---------------------------------------------------------------------------
 struct BatchLaunch {
@@ -2422,7 +2493,13 @@ using namespace bse;
 extern "C" size_t bse_block_eigh_ws(int64_t n, int32_t h_fp64, int32_t prec, int32_t nrefine) {
   (void)h_fp64;
   if (n < 1 || nrefine < 0 || nrefine > KMAX) return 0;
-  return ws_layout(n, prec == BSE_FP64, nullptr, nullptr, std::min<int64_t>(nrefine, n));
+  const int64_t K = std::min<int64_t>(nrefine, n);
+  return ws_layout(n, prec == BSE_FP64, nullptr, nullptr, K, takes_two_stage(n, K));
+}
+
+extern "C" int64_t bse_block_eigh_set_two_stage(int64_t nmin) {
+  if (nmin < 0) return g_two_stage_min.load();
+  return g_two_stage_min.exchange(std::max<int64_t>(nmin, 2));
 }
 
 extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64,
@@ -2437,10 +2514,18 @@ extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_
   if (nrefine < 0 || nrefine > KMAX)
     return fail(BSE_EINVAL, "nrefine = %d outside 0 .. %d", nrefine, KMAX);
   const int64_t K = std::min<int64_t>(nrefine, n);
-  const size_t need = ws_layout(n, prec == BSE_FP64, nullptr, nullptr, K);
+  const bool two = takes_two_stage(n, K);
+  const size_t need = ws_layout(n, prec == BSE_FP64, nullptr, nullptr, K, two);
   if (!ws || ws_bytes < need)
     return fail(BSE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t s = (hipStream_t)stream;
+  if (two) {
+    if (prec == BSE_FP64)
+      return h_fp64 ? eigh_run_2s<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
+                    : eigh_run_2s<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
+    return h_fp64 ? eigh_run_2s<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
+                  : eigh_run_2s<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
+  }
   if (prec == BSE_FP64)
     return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
                   : eigh_run<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);

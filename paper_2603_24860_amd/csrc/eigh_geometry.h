@@ -92,7 +92,35 @@ struct Desc {
   double *scr;               // [K][6 CMAX n] inverse-iteration scratch
   double *wref;              // [K] refined eigenvalues
   double2 *Tm;               // [cdiv(n - 1, NBK)][NBK][NBK] block-reflector factors T
+  // two-stage reduction (full -> band of width SBW -> tridiagonal); null
+  // unless the block takes that path
+  double2 *pb;               // [n][SBW] current panel, FP64 (reflectors below its diagonal)
+  double2 *grec;             // [2][nw][SBW] partial Gram rows of the next panel column
+  double2 *srec;             // [nw][SBW][SBW] partial columns of V^dag V
+  double2 *sbt;              // [SBW][SBW] block-reflector factor T of the panel
+  double2 *sbz;              // [SBW][SBW] Z = T^dag V^dag X
+  double2 *sbsc;             // [2][SBW] tau of each panel column, (beta, 0) of each
+  void *u;                   // [SBW][ldv] U = V T in the storage type of A
+  double2 *xp;               // [SBNS][SBW][ldv] split-K partial sums of X = A22 U
+  double2 *yrec;             // [nw][SBW][SBW] partial sums of V^dag X
+  double2 *band;             // [n][LDB] lower band of the reduced matrix, column by column
+  double2 *rfl;              // [n][SBW] latest reflector of each bulge-chasing sweep
+  double2 *rtau;             // [n] its tau
+  double2 *sink;             // [SINK] target of the stores of masked lanes (never read)
 };
+
+// Two-stage reduction of large single blocks.  Stage 1 reduces A to a lower
+// band of half-width SBW (panels of SBW columns: a QR of the panel below the
+// band, then the two-sided update of the trailing block, X = A22 V T on MFMA
+// and the rank-2 SBW update); stage 2 chases the band down to tridiagonal
+// form, one sweep per column, as tasks of one wave each.
+constexpr int SBW = 32;      // band half-width = panel width
+constexpr int LDB = 2 * SBW; // band pitch: the band and the fill of one bulge
+constexpr int SBR = 256;     // panel rows per workgroup of the panel kernels
+constexpr int SBNS = 8;      // K splits of the panel product X = A22 U
+constexpr int SBHM = 64;     // rows of X per workgroup of that product
+static_assert(SBW == NBK, "the stage-1 update reuses the NBK-wide trailing update");
+constexpr int SINK = 256;    // entries of the store sink (lanes of one workgroup)
 
 // ---------------------------------------------------------------------------
 // launch geometry, shared by the host (single block) and the batched kernels
@@ -170,6 +198,29 @@ __host__ __device__ __forceinline__ int64_t g_yslots(int64_t n) {
   return std::max<int64_t>(s, cdiv(n + 63, 256));
 }
 
+// two-stage geometry: workgroups of the panel kernels over m panel rows
+__host__ __device__ __forceinline__ int64_t g_sb_nw(int64_t m) { return m < 1 ? 1 : cdiv(m, SBR); }
+// complex K of one split of the panel product (a multiple of 16)
+__host__ __device__ __forceinline__ int64_t g_sb_kc(int64_t m) {
+  return std::max<int64_t>(16, cdiv(cdiv(m, SBNS), 16) * 16);
+}
+__host__ __device__ __forceinline__ int64_t g_sb_hemm_wgs(int64_t m) {
+  return cdiv(m, SBHM) * SBNS;
+}
+// bulge chasing: task (i, k) is step k of sweep i (i = 0 .. n - 2,
+// k = 0 .. (n - 2 - i) / SBW); launch t runs the tasks with 2 i + k = t
+__host__ __device__ __forceinline__ int64_t g_bc_kmax(int64_t n, int64_t i) {
+  return (n - 2 - i) / SBW;
+}
+__host__ __device__ __forceinline__ int64_t g_bc_ihi(int64_t n, int64_t t) {
+  return std::min<int64_t>(t / 2, n - 2);
+}
+__host__ __device__ __forceinline__ int64_t g_bc_ilo(int64_t n, int64_t t) {
+  const int64_t num = SBW * t - n + 2, den = 2 * SBW - 1;
+  return num <= 0 ? 0 : cdiv(num, den);
+}
+__host__ __device__ __forceinline__ int64_t g_bc_tmax(int64_t n) { return n < 2 ? -1 : 2 * (n - 2); }
+
 // relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
 __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
   const double eps_w = a_fp64 ? 2.2e-16 : 1.2e-7;
@@ -179,7 +230,8 @@ __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Lays out one block's workspace at base (nullptr: size only).
-inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0) {
+inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K = 0,
+                        bool two_stage = false) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char *p = base ? base + off : nullptr;
@@ -227,6 +279,22 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     t.scr = (double *)take(size_t(K) * (6 * CMAX) * n * 8);
     t.wref = (double *)take(size_t(K) * 8);
     t.Tm = (double2 *)take(size_t(std::max<int64_t>(cdiv(n - 1, NBK), 1)) * NBK * NBK * 16);
+  }
+  if (two_stage) {  // appended, so the regions above keep their offsets
+    const size_t nw = size_t(g_sb_nw(n));
+    t.pb = (double2 *)take(size_t(n) * SBW * 16);
+    t.grec = (double2 *)take(2 * nw * SBW * 16);
+    t.srec = (double2 *)take(nw * SBW * SBW * 16);
+    t.sbt = (double2 *)take(SBW * SBW * 16);
+    t.sbz = (double2 *)take(SBW * SBW * 16);
+    t.sbsc = (double2 *)take(2 * SBW * 16);
+    t.u = take(size_t(SBW) * ldv * (a_fp64 ? 16 : 8));
+    t.xp = (double2 *)take(size_t(SBNS) * SBW * ldv * 16);
+    t.yrec = (double2 *)take(nw * SBW * SBW * 16);
+    t.band = (double2 *)take(size_t(n) * LDB * 16);
+    t.rfl = (double2 *)take(size_t(n) * SBW * 16);
+    t.rtau = (double2 *)take(size_t(n) * 16);
+    t.sink = (double2 *)take(SINK * 16);
   }
   if (w) *w = t;
   return off;

@@ -13,14 +13,17 @@
 //   k_colB      ys[0..nbt)[rows] (tile forms), parta[0..npa), records of its
 //               workgroup in the other buffer, W[ir][rows], col[rows]
 //   k_her2k     the A entries of every tile, V and W columns 0..nbk
-//   k_tail, the tridiagonal and refinement kernels: their buffers whole.
+//   k_tail, the tridiagonal and refinement kernels: their buffers whole;
+//   two-stage reduction: the panel rows, records, band columns and X splits
+//   of every stage-1 launch, and the band, reflector and tridiagonal entries
+//   of every bulge-chasing task.
 // Every index is asserted to lie inside its region of the layout, and the
 // byte is touched, so an index past the region or past the workspace stops
 // the check (assertion or AddressSanitizer report).  Regions must not overlap.
 //
 //   g++ -std=c++17 -O1 -fsanitize=address,undefined -I paper_2603_24860_amd/csrc \
 //       tests/eigh_layout_check.cpp -o eigh_layout_check
-//   ./eigh_layout_check n a_fp64 K [n a_fp64 K ...]
+//   ./eigh_layout_check n a_fp64 K [n a_fp64 K ...]     (K = -1: two-stage reduction)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -103,12 +106,186 @@ void tri_of(int64_t wg, int64_t &bi, int64_t &bj) {
   bj = wg - bi * (bi + 1) / 2;
 }
 
+// the two-stage reduction (stage 1 panels, bulge chasing, band diagonal);
+// the copy-in, the initial reflection and the tridiagonal step are the
+// one-stage ones and are replayed by the caller
+int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
+  const size_t elu = a64 ? 16 : 8;
+  const int64_t nwmax = g_sb_nw(n);
+  C.add("pb", D.pb, 16, n * SBW);
+  C.add("grec", D.grec, 16, 2 * nwmax * SBW);
+  C.add("srec", D.srec, 16, nwmax * SBW * SBW);
+  C.add("sbt", D.sbt, 16, SBW * SBW);
+  C.add("sbz", D.sbz, 16, SBW * SBW);
+  C.add("sbsc", D.sbsc, 16, 2 * SBW);
+  C.add("u", D.u, elu, SBW * D.ldv);
+  C.add("xp", D.xp, 16, int64_t(SBNS) * SBW * D.ldv);
+  C.add("yrec", D.yrec, 16, nwmax * SBW * SBW);
+  C.add("band", D.band, 16, n * LDB);
+  C.add("rfl", D.rfl, 16, n * SBW);
+  C.add("rtau", D.rtau, 16, n);
+  C.add("sink", D.sink, 16, SINK);
+  C.layout_ok();
+  int64_t j0 = 0;
+  for (; j0 + SBW < n; j0 += SBW) {
+    const int64_t p0 = j0 + SBW, m = n - p0, nw = g_sb_nw(m);
+    const int nref = (int)std::min<int64_t>(SBW, m);
+    if (n - j0 < SBW + 1) return 1;  // a factored panel is always SBW wide
+    // k_sb_pstart / k_sb_pcol: rows wg SBR .. + SBR (clamped to m - 1), all SBW columns
+    for (int64_t wg = 0; wg < nw; ++wg) {
+      const int64_t r0 = wg * SBR, r1 = std::min<int64_t>(r0 + SBR, m) - 1;
+      if (r0 < m) {
+        C.at("A", (p0 + r0) * D.lda + j0, "k_sb_pstart");
+        C.at("A", (p0 + r1) * D.lda + j0 + SBW - 1, "k_sb_pstart");
+        C.range("pb", r0 * SBW, r1 * SBW + SBW, "k_sb_pstart/pcol");
+      } else {
+        C.range("pb", (m - 1) * SBW, m * SBW, "k_sb_pcol clamped");
+      }
+      C.range("grec", wg * SBW, wg * SBW + SBW, "k_sb_pstart");
+      for (int c = 0; c < nref; ++c) {
+        C.range("grec", ((c + 1) & 1) * nw * SBW + wg * SBW, ((c + 1) & 1) * nw * SBW + wg * SBW + SBW,
+                "k_sb_pcol out");
+        C.range("srec", (wg * SBW + c) * SBW, (wg * SBW + c) * SBW + SBW, "k_sb_pcol srec");
+      }
+    }
+    for (int c = 0; c < nref; ++c) {
+      C.range("grec", (c & 1) * nw * SBW, (c & 1) * nw * SBW + nw * SBW, "k_sb_pcol in");
+      C.range("pb", int64_t(c) * SBW, int64_t(c) * SBW + SBW, "k_sb_pcol top");
+      C.at("sbsc", c, "k_sb_pcol");
+      C.at("sbsc", SBW + c, "k_sb_pcol");
+    }
+    // k_sb_tmat
+    C.range("srec", 0, (nw - 1) * SBW * SBW + SBW * SBW, "k_sb_tmat");
+    C.range("sbt", 0, SBW * SBW, "k_sb_tmat");
+    for (int c = 0; c < SBW; ++c)
+      for (int d = 0; d < LDB; ++d) {
+        const int64_t j = j0 + c, row = j + d;
+        C.at("band", j * LDB + d, "k_sb_tmat band");
+        if (d <= SBW && row < n) {
+          if (row < p0) C.at("A", row * D.lda + j, "k_sb_tmat A");
+          else if (row - p0 < nref) C.at("pb", (row - p0) * SBW + c, "k_sb_tmat R");
+        }
+      }
+    // k_sb_u, k_sb_xred, k_sb_w: rows 0 .. m of V, W, U, the splits of X
+    for (int l = 0; l < SBW; ++l) {
+      C.range("V", int64_t(l) * D.ldv + p0, int64_t(l) * D.ldv + n, "k_sb_u V");
+      C.range("W", int64_t(l) * D.ldv + p0, int64_t(l) * D.ldv + n, "k_sb_xred/w W");
+      C.range("u", int64_t(l) * D.ldv + p0, int64_t(l) * D.ldv + n, "k_sb_u U");
+      for (int sp = 0; sp < SBNS; ++sp)
+        C.range("xp", (int64_t(sp) * SBW + l) * D.ldv + p0, (int64_t(sp) * SBW + l) * D.ldv + n,
+                "k_sb_hemm/xred xp");
+    }
+    C.range("pb", 0, m * SBW, "k_sb_u pb");
+    C.range("yrec", 0, nw * SBW * SBW, "k_sb_xred/z");
+    C.range("sbz", 0, SBW * SBW, "k_sb_z/w");
+    // k_sb_hemm: A rows p0 + min(r0 + ar, m - 1), columns p0 + [k0, k1)
+    const int64_t kc = g_sb_kc(m);
+    for (int64_t wg = 0; wg < g_sb_hemm_wgs(m); ++wg) {
+      const int64_t rb = wg / SBNS, sp = wg % SBNS, r0 = rb * SBHM;
+      const int64_t k0 = sp * kc, k1 = std::min<int64_t>(m, k0 + kc);
+      const int64_t ra = std::min<int64_t>(r0, m - 1), rz = std::min<int64_t>(r0 + SBHM - 1, m - 1);
+      if (k0 < k1) {
+        C.at("A", (p0 + ra) * D.lda + p0 + k0, "k_sb_hemm A");
+        C.at("A", (p0 + rz) * D.lda + p0 + k1 - 1, "k_sb_hemm A");
+        C.range("u", p0 + k0, p0 + k1, "k_sb_hemm U");
+        C.range("u", int64_t(SBW - 1) * D.ldv + p0 + k0, int64_t(SBW - 1) * D.ldv + p0 + k1,
+                "k_sb_hemm U");
+      }
+      for (int64_t a = r0; a < std::min<int64_t>(r0 + SBHM, m); a += SBHM - 1)
+        for (int l = 0; l < SBW; l += SBW - 1)
+          C.at("xp", (sp * SBW + l) * D.ldv + p0 + a, "k_sb_hemm out");
+    }
+    // k_her2k from p0, tile shape 0
+    {
+      const int BN = HerTile<float, 0>::BN, BM = HerTile<float, 0>::BM;
+      const int64_t t = cdiv(n - p0, int64_t(BN));
+      const int64_t gh = her_tri(t, BN) ? t * (t + 1) / 2 : t * t;
+      for (int64_t wg = 0; wg < gh; ++wg) {
+        int64_t bx, by;
+        if (!her_tri(t, BN)) {
+          bx = wg % t;
+          by = wg / t;
+        } else {
+          tri_of(wg, by, bx);
+        }
+        const int64_t a0 = p0 + by * (BM / 2), b0 = p0 + bx * BN;
+        if (a0 >= n || b0 >= n) continue;
+        const int64_t a1 = std::min<int64_t>(a0 + BM / 2, n) - 1;
+        const int64_t b1 = std::min<int64_t>(b0 + BN, n) - 1;
+        C.at("A", a0 * D.lda + b0, "k_sb_her2k");
+        C.at("A", a1 * D.lda + b1, "k_sb_her2k");
+        C.at("A", b1 * D.lda + a1, "k_sb_her2k mirror");
+      }
+    }
+  }
+  // k_sb_bandtail: columns j0 .. n
+  for (int64_t j = j0; j < n; ++j)
+    for (int d = 0; d < LDB; ++d) {
+      C.at("band", j * LDB + d, "k_sb_bandtail");
+      if (d <= SBW && j + d < n) C.at("A", (j + d) * D.lda + j, "k_sb_bandtail A");
+    }
+  // k_sb_chase: every task of every launch
+  int64_t tasks = 0;
+  for (int64_t t = 0; t <= g_bc_tmax(n); ++t) {
+    const int64_t lo = g_bc_ilo(n, t), hi = g_bc_ihi(n, t);
+    for (int64_t i = lo; i <= hi; ++i) {
+      const int64_t k = t - 2 * i, rk = i + 1 + k * SBW;
+      if (k < 0 || k > g_bc_kmax(n, i) || rk >= n) {
+        std::fprintf(stderr, "task (%lld, %lld) of launch %lld\n", (long long)i, (long long)k,
+                     (long long)t);
+        return 1;
+      }
+      const int L = (int)std::min<int64_t>(SBW, n - rk);
+      if (k > 0) {
+        const int64_t rp = rk - SBW;
+        for (int q = 0; q < SBW; q += SBW - 1)
+          for (int p = 0; p < L; p += std::max(1, L - 1)) {
+            const int64_t d = SBW + p - q;
+            if (d < 1 || d >= LDB) return 1;
+            C.at("band", (rp + q) * LDB + d, "k_sb_chase O");
+          }
+        C.at("rtau", i, "k_sb_chase");
+      } else {
+        C.range("band", i * LDB + 1, i * LDB + 1 + L, "k_sb_chase column");
+        C.at("e", i, "k_sb_chase");
+      }
+      // loads issued for every lane before masking: O over all 32 rows (or
+      // column i to offset SBW), D clamped to the last column
+      if (k > 0) {
+        const int64_t rp = rk - SBW;
+        C.at("band", rp * LDB + SBW + SBW - 1, "k_sb_chase O load");
+        C.at("band", (rp + SBW - 1) * LDB + 1, "k_sb_chase O load");
+      } else {
+        C.at("band", i * LDB + SBW, "k_sb_chase column load");
+      }
+      C.at("band", std::min<int64_t>(rk + SBW - 1, n - 1) * LDB + SBW - 1, "k_sb_chase D load");
+      C.range("rfl", i * SBW, i * SBW + SBW, "k_sb_chase");
+      C.at("band", rk * LDB, "k_sb_chase D");
+      C.at("band", (rk + L - 1) * LDB, "k_sb_chase D");
+      C.at("band", rk * LDB + L - 1, "k_sb_chase D");
+      ++tasks;
+    }
+  }
+  int64_t want = 0;
+  for (int64_t i = 0; i + 1 < n; ++i) want += g_bc_kmax(n, i) + 1;
+  if (tasks != want) {
+    std::fprintf(stderr, "%lld chase tasks launched, %lld in the sweeps\n", (long long)tasks,
+                 (long long)want);
+    return 1;
+  }
+  C.range("band", 0, n * LDB, "k_sb_diag");
+  C.range("sink", 0, SINK, "masked stores (thread index modulo SINK)");
+  return 0;
+}
+
 int run(int64_t n, bool a64, int64_t K) {
   const size_t el = a64 ? 16 : 8;
-  const size_t need = ws_layout(n, a64, nullptr, nullptr, K);
+  const bool two = K < 0;  // K = -1: the two-stage reduction (no refinement)
+  if (two) K = 0;
+  const size_t need = ws_layout(n, a64, nullptr, nullptr, K, two);
   std::vector<char> buf(need);
   Desc D{};
-  ws_layout(n, a64, &D, buf.data(), K);
+  ws_layout(n, a64, &D, buf.data(), K, two);
   Check C;
   C.base = buf.data();
   C.bytes = need;
@@ -162,9 +339,15 @@ int run(int64_t n, bool a64, int64_t K) {
   C.range("wraw", 0, n, "k_w0");
   C.at("tau", 0, "k_hemv0");
   C.at("beta0", 0, "k_hemv0");
+  if (two) {
+    if (run_two_stage(C, D, n, a64)) {
+      std::fprintf(stderr, "two-stage launch sequence out of bounds\n");
+      return 1;
+    }
+  }
   // ---- blocked columns ----
   int cur = 0;
-  for (int64_t j0 = 0; j0 < n; j0 += NBK) {
+  for (int64_t j0 = 0; j0 < (two ? 0 : n); j0 += NBK) {
     if (j0 == g_tail0(n)) {  // k_tail: rows and columns j0..n of A, the tridiagonal
       C.range("A", j0 * D.lda + j0, (n - 1) * D.lda + n, "k_tail");
       C.range("d", j0, n, "k_tail");
@@ -305,9 +488,9 @@ int run(int64_t n, bool a64, int64_t K) {
     C.range("rqp", 0, K * cdiv(n, 4), "k_hx_part");
     C.range("wref", 0, K, "k_rq_fin");
   }
-  std::printf("n = %lld %s K = %lld: workspace %zu B, %zu regions, %lld accesses in bounds\n",
-              (long long)n, a64 ? "FP64" : "FP32", (long long)K, need, C.regs.size(),
-              (long long)C.touches);
+  std::printf("n = %lld %s K = %lld%s: workspace %zu B, %zu regions, %lld accesses in bounds\n",
+              (long long)n, a64 ? "FP64" : "FP32", (long long)K, two ? " two-stage" : "", need,
+              C.regs.size(), (long long)C.touches);
   return 0;
 }
 

@@ -1,0 +1,192 @@
+"""GPU parity of the two-stage block eigensolver (full -> band -> tridiagonal).
+
+Dense Hermitian matrices of known spectrum (A = Q diag(lam) Q^dag, Q unitary,
+eigenvalues with multiplicity 1 or 3 like the T1u blocks) and known optical
+weights |Q^dag b|^2 are solved with the two-stage path forced on (the switch
+point lowered to the test's size) and held to the same bars as the
+one-stage solver: eigenvalues within 1e-11 |lam| (FP64 working storage) or
+the FP32 storage bar, cumulative oscillator strength within 1e-6 and every
+weighted pole within 1e-9 of the exact one (FP64).  The sizes run from the
+degenerate cases (n = 2, 3: no panel, a band already tridiagonal) through a
+single ragged panel (33, 34, 65), several panels with a partial last one
+(100, 162, 300, 600) to blocks with hundreds of panels and a bulge chase of
+thousands of launches (4500, 8400).  Workspaces start as NaN bytes, so a
+read of memory that no kernel wrote shows in the result.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bse as OB
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2603_24860_amd import bse as B
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return B
+
+
+@pytest.fixture
+def two_stage_from(lib):
+    """Sets the switch point for one test and restores it afterwards."""
+    old = lib.bse_block_eigh_set_two_stage(-1)
+    yield lambda nmin: lib.bse_block_eigh_set_two_stage(nmin)
+    lib.bse_block_eigh_set_two_stage(old)
+
+
+def _random_hermitian(n, seed, mult=1, spread=10.0):
+    rng = np.random.default_rng(seed)
+    nd = (n + mult - 1) // mult
+    lam = np.repeat(np.sort(rng.uniform(-spread, spread, nd)), mult)[:n]
+    X = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    Q, _ = np.linalg.qr(X)
+    A = (Q * lam) @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    return A, b, lam, Q.conj().T @ b
+
+
+def _householder_hermitian(n, seed, mult=1, spread=10.0, nref=3):
+    """A = Q diag(lam) Q^dag with Q a product of nref random reflectors (a
+    dense matrix of known spectrum built in O(n^2)); returns Q^dag b too."""
+    rng = np.random.default_rng(seed)
+    nd = (n + mult - 1) // mult
+    lam = np.repeat(np.sort(rng.uniform(-spread, spread, nd)), mult)[:n]
+    A = np.diag(lam).astype(np.complex128)
+    us = []
+    for _ in range(nref):
+        u = rng.normal(size=n) + 1j * rng.normal(size=n)
+        u /= np.linalg.norm(u)
+        us.append(u)
+        Au = A @ u
+        uA = u.conj() @ A
+        A = A - 2 * np.outer(u, uA) - 2 * np.outer(Au, u.conj()) + 4 * (u.conj() @ Au) * np.outer(u, u.conj())
+    A = 0.5 * (A + A.conj().T)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    qb = b.copy()
+    for u in reversed(us):
+        qb = qb - 2 * u * (u.conj() @ qb)
+    return A, b, lam, qb
+
+
+def _solve(lib, A, b, prec, h_dtype):
+    n = A.shape[0]
+    Hmu = torch.as_tensor(A, dtype=h_dtype, device="cuda")
+    Bmu = torch.as_tensor(b, dtype=torch.complex128, device="cuda")
+    h64 = 1 if h_dtype == torch.complex128 else 0
+    ws = torch.full((lib.bse_block_eigh_ws(n, h64, prec),), 255, dtype=torch.uint8, device="cuda")
+    om = torch.empty(n, dtype=torch.float64, device="cuda")
+    po, os_ = torch.empty_like(om), torch.empty_like(om)
+    lib.bse_block_eigh(Hmu, Bmu, prec, om, po, os_, ws)
+    torch.cuda.synchronize()
+    return om.cpu().numpy(), po.cpu().numpy(), os_.cpu().numpy()
+
+
+def _check_poles(lam, qb, pole, osc, tol=1e-9, wtol=1e-6):
+    """Every weighted cluster of the exact spectrum has a pole within tol, and
+    the cumulative strength sum_{pole < x} osc matches at every x more than
+    tol away from all poles."""
+    w = np.abs(qb) ** 2
+    st = OB.clusters(lam, 1e-9)
+    ce = np.array([lam[st[i]] for i in range(len(st) - 1)])
+    cw = np.array([w[st[i]:st[i + 1]].sum() for i in range(len(st) - 1)])
+    tot = cw.sum()
+    keep = osc > 1e-14 * tot
+    p, o = pole[keep], osc[keep]
+    for e, wt in zip(ce, cw):
+        if wt > 1e-8 * tot:
+            assert np.abs(p - e).min() < tol, (e, np.abs(p - e).min())
+    allp = np.sort(np.concatenate([p, ce]))
+    mids = 0.5 * (allp[1:] + allp[:-1])
+    xs = mids[(allp[1:] - allp[:-1]) > 2 * tol]
+    for x in xs:
+        assert abs(o[p < x].sum() - cw[ce < x].sum()) <= wtol * tot, x
+    assert abs(osc.sum() - tot) <= 1e-8 * tot
+
+
+@pytest.mark.parametrize("n,mult", [(2, 1), (3, 3), (33, 1), (34, 1), (65, 1), (100, 1),
+                                    (162, 3), (300, 1), (600, 3)])
+def test_two_stage_known_spectrum_fp64(lib, two_stage_from, n, mult):
+    say("two-stage fp64", n, mult)
+    two_stage_from(2)
+    A, b, lam, qb = _random_hermitian(n, seed=5 * n + mult, mult=mult)
+    om, po, os_ = _solve(lib, A, b, lib.FP64, torch.complex128)
+    err = np.abs(om - lam).max()
+    say("  max eigenvalue error", err)
+    assert err < 1e-11 * max(1, np.abs(lam).max())
+    _check_poles(lam, qb, po, os_)
+
+
+@pytest.mark.parametrize("n,mult", [(34, 1), (162, 3), (600, 3)])
+def test_two_stage_known_spectrum_fp32(lib, two_stage_from, n, mult):
+    """FP32 working storage: the eigenvalues move by ~eps32 |A| (|A| = 10)."""
+    say("two-stage fp32", n, mult)
+    two_stage_from(2)
+    A, b, lam, qb = _random_hermitian(n, seed=7 * n + mult, mult=mult)
+    om, po, os_ = _solve(lib, A, b, lib.FP32, torch.complex64)
+    err = np.abs(om - lam).max()
+    say("  max eigenvalue error", err)
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("n,precname,mult", [(4500, "FP64", 3), (4500, "FP32", 1),
+                                             (8400, "FP32", 3)])
+def test_two_stage_large_blocks(lib, two_stage_from, n, precname, mult):
+    """Blocks above the default switch point take the two-stage path: 140 to
+    262 panels, then 9000 to 16800 bulge-chasing launches.  FP32 storage:
+    the same bar as the one-stage solver (1e-4 at n = 4500, scaled by
+    sqrt(n / 4500))."""
+    say("two-stage large", n, precname, mult)
+    two_stage_from(4096)
+    A, b, lam, qb = _householder_hermitian(n, seed=91 + mult, mult=mult)
+    h_dtype = torch.complex128 if precname == "FP64" else torch.complex64
+    om, po, os_ = _solve(lib, A, b, getattr(lib, precname), h_dtype)
+    err = np.abs(om - lam).max()
+    say("  max eigenvalue error", err)
+    if precname == "FP64":
+        assert err < 1e-11 * np.abs(lam).max()
+        _check_poles(lam, qb, po, os_)
+    else:
+        assert err < 1e-4 * math.sqrt(n / 4500)
+
+
+def test_two_stage_matches_one_stage(lib, two_stage_from):
+    """The same block through both reductions (FP64): eigenvalues within
+    1e-12 |lam| of each other, the same total strength."""
+    n = 700
+    say("two-stage vs one-stage", n)
+    A, b, lam, qb = _random_hermitian(n, seed=1234, mult=3)
+    two_stage_from(1 << 20)
+    om1, po1, os1 = _solve(lib, A, b, lib.FP64, torch.complex128)
+    two_stage_from(2)
+    om2, po2, os2 = _solve(lib, A, b, lib.FP64, torch.complex128)
+    assert np.abs(om1 - om2).max() < 1e-12 * np.abs(lam).max()
+    assert abs(os1.sum() - os2.sum()) < 1e-10 * os1.sum()
+
+
+def test_switch_point_query(lib, two_stage_from):
+    """bse_block_eigh_set_two_stage returns the previous value; a negative
+    argument only queries; the workspace query follows the switch point."""
+    two_stage_from(5000)
+    assert lib.bse_block_eigh_set_two_stage(-1) == 5000
+    w1 = lib.bse_block_eigh_ws(4800, 0, lib.FP32)
+    two_stage_from(4800)
+    w2 = lib.bse_block_eigh_ws(4800, 0, lib.FP32)
+    assert w2 > w1
+    # refinement keeps the one-stage path and its workspace
+    wr = lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100)
+    two_stage_from(1 << 20)
+    assert lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100) == wr
+    assert lib.bse_block_eigh_ws(4800, 0, lib.FP32) == w1
