@@ -1125,21 +1125,37 @@ __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
   const int wm0 = (wv >> 1) * (BM / 2), wn0 = (wv & 1) * (BN / 2);
   const int K2 = 2 * nbk;  // complex reduction length: [V | W] against [W | V]
   for (int i0 = 0; i0 < K2; i0 += KC) {
+    // every load from an in-bounds address (rows clamped to n - 1, panel
+    // columns to K2 - 1), all issued before any is used; out-of-range
+    // entries are zeroed by selects, so no load sits behind a branch
+    double2 xa[NA], xb[NB];
 #pragma unroll
     for (int u = 0; u < NA; ++u) {  // consecutive threads: consecutive rows (column major V, W)
-      const int it = tid + ENT * u, r = it % (BM / 2), ii = it / (BM / 2), I = i0 + ii;
-      const int64_t a = a0 + r;
-      double2 x = {0, 0};
-      if (a < n && I < K2) x = I < nbk ? V[int64_t(I) * ldv + a] : W[int64_t(I - nbk) * ldv + a];
+      const int it = tid + ENT * u, r = it % (BM / 2), ii = it / (BM / 2);
+      const int I = std::min(i0 + ii, K2 - 1);
+      const int64_t ac = std::min<int64_t>(a0 + r, n - 1);
+      xa[u] = (I < nbk ? V + int64_t(I) * ldv : W + int64_t(I - nbk) * ldv)[ac];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int it = tid + ENT * u, r = it % BN, ii = it / BN;
+      const int I = std::min(i0 + ii, K2 - 1);
+      const int64_t bc = std::min<int64_t>(b0 + r, n - 1);
+      xb[u] = (I < nbk ? W + int64_t(I) * ldv : V + int64_t(I - nbk) * ldv)[bc];
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int it = tid + ENT * u, r = it % (BM / 2), ii = it / (BM / 2);
+      const bool ok = a0 + r < n && i0 + ii < K2;
+      const double2 x = {ok ? xa[u].x : 0.0, ok ? xa[u].y : 0.0};
       *reinterpret_cast<C2 *>(As + (2 * r) * P + 2 * ii) = C2{T(x.x), T(x.y)};
       *reinterpret_cast<C2 *>(As + (2 * r + 1) * P + 2 * ii) = C2{T(x.y), T(-x.x)};
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int it = tid + ENT * u, r = it % BN, ii = it / BN, I = i0 + ii;
-      const int64_t b = b0 + r;
-      double2 x = {0, 0};
-      if (b < n && I < K2) x = I < nbk ? W[int64_t(I) * ldv + b] : V[int64_t(I - nbk) * ldv + b];
+      const int it = tid + ENT * u, r = it % BN, ii = it / BN;
+      const bool ok = b0 + r < n && i0 + ii < K2;
+      const double2 x = {ok ? xb[u].x : 0.0, ok ? xb[u].y : 0.0};
       *reinterpret_cast<C2 *>(Bs + r * P + 2 * ii) = C2{T(x.x), T(x.y)};
     }
     __syncthreads();
@@ -1147,6 +1163,19 @@ __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
     __syncthreads();
   }
   const int r16 = lane & 15, g = lane >> 4;
+  // read-modify-write of the tile: every read first (clamped addresses),
+  // then the predicated writes, so no read waits behind a write
+  C2 old[MI][NI][2];
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const int64_t b = std::min<int64_t>(b0 + wn0 + 16 * ni + r16, n - 1);
+      const int64_t a = a0 + (wm0 + 16 * mi + 4 * g) / 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        old[mi][ni][h] = reinterpret_cast<const C2 *>(A)[std::min<int64_t>(a + h, n - 1) * lda + b];
+    }
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -1154,14 +1183,12 @@ __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
       const int64_t b = b0 + wn0 + 16 * ni + r16;
       const int64_t a = a0 + (wm0 + 16 * mi + 4 * g) / 2;
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        if (a + h < n && b < n) {
-          C2 *p = reinterpret_cast<C2 *>(A) + (a + h) * lda + b;
-          C2 x = *p;
-          x.x -= acc[mi][ni][2 * h];
-          x.y -= acc[mi][ni][2 * h + 1];
-          *p = x;
-        }
+      for (int h = 0; h < 2; ++h) {
+        C2 x = old[mi][ni][h];
+        x.x -= acc[mi][ni][2 * h];
+        x.y -= acc[mi][ni][2 * h + 1];
+        if (a + h < n && b < n) reinterpret_cast<C2 *>(A)[(a + h) * lda + b] = x;
+      }
     }
   if (!mirror || bx == by) return;  // a diagonal tile holds both triangles itself
   // mirror tile: A[b][a] -= conj(U[a][b])
@@ -1176,17 +1203,23 @@ __device__ __forceinline__ void b_her2k(int64_t n, int64_t c0, int nbk,
       }
   __syncthreads();  // (the last slab ended with a barrier: smem is free)
   const int il = tid % BN;
-#pragma unroll 4
-  for (int jl = tid / BN; jl < BN; jl += ENT / BN) {
+  constexpr int JM = BN / (ENT / BN);  // mirror entries per thread
+  C2 mold[JM];
+  const int64_t ac = std::min<int64_t>(a0 + il, n - 1);
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int jl = tid / BN + (ENT / BN) * q;
+    mold[q] = reinterpret_cast<const C2 *>(A)[std::min<int64_t>(b0 + jl, n - 1) * lda + ac];
+  }
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int jl = tid / BN + (ENT / BN) * q;
     const int64_t b = b0 + jl, a = a0 + il;
-    if (b < n && a < n) {
-      C2 *p = reinterpret_cast<C2 *>(A) + b * lda + a;
-      const C2 u = Us[il * UP + jl];
-      C2 x = *p;
-      x.x -= u.x;
-      x.y += u.y;
-      *p = x;
-    }
+    const C2 u = Us[il * UP + jl];
+    C2 x = mold[q];
+    x.x -= u.x;
+    x.y += u.y;
+    if (b < n && a < n) reinterpret_cast<C2 *>(A)[b * lda + a] = x;
   }
 }
 

@@ -339,16 +339,18 @@ __device__ __forceinline__ void b_sb_u(const Desc &D, int64_t j0, int wg) {
 // as a real GEMM: rows 2r / 2r + 1 of the A tile are (re, im) / (im, -re) of
 // A's row r, the B tile holds (re, -im) of U, so C[2r][l] = Re X[r][l] and
 // C[2r + 1][l] = Im X[r][l].  FP32 partial products are summed into FP64
-// every 128 complex columns of K.
+// every 128 complex columns of K.  Slabs of 32 (FP32) or 16 (FP64) complex
+// columns; the next slab is loaded into registers while the current one
+// runs on the matrix cores.
 template <typename TA>
 __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
   typedef typename C2T<TA>::t CA;
   constexpr bool F32 = std::is_same<TA, float>::value;
-  constexpr int BK = F32 ? 32 : 16, KC = BK / 2;  // real / complex K per slab
+  constexpr int BK = F32 ? 64 : 32, KC = BK / 2;  // real / complex K per slab
   constexpr int P = Pitch<TA, BK>::value, BM = 2 * SBHM, BN = SBW, MI = 4, NI = 1;
   constexpr int AL = SBHM * KC / ENT;  // complex A entries per thread and slab
   constexpr int BL = BN * KC / ENT;    // complex U entries per thread and slab
-  constexpr int FLUSH = F32 ? 8 : 1 << 30;  // slabs between FP64 sums
+  constexpr int FLUSH = F32 ? 128 / KC : 1 << 30;  // slabs between FP64 sums (128 terms)
   __shared__ __attribute__((aligned(16))) TA As[BM * P];
   __shared__ __attribute__((aligned(16))) TA Bs[BN * P];
   const int64_t n = D.n, p0 = j0 + SBW, m = n - p0;
@@ -373,16 +375,38 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) accd[mi][j] = 0;
   CA ra[AL], rbv[BL];
+  // Whole slabs (a uniform condition) load 16-byte vectors unconditionally
+  // (aligned: p0, the slab start and the thread offsets are multiples of 8
+  // complex entries, lda of 16); only the last, partial slab of a split
+  // loads entry by entry.  Rows past m were clamped to row m - 1 and are
+  // zeroed when staged.
+  typedef typename std::conditional<F32, float4, double2>::type V16;
+  constexpr int PER = 16 / int(sizeof(CA));  // complex entries per 16-byte load
   auto load = [&](int64_t kk) {
+    if (kk + KC <= k1) {
+      const V16 *a16 = reinterpret_cast<const V16 *>(ap + kk + ak);
+      const V16 *u16 = reinterpret_cast<const V16 *>(up + kk + bk);
 #pragma unroll
-    for (int i = 0; i < AL; ++i) {
-      const int64_t kx = kk + ak + i;
-      ra[i] = (arow_ok && kx < k1) ? ap[kx] : CA{0, 0};
-    }
+      for (int i = 0; i < AL / PER; ++i) {
+        const V16 v = a16[i];
+        memcpy(&ra[PER * i], &v, 16);
+      }
 #pragma unroll
-    for (int i = 0; i < BL; ++i) {
-      const int64_t kx = kk + bk + i;
-      rbv[i] = kx < k1 ? up[kx] : CA{0, 0};
+      for (int i = 0; i < BL / PER; ++i) {
+        const V16 v = u16[i];
+        memcpy(&rbv[PER * i], &v, 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < AL; ++i) {
+        const int64_t kx = kk + ak + i;
+        ra[i] = kx < k1 ? ap[kx] : CA{0, 0};
+      }
+#pragma unroll
+      for (int i = 0; i < BL; ++i) {
+        const int64_t kx = kk + bk + i;
+        rbv[i] = kx < k1 ? up[kx] : CA{0, 0};
+      }
     }
   };
   if (k0 < k1) load(k0);
@@ -391,10 +415,11 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int kq = ak + i;
-      As[(2 * ar) * P + 2 * kq] = ra[i].x;
-      As[(2 * ar) * P + 2 * kq + 1] = ra[i].y;
-      As[(2 * ar + 1) * P + 2 * kq] = ra[i].y;
-      As[(2 * ar + 1) * P + 2 * kq + 1] = -ra[i].x;
+      const TA ax = arow_ok ? ra[i].x : TA(0), ay = arow_ok ? ra[i].y : TA(0);
+      As[(2 * ar) * P + 2 * kq] = ax;
+      As[(2 * ar) * P + 2 * kq + 1] = ay;
+      As[(2 * ar + 1) * P + 2 * kq] = ay;
+      As[(2 * ar + 1) * P + 2 * kq + 1] = -ax;
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {

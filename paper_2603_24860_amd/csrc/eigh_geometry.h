@@ -200,9 +200,9 @@ __host__ __device__ __forceinline__ int64_t g_yslots(int64_t n) {
 
 // two-stage geometry: workgroups of the panel kernels over m panel rows
 __host__ __device__ __forceinline__ int64_t g_sb_nw(int64_t m) { return m < 1 ? 1 : cdiv(m, SBR); }
-// complex K of one split of the panel product (a multiple of 16)
+// complex K of one split of the panel product (a multiple of the FP32 slab, 32)
 __host__ __device__ __forceinline__ int64_t g_sb_kc(int64_t m) {
-  return std::max<int64_t>(16, cdiv(cdiv(m, SBNS), 16) * 16);
+  return std::max<int64_t>(32, cdiv(cdiv(m, SBNS), 32) * 32);
 }
 __host__ __device__ __forceinline__ int64_t g_sb_hemm_wgs(int64_t m) {
   return cdiv(m, SBHM) * SBNS;
