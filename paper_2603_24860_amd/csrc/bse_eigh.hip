@@ -2344,12 +2344,13 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
     BSE_LAUNCH("k_sb_pstart", k_sb_pstart<TA>, dim3(nw), dim3(ENT), 0, s, D, j0);
     for (int c = 0; c < nref; ++c)
       BSE_LAUNCH("k_sb_pcol", k_sb_pcol, dim3(nw), dim3(PCT), 0, s, D, j0, c, nw);
-    BSE_LAUNCH("k_sb_tmat", k_sb_tmat<TA>, dim3(1), dim3(ENT), 0, s, D, j0, nw);
+    BSE_LAUNCH("k_sb_tmat", k_sb_tmat<TA>, dim3(1), dim3(RNT), 0, s, D, j0, nw);
     BSE_LAUNCH("k_sb_u", k_sb_u<TA>, rows, dim3(ENT), 0, s, D, j0);
     BSE_LAUNCH("k_sb_hemm", k_sb_hemm<TA>, dim3((unsigned)g_sb_hemm_wgs(m)), dim3(ENT), 0, s, D,
                j0);
-    BSE_LAUNCH("k_sb_xred", k_sb_xred, dim3(nw), dim3(ENT), 0, s, D, j0);
-    BSE_LAUNCH("k_sb_z", k_sb_z, dim3(1), dim3(ENT), 0, s, D, nw);
+    const int nx = (int)g_sb_nx(m);
+    BSE_LAUNCH("k_sb_xred", k_sb_xred, dim3(nx), dim3(ENT), 0, s, D, j0);
+    BSE_LAUNCH("k_sb_z", k_sb_z, dim3(1), dim3(RNT), 0, s, D, nx);
     BSE_LAUNCH("k_sb_w", k_sb_w, rows, dim3(ENT), 0, s, D, j0);
     BSE_LAUNCH("k_her2k", k_sb_her2k<TA>, dim3((unsigned)sb_her2k_wgs<TA>(n, p0)), dim3(ENT), 0,
                s, D, p0);

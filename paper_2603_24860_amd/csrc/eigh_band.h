@@ -224,41 +224,52 @@ __device__ __forceinline__ void b_sb_pcol(const Desc &D, int64_t j0, int c, int 
 template <typename TA>
 __device__ __forceinline__ void b_sb_tmat(const Desc &D, int64_t j0, int nw) {
   typedef typename C2T<TA>::t CA;
-  __shared__ double2 S[SBW][SBW + 1], T[SBW][SBW + 1];
+  __shared__ double2 S[SBW][SBW + 1], T[SBW][SBW + 1], taus[SBW];
   const int64_t n = D.n, p0 = j0 + SBW, m = n - p0;
   const int nref = (int)std::min<int64_t>(SBW, m);
   const int tid = threadIdx.x;
-  // S[l][c] = sum over the records, eight loads in flight per element
-  for (int e = tid; e < SBW * SBW; e += ENT) {
-    const int c = e / SBW, l = e % SBW;
+  // S[l][c] = sum over the records: one entry per thread (RNT = SBW^2),
+  // sixteen loads in flight
+  static_assert(RNT == SBW * SBW, "k_sb_tmat: one thread per entry of S");
+  {
+    const int e = tid, c = e / SBW, l = e % SBW;
     double2 s = {0, 0};
     if (l < c && c < nref) {
-      for (int w0 = 0; w0 < nw; w0 += 8) {
-        double2 v[8];
+      for (int w0 = 0; w0 < nw; w0 += 16) {
+        double2 v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 16; ++u)
           v[u] = D.srec[(int64_t(std::min(w0 + u, nw - 1)) * SBW + c) * SBW + l];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 16; ++u)
           if (w0 + u < nw) s = cadd(s, v[u]);
       }
     }
     S[l][c] = s;
     T[l][c] = (l == c && c < nref) ? D.sbsc[c] : double2{0, 0};
+    if (tid < SBW) taus[tid] = D.sbsc[tid];
   }
   __syncthreads();
-  for (int c = 1; c < nref; ++c) {
-    if (tid < c) {
-      double2 acc = {0, 0};
-      for (int l2 = tid; l2 < c; ++l2) acc = cadd(acc, cmul(T[tid][l2], S[l2][c]));
-      const double2 tc = D.sbsc[c];
-      T[tid][c] = cmul(double2{-tc.x, -tc.y}, acc);
+  // Row l of T needs only its own earlier entries and S: half-wave l holds
+  // row l, lane k its entry T[l][k] in a register; column c is a sum over the
+  // 32 lanes of the half-wave (xor shuffles), taken by lane c.  No barrier.
+  {
+    const int l = tid / SBW, k = tid % SBW;
+    double2 tlk = T[l][k];  // tau on the diagonal, zero elsewhere
+    for (int c = 1; c < nref; ++c) {
+      double2 t = csel(k >= l && k < c, cmul(tlk, S[k][c]), double2{0, 0});
+#pragma unroll
+      for (int o = 1; o < SBW; o <<= 1) {
+        t.x += __shfl_xor(t.x, o, 64);
+        t.y += __shfl_xor(t.y, o, 64);
+      }
+      const double2 tc = taus[c];
+      if (k == c && l < c) tlk = cmul(double2{-tc.x, -tc.y}, t);
     }
-    __syncthreads();
+    D.sbt[tid] = tlk;
   }
-  for (int e = tid; e < SBW * SBW; e += ENT) D.sbt[e] = T[e / SBW][e % SBW];
   const CA *A = reinterpret_cast<const CA *>(D.A);
-  for (int e = tid; e < SBW * LDB; e += ENT) {
+  for (int e = tid; e < SBW * LDB; e += RNT) {
     const int c = e / LDB, d = e % LDB;
     const int64_t j = j0 + c, row = j + d;
     double2 val = {0, 0};
@@ -457,30 +468,39 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
   }
 }
 
-// X = sum of the splits (kept in W), partial V^dag X of this workgroup's rows
+// X = sum of the splits (kept in W), partial V^dag X of this workgroup's 64
+// rows (one record per workgroup)
 __device__ __forceinline__ void b_sb_xred(const Desc &D, int64_t j0, int wg) {
   __shared__ double2 Vs[64][SBW + 1], Xs[64][SBW + 1];
   const int64_t n = D.n, p0 = j0 + SBW, m = n - p0;
   const int tid = threadIdx.x;
   const int yl = tid / 8, yq = 4 * (tid % 8);  // Y entries (yl, yq .. yq + 3)
   double2 y[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  for (int ch = 0; ch < SBR / 64; ++ch) {
-    const int64_t rb = int64_t(wg) * SBR + ch * 64;
-    if (rb >= m) break;
+  {
+    const int64_t rb = int64_t(wg) * 64;
+    constexpr int NE = 64 * SBW / ENT;
+    // every load first (rows clamped to m - 1), then the sums, then the
+    // predicated stores of X
+    double2 xs[NE][SBNS], vv[NE];
 #pragma unroll
-    for (int i = 0; i < 64 * SBW / ENT; ++i) {
+    for (int i = 0; i < NE; ++i) {
       const int e = tid + ENT * i, l = e / 64, rr = e % 64;
-      const int64_t r = rb + rr;
-      double2 x = {0, 0}, v = {0, 0};
-      if (r < m) {
-        const int64_t o = int64_t(l) * D.ldv + p0 + r;
+      const int64_t o = int64_t(l) * D.ldv + p0 + std::min<int64_t>(rb + rr, m - 1);
 #pragma unroll
-        for (int s = 0; s < SBNS; ++s) x = cadd(x, D.xp[int64_t(s) * SBW * D.ldv + o]);
-        v = D.V[o];
-        D.W[o] = x;
-      }
+      for (int s = 0; s < SBNS; ++s) xs[i][s] = D.xp[int64_t(s) * SBW * D.ldv + o];
+      vv[i] = D.V[o];
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + ENT * i, l = e / 64, rr = e % 64;
+      const bool in = rb + rr < m;
+      double2 x = xs[i][0];
+#pragma unroll
+      for (int s = 1; s < SBNS; ++s) x = cadd(x, xs[i][s]);
+      x = csel(in, x, double2{0, 0});
       Xs[rr][l] = x;
-      Vs[rr][l] = v;
+      Vs[rr][l] = csel(in, vv[i], double2{0, 0});
+      if (in) D.W[int64_t(l) * D.ldv + p0 + rb + rr] = x;
     }
     __syncthreads();
     for (int rr = 0; rr < 64; ++rr) {
@@ -494,30 +514,26 @@ __device__ __forceinline__ void b_sb_xred(const Desc &D, int64_t j0, int wg) {
   for (int q = 0; q < 4; ++q) D.yrec[(int64_t(wg) * SBW + yl) * SBW + yq + q] = y[q];
 }
 
-// Z = T^dag (sum of the partial V^dag X)
+// Z = T^dag (sum of the partial V^dag X); one thread per entry (RNT = SBW^2)
 __device__ __forceinline__ void b_sb_z(const Desc &D, int nw) {
   __shared__ double2 Ys[SBW][SBW + 1], Ts[SBW][SBW + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < SBW * SBW; e += ENT) {
-    double2 y = {0, 0};
-    for (int w0 = 0; w0 < nw; w0 += 8) {
-      double2 v[8];
+  const int e = threadIdx.x;
+  double2 y = {0, 0};
+  for (int w0 = 0; w0 < nw; w0 += 16) {
+    double2 v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = D.yrec[int64_t(std::min(w0 + u, nw - 1)) * SBW * SBW + e];
+    for (int u = 0; u < 16; ++u) v[u] = D.yrec[int64_t(std::min(w0 + u, nw - 1)) * SBW * SBW + e];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (w0 + u < nw) y = cadd(y, v[u]);
-    }
-    Ys[e / SBW][e % SBW] = y;
-    Ts[e / SBW][e % SBW] = D.sbt[e];
+    for (int u = 0; u < 16; ++u)
+      if (w0 + u < nw) y = cadd(y, v[u]);
   }
+  Ys[e / SBW][e % SBW] = y;
+  Ts[e / SBW][e % SBW] = D.sbt[e];
   __syncthreads();
-  for (int e = tid; e < SBW * SBW; e += ENT) {
-    const int l = e / SBW, l2 = e % SBW;
-    double2 z = {0, 0};
-    for (int k = 0; k <= l; ++k) z = cadd(z, cmulc(Ts[k][l], Ys[k][l2]));  // T upper triangular
-    D.sbz[e] = z;
-  }
+  const int l = e / SBW, l2 = e % SBW;
+  double2 z = {0, 0};
+  for (int k = 0; k <= l; ++k) z = cadd(z, cmulc(Ts[k][l], Ys[k][l2]));  // T upper triangular
+  D.sbz[e] = z;
 }
 
 // W = X - V Z / 2: a workgroup takes 64 panel rows, thread (row r, group g)
@@ -576,7 +592,7 @@ __global__ __launch_bounds__(PCT) void k_sb_pcol(Desc D, int64_t j0, int c, int 
   b_sb_pcol(D, j0, c, nw, int(blockIdx.x));
 }
 template <typename TA>
-__global__ __launch_bounds__(ENT) void k_sb_tmat(Desc D, int64_t j0, int nw) {
+__global__ __launch_bounds__(RNT) void k_sb_tmat(Desc D, int64_t j0, int nw) {
   b_sb_tmat<TA>(D, j0, nw);
 }
 template <typename TA>
@@ -594,7 +610,7 @@ __global__ __launch_bounds__(ENT) void k_sb_hemm(Desc D, int64_t j0) {
 __global__ __launch_bounds__(ENT) void k_sb_xred(Desc D, int64_t j0) {
   b_sb_xred(D, j0, int(blockIdx.x));
 }
-__global__ __launch_bounds__(ENT) void k_sb_z(Desc D, int nw) { b_sb_z(D, nw); }
+__global__ __launch_bounds__(RNT) void k_sb_z(Desc D, int nw) { b_sb_z(D, nw); }
 __global__ __launch_bounds__(ENT) void k_sb_w(Desc D, int64_t j0) {
   b_sb_w(D, j0, int(blockIdx.x));
 }

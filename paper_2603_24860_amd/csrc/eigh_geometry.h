@@ -204,6 +204,8 @@ __host__ __device__ __forceinline__ int64_t g_sb_nw(int64_t m) { return m < 1 ? 
 __host__ __device__ __forceinline__ int64_t g_sb_kc(int64_t m) {
   return std::max<int64_t>(32, cdiv(cdiv(m, SBNS), 32) * 32);
 }
+// workgroups (and records) of the split sum k_sb_xred: 64 panel rows each
+__host__ __device__ __forceinline__ int64_t g_sb_nx(int64_t m) { return m < 1 ? 1 : cdiv(m, 64); }
 __host__ __device__ __forceinline__ int64_t g_sb_hemm_wgs(int64_t m) {
   return cdiv(m, SBHM) * SBNS;
 }
@@ -290,7 +292,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     t.sbsc = (double2 *)take(2 * SBW * 16);
     t.u = take(size_t(SBW) * ldv * (a_fp64 ? 16 : 8));
     t.xp = (double2 *)take(size_t(SBNS) * SBW * ldv * 16);
-    t.yrec = (double2 *)take(nw * SBW * SBW * 16);
+    t.yrec = (double2 *)take(size_t(g_sb_nx(n)) * SBW * SBW * 16);
     t.band = (double2 *)take(size_t(n) * LDB * 16);
     t.rfl = (double2 *)take(size_t(n) * SBW * 16);
     t.rtau = (double2 *)take(size_t(n) * 16);

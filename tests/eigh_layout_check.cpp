@@ -120,7 +120,7 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
   C.add("sbsc", D.sbsc, 16, 2 * SBW);
   C.add("u", D.u, elu, SBW * D.ldv);
   C.add("xp", D.xp, 16, int64_t(SBNS) * SBW * D.ldv);
-  C.add("yrec", D.yrec, 16, nwmax * SBW * SBW);
+  C.add("yrec", D.yrec, 16, g_sb_nx(n) * SBW * SBW);
   C.add("band", D.band, 16, n * LDB);
   C.add("rfl", D.rfl, 16, n * SBW);
   C.add("rtau", D.rtau, 16, n);
@@ -176,7 +176,7 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
                 "k_sb_hemm/xred xp");
     }
     C.range("pb", 0, m * SBW, "k_sb_u pb");
-    C.range("yrec", 0, nw * SBW * SBW, "k_sb_xred/z");
+    C.range("yrec", 0, g_sb_nx(m) * SBW * SBW, "k_sb_xred/z");
     C.range("sbz", 0, SBW * SBW, "k_sb_z/w");
     // k_sb_hemm: A rows p0 + min(r0 + ar, m - 1), columns p0 + [k0, k1)
     const int64_t kc = g_sb_kc(m);
