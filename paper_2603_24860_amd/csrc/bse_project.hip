@@ -46,7 +46,9 @@ struct SeedSrc {
   double scale;
 };
 
-template <typename T, bool SEEDSRC, int NCT>
+// PAIR (FP32 H, nv nc even): two entries per 16-byte load; a run of nv nc
+// entries starts at an even entry, so a pair never straddles two runs.
+template <typename T, bool SEEDSRC, int NCT, bool PAIR = false>
 __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(NCT == 1 && !SEEDSRC && sizeof(T) == 4 ? 6 : 1, 8))) void k_project(int nv, int nc, const T *__restrict__ H,
                                                  int64_t ldh, const int32_t *__restrict__ mem_off,
                                                  const int32_t *__restrict__ members,
@@ -94,12 +96,30 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(NCT == 1 &&
   __syncthreads();  // m1s, m2s
   // chunk loads go to registers; the next chunk's loads are in flight while
   // the current one is contracted from LDS
-  C2 x[PCH / PNT];
+  static_assert(!PAIR || (sizeof(T) == 4 && !SEEDSRC), "pairs: FP32 H only");
+  constexpr int NL = PAIR ? PCH / (2 * PNT) : PCH / PNT;  // loads per thread and chunk
+  typedef typename std::conditional<PAIR, float4, C2>::type LV;
+  LV x[NL];
   // every load is issued unconditionally from a clamped, in-bounds index and
   // entries past the chunk are zeroed afterwards, so the loads do not wait on
   // one another
   auto fetch = [&](int i0) {
     const int nr = std::min(RU, L1 - i0);
+    if constexpr (PAIR) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int q = threadIdx.x + PNT * u;
+        const int e = std::min(2 * q, nr * per - 2);
+        const int ii = e / per, rem = e - ii * per, i2 = rem / nb, b2 = rem - i2 * nb;
+        const int64_t a = (int64_t(m1s[i0 + ii]) * nv + v) * nc + c;
+        x[u] = *reinterpret_cast<const float4 *>(reinterpret_cast<const C2 *>(H) + a * ldh +
+                                                 int64_t(m2s[i2]) * nb + b2);
+      }
+#pragma unroll
+      for (int u = 0; u < NL; ++u)
+        if (2 * (threadIdx.x + PNT * u) >= nr * per) x[u] = LV{0, 0, 0, 0};
+      return;
+    } else {
 #pragma unroll
     for (int u = 0; u < PCH / PNT; ++u) {
       const int e0 = threadIdx.x + PNT * u;
@@ -124,13 +144,19 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(NCT == 1 &&
 #pragma unroll
     for (int u = 0; u < PCH / PNT; ++u)
       if (threadIdx.x + PNT * u >= nr * per) x[u] = C2{0, 0};
+    }
   };
   fetch(0);
   for (int i0 = 0; i0 < L1; i0 += RU) {
     const int nr = std::min(RU, L1 - i0);
     __syncthreads();  // the previous chunk has been consumed
 #pragma unroll
-    for (int u = 0; u < PCH / PNT; ++u) rows[threadIdx.x + PNT * u] = x[u];
+    for (int u = 0; u < NL; ++u) {
+      if constexpr (PAIR)
+        reinterpret_cast<float4 *>(rows)[threadIdx.x + PNT * u] = x[u];
+      else
+        rows[threadIdx.x + PNT * u] = x[u];
+    }
     __syncthreads();
     if (i0 + RU < L1) fetch(i0 + RU);
 #pragma unroll
@@ -301,14 +327,18 @@ extern "C" int32_t bse_project_blocks(const bse_problem *p, const void *H, int64
         return fail(BSE_EUNSUPPORTED, "r' nv nc exceeds %d columns", PNT * PMAXCOL);
       dim3 g((unsigned)nb, (unsigned)p->nkorb, (unsigned)p->nkorb);
       const bool one = 9 * nb <= PNT;  // every output column of a block row in one thread
-#define BSE_PROJ(T, NCT)                                                                      \
-  BSE_LAUNCH("k_project", (k_project<T, false, NCT>), g, dim3(PNT), 0, s, p->nv, p->nc,       \
+#define BSE_PROJ(T, NCT, PR)                                                                  \
+  BSE_LAUNCH("k_project", (k_project<T, false, NCT, PR>), g, dim3(PNT), 0, s, p->nv, p->nc,   \
              (const T *)H, ldh, b.mem_off, b.members, b.orb_off, b.orb_dim, b.ub_off, b.ubasis, \
              (T *)Hmu[ib], ldmu[ib], SeedSrc{})
+      // pairs of FP32 entries need nv nc even and 16-byte aligned rows
+      const bool pair = nb % 2 == 0 && ldh % 2 == 0 && (reinterpret_cast<uintptr_t>(H) & 15) == 0;
       if (h_fp64) {
-        if (one) BSE_PROJ(double, 1); else BSE_PROJ(double, 2);
+        if (one) BSE_PROJ(double, 1, false); else BSE_PROJ(double, 2, false);
+      } else if (pair) {
+        if (one) BSE_PROJ(float, 1, true); else BSE_PROJ(float, 2, true);
       } else {
-        if (one) BSE_PROJ(float, 1); else BSE_PROJ(float, 2);
+        if (one) BSE_PROJ(float, 1, false); else BSE_PROJ(float, 2, false);
       }
 #undef BSE_PROJ
       BSE_HIP_CHECK(hipGetLastError());
