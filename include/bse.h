@@ -176,7 +176,11 @@ typedef struct {
 } bse_problem;
 
 /* Workspace bytes that let bse_build run its direct term in the fewest passes
- * (capped; any size >= bse_build_ws_min works). */
+ * (capped; any size >= bse_build_ws_min works).  BF16X3 needs exactly
+ * bse_build_ws_min = bse_build_ws: the BF16 hi and lo planes of W
+ * (4 nqorb nmb^2 bytes), written at the start of every build; the workspace
+ * must be 16-byte aligned (BSE_EWORKSPACE if smaller, BSE_EINVAL if
+ * misaligned). */
 size_t bse_build_ws(const bse_problem *p, int32_t prec);
 size_t bse_build_ws_min(const bse_problem *p, int32_t prec);
 /* H: complex double (prec FP64) or complex float (FP32, BF16X3), leading

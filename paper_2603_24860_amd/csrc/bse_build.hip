@@ -669,18 +669,22 @@ size_t per_q_bytes(const bse_problem *p, int32_t prec) {
 // used by other translation units (BF16 split form)
 int32_t build_check_problem(const bse_problem *p, int32_t prec) { return check_problem(p, prec); }
 
+size_t build_bf16x3_ws(const bse_problem *p);
+
 }  // namespace bse
 
 using namespace bse;
 
 extern "C" size_t bse_build_ws_min(const bse_problem *p, int32_t prec) {
   if (check_problem(p, prec)) return 0;
+  if (prec == BSE_BF16X3) return build_bf16x3_ws(p);
   if (fused_ok(p)) return 256;  // the fused direct terms need no buffer
   return per_q_bytes(p, prec);
 }
 
 extern "C" size_t bse_build_ws(const bse_problem *p, int32_t prec) {
   if (check_problem(p, prec)) return 0;
+  if (prec == BSE_BF16X3) return build_bf16x3_ws(p);
   if (fused_ok(p)) return 256;
   const size_t pq = per_q_bytes(p, prec);
   const size_t nk = size_t(p->grid[0]) * p->grid[1] * p->grid[2];

@@ -46,19 +46,23 @@ __device__ __forceinline__ f32x4 mma3(f32x4 acc, bf16x8 ah, bf16x8 al, bf16x8 bh
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
 }
 
-__device__ __forceinline__ void split1(float x, __bf16 &h, __bf16 &l) {
-  h = (__bf16)x;
-  l = (__bf16)(x - (float)h);
-}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
+// x -> hi = bf16(x), lo = bf16(x - hi), two values per conversion
+// (v_cvt_pk_bf16_f32 rounds to nearest even; bf16 -> f32 is exact)
 template <int N, typename V>
 __device__ __forceinline__ void splitn(const float *x, V &h, V &l) {
+  static_assert(N % 2 == 0, "values are split in pairs");
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    __bf16 a, b;
-    split1(x[i], a, b);
-    h[i] = a;
-    l[i] = b;
+  for (int i = 0; i < N; i += 2) {
+    const f32x2 v = {x[i], x[i + 1]};
+    const bf16x2 hp = __builtin_convertvector(v, bf16x2);
+    const bf16x2 lp = __builtin_convertvector(v - __builtin_convertvector(hp, f32x2), bf16x2);
+    h[i] = hp[0];
+    h[i + 1] = hp[1];
+    l[i] = lp[0];
+    l[i + 1] = lp[1];
   }
 }
 
@@ -182,14 +186,41 @@ __global__ __launch_bounds__(NT) void k_exchange_bf3(int nk, int nv, int nc, int
 }
 
 // ---------------------------------------------------------------------------
+// W_q (FP32, [nqorb][nmb][nmb]) -> hi and lo BF16 planes of the same layout,
+// once per build: every workgroup of a q reads all of W_q, so splitting it in
+// the direct kernel would repeat the same conversions N_k / KC times.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_split_w(int64_t n4, const float4 *__restrict__ w,
+                                                bf16x4 *__restrict__ wh, bf16x4 *__restrict__ wl) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n4; i += int64_t(gridDim.x) * NT) {
+    const float4 x = w[i];
+    const float e[4] = {x.x, x.y, x.z, x.w};
+    bf16x4 h, l;
+    splitn<4>(e, h, l);
+    wh[i] = h;
+    wl[i] = l;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // direct term, fused: one workgroup per (q, KC consecutive k), all Nmb rows.
 //   stage 1  T^T[I][(k, t, vv')] = sum_J W_q[I][J] Re/Im(Mv(k, k-q)[vv'][J]);
-//            wave w owns rows I in [w 16 MI, (w+1) 16 MI)
+//            wave w owns rows I in [w 16 MI, (w+1) 16 MI).  W comes from its
+//            hi/lo planes in 16-byte pieces, Mv is split here; the next K
+//            slab is loaded while the MFMAs of the current one run.
 //   stage 2  D[cc'][vv'] = sum_I conj(Mc(k, k-q)[cc'][I]) T[vv'][I]: lane
 //            (g, c) of tiles mi and mi+1 holds T rows 16 mi + 4 g + j and
 //            16 (mi+1) + 4 g + j (j < 4) at column c, the 8 K values of one
-//            16x16x32 step; the A operand reads Mc at the same I.
-// Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48.
+//            16x16x32 step; the A operand reads Mc at the same I.  The four
+//            real products go to four accumulators, so neither the sign of a
+//            conjugated class nor the minus of the imaginary part costs a
+//            split of its own.
+// LDS rows have a pitch of 80 bytes; the writers of one 16-row group take rows
+// 4 j + b with j varying fastest across lanes, which puts the rows that one
+// LDS write cycle covers 320 bytes apart (distinct banks for 32 and for 64
+// banks of 4 bytes); the 16-byte MFMA reads of rows r16 = 0..15 are spread by
+// the 80-byte pitch.
+// Requires nmb = 64 MI, nv^2 <= 16, nc^2 <= 48, KC = 2.
 // ---------------------------------------------------------------------------
 template <int MI, int KC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 : 2, 8))) void k_direct_bf3(int n1, int n2, int n3, int nv, int nc,
@@ -198,17 +229,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
                                                    const uint8_t *__restrict__ pconj,
                                                    const float *__restrict__ mv,
                                                    const float *__restrict__ mc,
-                                                   const float *__restrict__ w,
+                                                   const __bf16 *__restrict__ wh,
+                                                   const __bf16 *__restrict__ wl,
                                                    float *__restrict__ H, int64_t ldh,
                                                    double scale) {
   constexpr int BK = 32, P = BK + 8;       // K slab (J) and bf16 row pitch
   constexpr int NMB = 64 * MI;             // rows I of W
   constexpr int NI = 2 * KC;               // column blocks: (k, re/im)
   constexpr int NCOL = 16 * NI;            // B rows in LDS
-  constexpr int NA = NMB * BK / 4 / NT;    // float4 loads of W per thread per slab
-  constexpr int BPR = 2 * BK / 4;          // float4 loads per complex Mv row per slab
-  constexpr int NB = KC * 16 * BPR / NT;   // Mv loads per thread per slab
-  static_assert(NA >= 1 && NB >= 1, "tile too small");
+  constexpr int NA = NMB * (BK / 8) / NT;  // 16-byte pieces of each W plane per thread per slab
+  static_assert(NA == MI && KC == 2, "one W row group of 64 per thread slot, 8 Mv pieces per row");
   constexpr int STAGE = 2 * (NMB + NCOL) * P * 2;  // bytes: hi + lo tiles
   constexpr int NCB = 3;                   // c c' row blocks of stage 2
   constexpr int RED = 4 * NCB * 16 * 16 * 8;       // bytes: float2 partial D per wave
@@ -217,40 +247,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
   __bf16 *Bh = Al + NMB * P, *Bl = Bh + NCOL * P;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nk = n1 * n2 * n3, nvv = nv * nv, ncc = nc * nc;
-  const int nmb = NMB;
   const int q = blockIdx.y;
   const int k0 = blockIdx.x * KC;
-  const float *wq = w + int64_t(qorb[q]) * nmb * nmb;
-  // B-row sources: row = kk * 16 + vv' (re and im rows of one complex row)
-  const float2 *brow[NB];
-  float bsgn[NB];
-  int boff[NB];
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const int it = tid + NT * u, row = it / BPR, c = it % BPR, kk = row / 16, vv = row % 16;
-    const int k = k0 + kk;
-    brow[u] = nullptr;
-    bsgn[u] = 1.f;
-    if (k < nk && vv < nvv) {
+  // W pieces: thread slot u covers row arow + 64 u, bf16 columns 8 ac .. 8 ac + 7 of the slab
+  const int ac = tid & 3, arow = 16 * (tid >> 6) + 4 * ((tid >> 2) & 3) + ((tid >> 4) & 3);
+  const int64_t wbase = (int64_t(qorb[q]) * NMB + arow) * NMB + 8 * ac;
+  const int aoff = arow * P + 8 * ac;
+  // Mv piece: complex values 4 bc .. 4 bc + 3 of row kk * 16 + vv'
+  const int bc = tid & 7, bkk = tid >> 7, bvv = 4 * ((tid >> 3) & 3) + ((tid >> 5) & 3);
+  const float4 *bsrc = reinterpret_cast<const float4 *>(mv) + 2 * bc;  // a readable row if masked
+  float bre = 0.f, bim = 0.f;  // scale of the real and imaginary parts (0: no such row)
+  {
+    const int k = k0 + bkk;
+    if (k < nk && bvv < nvv) {
       const int kq = kminus(k, q, n1, n2, n3);
       const int64_t p = int64_t(k) * nk + kq;
       const bool cj = pconj[p] != 0;
-      const int v = vv / nv, v2 = vv % nv;
+      const int v = bvv / nv, v2 = bvv % nv;
       const int s1 = cj ? v2 : v, s2 = cj ? v : v2;
-      brow[u] = reinterpret_cast<const float2 *>(mv) +
-                ((int64_t(pidx[p]) * nv + s1) * nv + s2) * nmb + 2 * c;
-      bsgn[u] = cj ? -1.f : 1.f;
+      bsrc = reinterpret_cast<const float4 *>(mv) +
+             (((int64_t(pidx[p]) * nv + s1) * nv + s2) * NMB) / 2 + 2 * bc;
+      bre = 1.f;
+      bim = cj ? -1.f : 1.f;
     }
-    boff[u] = ((2 * kk) * 16 + vv) * P + 2 * c;
   }
-  const float *wrow[NA];
-  int aoff[NA];
-#pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    const int it = tid + NT * u, row = it / (BK / 4), c = it % (BK / 4);
-    wrow[u] = wq + int64_t(row) * nmb + c * 4;
-    aoff[u] = row * P + c * 4;
-  }
+  const int boff = ((2 * bkk) * 16 + bvv) * P + 4 * bc;
   f32x4 acc[MI][NI];
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
@@ -258,34 +279,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
     for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f32x4{0, 0, 0, 0};
   const int wm0 = wv * 16 * MI;
   const int r16 = lane & 15, g = lane >> 4;
-  for (int j0 = 0; j0 < nmb; j0 += BK) {
-    float4 ra[NA], rb[NB];
+  const u32x4 *whp = reinterpret_cast<const u32x4 *>(wh + wbase);
+  const u32x4 *wlp = reinterpret_cast<const u32x4 *>(wl + wbase);
+  constexpr int WU = 64 * NMB / 8;  // u32x4 stride of 64 W rows
+  u32x4 pah[NA], pal[NA];
 #pragma unroll
-    for (int u = 0; u < NA; ++u) ra[u] = *reinterpret_cast<const float4 *>(wrow[u] + j0);
-#pragma unroll
-    for (int u = 0; u < NB; ++u)
-      rb[u] = brow[u] ? *reinterpret_cast<const float4 *>(brow[u] + j0) : float4{0, 0, 0, 0};
+  for (int u = 0; u < NA; ++u) {
+    pah[u] = whp[WU * u];
+    pal[u] = wlp[WU * u];
+  }
+  float4 pb0 = bsrc[0], pb1 = bsrc[1];
+  for (int j0 = 0; j0 < NMB; j0 += BK) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const float e[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
-      bf16x4 h, l;
-      splitn<4>(e, h, l);
-      *reinterpret_cast<bf16x4 *>(Ah + aoff[u]) = h;
-      *reinterpret_cast<bf16x4 *>(Al + aoff[u]) = l;
+      *reinterpret_cast<u32x4 *>(Ah + aoff + 64 * u * P) = pah[u];
+      *reinterpret_cast<u32x4 *>(Al + aoff + 64 * u * P) = pal[u];
     }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      // two complex values: re parts to the re row, (signed) im parts to the im row
-      const float er[2] = {rb[u].x, rb[u].z}, ei[2] = {bsgn[u] * rb[u].y, bsgn[u] * rb[u].w};
-      bf16x2 hr, lr, hi, li;
-      splitn<2>(er, hr, lr);
-      splitn<2>(ei, hi, li);
-      *reinterpret_cast<bf16x2 *>(Bh + boff[u]) = hr;
-      *reinterpret_cast<bf16x2 *>(Bl + boff[u]) = lr;
-      *reinterpret_cast<bf16x2 *>(Bh + boff[u] + 16 * P) = hi;
-      *reinterpret_cast<bf16x2 *>(Bl + boff[u] + 16 * P) = li;
+    {
+      // four complex values: real parts to the re row, (signed) imaginary parts to the im row
+      const float er[4] = {bre * pb0.x, bre * pb0.z, bre * pb1.x, bre * pb1.z};
+      const float ei[4] = {bim * pb0.y, bim * pb0.w, bim * pb1.y, bim * pb1.w};
+      bf16x4 hr, lr, hi, li;
+      splitn<4>(er, hr, lr);
+      splitn<4>(ei, hi, li);
+      *reinterpret_cast<bf16x4 *>(Bh + boff) = hr;
+      *reinterpret_cast<bf16x4 *>(Bl + boff) = lr;
+      *reinterpret_cast<bf16x4 *>(Bh + boff + 16 * P) = hi;
+      *reinterpret_cast<bf16x4 *>(Bl + boff + 16 * P) = li;
     }
     __syncthreads();
+    {
+      // the next slab, in flight during the MFMAs (the last slab fetches itself again)
+      const int jn = min(j0 + BK, NMB - BK);
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        pah[u] = whp[WU * u + jn / 8];
+        pal[u] = wlp[WU * u + jn / 8];
+      }
+      pb0 = bsrc[jn / 2];
+      pb1 = bsrc[jn / 2 + 1];
+    }
     bf16x8 bh[NI], bl[NI];
 #pragma unroll
     for (int ni = 0; ni < NI; ++ni) {
@@ -305,18 +338,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
   const int ncb = (ncc + 15) / 16;
   float2 *red = reinterpret_cast<float2 *>(lds);  // [4][NCB*16][16]
   float2 *Hc = reinterpret_cast<float2 *>(H);
+  // Mc row (c, c') of this lane's A rows in each c c' block: as stored (low
+  // 16 bits) and band-swapped for a conjugated class (high 16 bits); -1 past
+  // the last pair
+  int mrow[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int cc = 16 * cb + r16, c = cc / nc, c2 = cc % nc;
+    mrow[cb] = cc < ncc ? ((c2 * nc + c) << 16) | (c * nc + c2) : -1;
+  }
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk) {
     const int k = k0 + kk;
-    f32x4 dre[NCB], dim[NCB];
+    // Re Mc Re T, Im Mc Im T, Re Mc Im T, Im Mc Re T (Mc as stored)
+    f32x4 d_rr[NCB], d_ii[NCB], d_ri[NCB], d_ir[NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) dre[cb] = dim[cb] = f32x4{0, 0, 0, 0};
+    for (int cb = 0; cb < NCB; ++cb) d_rr[cb] = d_ii[cb] = d_ri[cb] = d_ir[cb] = f32x4{0, 0, 0, 0};
     int kq = 0;
+    float sg = 1.f;
     if (k < nk) {
       kq = kminus(k, q, n1, n2, n3);
       const int64_t p = int64_t(k) * nk + kq;
       const bool cj = pconj[p] != 0;
-      const float sg = cj ? -1.f : 1.f;
+      sg = cj ? -1.f : 1.f;
       const int cls = pidx[p];
 #pragma unroll
       for (int mp = 0; mp < MI; mp += 2) {
@@ -336,15 +380,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           if (cb >= ncb) break;
-          const int cc = 16 * cb + r16;
-          float are[8], aim[8], nim[8];
+          const int mr = mrow[cb] < 0 ? -1 : cj ? mrow[cb] >> 16 : mrow[cb] & 0xffff;
+          float are[8], aim[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) are[j] = aim[j] = 0.f;
-          if (cc < ncc) {
-            const int c = cc / nc, c2 = cc % nc;
-            const int s1 = cj ? c2 : c, s2 = cj ? c : c2;
+          if (mr >= 0) {
             const float4 *src = reinterpret_cast<const float4 *>(
-                reinterpret_cast<const float2 *>(mc) + ((int64_t(cls) * nc + s1) * nc + s2) * nmb);
+                reinterpret_cast<const float2 *>(mc) + (int64_t(cls) * ncc + mr) * NMB);
             // Mc at I0 .. I0+3 and (second tile) I0+16 .. I0+19
             const float4 m0 = src[I0 / 2], m1 = src[I0 / 2 + 1];
             const float4 m2 = two ? src[(I0 + 16) / 2] : float4{0, 0, 0, 0};
@@ -354,30 +396,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
             are[4] = m2.x; aim[4] = m2.y; are[5] = m2.z; aim[5] = m2.w;
             are[6] = m3.x; aim[6] = m3.y; are[7] = m3.z; aim[7] = m3.w;
           }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            aim[j] *= sg;  // Mc = are + i aim
-            nim[j] = -aim[j];
-          }
-          bf16x8 arh, arl, aih, ail, anh, anl;
+          bf16x8 arh, arl, aih, ail;
           splitn<8>(are, arh, arl);
           splitn<8>(aim, aih, ail);
-          splitn<8>(nim, anh, anl);
-          // conj(Mc) T = (are tre + aim tim) + i (are tim - aim tre)
-          dre[cb] = mma3(dre[cb], arh, arl, trh, trl);
-          dre[cb] = mma3(dre[cb], aih, ail, tih, til);
-          dim[cb] = mma3(dim[cb], arh, arl, tih, til);
-          dim[cb] = mma3(dim[cb], anh, anl, trh, trl);
+          d_rr[cb] = mma3(d_rr[cb], arh, arl, trh, trl);
+          d_ii[cb] = mma3(d_ii[cb], aih, ail, tih, til);
+          d_ri[cb] = mma3(d_ri[cb], arh, arl, tih, til);
+          d_ir[cb] = mma3(d_ir[cb], aih, ail, trh, trl);
         }
       }
     }
-    // partial D of this wave -> LDS, then the sum over waves -> H
+    // partial D of this wave -> LDS, then the sum over waves -> H.  With
+    // Mc = re + i sg im:  conj(Mc) T = (re Re T + sg im Im T) + i (re Im T - sg im Re T)
     __syncthreads();  // stage-1 tiles (kk = 0) or the previous reduction are no longer read
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        red[(wv * NCB * 16 + 16 * cb + 4 * g + j) * 16 + r16] = float2{dre[cb][j], dim[cb][j]};
+        red[(wv * NCB * 16 + 16 * cb + 4 * g + j) * 16 + r16] =
+            float2{d_rr[cb][j] + sg * d_ii[cb][j], d_ri[cb][j] - sg * d_ir[cb][j]};
     __syncthreads();
     if (k < nk) {
       for (int e = tid; e < ncc * nvv; e += NT) {
@@ -403,10 +440,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MI <= 4 ? 3 
 
 }  // namespace
 
+// workspace of the split-BF16 build: the hi and lo BF16 planes of W
+// ([nqorb][nmb][nmb] each)
+size_t build_bf16x3_ws(const bse_problem *p) {
+  const size_t planes = size_t(p->nqorb) * p->nmb * p->nmb * 2 * sizeof(__bf16);
+  return std::max<size_t>(256, (planes + 255) / 256 * 256);
+}
+
 int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_t ws_bytes,
                      bse_stream stream) {
-  (void)ws;
-  (void)ws_bytes;
   const int n1 = p->grid[0], n2 = p->grid[1], n3 = p->grid[2];
   const int nk = n1 * n2 * n3;
   const int64_t N = int64_t(nk) * p->nv * p->nc;
@@ -415,6 +457,11 @@ int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_
   if (!fused_shape(p->nmb, p->nv, p->nc))
     return fail(BSE_EUNSUPPORTED,
                 "split-BF16 build needs Nmb = 64 m (m <= 6), nv <= 4 and nc <= 6");
+  if (!ws || ws_bytes < build_bf16x3_ws(p))
+    return fail(BSE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes,
+                build_bf16x3_ws(p));
+  if (reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+    return fail(BSE_EINVAL, "workspace must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   const double inv_nk = 1.0 / nk;
   dim3 gx((unsigned)((N + XBN - 1) / XBN), (unsigned)((2 * N + XBM - 1) / XBM));
@@ -423,13 +470,19 @@ int32_t build_bf16x3(const bse_problem *p, void *H, int64_t ldh, void *ws, size_
              p->korb, (const float *)p->mx, p->vdiag, p->ev, p->ec, (float *)H, ldh,
              2.0 * inv_nk);
   BSE_HIP_CHECK(hipGetLastError());
+  const int64_t nw = int64_t(p->nqorb) * p->nmb * p->nmb;  // a multiple of 4096
+  __bf16 *wh = reinterpret_cast<__bf16 *>(ws), *wl = wh + nw;
+  const int64_t n4 = nw / 4;
+  BSE_LAUNCH("k_split_w", k_split_w, dim3((unsigned)std::min<int64_t>((n4 + NT - 1) / NT, 8192)),
+             dim3(NT), 0, s, n4, (const float4 *)p->w, (bf16x4 *)wh, (bf16x4 *)wl);
+  BSE_HIP_CHECK(hipGetLastError());
   constexpr int KC = 2;
   dim3 gf((unsigned)((nk + KC - 1) / KC), (unsigned)nk);
 #define BSE_BF3_CASE(M)                                                                       \
   case M:                                                                                   \
     BSE_LAUNCH("k_direct_bf3", (k_direct_bf3<M, KC>), gf, dim3(NT), 0, s, n1, n2, n3, p->nv,  \
                p->nc, p->qorb, p->pidx, p->pconj, (const float *)p->mv, (const float *)p->mc, \
-               (const float *)p->w, (float *)H, ldh, inv_nk);                                \
+               wh, wl, (float *)H, ldh, inv_nk);                                         \
     break;
   switch (p->nmb / 64) {
     BSE_BF3_CASE(1)
