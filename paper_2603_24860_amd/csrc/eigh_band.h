@@ -124,6 +124,7 @@ __device__ __forceinline__ void b_sb_pstart(const Desc &D, int64_t j0, int wg) {
 constexpr int PCT = 512;
 constexpr int PS_ = PCT / SBW;   // row slots of a workgroup
 constexpr int PK = SBR / PS_;    // rows per thread
+static_assert(SBR % 64 == 0 && SBR % PS_ == 0, "panel rows: whole 64-row chunks and slots");
 __device__ __forceinline__ void b_sb_pcol(const Desc &D, int64_t j0, int c, int nw, int wg) {
   __shared__ double2 red[PS_][SBW], red2[PS_][SBW];
   __shared__ double2 top[SBW], gs[SBW], vcol[SBR], vnext[SBR];

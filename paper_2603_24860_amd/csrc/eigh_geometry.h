@@ -116,7 +116,7 @@ struct Desc {
 // form, one sweep per column, as tasks of one wave each.
 constexpr int SBW = 32;      // band half-width = panel width
 constexpr int LDB = 2 * SBW; // band pitch: the band and the fill of one bulge
-constexpr int SBR = 256;     // panel rows per workgroup of the panel kernels
+constexpr int SBR = 64;      // panel rows per workgroup of the panel kernels
 constexpr int SBNS = 8;      // K splits of the panel product X = A22 U
 constexpr int SBHM = 64;     // rows of X per workgroup of that product
 static_assert(SBW == NBK, "the stage-1 update reuses the NBK-wide trailing update");
