@@ -363,7 +363,9 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
   constexpr int AL = SBHM * KC / ENT;  // complex A entries per thread and slab
   constexpr int BL = BN * KC / ENT;    // complex U entries per thread and slab
   constexpr int FLUSH = F32 ? 128 / KC : 1 << 30;  // slabs between FP64 sums (128 terms)
-  __shared__ __attribute__((aligned(16))) TA As[BM * P];
+  constexpr int PT = BM + 16 / int(sizeof(TA));  // pitch of a K-major A slab
+  constexpr int AS = BM * P > BK * PT ? BM * P : BK * PT;
+  __shared__ __attribute__((aligned(16))) TA As[AS];
   __shared__ __attribute__((aligned(16))) TA Bs[BN * P];
   const int64_t n = D.n, p0 = j0 + SBW, m = n - p0;
   const int rb = wg / SBNS, sp = wg % SBNS;
@@ -387,6 +389,12 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) accd[mi][j] = 0;
   CA ra[AL], rbv[BL];
+  // Only entries on or below the diagonal are read (the trailing update keeps
+  // just the lower triangle up to date); an entry above it is the conjugate
+  // of its mirror.  A slab wholly left of this row block's diagonal reads
+  // rows (thread: row ar, columns ak ..); one wholly right of it reads the
+  // mirror's rows (thread: column kt, rows rt .. rt + AL - 1) and is staged
+  // K-major, as it comes; a slab across the diagonal reads entry by entry.
   // Whole slabs (a uniform condition) load 16-byte vectors unconditionally
   // (aligned: p0, the slab start and the thread offsets are multiples of 8
   // complex entries, lda of 16); only the last, partial slab of a split
@@ -394,26 +402,60 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
   // zeroed when staged.
   typedef typename std::conditional<F32, float4, double2>::type V16;
   constexpr int PER = 16 / int(sizeof(CA));  // complex entries per 16-byte load
+  const int kt = tid / (SBHM / AL), rt = (tid % (SBHM / AL)) * AL;
+  static_assert(KC * (SBHM / AL) == ENT, "one mirror piece per thread");
+  const CA *atp = A + p0 * D.lda + p0 + r0 + rt;  // + k lda: A[p0 + k][p0 + r0 + rt ..]
+  auto side = [&](int64_t kk) { return kk + KC - 1 <= r0 ? 0 : (kk >= r0 + SBHM ? 1 : 2); };
   auto load = [&](int64_t kk) {
-    if (kk + KC <= k1) {
+    const int sd = side(kk);
+    if (sd == 0 && kk + KC <= k1) {
       const V16 *a16 = reinterpret_cast<const V16 *>(ap + kk + ak);
-      const V16 *u16 = reinterpret_cast<const V16 *>(up + kk + bk);
+#pragma unroll
+      for (int i = 0; i < AL / PER; ++i) {
+        const V16 v = a16[i];
+        memcpy(&ra[PER * i], &v, 16);
+      }
+    } else if (sd == 1 && kk + KC <= k1 && r0 + rt + AL <= m) {
+      const V16 *a16 = reinterpret_cast<const V16 *>(atp + (kk + kt) * D.lda);
 #pragma unroll
       for (int i = 0; i < AL / PER; ++i) {
         const V16 v = a16[i];
         memcpy(&ra[PER * i], &v, 16);
       }
 #pragma unroll
+      for (int i = 0; i < AL; ++i) ra[i].y = -ra[i].y;
+    } else if (sd == 1) {
+      const int64_t k = kk + kt;
+#pragma unroll
+      for (int i = 0; i < AL; ++i) {
+        const CA v = (k < k1 && r0 + rt + i < m) ? atp[k * D.lda + i] : CA{0, 0};
+        ra[i] = CA{v.x, -v.y};
+      }
+    } else {
+      const int64_t r = r0 + ar;
+#pragma unroll
+      for (int i = 0; i < AL; ++i) {
+        const int64_t k = kk + ak + i;
+        CA v = {0, 0};
+        if (k < k1 && r < m) {
+          if (k <= r) {
+            v = A[(p0 + r) * D.lda + p0 + k];
+          } else {
+            v = A[(p0 + k) * D.lda + p0 + r];
+            v.y = -v.y;
+          }
+        }
+        ra[i] = v;
+      }
+    }
+    if (kk + KC <= k1) {
+      const V16 *u16 = reinterpret_cast<const V16 *>(up + kk + bk);
+#pragma unroll
       for (int i = 0; i < BL / PER; ++i) {
         const V16 v = u16[i];
         memcpy(&rbv[PER * i], &v, 16);
       }
     } else {
-#pragma unroll
-      for (int i = 0; i < AL; ++i) {
-        const int64_t kx = kk + ak + i;
-        ra[i] = kx < k1 ? ap[kx] : CA{0, 0};
-      }
 #pragma unroll
       for (int i = 0; i < BL; ++i) {
         const int64_t kx = kk + bk + i;
@@ -424,14 +466,25 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
   if (k0 < k1) load(k0);
   int slab = 0;
   for (int64_t kk = k0; kk < k1; kk += KC, ++slab) {
+    if (side(kk) == 1) {
 #pragma unroll
-    for (int i = 0; i < AL; ++i) {
-      const int kq = ak + i;
-      const TA ax = arow_ok ? ra[i].x : TA(0), ay = arow_ok ? ra[i].y : TA(0);
-      As[(2 * ar) * P + 2 * kq] = ax;
-      As[(2 * ar) * P + 2 * kq + 1] = ay;
-      As[(2 * ar + 1) * P + 2 * kq] = ay;
-      As[(2 * ar + 1) * P + 2 * kq + 1] = -ax;
+      for (int i = 0; i < AL; ++i) {
+        // real K rows 2 kt (re, im) and 2 kt + 1 (im, -re) of A rows rt + i
+        const int rr = rt + i;
+        const TA ax = ra[i].x, ay = ra[i].y;  // rows past m were loaded as 0
+        *reinterpret_cast<CA *>(As + (2 * kt) * PT + 2 * rr) = CA{ax, ay};
+        *reinterpret_cast<CA *>(As + (2 * kt + 1) * PT + 2 * rr) = CA{ay, -ax};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < AL; ++i) {
+        const int kq = ak + i;
+        const TA ax = arow_ok ? ra[i].x : TA(0), ay = arow_ok ? ra[i].y : TA(0);
+        As[(2 * ar) * P + 2 * kq] = ax;
+        As[(2 * ar) * P + 2 * kq + 1] = ay;
+        As[(2 * ar + 1) * P + 2 * kq] = ay;
+        As[(2 * ar + 1) * P + 2 * kq + 1] = -ax;
+      }
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
@@ -441,7 +494,10 @@ __device__ __forceinline__ void b_sb_hemm(const Desc &D, int64_t j0, int wg) {
     }
     __syncthreads();
     if (kk + KC < k1) load(kk + KC);
-    mfma_slab<TA, MI, NI, BK>(acc, As, Bs, wm0, wn0, lane);
+    if (side(kk) == 1)
+      mfma_slab_at<TA, MI, NI, BK, PT>(acc, As, Bs, wm0, wn0, lane);
+    else
+      mfma_slab<TA, MI, NI, BK>(acc, As, Bs, wm0, wn0, lane);
     __syncthreads();
     if (F32 && (slab + 1) % FLUSH == 0) {
 #pragma unroll
@@ -563,7 +619,9 @@ __device__ __forceinline__ void b_sb_w(const Desc &D, int64_t j0, int wg) {
     for (int q = 0; q < 8; ++q) D.W[int64_t(8 * lg + q) * D.ldv + p0 + r] = x[q];
 }
 
-// trailing update of the panel: A[p0:, p0:] -= V W^dag + W V^dag
+// trailing update of the panel: A[p0:, p0:] -= V W^dag + W V^dag.  From HER_TRI_M
+// trailing rows on only the tiles on or below the diagonal are updated (no
+// mirror tiles): the later panels read A on or below its diagonal only.
 template <typename TA>
 __device__ __forceinline__ void b_sb_her2k(const Desc &D, int64_t p0, int wg) {
   constexpr int BN = HerTile<TA, 0>::BN;
@@ -575,7 +633,7 @@ __device__ __forceinline__ void b_sb_her2k(const Desc &D, int64_t p0, int wg) {
     while (by * (by + 1) / 2 > wg) --by;
     while ((by + 1) * (by + 2) / 2 <= wg) ++by;
     const int64_t bx = wg - by * (by + 1) / 2;
-    b_her2k<TA, 0>(D.n, p0, SBW, D.V, D.W, D.ldv, (TA *)D.A, D.lda, bx, by, true);
+    b_her2k<TA, 0>(D.n, p0, SBW, D.V, D.W, D.ldv, (TA *)D.A, D.lda, bx, by, false);
   }
 }
 template <typename TA>
@@ -630,18 +688,20 @@ __global__ __launch_bounds__(ENT) void k_sb_her2k(Desc D, int64_t p0) {
 //   k = 0: the new reflector annihilates column i below row i + 1 (e_i =
 //          beta);
 //   both: the two-sided update of the diagonal block D = A[R_k, R_k].
-// Thread t holds entries (p, q) = (t % 32, g + 8 u), g = t / 32, u = 0 .. 3,
+// Thread t holds entries (p, q) = (t % 32, g + BCG u), g = t / 32, u < BCU,
 // of each block: a wave holds g = 2 w, 2 w + 1, so sums over q combine the
-// two halves of a wave and then the four waves in LDS; sums over p are taken
+// two halves of a wave and then the waves in LDS; sums over p are taken
 // from an LDS copy.  Loads are coalesced along p (the band is stored by
 // columns); D's upper triangle comes from its lower one through LDS.
-constexpr int BCT = 256;
+constexpr int BCT = 512;
 constexpr int BCU = SBW * SBW / BCT;  // entries per thread and block
+constexpr int BCG = BCT / SBW;        // row groups g (q = g + BCG u)
+constexpr int BCR = SBW / BCG;        // rows p per group in the sums over p
 __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi) {
   __shared__ double2 Ms[SBW][SBW + 1];      // D in full, then O
   __shared__ double2 part[BCT / 64][SBW];   // per-wave sums over q
   __shared__ double2 c0s[SBW];              // column 0 of O after the right update
-  __shared__ double2 zp[BCT / SBW][SBW];    // partial sums over p of conj(u) O
+  __shared__ double2 zp[BCG][SBW];    // partial sums over p of conj(u) O
   __shared__ double xsum;
   const int64_t n = D.n, i = ihi - int64_t(blockIdx.x), k = t - 2 * i;
   const int64_t rk = i + 1 + k * SBW, rp = k > 0 ? rk - SBW : i;
@@ -652,7 +712,7 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   double2 o[BCU], uq[BCU], dl[BCU];
 #pragma unroll
   for (int u = 0; u < BCU; ++u) {
-    const int q = g + 8 * u;
+    const int q = g + BCG * u;
     const int64_t ao = k > 0 ? (rp + q) * LDB + SBW + p - q : i * LDB + 1 + p;
     o[u] = band[ao];
     uq[u] = D.rfl[i * SBW + q];
@@ -662,7 +722,7 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   const double2 tprev = D.rtau[i];
 #pragma unroll
   for (int u = 0; u < BCU; ++u) {
-    const int q = g + 8 * u;
+    const int q = g + BCG * u;
     o[u] = csel(p < L && (k > 0 || q == 0), o[u], double2{0, 0});
     const bool in = p < L && q <= p;
     dl[u] = csel(in, dl[u], double2{0, 0});
@@ -684,7 +744,7 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   __syncthreads();  // Ms (D in full) and the partial sums of O u
   double2 dm[BCU];
 #pragma unroll
-  for (int u = 0; u < BCU; ++u) dm[u] = Ms[p][g + 8 * u];
+  for (int u = 0; u < BCU; ++u) dm[u] = Ms[p][g + BCG * u];
   if (k > 0) {
     double2 y = part[0][p];
 #pragma unroll
@@ -709,18 +769,18 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   double2 uc[BCU];
 #pragma unroll
   for (int u = 0; u < BCU; ++u) {
-    const int q = g + 8 * u;
+    const int q = g + BCG * u;
     uc[u] = csel(q == 0, double2{1, 0}, csel(q < L, cmul(sc, c0s[q]), double2{0, 0}));
   }
   if (k > 0) {
     // z[q] = sum_p conj(u[p]) O[p][q]; O -= conj(tau) u z^T (q >= 1)
 #pragma unroll
-    for (int u = 0; u < BCU; ++u) Ms[p][g + 8 * u] = o[u];
+    for (int u = 0; u < BCU; ++u) Ms[p][g + BCG * u] = o[u];
     __syncthreads();
-    double2 z = {0, 0};  // column p of O over the rows 4 g .. 4 g + 3
+    double2 z = {0, 0};  // column p of O over the rows BCR g .. BCR g + BCR - 1
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int pr = 4 * g + a;
+    for (int a = 0; a < BCR; ++a) {
+      const int pr = BCR * g + a;
       const double2 upr = csel(pr == 0, double2{1, 0}, csel(pr < L, cmul(sc, c0s[pr]), double2{0, 0}));
       z = cadd(z, cmulc(upr, Ms[pr][p]));
     }
@@ -729,10 +789,10 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
     const double2 cu = cmul(cconj(tau), up);
 #pragma unroll
     for (int u = 0; u < BCU; ++u) {
-      const int q = g + 8 * u;
+      const int q = g + BCG * u;
       double2 zq = zp[0][q];
 #pragma unroll
-      for (int gg = 1; gg < BCT / SBW; ++gg) zq = cadd(zq, zp[gg][q]);
+      for (int gg = 1; gg < BCG; ++gg) zq = cadd(zq, zp[gg][q]);
       o[u] = csel(q == 0, csel(p == 0, double2{beta, 0}, double2{0, 0}), csub(o[u], cmul(cu, zq)));
     }
   } else {
@@ -760,7 +820,7 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   const double2 wp = csub(cmul(tau, yp), cscale(0.5 * t2 * gam, up));
 #pragma unroll
   for (int u = 0; u < BCU; ++u) {
-    const int q = g + 8 * u;
+    const int q = g + BCG * u;
     double2 yq = part[0][q];
 #pragma unroll
     for (int w = 1; w < BCT / 64; ++w) yq = cadd(yq, part[w][q]);
@@ -775,13 +835,13 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   double2 *sk = D.sink + tid % SINK;
 #pragma unroll
   for (int u = 0; u < BCU; ++u) {
-    const int q = g + 8 * u;
+    const int q = g + BCG * u;
     double2 *dst = k > 0 ? band + (rp + q) * LDB + SBW + p - q : (q == 0 ? band + i * LDB + 1 + p : sk);
     *dst = o[u];
   }
 #pragma unroll
   for (int u = 0; u < BCU; ++u) {
-    const int q = g + 8 * u;
+    const int q = g + BCG * u;
     double2 *dst = (q <= p && p < L) ? band + (rk + q) * LDB + p - q : sk;
     *dst = dm[u];
   }

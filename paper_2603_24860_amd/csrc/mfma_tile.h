@@ -80,6 +80,34 @@ __device__ __forceinline__ void mfma_slab(typename Mfma<T>::acc_t (&acc)[MI][NI]
   }
 }
 
+// The same with A stored K-major: At[k * PT + row] (the four K values of a
+// lane are read one by one down a column; the 16 rows of a fragment are
+// consecutive in LDS).
+template <typename T, int MI, int NI, int BK, int PT>
+__device__ __forceinline__ void mfma_slab_at(typename Mfma<T>::acc_t (&acc)[MI][NI], const T *At,
+                                             const T *Bs, int wm0, int wn0, int lane) {
+  constexpr int P = Pitch<T, BK>::value;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < BK; kk += 16) {
+    typename Mfma<T>::frag_t a[MI], b[NI];
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[mi][i] = At[(kk + 4 * g + i) * PT + wm0 + 16 * mi + Mfma<T>::arow(r)];
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+      b[ni] = lds_frag<T>(Bs + (wn0 + 16 * ni + r) * P + kk + 4 * g);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = Mfma<T>::mma(a[mi][i], b[ni][i], acc[mi][ni]);
+  }
+}
+
 template <typename T, int MI, int NI>
 __device__ __forceinline__ void acc_zero(typename Mfma<T>::acc_t (&acc)[MI][NI]) {
 #pragma unroll
