@@ -191,6 +191,12 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
         C.range("u", int64_t(SBW - 1) * D.ldv + p0 + k0, int64_t(SBW - 1) * D.ldv + p0 + k1,
                 "k_sb_hemm U");
       }
+      // entries above the diagonal come from their mirrors A[p0 + k][p0 + r], r < m
+      if (k0 < k1 && k1 > r0 + 1 && r0 < m) {
+        const int64_t kf = std::max<int64_t>(k0, r0 + 1);
+        C.at("A", (p0 + kf) * D.lda + p0 + ra, "k_sb_hemm mirror");
+        C.at("A", (p0 + k1 - 1) * D.lda + p0 + rz, "k_sb_hemm mirror");
+      }
       for (int64_t a = r0; a < std::min<int64_t>(r0 + SBHM, m); a += SBHM - 1)
         for (int l = 0; l < SBW; l += SBW - 1)
           C.at("xp", (sp * SBW + l) * D.ldv + p0 + a, "k_sb_hemm out");
