@@ -104,6 +104,9 @@ __device__ __forceinline__ void b_sb_pstart(const Desc &D, int64_t j0, int wg) {
     if (r < m) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) D.pb[r * SBW + 8 * part + u] = x[ch][u];
+      if (r == 0)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) D.ptop[8 * part + u] = x[ch][u];
       if (r >= 1)
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc[u] = cadd(acc[u], cmulc(x0, x[ch][u]));
@@ -116,7 +119,11 @@ __device__ __forceinline__ void b_sb_pstart(const Desc &D, int64_t j0, int wg) {
 // workgroup's rows (the reflector is stored below the diagonal of pb, beta on
 // it), then the partial Gram row of column c + 1 and the partial column c of
 // V^dag V.  Records of column c are read from grec[c & 1], those of c + 1
-// written to grec[(c + 1) & 1].  Thread t owns column j = t % SBW of the rows
+// written to grec[(c + 1) & 1].  Row c of the panel, which every workgroup
+// needs, is read from ptop[c & 1], not from pb: the workgroup holding it
+// rewrites it in pb during the same launch (a late workgroup would read the
+// updated row); that workgroup writes row c + 1, as updated here, to
+// ptop[(c + 1) & 1].  Thread t owns column j = t % SBW of the rows
 // s + PS_ k (slot s = t / SBW, k = 0 .. SBR / PS_ - 1): row accesses are
 // coalesced and every reduction over rows is local, then over the PS_ slots
 // in LDS; the values of columns c and c + 1 that every thread of a row needs
@@ -139,7 +146,7 @@ __device__ __forceinline__ void b_sb_pcol(const Desc &D, int64_t j0, int c, int 
   double2 rr[RU];
 #pragma unroll
   for (int u = 0; u < RU; ++u) rr[u] = rin[std::min(sl + PS_ * u, nw - 1) * SBW + j];
-  const double2 tp = D.pb[int64_t(c) * SBW + j];
+  const double2 tp = D.ptop[(c & 1) * SBW + j];
   double2 x[PK];
 #pragma unroll
   for (int k = 0; k < PK; ++k) x[k] = D.pb[std::min<int64_t>(rb + sl + PS_ * k, m - 1) * SBW + j];
@@ -191,6 +198,12 @@ __device__ __forceinline__ void b_sb_pcol(const Desc &D, int64_t j0, int c, int 
   for (int k = 0; k < PK; ++k) {
     const int64_t r = rb + sl + PS_ * k;
     double2 *dst = (r < m && j >= c) ? D.pb + r * SBW + j : D.sink + tid % SINK;
+    *dst = x[k];
+  }
+#pragma unroll
+  for (int k = 0; k < PK; ++k) {
+    const int64_t r = rb + sl + PS_ * k;
+    double2 *dst = (r == c + 1 && r < m) ? D.ptop + ((c + 1) & 1) * SBW + j : D.sink + tid % SINK;
     *dst = x[k];
   }
   __syncthreads();
@@ -754,11 +767,13 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
     for (int u = 0; u < BCU; ++u) o[u] = csub(o[u], cmul(ty, cconj(uq[u])));
   }
   // ---- new reflector from column 0 (held by the threads with g = 0, u = 0) ----
-  if (g == 0) {
-    c0s[p] = o[0];
-    double xs = (p >= 1 && p < L) ? o[0].x * o[0].x + o[0].y * o[0].y : 0.0;
-    xs = wave_sum(xs);  // lanes 32 .. 63 of wave 0 (g = 1) hold no column-0 entries
-    if (p == 0) xsum = xs;
+  if (g == 0) c0s[p] = o[0];
+  if (wv == 0) {
+    // all 64 lanes take part in the sum (lanes 32 .. 63, g = 1, hold no
+    // column-0 entries and add 0)
+    double xs = (g == 0 && p >= 1 && p < L) ? o[0].x * o[0].x + o[0].y * o[0].y : 0.0;
+    xs = wave_sum(xs);
+    if (tid == 0) xsum = xs;
   }
   __syncthreads();  // c0s, xsum; the reads of Ms and part are done
   double beta;

@@ -100,6 +100,7 @@ struct Desc {
   double2 *sbt;              // [SBW][SBW] block-reflector factor T of the panel
   double2 *sbz;              // [SBW][SBW] Z = T^dag V^dag X
   double2 *sbsc;             // [2][SBW] tau of each panel column, (beta, 0) of each
+  double2 *ptop;             // [2][SBW] row c of the panel before column c's reflector
   void *u;                   // [SBW][ldv] U = V T in the storage type of A
   double2 *xp;               // [SBNS][SBW][ldv] split-K partial sums of X = A22 U
   double2 *yrec;             // [nw][SBW][SBW] partial sums of V^dag X
@@ -290,6 +291,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     t.sbt = (double2 *)take(SBW * SBW * 16);
     t.sbz = (double2 *)take(SBW * SBW * 16);
     t.sbsc = (double2 *)take(2 * SBW * 16);
+    t.ptop = (double2 *)take(2 * SBW * 16);
     t.u = take(size_t(SBW) * ldv * (a_fp64 ? 16 : 8));
     t.xp = (double2 *)take(size_t(SBNS) * SBW * ldv * 16);
     t.yrec = (double2 *)take(size_t(g_sb_nx(n)) * SBW * SBW * 16);

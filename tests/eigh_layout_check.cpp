@@ -118,6 +118,7 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
   C.add("sbt", D.sbt, 16, SBW * SBW);
   C.add("sbz", D.sbz, 16, SBW * SBW);
   C.add("sbsc", D.sbsc, 16, 2 * SBW);
+  C.add("ptop", D.ptop, 16, 2 * SBW);
   C.add("u", D.u, elu, SBW * D.ldv);
   C.add("xp", D.xp, 16, int64_t(SBNS) * SBW * D.ldv);
   C.add("yrec", D.yrec, 16, g_sb_nx(n) * SBW * SBW);
@@ -142,6 +143,7 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
         C.range("pb", (m - 1) * SBW, m * SBW, "k_sb_pcol clamped");
       }
       C.range("grec", wg * SBW, wg * SBW + SBW, "k_sb_pstart");
+      if (wg == 0) C.range("ptop", 0, SBW, "k_sb_pstart top");
       for (int c = 0; c < nref; ++c) {
         C.range("grec", ((c + 1) & 1) * nw * SBW + wg * SBW, ((c + 1) & 1) * nw * SBW + wg * SBW + SBW,
                 "k_sb_pcol out");
@@ -150,7 +152,8 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
     }
     for (int c = 0; c < nref; ++c) {
       C.range("grec", (c & 1) * nw * SBW, (c & 1) * nw * SBW + nw * SBW, "k_sb_pcol in");
-      C.range("pb", int64_t(c) * SBW, int64_t(c) * SBW + SBW, "k_sb_pcol top");
+      C.range("ptop", (c & 1) * SBW, (c & 1) * SBW + SBW, "k_sb_pcol top");
+      if (c + 1 < m) C.range("ptop", ((c + 1) & 1) * SBW, ((c + 1) & 1) * SBW + SBW, "k_sb_pcol next top");
       C.at("sbsc", c, "k_sb_pcol");
       C.at("sbsc", SBW + c, "k_sb_pcol");
     }

@@ -190,3 +190,42 @@ def test_switch_point_query(lib, two_stage_from):
     two_stage_from(1 << 20)
     assert lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100) == wr
     assert lib.bse_block_eigh_ws(4800, 0, lib.FP32) == w1
+
+
+def test_two_stage_with_concurrent_kernels(lib, two_stage_from):
+    """A second stream keeps the GPU busy with matrix products while the
+    two-stage solve runs on the current one, so the workgroups of one launch
+    start at different times (a panel column once read the panel's top row
+    from memory that the first workgroup of the same launch rewrites).
+    FP64 working storage: eigenvalues within 1e-11 |lam|, poles and
+    strengths as in the other FP64 cases; then the FP32 storage bar."""
+    n = 4500
+    say("two-stage under concurrent load", n)
+    two_stage_from(4096)
+    A, b, lam, qb = _householder_hermitian(n, seed=97, mult=3)
+    X = torch.randn(4096, 4096, device="cuda")
+    side = torch.cuda.Stream()
+    for prec, h_dtype in ((lib.FP64, torch.complex128), (lib.FP32, torch.complex64)):
+        Hmu = torch.as_tensor(A, dtype=h_dtype, device="cuda")
+        Bmu = torch.as_tensor(b, dtype=torch.complex128, device="cuda")
+        h64 = 1 if h_dtype == torch.complex128 else 0
+        ws = torch.full((lib.bse_block_eigh_ws(n, h64, prec),), 255, dtype=torch.uint8, device="cuda")
+        om = torch.empty(n, dtype=torch.float64, device="cuda")
+        po, os_ = torch.empty_like(om), torch.empty_like(om)
+        torch.cuda.synchronize()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            Y = X
+            for _ in range(200):
+                Y = torch.tanh(Y @ X * 1e-3)
+        lib.bse_block_eigh(Hmu, Bmu, prec, om, po, os_, ws)
+        torch.cuda.synchronize()
+        assert torch.isfinite(Y).all()
+        om, po, os_ = om.cpu().numpy(), po.cpu().numpy(), os_.cpu().numpy()
+        err = np.abs(om - lam).max()
+        say("  prec", prec, "max eigenvalue error", err)
+        if prec == lib.FP64:
+            assert err < 1e-11 * np.abs(lam).max()
+            _check_poles(lam, qb, po, os_)
+        else:
+            assert err < 1e-4
