@@ -34,7 +34,7 @@ class Request:
     (seconds relative to the start of Server.run) and the number of lowest
     eigenvalues to refine in FP64 (0: none)."""
     __slots__ = ("rid", "system", "prec", "arrival", "nrefine", "start", "done", "result", "ev",
-                 "bufs", "footprint", "status")
+                 "bufs", "footprint", "status", "attempts", "errors")
 
     def __init__(self, rid, system, prec, arrival, nrefine=0):
         self.rid, self.system, self.prec, self.arrival = rid, system, prec, arrival
@@ -45,6 +45,8 @@ class Request:
         self.bufs = None
         self.footprint = 0
         self.status = "waiting"
+        self.attempts = 0
+        self.errors = []
 
 
 def _free_plans(cache):
@@ -102,11 +104,21 @@ class Server:
     """slots: HIP streams (requests in flight); hbm_budget: bytes of HBM the
     requests in flight may hold together; a request whose footprint exceeds
     big_bytes is large, and at most big_slots large requests are in flight, so
-    small requests are not queued behind long ones."""
+    small requests are not queued behind long ones.
+
+    A request whose launch raises (a BseError from the library, a device
+    allocation failure) or whose results come back non-finite gives back its
+    slot and HBM share and is queued again, up to max_retries more attempts;
+    after that it is marked "failed" (Server.failed) and the others go on.
+    fault(req), when set, is called before each attempt's work and may raise:
+    a host-side hook that lets tests make an attempt fail."""
 
     def __init__(self, slots=4, hbm_budget=288e9, device="cuda", big_bytes=4e9, big_slots=1,
-                 seed=False):
+                 seed=False, max_retries=2):
         self.device = device
+        self.max_retries = max_retries
+        self.fault = None
+        self.failed = []
         self.seed = seed
         self.nslots = slots
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
@@ -137,6 +149,8 @@ class Server:
         eig_prec = B.FP32 if prec == B.BF16X3 else prec
         n = ss.blk.n
         h = st.cuda_stream
+        if self.fault is not None:
+            self.fault(req)
         with torch.cuda.stream(st):
             Hmu = torch.empty((n, n), dtype=CDT[prec], device=self.device)
             Bmu = torch.empty(n, dtype=torch.complex128, device=self.device)
@@ -199,8 +213,31 @@ class Server:
                 self.max_big = max(self.max_big, self.big_inflight)
             req.start = now
             req.status = "running"
-            self._launch(req, slot)
+            req.attempts += 1
+            try:
+                self._launch(req, slot)
+            except (B.BseError, torch.cuda.OutOfMemoryError) as e:
+                req.bufs = req.ev = None
+                self._release(req, slot)
+                self._retry_or_fail(req, e)
+                break  # let the requests in flight finish before the next attempt
             self.running[req.rid] = (req, slot)
+
+    def _release(self, req, slot):
+        self.used -= req.footprint
+        if req.footprint > self.big_bytes:
+            self.big_inflight -= 1
+        req.footprint = 0
+        self.free.append(slot)
+
+    def _retry_or_fail(self, req, err):
+        req.errors.append(str(err))
+        if req.attempts <= self.max_retries:
+            req.status = "waiting"
+            self.waiting.appendleft(req)  # first in line again
+        else:
+            req.status = "failed"
+            self.failed.append(req)
 
     def _poll(self):
         done = [rid for rid, (req, _) in self.running.items() if req.ev.query()]
@@ -209,22 +246,23 @@ class Server:
             req, slot = self.running.pop(rid)
             host = req.bufs[-1]
             n = host["omega"].numel()
-            req.result = {k: v.numpy().copy() for k, v in host.items()}
+            result = {k: v.numpy().copy() for k, v in host.items()}
+            req.bufs = None
+            req.ev = None
+            self._release(req, slot)
+            if not all(np.isfinite(v).all() for v in result.values()):
+                self._retry_or_fail(req, "non-finite results")
+                continue
+            req.result = result
             req.result["lowest"] = req.result["omega"][:min(100, n)]
             req.done = now
             req.status = "done"
-            req.bufs = None
-            req.ev = None
-            self.used -= req.footprint
-            if req.footprint > self.big_bytes:
-                self.big_inflight -= 1
-            self.free.append(slot)
             self.finished.append(req)
         return len(done)
 
     def run(self, requests, t0=None):
         """Serve `requests` (sorted by arrival, seconds relative to t0); returns
-        when all are finished or rejected."""
+        the finished ones when every request is finished, rejected or failed."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         t0 = time.perf_counter() if t0 is None else t0
         for r in pending:

@@ -181,3 +181,23 @@ def test_partner_basis_matches_projector(cfg, irrep, rows):
         assert np.abs(Pm @ U - U).max() < 1e-13
     with pytest.raises(B.BseError):
         B.bse_block_basis(gname, cfg["grid"], "A1g", cfg["nv"], cfg["nc"], partner=0)
+
+
+def test_hip_failure_maps_to_edevice():
+    """A failing HIP runtime call surfaces as BSE_EDEVICE with a message
+    naming the call.  On a host without a GPU the first runtime call of an
+    entry point fails for real (hipGetDevice / hipEventCreate), so this runs
+    where no GPU is visible; no kernel is launched."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("needs a host without a GPU")
+    buf = (ctypes.c_int32 * 2)()
+    us = ctypes.c_double()
+    for mode, call in ((1, b"hipGetDevice"), (0, b"hipEventCreate")):
+        assert B.lib.bse_sync_probe(mode, 1, 1, buf, ctypes.byref(us), None) == _lib.EDEVICE
+        msg = B.lib.bse_last_error()
+        assert call in msg and b"failed" in msg, msg
+    # the Python binding raises it as a BseError with that status
+    with pytest.raises(B.BseError) as e:
+        B.check(B.lib.bse_sync_probe(1, 1, 1, buf, ctypes.byref(us), None))
+    assert e.value.status == _lib.EDEVICE

@@ -189,3 +189,52 @@ def test_seeded_served(env):
         ref = solo[(r.system, r.prec, r.nrefine)]
         for k in ("omega", "pole", "osc", "eps2"):
             assert np.array_equal(r.result[k], ref[k]), (r.rid, r.system, k)
+
+
+def test_failed_attempts_are_retried(env, monkeypatch):
+    """A request whose attempt fails gives back its slot and HBM share and is
+    queued again; its result equals an undisturbed solve bitwise.  One that
+    fails on every attempt ends as failed after max_retries and holds up no
+    other request.  Failures are made on the host: Server.fault raises before
+    an attempt's work (as a failing library call would), and a wrapped
+    bse_spectrum writes NaN into one attempt's spectrum, which the server
+    detects when the request completes."""
+    from paper_2603_24860_amd import serve
+    from paper_2603_24860_amd.serve import Request
+    B = env[0]
+    say("served retries")
+    base = _server(env, 1).run([Request(0, "oh4/fp32", B.FP32, 0.0)])[0].result
+    orig = serve.B.bse_spectrum
+    state = {"nan_rid": 4, "nan_done": False}
+
+    def spectrum(po, osc, scale, eta, w, e2, stream=None):
+        orig(po, osc, scale, eta, w, e2, stream=stream)
+        if state.pop("poison", False):
+            e2.fill_(float("nan"))  # queued on the request's stream
+
+    monkeypatch.setattr(serve.B, "bse_spectrum", spectrum)
+    srv = _server(env, 2, max_retries=2)
+
+    def fault(req):
+        if req.rid in (1, 2) and req.attempts == 1:
+            raise B.BseError(B._lib.EDEVICE, "injected failure of the first attempt")
+        if req.rid == 3:
+            raise B.BseError(B._lib.EDEVICE, "injected failure of every attempt")
+        if req.rid == state["nan_rid"] and not state["nan_done"]:
+            state["nan_done"] = True
+            state["poison"] = True
+
+    srv.fault = fault
+    reqs = [Request(i, "oh4/fp32", B.FP32, 0.0) for i in range(6)]
+    done = srv.run(reqs)
+    by = {r.rid: r for r in reqs}
+    assert sorted(r.rid for r in done) == [0, 1, 2, 4, 5]
+    assert [r.rid for r in srv.failed] == [3]
+    assert by[3].status == "failed" and by[3].attempts == 3 and len(by[3].errors) == 3
+    assert by[1].attempts == 2 and by[2].attempts == 2 and by[4].attempts == 2
+    assert by[0].attempts == 1 and by[5].attempts == 1
+    assert "non-finite" in by[4].errors[0]
+    for r in done:
+        for k in ("omega", "pole", "osc", "eps2"):
+            assert np.array_equal(r.result[k], base[k]), (r.rid, k)
+    assert srv.used == 0 and sorted(srv.free) == [0, 1] and srv.big_inflight == 0
