@@ -1402,6 +1402,14 @@ __device__ __forceinline__ void b_bisect(int64_t n, const double *__restrict__ d
 // are <= sc[4]; its head (first index) gets the cluster centre as pole and
 // beta0^2 times the residue of G(z) = [(z - T)^-1]_00 as strength, the other
 // members get zero strength.  One wave per index; lanes are contour nodes.
+// The contour is a circle about the centre c of radius sqrt(half g) (half:
+// half-width of the cluster, g: distance from c to the nearest eigenvalue
+// outside it), which holds the members at a ratio sqrt(half / g) of its
+// radius and the neighbours at the same ratio beyond it.  A run whose
+// half-width exceeds g / 4 (a dense spectrum, where the gaps of FP32 working
+// storage's tolerance chain many distinct eigenvalues) cannot be held apart
+// that way; it is split into its runs of gaps within the FP64 resolution,
+// each with a contour of its own.
 constexpr int NCONT = 64;  // trapezoidal nodes on the circle (32 in the upper half)
 __device__ __forceinline__ void b_weights(int64_t n, const double *__restrict__ d,
                                                  const double *__restrict__ e2,
@@ -1415,20 +1423,54 @@ __device__ __forceinline__ void b_weights(int64_t n, const double *__restrict__ 
   if (i >= n) return;
   const double ctol = sc[4];
   const double li = omega[i];
-  if (i > 0 && li - omega[i - 1] <= ctol) {
+  // the run of i: consecutive gaps <= ctol, 64 gaps examined per step
+  int64_t i0 = i, j = i;
+  while (i0 > 0) {
+    const int64_t k = i0 - 1 - lane, kc = k < 0 ? 0 : k;  // gap omega[k] .. omega[k + 1]
+    const bool brk = k < 0 || omega[kc + 1] - omega[kc] > ctol;
+    const unsigned long long m = __ballot(brk);
+    if (m) {
+      i0 -= __builtin_ctzll(m);
+      break;
+    }
+    i0 -= 64;
+  }
+  while (j + 1 < n) {
+    const int64_t k = j + lane, kc = k + 1 < n ? k : n - 2;
+    const bool brk = k + 1 >= n || omega[kc + 1] - omega[kc] > ctol;
+    const unsigned long long m = __ballot(brk);
+    if (m) {
+      j += __builtin_ctzll(m);
+      break;
+    }
+    j += 64;
+  }
+  double c, half, g;
+  auto geometry = [&](int64_t a, int64_t b) {
+    c = 0.5 * (omega[a] + omega[b]);
+    half = 0.5 * (omega[b] - omega[a]);
+    g = 1e300;
+    if (a > 0) g = fmin(g, c - omega[a - 1]);
+    if (b + 1 < n) g = fmin(g, omega[b + 1] - c);
+    if (g > 1e299) g = fmax(1.0, sc[2]);
+  };
+  geometry(i0, j);
+  if (half > 0.25 * g) {
+    const double dtol = 8.0 * 2.2e-16 * sqrt(double(n)) * fmax(1.0, sc[2]);
+    int64_t a = i, b = i;
+    while (a > i0 && omega[a] - omega[a - 1] <= dtol) --a;
+    while (b < j && omega[b + 1] - omega[b] <= dtol) ++b;
+    i0 = a;
+    j = b;
+    geometry(i0, j);
+  }
+  if (i != i0) {
     if (lane == 0) {
       pole[i] = li;
       osc[i] = 0.0;
     }
     return;
   }
-  int64_t j = i;
-  while (j + 1 < n && omega[j + 1] - omega[j] <= ctol) ++j;
-  const double c = 0.5 * (omega[i] + omega[j]), half = 0.5 * (omega[j] - omega[i]);
-  double g = 1e300;
-  if (i > 0) g = fmin(g, c - omega[i - 1]);
-  if (j + 1 < n) g = fmin(g, omega[j + 1] - c);
-  if (g > 1e299) g = fmax(1.0, sc[2]);
   const double rad = sqrt(fmax(half, 1e-6 * g) * g);
   double wsum = 0.0;
   if (lane < NCONT / 2) {

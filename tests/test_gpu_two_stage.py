@@ -229,3 +229,51 @@ def test_two_stage_with_concurrent_kernels(lib, two_stage_from):
             _check_poles(lam, qb, po, os_)
         else:
             assert err < 1e-4
+
+
+def test_two_stage_block_of_40000(lib):
+    """The top of the block-size range the served form is specified for:
+    n = 40000, FP32 working storage, built on the GPU as Q diag(lam) Q^dag
+    with Q a product of three reflectors (FP64, then rounded to FP32).
+    Eigenvalues within the FP32 storage bar of the large-block tests
+    (1e-4 sqrt(n / 4500) eV), total oscillator strength within 1e-5 of
+    |Q^dag b|^2 summed, and a weighted pole near each of ten exact
+    eigenvalues spread over the spectrum."""
+    n = 40000
+    say("two-stage n =", n)
+    rng = np.random.default_rng(40000)
+    lam = np.sort(rng.uniform(-10, 10, n))
+    A = torch.diag(torch.as_tensor(lam, dtype=torch.complex128, device="cuda"))
+    us = []
+    for _ in range(3):
+        u = torch.as_tensor(rng.normal(size=n) + 1j * rng.normal(size=n), device="cuda")
+        u /= torch.linalg.norm(u)
+        Au = A @ u
+        uA = u.conj() @ A
+        g = u.conj() @ Au
+        A -= 2 * torch.outer(u, uA)
+        A -= 2 * torch.outer(Au, u.conj())
+        A += (4 * g) * torch.outer(u, u.conj())
+        us.append(u)
+    Hmu = A.to(torch.complex64)
+    del A
+    torch.cuda.empty_cache()
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    qb = torch.as_tensor(b, device="cuda")
+    for u in reversed(us):
+        qb = qb - 2 * u * (u.conj() @ qb)
+    w = (qb.abs() ** 2).cpu().numpy()
+    Bmu = torch.as_tensor(b, dtype=torch.complex128, device="cuda")
+    ws = torch.empty(lib.bse_block_eigh_ws(n, 0, lib.FP32), dtype=torch.uint8, device="cuda")
+    om = torch.empty(n, dtype=torch.float64, device="cuda")
+    po, os_ = torch.empty_like(om), torch.empty_like(om)
+    lib.bse_block_eigh(Hmu, Bmu, lib.FP32, om, po, os_, ws)
+    torch.cuda.synchronize()
+    om, po, os_ = om.cpu().numpy(), po.cpu().numpy(), os_.cpu().numpy()
+    err = np.abs(om - lam).max()
+    say("  max eigenvalue error", err, "total strength", os_.sum(), w.sum())
+    assert err < 1e-4 * math.sqrt(n / 4500)
+    assert abs(os_.sum() - w.sum()) < 1e-5 * w.sum()
+    keep = os_ > 0
+    for i in np.linspace(0, n - 1, 10).astype(int):
+        assert np.abs(po[keep] - lam[i]).min() < 1e-3
