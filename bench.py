@@ -271,14 +271,15 @@ def bench_batched(args):
     bs.close()
 
 
-def bench_served(args, large=False):
+def bench_served(args, large=False, wide=False):
     """Served form: a Poisson stream of BSE solve requests over a mix of
     resident systems (cubic cfg1 / cfg2 / cfg3 shapes and three layered D6h
-    systems of the batched family, blocks of 162 to 10080), FP32 builds or
-    split-BF16 builds with FP64 refinement, continuous batching on four streams
-    with admission by HBM footprint (288 GB).  Every result, and every result of
-    the plain FP64 path it is compared with, is checked against the oracle's
-    stored block spectrum of its system (lowest 100 within 0.1 meV)."""
+    systems of the batched family, blocks of 162 to 10080; wide: all 64
+    systems of the batched family), FP32 builds or split-BF16 builds with FP64
+    refinement, continuous batching on four streams with admission by HBM
+    footprint (288 GB).  Every result, and every result of the plain FP64 path
+    it is compared with, is checked against the oracle's stored block spectrum
+    of its system (lowest 100 within 0.1 meV)."""
     import torch
     import synth
     import workloads
@@ -294,6 +295,8 @@ def bench_served(args, large=False):
             "d6h-8": pick[8], "d6h-13": pick[13], "d6h-20": pick[20]}
     if large:
         cfgs["cfg3"] = synth.config("cfg3")
+    if wide:
+        cfgs = {c["name"]: c for c in d6}
     t0 = time.perf_counter()
     sysobjs = {}
     for name, c in cfgs.items():
@@ -304,7 +307,8 @@ def bench_served(args, large=False):
     # oracle alone) and their frequency grids
     grids = {}
     ref = {}
-    with open(os.path.join(ROOT, "tests", "golden", "served_oracle.json")) as f:
+    with open(os.path.join(ROOT, "tests", "golden",
+                           "served_cfg4_oracle.json" if wide else "served_oracle.json")) as f:
         served = json.load(f)
     for name in cfgs:
         g = served[name] if name in served else oracle_reference(name)
@@ -319,6 +323,9 @@ def bench_served(args, large=False):
            ("d6h-20", "fp32", B.FP32, 0.20, 0)]
     if large:  # a small share of cfg3 requests (T1u block 10080)
         mix += [("cfg3", "fp32", B.FP32, 0.02, 0), ("cfg3", "fp32", B.BF16X3, 0.02, 100)]
+    if wide:  # every system of the batched family, FP32 or refined split BF16
+        mix = ([(name, "fp32", B.FP32, 0.6 / len(cfgs), 0) for name in cfgs]
+               + [(name, "fp32", B.BF16X3, 0.4 / len(cfgs), 100) for name in cfgs])
     wts = np.array([m[3] for m in mix])
     wts /= wts.sum()
 
@@ -337,7 +344,10 @@ def bench_served(args, large=False):
         return out
 
     # warm-up of every request type
-    server(4).run(draw(3 * len(mix)))
+    if wide:
+        server(4).run([Request(i, f"{m[0]}/{m[1]}", m[2], 0.0, m[4]) for i, m in enumerate(mix)])
+    else:
+        server(4).run(draw(3 * len(mix)))
     # plain FP64 GPU form over the same mix, one request after the other
     nplain = 100 if large else 150
     t1 = time.perf_counter()
@@ -380,19 +390,27 @@ def bench_served(args, large=False):
         "n_gpus": 1, "steps": len(done), "warmup": 3 * len(mix),
         "ms_per_step": round(wall * 1e3 / len(done), 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32+bf16x3",
-        "data": "synthetic (seeded; resident cubic cfg1/cfg2" + ("/cfg3" if large else "")
-                + " and three D6h systems)",
-        "config": {"workload": ("cfg5l" if large else "cfg5") + ": Poisson stream over cfg1 "
+        "data": ("synthetic (seeded; the 64 resident D6h systems of the batched family)" if wide
+                 else "synthetic (seeded; resident cubic cfg1/cfg2" + ("/cfg3" if large else "")
+                 + " and three D6h systems)"),
+        "config": {"workload": ("cfg5w: Poisson stream over all 64 D6h systems of the batched "
+                                "family (6x6x1 .. 24x24x1 grids, E1u blocks of %d to %d), FP32 "
+                                "builds or split-BF16 builds with FP64 refinement of the lowest "
+                                "100" % (min(served[n]["n"] for n in cfgs),
+                                         max(served[n]["n"] for n in cfgs)) if wide else
+                                ("cfg5l" if large else "cfg5") + ": Poisson stream over cfg1 "
                                "(T1u 162), cfg2 (T1u 2160), " + ("cfg3 (T1u 10080), " if large
                                                                   else "")
                                + "D6h 8x8x1 / 13x13x1 / 20x20x1 (E1u) systems, FP32 builds or "
-                               "split-BF16 builds with FP64 refinement of the lowest 100"
+                               "split-BF16 builds with FP64 refinement of the lowest 100")
                                + ("; FP32 requests by the seed construction, block projected "
                                   "from the seed pieces (no H)" if args.seed else ""),
                    "requests": len(done),
                    "arrival_rate_per_s": round(lam, 3),
-                   "mix": [{"system": m[0], "precision": {B.FP32: "fp32", B.BF16X3: "bf16x3"}[m[2]],
-                            "weight": m[3], "nrefine": m[4]} for m in mix]},
+                   "mix": ([{"systems": len(cfgs), "fp32_weight": 0.6, "bf16x3_weight": 0.4,
+                             "bf16x3_nrefine": 100}] if wide else
+                           [{"system": m[0], "precision": {B.FP32: "fp32", B.BF16X3: "bf16x3"}[m[2]],
+                             "weight": m[3], "nrefine": m[4]} for m in mix])},
         "latency_ms": {"p50": round(st["p50_ms"], 3), "p99": round(st["p99_ms"], 3),
                        "mean": round(st["mean_ms"], 3)},
         "saturation_solves_per_s": round(sat, 3),
@@ -416,7 +434,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg3",
                     help="cfg1 / cfg2 / cfg3: one system; cfg4: the batched form (64 D6h "
-                         "systems); cfg5: the served form (Poisson request stream); cfg5l: "
+                         "systems); cfg5: the served form (Poisson request stream); cfg5w: "
+                         "the served form over all 64 systems of the batched family; cfg5l: "
                          "the served form with a share of cfg3 requests")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -502,8 +521,8 @@ def main():
     from paper_2603_24860_amd.system import Solver
     if args.workload == "cfg4":
         return bench_batched(args)
-    if args.workload in ("cfg5", "cfg5l"):
-        return bench_served(args, large=args.workload == "cfg5l")
+    if args.workload in ("cfg5", "cfg5l", "cfg5w"):
+        return bench_served(args, large=args.workload == "cfg5l", wide=args.workload == "cfg5w")
 
     prec = {"fp32": B.FP32, "fp64": B.FP64, "bf16x3": B.BF16X3}[args.prec]
     cfg = synth.config(args.workload)
