@@ -59,45 +59,55 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int nb = nv * nc;
   const int64_t N = int64_t(nk) * nb;
   const int64_t a0 = int64_t(blockIdx.y) * (BM / 2), b0 = int64_t(blockIdx.x) * BN;
-  // row pointers of the rows this thread loads
+  // row pointers of the rows this thread loads; rows past N read row 0 and
+  // are zeroed by a mask, so no load sits behind a branch
   const C2 *arow[NA];
   const C2 *brow[NB];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
     const int64_t a = a0 + (tid + NT * u) / KC;
-    arow[u] = a < N ? reinterpret_cast<const C2 *>(mx) +
-                          (int64_t(korb[a / nb]) * nb + a % nb) * nmb
-                    : nullptr;
+    const int64_t ac = a < N ? a : 0;
+    arow[u] = reinterpret_cast<const C2 *>(mx) + (int64_t(korb[ac / nb]) * nb + ac % nb) * nmb;
   }
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int64_t b = b0 + (tid + NT * u) / KC;
-    brow[u] = b < N ? reinterpret_cast<const C2 *>(mx) +
-                          (int64_t(korb[b / nb]) * nb + b % nb) * nmb
-                    : nullptr;
+    const int64_t bc = b < N ? b : 0;
+    brow[u] = reinterpret_cast<const C2 *>(mx) + (int64_t(korb[bc / nb]) * nb + bc % nb) * nmb;
   }
   typename Mfma<T>::acc_t acc[MI][NI];
   acc_zero<T, MI, NI>(acc);
   const int wm0 = (wv >> 1) * (BM / 2), wn0 = (wv & 1) * (BN / 2);
-  for (int i0 = 0; i0 < nmb; i0 += KC) {
+  // every slab's loads are issued together from in-bounds addresses (entries
+  // past nmb read entry nmb - 1 and are zeroed when staged): no load waits
+  // behind a branch
+  C2 xa[NA], xb[NB];
+  T va[NA];
+  auto load = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int it = tid + NT * u, r = it / KC, i = it % KC, I = i0 + i;
-      C2 x = {T(0), T(0)};
-      T vI = T(0);
-      if (arow[u] && I < nmb) {
-        x = arow[u][I];
-        vI = T(vdiag[I]);
-      }
+      const int I = min(i0 + (tid + NT * u) % KC, nmb - 1);
+      xa[u] = arow[u][I];
+      va[u] = T(vdiag[I]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) xb[u] = brow[u][min(i0 + (tid + NT * u) % KC, nmb - 1)];
+  };
+  for (int i0 = 0; i0 < nmb; i0 += KC) {
+    load(i0);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int it = tid + NT * u, r = it / KC, i = it % KC;
+      const T vI = (i0 + i < nmb && a0 + r < N) ? va[u] : T(0);
+      const C2 x = xa[u];
       *reinterpret_cast<C2 *>(As + (2 * r) * P + 2 * i) = C2{x.x * vI, x.y * vI};
       *reinterpret_cast<C2 *>(As + (2 * r + 1) * P + 2 * i) = C2{x.y * vI, -x.x * vI};
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int it = tid + NT * u, r = it / KC, i = it % KC, I = i0 + i;
-      C2 x = {T(0), T(0)};
-      if (brow[u] && I < nmb) x = brow[u][I];
-      *reinterpret_cast<C2 *>(Bs + r * P + 2 * i) = x;
+      const int it = tid + NT * u, r = it / KC, i = it % KC;
+      const T m = (i0 + i < nmb && b0 + r < N) ? T(1) : T(0);
+      *reinterpret_cast<C2 *>(Bs + r * P + 2 * i) = C2{xb[u].x * m, xb[u].y * m};
     }
     __syncthreads();
     mfma_slab<T, MI, NI, BK>(acc, As, Bs, wm0, wn0, lane);

@@ -88,21 +88,20 @@ __global__ __launch_bounds__(NT) void k_exchange_bf3(int nk, int nv, int nc, int
   const int nb = nv * nc;
   const int64_t N = int64_t(nk) * nb;
   const int64_t a0 = int64_t(blockIdx.y) * (XBM / 2), b0 = int64_t(blockIdx.x) * XBN;
+  // rows past N read row 0 and are zeroed when staged, entries past nmb read
+  // entry nmb - 1: every load is issued from an in-bounds address, none
+  // behind a branch
   const float2 *arow[NA];
   const float2 *brow[NB];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
-    const int64_t a = a0 + (tid + NT * u) / KC;
-    arow[u] = a < N ? reinterpret_cast<const float2 *>(mx) +
-                          (int64_t(korb[a / nb]) * nb + a % nb) * nmb
-                    : nullptr;
+    const int64_t a = a0 + (tid + NT * u) / KC, ac = a < N ? a : 0;
+    arow[u] = reinterpret_cast<const float2 *>(mx) + (int64_t(korb[ac / nb]) * nb + ac % nb) * nmb;
   }
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
-    const int64_t b = b0 + (tid + NT * u) / KC;
-    brow[u] = b < N ? reinterpret_cast<const float2 *>(mx) +
-                          (int64_t(korb[b / nb]) * nb + b % nb) * nmb
-                    : nullptr;
+    const int64_t b = b0 + (tid + NT * u) / KC, bc = b < N ? b : 0;
+    brow[u] = reinterpret_cast<const float2 *>(mx) + (int64_t(korb[bc / nb]) * nb + bc % nb) * nmb;
   }
   f32x4 acc[MI][NI];
 #pragma unroll
@@ -116,14 +115,22 @@ __global__ __launch_bounds__(NT) void k_exchange_bf3(int nk, int nv, int nc, int
     float va[NA];
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int I = i0 + (tid + NT * u) % KC;
-      xa[u] = (arow[u] && I < nmb) ? arow[u][I] : float2{0, 0};
-      va[u] = I < nmb ? float(vdiag[I]) : 0.f;
+      const int I = min(i0 + (tid + NT * u) % KC, nmb - 1);
+      xa[u] = arow[u][I];
+      va[u] = float(vdiag[I]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) xb[u] = brow[u][min(i0 + (tid + NT * u) % KC, nmb - 1)];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int it = tid + NT * u;
+      va[u] = (i0 + it % KC < nmb && a0 + it / KC < N) ? va[u] : 0.f;
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int I = i0 + (tid + NT * u) % KC;
-      xb[u] = (brow[u] && I < nmb) ? brow[u][I] : float2{0, 0};
+      const int it = tid + NT * u;
+      const bool ok = i0 + it % KC < nmb && b0 + it / KC < N;
+      xb[u] = float2{ok ? xb[u].x : 0.f, ok ? xb[u].y : 0.f};
     }
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
