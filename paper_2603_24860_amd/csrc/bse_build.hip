@@ -422,9 +422,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int wm0 = wv * 16 * MI;
   // per-thread load slots of the W rows (A) and the split Mv rows (B)
   typedef typename std::conditional<VEC == 4, float4, double2>::type V16;
-  __shared__ __attribute__((aligned(16))) C2 bzero_s[4];  // source of rows without data
-  if (tid < 4) bzero_s[tid] = C2{T(0), T(0)};
-  __syncthreads();
   // LDS rows of 16-byte chunks.  FP32: no padding, chunk c of row r stored at
   // c ^ ((r >> 1) & 3), so the eight lanes of one b128 access (eight rows at
   // one chunk for the MFMA fragments, two rows at four chunks for the stores)
@@ -440,13 +437,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     wrow0 = wq + int64_t(row) * nmb + c * VEC;
     aoff0 = row * PP + swz(row, c) * VEC;
   }
+  // a B row without data reads the first entries of mv (global memory, so
+  // every load is a global one) and is zeroed by bmask
   const C2 *bsrc[NB];
   int bstride[NB], boff[NB], boff2[NB];
+  T bmask[NB];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int it = tid + NT * u, row = it / BPR, c = it % BPR, kk = row / 16, vv = row % 16;
-    bsrc[u] = brow[u] ? brow[u] + (VEC == 4 ? 2 * c : c) : bzero_s;
+    bsrc[u] = (brow[u] ? brow[u] : reinterpret_cast<const C2 *>(mv)) + (VEC == 4 ? 2 * c : c);
     bstride[u] = brow[u] ? 1 : 0;
+    bmask[u] = brow[u] ? T(1) : T(0);
     const int r0 = (2 * kk) * 16 + vv, r1 = r0 + 16;  // real and imaginary rows
     if (VEC == 4) {  // two complex = four floats: the re pair and the im pair
       boff[u] = r0 * PP + swz(r0, c >> 1) * 4 + 2 * (c & 1);
@@ -471,7 +472,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 #pragma unroll
     for (int u = 0; u < NA; ++u) *reinterpret_cast<V16 *>(As + aoff0 + u * RSTEP * PP) = ra[u];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) split_store<VEC>(rb[u], Bs + boff[u], Bs + boff2[u], 0, bsgn[u]);
+    for (int u = 0; u < NB; ++u) {
+      V16 x = rb[u];
+      if constexpr (VEC == 4) {
+        x.x *= bmask[u]; x.y *= bmask[u]; x.z *= bmask[u]; x.w *= bmask[u];
+      } else {
+        x.x *= bmask[u]; x.y *= bmask[u];
+      }
+      split_store<VEC>(x, Bs + boff[u], Bs + boff2[u], 0, bsgn[u]);
+    }
     __syncthreads();
     if (SWZ) {
       // B fragments held for the slab, A fragments one row block at a time
@@ -502,6 +511,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int ncb = (ncc + 15) / 16;
   C2 *red = reinterpret_cast<C2 *>(lds);  // [4][NCB*16][16]
   C2 *Hc = reinterpret_cast<C2 *>(H);
+  // Mc row (c, c') of this lane's A row in each c c' block: as stored (low
+  // 16 bits) and band-swapped for a conjugated class (high 16 bits); -1 past
+  // the last pair (that row reads the class's first row and is zeroed)
+  int mrow[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int cc = 16 * cb + Mfma<T>::arow(r16), c = cc / nc, c2 = cc % nc;
+    mrow[cb] = cc < ncc ? ((c2 * nc + c) << 16) | (c * nc + c2) : -1;
+  }
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk) {
     const int k = kof(kk);
@@ -520,22 +538,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         if (cb >= ncb) break;
-        const int cc = 16 * cb + Mfma<T>::arow(r16);
-        const C2 *arowp = nullptr;
-        if (cc < ncc) {
-          const int c = cc / nc, c2 = cc % nc;
-          const int s1 = cj ? c2 : c, s2 = cj ? c : c2;
-          arowp = reinterpret_cast<const C2 *>(mc) + ((int64_t(cls) * nc + s1) * nc + s2) * nmb;
-        }
+        const int mr = mrow[cb] < 0 ? 0 : cj ? mrow[cb] >> 16 : mrow[cb] & 0xffff;
+        const T am = mrow[cb] < 0 ? T(0) : T(1), sgm = sg * am;
+        const C2 *arowp = reinterpret_cast<const C2 *>(mc) + (int64_t(cls) * ncc + mr) * nmb;
 #pragma unroll
         for (int mi = 0; mi < MI; ++mi) {
           const int I0 = wm0 + 16 * mi + 4 * g;
+          // four consecutive entries, 16-byte aligned (nmb and I0 multiples of 4)
           C2 m[4];
+          const V16 *m16 = reinterpret_cast<const V16 *>(arowp + I0);
+          if constexpr (VEC == 4) {
+            const V16 a = m16[0], b = m16[1];
+            m[0] = C2{T(a.x), T(a.y)};
+            m[1] = C2{T(a.z), T(a.w)};
+            m[2] = C2{T(b.x), T(b.y)};
+            m[3] = C2{T(b.z), T(b.w)};
+          } else {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) m[j] = arowp ? arowp[I0 + j] : C2{T(0), T(0)};
+            for (int j = 0; j < 4; ++j) memcpy(&m[j], &m16[j], sizeof(C2));
+          }
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const T are = m[j].x, aim = sg * m[j].y;   // Mc = are + i aim
+            const T are = am * m[j].x, aim = sgm * m[j].y;   // Mc = are + i aim
             const T tre = acc[mi][2 * kk][j], tim = acc[mi][2 * kk + 1][j];
             // conj(Mc) T = (are tre + aim tim) + i (are tim - aim tre)
             dre[cb] = Mfma<T>::mma(are, tre, dre[cb]);
