@@ -2080,37 +2080,48 @@ __global__ __launch_bounds__(ENT) void k_bx_tmat(Desc D) {
   for (int q = tid; q < NBK * NBK; q += ENT) T[q] = ts[q / NBK][q % NBK];
 }
 
+// OFF = 1: the one-stage reduction (reflector of column j from row j + 1,
+// x starts as z); OFF = SBW: stage 1 of the two-stage one (reflector c of
+// the panel at j0 from row j0 + c + SBW, stored with its zeros and unit entry
+// over the panel's m rows, T kept by k_sb_tmat, x already holds the
+// back-transform through the bulge chase).
+template <int OFF>
 __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
   __shared__ double sh[ENT / 64];
   __shared__ double2 sw[ENT / 64][NBK];
   __shared__ double2 st[NBK];
   const int64_t n = D.n, ldv = D.ldv, l = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const double *z = D.Z + size_t(l) * n;
   double2 *x = D.X + size_t(l) * n;
-  for (int64_t k = tid; k < n; k += ENT) x[k] = double2{z[k], 0.0};
-  const int64_t npan = n >= 2 ? cdiv(n - 1, NBK) : 0;
+  if (OFF == 1) {
+    const double *z = D.Z + size_t(l) * n;
+    for (int64_t k = tid; k < n; k += ENT) x[k] = double2{z[k], 0.0};
+  }
+  const int64_t npan = OFF == 1 ? (n >= 2 ? cdiv(n - 1, NBK) : 0) : g_sb_npan(n);
   for (int64_t p = npan - 1; p >= 0; --p) {
     const int64_t j0 = p * NBK;
-    const int bp = int(std::min<int64_t>(NBK, n - 1 - j0));
-    const double2 *V = D.Vall + j0 * ldv;
+    const int bp = int(std::min<int64_t>(NBK, n - OFF - j0));
+    // entry (row r, reflector c): Vall[j0 + c][r], or vrow's panel [c][r - j0 - OFF]
+    const double2 *V = OFF == 1 ? D.Vall + j0 * ldv : D.vrow;
+    const int64_t vo = OFF == 1 ? 0 : g_sb_voff(n, p) * NBK - j0 - OFF;  // + r >= 0
+    const int64_t sr = 1, sc = OFF == 1 ? ldv : n - j0 - OFF;
     const double2 *T = D.Tm + size_t(p) * NBK * NBK;
-    // w = V^dag x over the panel's rows (v_c is zero above row j0 + c + 1)
+    // w = V^dag x over the panel's rows (v_c is zero above row j0 + c + OFF)
     double2 w[NBK];
 #pragma unroll
     for (int c = 0; c < NBK; ++c) w[c] = double2{0, 0};
     // every load is unconditional (column index clamped in bounds) and the
     // support mask is applied to the value, so the loads of a row overlap
-    for (int64_t r = (j0 + 1) / ENT * ENT + tid; r < n; r += ENT) {
-      if (r < j0 + 1) continue;
+    for (int64_t r = (j0 + OFF) / ENT * ENT + tid; r < n; r += ENT) {
+      if (r < j0 + OFF) continue;
       const double2 xr = x[r];
       double2 vr[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) vr[c] = V[std::min(c, bp - 1) * ldv + r];
+      for (int c = 0; c < NBK; ++c) vr[c] = V[vo + std::min(c, bp - 1) * sc + r * sr];
 #pragma unroll
       for (int c = 0; c < NBK; ++c) {
         const double2 t = cmulc(vr[c], xr);
-        const bool ok = c < bp && r >= j0 + c + 1;
+        const bool ok = c < bp && r >= j0 + c + OFF;
         w[c].x += ok ? t.x : 0.0;
         w[c].y += ok ? t.y : 0.0;
       }
@@ -2138,16 +2149,16 @@ __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
     double2 tc[NBK];
 #pragma unroll
     for (int c = 0; c < NBK; ++c) tc[c] = st[c];
-    for (int64_t r = (j0 + 1) / ENT * ENT + tid; r < n; r += ENT) {
-      if (r < j0 + 1) continue;
+    for (int64_t r = (j0 + OFF) / ENT * ENT + tid; r < n; r += ENT) {
+      if (r < j0 + OFF) continue;
       double2 xr = x[r];
       double2 vr[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) vr[c] = V[std::min(c, bp - 1) * ldv + r];
+      for (int c = 0; c < NBK; ++c) vr[c] = V[vo + std::min(c, bp - 1) * sc + r * sr];
 #pragma unroll
       for (int c = 0; c < NBK; ++c) {
         const double2 t = cmul(vr[c], tc[c]);
-        const bool ok = c < bp && r >= j0 + c + 1;
+        const bool ok = c < bp && r >= j0 + c + OFF;
         xr.x -= ok ? t.x : 0.0;
         xr.y -= ok ? t.y : 0.0;
       }
@@ -2346,7 +2357,7 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
     BSE_LAUNCH("k_invit", k_invit, dim3((unsigned)K), dim3(ENT), 0, s, D);
     if (n >= 2)
       BSE_LAUNCH("k_bx_tmat", k_bx_tmat, dim3((unsigned)cdiv(n - 1, NBK)), dim3(ENT), 0, s, D);
-    BSE_LAUNCH("k_backxf", k_backxf, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    BSE_LAUNCH("k_backxf", k_backxf<1>, dim3((unsigned)K), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, 4), (unsigned)K), dim3(ENT), 0,
                s, D);
     BSE_LAUNCH("k_rq_fin", k_rq_fin, dim3(1), dim3(ENT), 0, s, D);
@@ -2356,13 +2367,16 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
 }
 
 // ---------------------------------------------------------------------------
-// single block, two-stage reduction (no refinement)
+// single block, two-stage reduction; with refinement (K > 0) every reflector
+// of both stages is kept and the eigenvectors of T are carried back through
+// the chase (k_bx_chase), then through the stage-1 panels and the initial
+// reflection (k_backxf<SBW>)
 // ---------------------------------------------------------------------------
 template <typename TH, typename TA>
 int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
-                    double *pole, double *osc, void *ws, hipStream_t s) {
+                    double *pole, double *osc, void *ws, hipStream_t s, int64_t K) {
   Desc D;
-  ws_layout(n, sizeof(TA) == 8, &D, (char *)ws, 0, true);
+  ws_layout(n, sizeof(TA) == 8, &D, (char *)ws, K, true);
   D.H = Hmu;
   D.ld = ld;
   D.B = (const double2 *)Bmu;
@@ -2403,8 +2417,12 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
   for (int64_t t = 0; t <= g_bc_tmax(n); ++t) {
     const int64_t lo = g_bc_ilo(n, t), hi = g_bc_ihi(n, t);
     if (lo > hi) continue;
-    BSE_LAUNCH("k_sb_chase", k_sb_chase, dim3((unsigned)(hi - lo + 1)), dim3(BCT), 0, s, D, t,
-               hi);
+    if (K > 0)
+      BSE_LAUNCH("k_sb_chase", k_sb_chase<true>, dim3((unsigned)(hi - lo + 1)), dim3(BCT), 0, s,
+                 D, t, hi);
+    else
+      BSE_LAUNCH("k_sb_chase", k_sb_chase<false>, dim3((unsigned)(hi - lo + 1)), dim3(BCT), 0, s,
+                 D, t, hi);
   }
   BSE_LAUNCH("k_sb_diag", k_sb_diag, dim3((unsigned)cdiv(n, ENT)), dim3(ENT), 0, s, D);
   BSE_HIP_CHECK(hipGetLastError());
@@ -2416,13 +2434,25 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
   BSE_LAUNCH("k_bisect", (k_bisect<TH, TA, 4>), grid(K_BISECT), dim3(ENT), 0, s, D, 1);
   BSE_LAUNCH("k_weights", (k_weights<TH, TA, 4>), grid(K_WEIGHTS), dim3(ENT), 0, s, D, 0);
   BSE_HIP_CHECK(hipGetLastError());
+  if (K > 0) {
+    BSE_LAUNCH("k_invit", k_invit, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    if (n <= BXL)
+      BSE_LAUNCH("k_bx_chase", k_bx_chase_lds, dim3((unsigned)K), dim3(BXT), 0, s, D);
+    else
+      BSE_LAUNCH("k_bx_chase", k_bx_chase, dim3((unsigned)K), dim3(BXC), 0, s, D);
+    BSE_LAUNCH("k_backxf", k_backxf<SBW>, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, 4), (unsigned)K), dim3(ENT), 0,
+               s, D);
+    BSE_LAUNCH("k_rq_fin", k_rq_fin, dim3(1), dim3(ENT), 0, s, D);
+    BSE_HIP_CHECK(hipGetLastError());
+  }
   return BSE_OK;
 }
 
-// Smallest block that takes the two-stage reduction (solves without
-// refinement only); process-wide, set by bse_block_eigh_set_two_stage.
+// Smallest block that takes the two-stage reduction; process-wide, set by
+// bse_block_eigh_set_two_stage.
 std::atomic<int64_t> g_two_stage_min{4096};
-inline bool takes_two_stage(int64_t n, int64_t K) { return K == 0 && n >= g_two_stage_min.load(); }
+inline bool takes_two_stage(int64_t n, int64_t) { return n >= g_two_stage_min.load(); }
 
 // ---------------------------------------------------------------------------
 // batched: every active block advances one step per launch
@@ -2597,10 +2627,10 @@ extern "C" int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_
   hipStream_t s = (hipStream_t)stream;
   if (two) {
     if (prec == BSE_FP64)
-      return h_fp64 ? eigh_run_2s<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
-                    : eigh_run_2s<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
-    return h_fp64 ? eigh_run_2s<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s)
-                  : eigh_run_2s<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s);
+      return h_fp64 ? eigh_run_2s<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
+                    : eigh_run_2s<float, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
+    return h_fp64 ? eigh_run_2s<double, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)
+                  : eigh_run_2s<float, float>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K);
   }
   if (prec == BSE_FP64)
     return h_fp64 ? eigh_run<double, double>(n, Hmu, ld, Bmu, omega, pole, osc, ws, s, K)

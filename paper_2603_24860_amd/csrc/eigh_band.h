@@ -281,6 +281,8 @@ __device__ __forceinline__ void b_sb_tmat(const Desc &D, int64_t j0, int nw) {
       if (k == c && l < c) tlk = cmul(double2{-tc.x, -tc.y}, t);
     }
     D.sbt[tid] = tlk;
+    // with refinement every panel's T is kept for the back-transformation
+    if (D.rall) D.Tm[(j0 / SBW) * (SBW * SBW) + tid] = tlk;
   }
   const CA *A = reinterpret_cast<const CA *>(D.A);
   for (int e = tid; e < SBW * LDB; e += RNT) {
@@ -355,6 +357,11 @@ __device__ __forceinline__ void b_sb_u(const Desc &D, int64_t j0, int wg) {
       const int l = 8 * lg + q;
       D.V[int64_t(l) * D.ldv + p0 + r] = Vs[rr][l];
       U[int64_t(l) * D.ldv + p0 + r] = CA{TA(acc[q].x), TA(acc[q].y)};
+    }
+    if (D.rall) {  // refinement: the panel's reflectors kept, packed by columns
+      double2 *vp = D.vrow + g_sb_voff(n, j0 / SBW) * SBW + r;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vp[(8 * lg + q) * m] = Vs[rr][8 * lg + q];
     }
   }
 }
@@ -710,6 +717,8 @@ constexpr int BCT = 512;
 constexpr int BCU = SBW * SBW / BCT;  // entries per thread and block
 constexpr int BCG = BCT / SBW;        // row groups g (q = g + BCG u)
 constexpr int BCR = SBW / BCG;        // rows p per group in the sums over p
+// KEEP (refinement): every reflector is also stored for the back-transformation
+template <bool KEEP>
 __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi) {
   __shared__ double2 Ms[SBW][SBW + 1];      // D in full, then O
   __shared__ double2 part[BCT / 64][SBW];   // per-wave sums over q
@@ -863,10 +872,140 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   // ---- the reflector of the next step of this sweep ----
   if (g == 0) D.rfl[i * SBW + p] = up;
   if (tid == 0) D.rtau[i] = tau;
+  if (KEEP && g == 0 && p < L)  // tau in place of u_0 = 1
+    D.rall[g_bc_off(n, i) + k * SBW + p] = p == 0 ? tau : up;
 }
 
 // d from the band's diagonal
 __global__ __launch_bounds__(ENT) void k_sb_diag(Desc D) {
   const int64_t r = int64_t(blockIdx.x) * ENT + threadIdx.x;
   if (r < D.n) D.d[r] = D.band[r * LDB].x;
+}
+
+// ---------------------------------------------------------------------------
+// back-transformation through the bulge chase (refinement): x = Q2 z for
+// each eigenvector z of T, Q2 the product of the chase's reflectors
+// H = I - tau u u^dag in the order they were made (each task turned D into
+// H^dag D H).  The reflectors of one sweep act on disjoint row blocks, and a
+// reflector of sweep i was made after every reflector of an earlier sweep
+// that shares a row with it, so applying whole sweeps from the last to the
+// first is the reverse order.  One workgroup per vector.  The stored entry of
+// row 0 of a task holds its tau (u_0 = 1).  Within a sweep a row is read and
+// written by one lane only; a barrier separates the sweeps.
+//   k_bx_chase_lds  blocks of up to BXL rows: x in LDS (FP64); BXW lanes per
+//                   task, BXQ consecutive rows per lane, u^dag x summed over
+//                   the lane's rows and then over the task's lanes (xor
+//                   shuffles); the reflectors of the next sweep are loaded
+//                   while the current one is applied (they do not depend on x)
+//   k_bx_chase      larger blocks: x in global memory, SBW lanes per task
+//                   (one row each), BXU tasks per group with their loads in
+//                   flight together
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
+  __shared__ double2 xs[BXL];
+  const int64_t n = D.n, l = blockIdx.x;
+  const int tid = threadIdx.x, pl = tid % BXW, grp = tid / BXW;
+  const int base = (tid & 63) & ~(BXW - 1);  // lane 0 of this task in the wave
+  const double *z = D.Z + l * n;
+  double2 *x = D.X + l * n;
+  for (int64_t r = tid; r < n; r += BXT) xs[r] = double2{z[r], 0.0};
+  double2 wn[BXRL][BXQ];  // stored entries of the next sweep, this lane's rows
+#define BX_FETCH(I)                                                              \
+  {                                                                              \
+    const int64_t i_ = (I), nt_ = g_bc_kmax(n, i_) + 1;                          \
+    const double2 *r_ = D.rall + g_bc_off(n, i_);                                \
+    _Pragma("unroll") for (int j = 0; j < BXRL; ++j) {                           \
+      const int64_t k = grp + BXGL * j, r = i_ + 1 + k * SBW + BXQ * pl;         \
+      _Pragma("unroll") for (int q = 0; q < BXQ; ++q)                            \
+        wn[j][q] = r_[k < nt_ && r + q < n ? r + q - i_ - 1 : 0];                \
+    }                                                                            \
+  }
+  BX_FETCH(n - 2)
+  __syncthreads();
+  for (int64_t i = n - 2; i >= 0; --i) {
+    const int64_t nt = g_bc_kmax(n, i) + 1;
+    double2 w[BXRL][BXQ];
+#pragma unroll
+    for (int j = 0; j < BXRL; ++j)
+#pragma unroll
+      for (int q = 0; q < BXQ; ++q) w[j][q] = wn[j][q];
+    BX_FETCH(i > 0 ? i - 1 : 0)
+#pragma unroll
+    for (int j = 0; j < BXRL; ++j) {
+      const int64_t k = grp + BXGL * j;
+      if (k < nt) {  // the same for the lanes of a task
+        const int64_t r0 = i + 1 + k * SBW + BXQ * pl;
+        const double2 tau = {__shfl(w[j][0].x, base, 64), __shfl(w[j][0].y, base, 64)};
+        double2 u[BXQ], xv[BXQ], y = {0, 0};
+#pragma unroll
+        for (int q = 0; q < BXQ; ++q) {
+          const bool in = r0 + q < n;
+          u[q] = csel(in, csel(pl == 0 && q == 0, double2{1, 0}, w[j][q]), double2{0, 0});
+          xv[q] = xs[in ? r0 + q : i + 1];
+          y = cadd(y, cmulc(u[q], xv[q]));
+        }
+#pragma unroll
+        for (int o = 1; o < BXW; o <<= 1) {
+          y.x += __shfl_xor(y.x, o, 64);
+          y.y += __shfl_xor(y.y, o, 64);
+        }
+        const double2 f = cmul(tau, y);
+#pragma unroll
+        for (int q = 0; q < BXQ; ++q)
+          if (r0 + q < n) xs[r0 + q] = csub(xv[q], cmul(f, u[q]));
+      }
+    }
+    __syncthreads();
+  }
+#undef BX_FETCH
+  for (int64_t r = tid; r < n; r += BXT) x[r] = xs[r];
+}
+
+// one reflector on the SBW lanes of a group (lane p: row rk + p), for
+// k_bx_chase: x -= tau u (u^dag x); w is the stored entry (tau on lane 0),
+// in says whether the lane has a row
+__device__ __forceinline__ double2 bx_apply(double2 w, double2 xv, bool in, int p) {
+  const int base = (threadIdx.x & 63) & ~(SBW - 1);
+  const double2 tau = {__shfl(w.x, base, 64), __shfl(w.y, base, 64)};
+  const double2 u = csel(in, csel(p == 0, double2{1, 0}, w), double2{0, 0});
+  double2 y = cmulc(u, xv);
+#pragma unroll
+  for (int o = 1; o < SBW; o <<= 1) {
+    y.x += __shfl_xor(y.x, o, 64);
+    y.y += __shfl_xor(y.y, o, 64);
+  }
+  return csub(xv, cmul(cmul(tau, y), u));
+}
+
+__global__ __launch_bounds__(BXC) void k_bx_chase(Desc D) {
+  const int64_t n = D.n, l = blockIdx.x;
+  const int tid = threadIdx.x, p = tid % SBW, grp = tid / SBW;
+  const double *z = D.Z + l * n;
+  double2 *x = D.X + l * n;
+  for (int64_t r = tid; r < n; r += BXC) x[r] = double2{z[r], 0.0};
+  __syncthreads();
+  for (int64_t i = n - 2; i >= 0; --i) {
+    const int64_t nt = g_bc_kmax(n, i) + 1;  // tasks of sweep i
+    const double2 *ri = D.rall + g_bc_off(n, i);
+    for (int64_t k0 = 0; k0 < nt; k0 += BXG * BXU) {
+      double2 w[BXU], xv[BXU];
+      int64_t row[BXU];
+      bool in[BXU];
+#pragma unroll
+      for (int j = 0; j < BXU; ++j) {  // every load from an in-bounds address
+        const int64_t k = k0 + grp + BXG * j, r = i + 1 + k * SBW + p;
+        in[j] = k < nt && r < n;
+        row[j] = in[j] ? r : i + 1;
+        w[j] = ri[k < nt ? row[j] - i - 1 : 0];
+        xv[j] = x[row[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < BXU; ++j) xv[j] = bx_apply(w[j], xv[j], in[j], p);
+#pragma unroll
+      for (int j = 0; j < BXU; ++j)
+        if (in[j]) x[row[j]] = xv[j];
+    }
+    __syncthreads();
+  }
 }

@@ -108,6 +108,11 @@ struct Desc {
   double2 *rfl;              // [n][SBW] latest reflector of each bulge-chasing sweep
   double2 *rtau;             // [n] its tau
   double2 *sink;             // [SINK] target of the stores of masked lanes (never read)
+  // two-stage reduction with refinement (K > 0): every reflector of both
+  // stages, for the back-transformation; null otherwise
+  double2 *rall;             // chase, packed: sweep i at g_bc_off(n, i), rows i + 1 .. n - 1;
+                             // each task's first entry (u_0 = 1) holds its tau
+  double2 *vrow;             // stage 1, panel p (m rows) at g_sb_voff(n, p) SBW: [SBW][m]
 };
 
 // Two-stage reduction of large single blocks.  Stage 1 reduces A to a lower
@@ -223,6 +228,35 @@ __host__ __device__ __forceinline__ int64_t g_bc_ilo(int64_t n, int64_t t) {
   return num <= 0 ? 0 : cdiv(num, den);
 }
 __host__ __device__ __forceinline__ int64_t g_bc_tmax(int64_t n) { return n < 2 ? -1 : 2 * (n - 2); }
+// stored chase reflectors: sweep i covers rows i + 1 .. n - 1 (its tasks'
+// row blocks, in order), packed after the sweeps before it; most tasks of a
+// sweep
+__host__ __device__ __forceinline__ int64_t g_bc_off(int64_t n, int64_t i) {
+  return i * (n - 1) - i * (i - 1) / 2;
+}
+__host__ __device__ __forceinline__ int64_t g_bc_nks(int64_t n) {
+  return n < 2 ? 1 : (n - 2) / SBW + 1;
+}
+// panels of stage 1 (columns j0 = p SBW with rows below the band)
+__host__ __device__ __forceinline__ int64_t g_sb_npan(int64_t n) {
+  return n > SBW ? cdiv(n - SBW, SBW) : 0;
+}
+// back-transformation through the chase: k_bx_chase_lds (x in LDS) for
+// blocks up to BXL rows, k_bx_chase above
+constexpr int BXL = 10240;                // rows of x held in LDS
+constexpr int BXT = 512;                  // threads of k_bx_chase_lds
+constexpr int BXQ = 4;                    // rows per lane
+constexpr int BXW = SBW / BXQ;            // lanes per task
+constexpr int BXGL = BXT / BXW;           // tasks per round
+constexpr int BXRL = ((BXL - 2) / SBW + 1 + BXGL - 1) / BXGL;  // rounds per sweep
+static_assert(BXL * 16 <= 160 * 1024, "x of k_bx_chase_lds fills at most the LDS");
+constexpr int BXC = 1024;                 // threads of k_bx_chase
+constexpr int BXG = BXC / SBW;            // task groups
+constexpr int BXU = 4;                    // tasks per group and batch
+// rows of the stage-1 panels before panel p (panel p has n - SBW (p + 1) rows)
+__host__ __device__ __forceinline__ int64_t g_sb_voff(int64_t n, int64_t p) {
+  return p * (n - SBW) - SBW * (p * (p - 1) / 2);
+}
 
 // relative cluster tolerance of the weights: 8 eps sqrt(n) of the storage type of A
 __host__ __device__ __forceinline__ double ctol_rel(int64_t n, bool a_fp64) {
@@ -275,7 +309,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
   t.status = (int32_t *)take(4 * 4);
   t.K = K;
   if (K > 0) {
-    t.Vall = (double2 *)take(size_t(n) * ldv * 16);
+    t.Vall = two_stage ? nullptr : (double2 *)take(size_t(n) * ldv * 16);
     t.Z = (double *)take(size_t(K) * n * 8);
     t.X = (double2 *)take(size_t(K) * n * 16);
     t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, 4)) * 16);
@@ -299,6 +333,10 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     t.rfl = (double2 *)take(size_t(n) * SBW * 16);
     t.rtau = (double2 *)take(size_t(n) * 16);
     t.sink = (double2 *)take(SINK * 16);
+    if (K > 0) {
+      t.rall = (double2 *)take(size_t(std::max<int64_t>(g_bc_off(n, n - 1), 1)) * 16);
+      t.vrow = (double2 *)take(size_t(std::max<int64_t>(g_sb_voff(n, g_sb_npan(n)), 1)) * SBW * 16);
+    }
   }
   if (w) *w = t;
   return off;

@@ -23,7 +23,7 @@
 //
 //   g++ -std=c++17 -O1 -fsanitize=address,undefined -I paper_2603_24860_amd/csrc \
 //       tests/eigh_layout_check.cpp -o eigh_layout_check
-//   ./eigh_layout_check n a_fp64 K [n a_fp64 K ...]     (K = -1: two-stage reduction)
+//   ./eigh_layout_check n a_fp64 K [n a_fp64 K ...]     (K = -1 - k: two-stage reduction, k refined)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -126,6 +126,12 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
   C.add("rfl", D.rfl, 16, n * SBW);
   C.add("rtau", D.rtau, 16, n);
   C.add("sink", D.sink, 16, SINK);
+  const int64_t K = D.K;
+  if (K > 0) {
+    C.add("rall", D.rall, 16, std::max<int64_t>(g_bc_off(n, n - 1), 1));
+    C.add("vrow", D.vrow, 16, std::max<int64_t>(g_sb_voff(n, g_sb_npan(n)), 1) * SBW);
+    if (D.Vall) return 1;  // the two-stage path keeps its reflectors by rows only
+  }
   C.layout_ok();
   int64_t j0 = 0;
   for (; j0 + SBW < n; j0 += SBW) {
@@ -160,6 +166,13 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
     // k_sb_tmat
     C.range("srec", 0, (nw - 1) * SBW * SBW + SBW * SBW, "k_sb_tmat");
     C.range("sbt", 0, SBW * SBW, "k_sb_tmat");
+    if (K > 0) {
+      C.range("Tm", (j0 / SBW) * SBW * SBW, (j0 / SBW + 1) * SBW * SBW, "k_sb_tmat T kept");
+      // k_sb_u: panel rows 0 .. m, all SBW entries, row-major from g_sb_voff
+      if (g_sb_voff(n, j0 / SBW + 1) - g_sb_voff(n, j0 / SBW) != m) return 1;
+      C.range("vrow", g_sb_voff(n, j0 / SBW) * SBW, (g_sb_voff(n, j0 / SBW) + m) * SBW,
+              "k_sb_u rows kept");
+    }
     for (int c = 0; c < SBW; ++c)
       for (int d = 0; d < LDB; ++d) {
         const int64_t j = j0 + c, row = j + d;
@@ -269,6 +282,11 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
       }
       C.at("band", std::min<int64_t>(rk + SBW - 1, n - 1) * LDB + SBW - 1, "k_sb_chase D load");
       C.range("rfl", i * SBW, i * SBW + SBW, "k_sb_chase");
+      if (K > 0) {  // the reflector kept: rows rk .. rk + L of sweep i, packed
+        if (rk - i - 1 != k * SBW) return 1;
+        C.range("rall", g_bc_off(n, i) + k * SBW, g_bc_off(n, i) + k * SBW + L, "k_sb_chase keep");
+        if (g_bc_off(n, i) + k * SBW + L > g_bc_off(n, i) + (n - 1 - i)) return 1;  // own sweep
+      }
       C.at("band", rk * LDB, "k_sb_chase D");
       C.at("band", (rk + L - 1) * LDB, "k_sb_chase D");
       C.at("band", rk * LDB + L - 1, "k_sb_chase D");
@@ -284,13 +302,39 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
   }
   C.range("band", 0, n * LDB, "k_sb_diag");
   C.range("sink", 0, SINK, "masked stores (thread index modulo SINK)");
+  if (K > 0) {
+    // k_bx_chase / k_bx_chase_lds: every task of every sweep (its rows, the
+    // entry of its row 0 with tau), loads of masked lanes from the sweep's
+    // first entry; the LDS form's x covers rows 0 .. n <= BXL
+    for (int64_t i = n - 2; i >= 0; --i) {
+      const int64_t nt = g_bc_kmax(n, i) + 1;
+      if (n <= BXL && nt > int64_t(BXGL) * BXRL) return 1;  // tasks beyond the rounds
+      for (int64_t k = 0; k < nt; ++k) {
+        const int64_t r0 = i + 1 + k * SBW, r1 = std::min<int64_t>(r0 + SBW, n);
+        C.range("rall", g_bc_off(n, i) + (r0 - i - 1), g_bc_off(n, i) + (r1 - i - 1), "k_bx_chase u");
+        if (g_bc_off(n, i) + (r1 - i - 1) > g_bc_off(n, i + 1)) return 1;  // inside its sweep
+        C.range("X", r0, r1, "k_bx_chase x");
+        C.range("X", (K - 1) * n + r0, (K - 1) * n + r1, "k_bx_chase x");
+      }
+      C.at("rall", g_bc_off(n, i), "k_bx_chase masked lanes");
+    }
+    C.range("Z", 0, K * n, "k_bx_chase z");
+    // k_backxf<SBW>: panel p, rows j0 + SBW .. n of vrow (all SBW entries)
+    for (int64_t p = g_sb_npan(n) - 1; p >= 0; --p) {
+      const int64_t pj = p * NBK, m = n - SBW - pj;
+      if (m < 1) return 1;
+      const int64_t o = g_sb_voff(n, p) * SBW;
+      C.range("vrow", o, o + m * SBW, "k_backxf<SBW> V");
+      C.range("Tm", p * NBK * NBK, (p + 1) * NBK * NBK, "k_backxf<SBW> T");
+    }
+  }
   return 0;
 }
 
 int run(int64_t n, bool a64, int64_t K) {
   const size_t el = a64 ? 16 : 8;
-  const bool two = K < 0;  // K = -1: the two-stage reduction (no refinement)
-  if (two) K = 0;
+  const bool two = K < 0;  // K = -1 - k: the two-stage reduction with k refined
+  if (two) K = -1 - K;
   const size_t need = ws_layout(n, a64, nullptr, nullptr, K, two);
   std::vector<char> buf(need);
   Desc D{};
@@ -325,7 +369,7 @@ int run(int64_t n, bool a64, int64_t K) {
   C.add("beta0", D.beta0, 8, 1);
   C.add("status", D.status, 4, 4);
   if (K > 0) {
-    C.add("Vall", D.Vall, 16, n * D.ldv);
+    C.add("Vall", D.Vall, 16, D.Vall ? n * D.ldv : 0);
     C.add("Z", D.Z, 8, K * n);
     C.add("X", D.X, 16, K * n);
     C.add("rqp", D.rqp, 16, K * cdiv(n, 4));
@@ -492,7 +536,7 @@ int run(int64_t n, bool a64, int64_t K) {
   if (K > 0) {
     C.range("Z", 0, K * n, "k_invit");
     C.range("scr", 0, K * 6 * CMAX * n, "k_invit");
-    C.range("Tm", 0, std::max<int64_t>(cdiv(n - 1, NBK), 1) * NBK * NBK, "k_bx_tmat");
+    if (!two) C.range("Tm", 0, std::max<int64_t>(cdiv(n - 1, NBK), 1) * NBK * NBK, "k_bx_tmat");
     C.range("X", 0, K * n, "k_backxf");
     C.range("rqp", 0, K * cdiv(n, 4), "k_hx_part");
     C.range("wref", 0, K, "k_rq_fin");

@@ -176,6 +176,59 @@ def test_two_stage_matches_one_stage(lib, two_stage_from):
     assert abs(os1.sum() - os2.sum()) < 1e-10 * os1.sum()
 
 
+def _solve_refined(lib, A, b, nref):
+    n = A.shape[0]
+    Hmu = torch.as_tensor(A, dtype=torch.complex128, device="cuda")
+    Bmu = torch.as_tensor(b, dtype=torch.complex128, device="cuda")
+    ws = torch.full((lib.bse_block_eigh_ws(n, 1, lib.FP32, nref),), 255, dtype=torch.uint8,
+                    device="cuda")
+    om = torch.empty(n, dtype=torch.float64, device="cuda")
+    po, os_ = torch.empty_like(om), torch.empty_like(om)
+    lib.bse_block_eigh(Hmu, Bmu, lib.FP32, om, po, os_, ws, nrefine=nref)
+    st = lib.bse_block_eigh_status(n, lib.FP32, nref, ws, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    return om.cpu().numpy(), po.cpu().numpy(), os_.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("n,mult,K", [(2, 1, 2), (3, 3, 2), (34, 1, 20), (65, 1, 65),
+                                       (162, 3, 100), (600, 3, 100),
+                                       (4500, 1, 100), (4500, 3, 100), (10300, 1, 50)])
+def test_two_stage_refinement(lib, two_stage_from, n, mult, K):
+    """FP32 working storage through the two-stage reduction with FP64
+    refinement of the lowest K against an FP64 H_mu: the eigenvectors of T go
+    back through every bulge-chasing reflector and every stage-1 panel, and
+    their Rayleigh quotients reach FP64 accuracy (the bars of the one-stage
+    refinement: 1e-9 |lam| and 100x below the unrefined error); the rest of
+    the spectrum and the strengths are the unrefined two-stage ones (to FP64
+    rounding: the chase that keeps its reflectors is a kernel of its own, so
+    the last bits of its FP64 arithmetic may differ).  4500: 140 panels and 9000 chase launches (default switch point);
+    10300: above the rows whose vector fits in LDS (the chase's reflectors
+    applied to x in global memory)."""
+    say("two-stage refinement", n, mult, K)
+    if n >= 4096:
+        two_stage_from(4096)
+        A, b, lam, qb = _householder_hermitian(n, seed=313 + mult, mult=mult)
+    else:
+        two_stage_from(2)
+        A, b, lam, qb = _random_hermitian(n, seed=11 * n + mult, mult=mult)
+    o0, p0, s0, _ = _solve_refined(lib, A, b, 0)
+    o1, p1, s1, st = _solve_refined(lib, A, b, K)
+    k = min(K, n)
+    ex = np.sort(lam)
+    e0 = np.abs(o0[:k] - ex[:k]).max()
+    e1 = np.abs(o1[:k] - ex[:k]).max()
+    say("  lowest", k, "error unrefined", e0, "refined", e1, "status", st)
+    assert st[:2] == [0, 0]
+    assert e1 < 1e-9 * max(1.0, np.abs(lam).max())
+    assert e1 <= e0 / 100 or e0 < 1e-12
+    top = max(1.0, np.abs(lam).max())
+    if k < n:
+        assert np.abs(o0[k:] - o1[k:]).max() <= 1e-12 * top
+    # a strength shares that rounding through the contour of its cluster
+    assert np.abs(s0 - s1).max() <= 1e-10 * s0.sum()
+    assert abs(s0.sum() - s1.sum()) <= 1e-12 * s0.sum()
+
+
 def test_switch_point_query(lib, two_stage_from):
     """bse_block_eigh_set_two_stage returns the previous value; a negative
     argument only queries; the workspace query follows the switch point."""
@@ -185,10 +238,13 @@ def test_switch_point_query(lib, two_stage_from):
     two_stage_from(4800)
     w2 = lib.bse_block_eigh_ws(4800, 0, lib.FP32)
     assert w2 > w1
-    # refinement keeps the one-stage path and its workspace
-    wr = lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100)
+    # refinement follows the switch point too; its two-stage workspace also
+    # keeps every reflector of both stages (the chase's alone: n (n - 1) / 2
+    # entries of 16 bytes)
+    wr2 = lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100)
     two_stage_from(1 << 20)
-    assert lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100) == wr
+    wr1 = lib.bse_block_eigh_ws(4800, 0, lib.FP32, 100)
+    assert wr2 != wr1 and wr2 - w2 >= 16 * 4800 * 4799 // 2 and wr1 > w1
     assert lib.bse_block_eigh_ws(4800, 0, lib.FP32) == w1
 
 
