@@ -872,8 +872,8 @@ __global__ __launch_bounds__(BCT) void k_sb_chase(Desc D, int64_t t, int64_t ihi
   // ---- the reflector of the next step of this sweep ----
   if (g == 0) D.rfl[i * SBW + p] = up;
   if (tid == 0) D.rtau[i] = tau;
-  if (KEEP && g == 0 && p < L)  // tau in place of u_0 = 1
-    D.rall[g_bc_off(n, i) + k * SBW + p] = p == 0 ? tau : up;
+  if (KEEP && g == 0 && p < L)  // kept for the back-transformation; tau in place of u_0 = 1
+    D.rall[g_bc_off(n, i) + k * SBW + p] = csel(p == 0, tau, up);
 }
 
 // d from the band's diagonal
@@ -904,62 +904,67 @@ __global__ __launch_bounds__(ENT) void k_sb_diag(Desc D) {
 
 __global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
   __shared__ double2 xs[BXL];
-  const int64_t n = D.n, l = blockIdx.x;
+  const int n = (int)D.n;  // <= BXL: every index below fits in 32 bits
+  const int64_t l = blockIdx.x;
   const int tid = threadIdx.x, pl = tid % BXW, grp = tid / BXW;
   const int base = (tid & 63) & ~(BXW - 1);  // lane 0 of this task in the wave
   const double *z = D.Z + l * n;
   double2 *x = D.X + l * n;
-  for (int64_t r = tid; r < n; r += BXT) xs[r] = double2{z[r], 0.0};
-  double2 wn[BXRL][BXQ];  // stored entries of the next sweep, this lane's rows
-#define BX_FETCH(I)                                                              \
+  for (int r = tid; r < n; r += BXT) xs[r] = double2{z[r], 0.0};
+  // stored entries of a sweep, this lane's rows: two sets, the one of the
+  // sweep being applied and the one being loaded for the next sweep
+  double2 wa[BXRL][BXQ], wb[BXRL][BXQ];
+#define BX_FETCH(W, I)                                                           \
   {                                                                              \
-    const int64_t i_ = (I), nt_ = g_bc_kmax(n, i_) + 1;                          \
-    const double2 *r_ = D.rall + g_bc_off(n, i_);                                \
+    const int i_ = (I), nt_ = (int)g_bc_kmax(n, i_) + 1;                          \
+    const double2 *r_ = D.rall + (int)g_bc_off(n, i_);                                \
     _Pragma("unroll") for (int j = 0; j < BXRL; ++j) {                           \
-      const int64_t k = grp + BXGL * j, r = i_ + 1 + k * SBW + BXQ * pl;         \
+      const int k = grp + BXGL * j, r = i_ + 1 + k * SBW + BXQ * pl;         \
       _Pragma("unroll") for (int q = 0; q < BXQ; ++q)                            \
-        wn[j][q] = r_[k < nt_ && r + q < n ? r + q - i_ - 1 : 0];                \
+        W[j][q] = r_[k < nt_ && r + q < n ? r + q - i_ - 1 : 0];                 \
     }                                                                            \
   }
-  BX_FETCH(n - 2)
-  __syncthreads();
-  for (int64_t i = n - 2; i >= 0; --i) {
-    const int64_t nt = g_bc_kmax(n, i) + 1;
-    double2 w[BXRL][BXQ];
-#pragma unroll
-    for (int j = 0; j < BXRL; ++j)
-#pragma unroll
-      for (int q = 0; q < BXQ; ++q) w[j][q] = wn[j][q];
-    BX_FETCH(i > 0 ? i - 1 : 0)
-#pragma unroll
-    for (int j = 0; j < BXRL; ++j) {
-      const int64_t k = grp + BXGL * j;
-      if (k < nt) {  // the same for the lanes of a task
-        const int64_t r0 = i + 1 + k * SBW + BXQ * pl;
-        const double2 tau = {__shfl(w[j][0].x, base, 64), __shfl(w[j][0].y, base, 64)};
-        double2 u[BXQ], xv[BXQ], y = {0, 0};
-#pragma unroll
-        for (int q = 0; q < BXQ; ++q) {
-          const bool in = r0 + q < n;
-          u[q] = csel(in, csel(pl == 0 && q == 0, double2{1, 0}, w[j][q]), double2{0, 0});
-          xv[q] = xs[in ? r0 + q : i + 1];
-          y = cadd(y, cmulc(u[q], xv[q]));
-        }
-#pragma unroll
-        for (int o = 1; o < BXW; o <<= 1) {
-          y.x += __shfl_xor(y.x, o, 64);
-          y.y += __shfl_xor(y.y, o, 64);
-        }
-        const double2 f = cmul(tau, y);
-#pragma unroll
-        for (int q = 0; q < BXQ; ++q)
-          if (r0 + q < n) xs[r0 + q] = csub(xv[q], cmul(f, u[q]));
-      }
-    }
-    __syncthreads();
+  // sweep I with the entries in WC, the next sweep's loaded into WN; the
+  // barrier covers the LDS writes only, so those loads stay in flight across it
+#define BX_SWEEP(I, WC, WN)                                                      \
+  {                                                                              \
+    const int sw_ = (I), nt = (int)g_bc_kmax(n, sw_) + 1;                             \
+    BX_FETCH(WN, sw_ > 0 ? sw_ - 1 : 0)                                              \
+    __asm__ volatile("" ::: "memory"); /* the loads are issued here */           \
+    _Pragma("unroll") for (int j = 0; j < BXRL; ++j) {                           \
+      const int k = grp + BXGL * j;                                          \
+      if (k < nt) { /* the same for the lanes of a task */                       \
+        const int r0 = sw_ + 1 + k * SBW + BXQ * pl;                           \
+        const double2 tau = {__shfl(WC[j][0].x, base, 64), __shfl(WC[j][0].y, base, 64)}; \
+        double2 u[BXQ], xv[BXQ], y = {0, 0};                                     \
+        _Pragma("unroll") for (int q = 0; q < BXQ; ++q) {                        \
+          const bool in = r0 + q < n;                                            \
+          u[q] = csel(in, csel(pl == 0 && q == 0, double2{1, 0}, WC[j][q]), double2{0, 0}); \
+          xv[q] = xs[in ? r0 + q : sw_ + 1];                                       \
+          y = cadd(y, cmulc(u[q], xv[q]));                                       \
+        }                                                                        \
+        _Pragma("unroll") for (int o = 1; o < BXW; o <<= 1) {                    \
+          y.x += __shfl_xor(y.x, o, 64);                                         \
+          y.y += __shfl_xor(y.y, o, 64);                                         \
+        }                                                                        \
+        const double2 f = cmul(tau, y);                                          \
+        _Pragma("unroll") for (int q = 0; q < BXQ; ++q)                          \
+          if (r0 + q < n) xs[r0 + q] = csub(xv[q], cmul(f, u[q]));              \
+      }                                                                          \
+    }                                                                            \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");              \
+    __builtin_amdgcn_s_barrier();                                                \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");              \
   }
+  BX_FETCH(wa, n - 2)
+  __syncthreads();  // xs complete
+  for (int i = n - 2; i >= 0; i -= 2) {
+    BX_SWEEP(i, wa, wb)
+    if (i >= 1) BX_SWEEP(i - 1, wb, wa)
+  }
+#undef BX_SWEEP
 #undef BX_FETCH
-  for (int64_t r = tid; r < n; r += BXT) x[r] = xs[r];
+  for (int r = tid; r < n; r += BXT) x[r] = xs[r];
 }
 
 // one reflector on the SBW lanes of a group (lane p: row rk + p), for
