@@ -294,8 +294,8 @@ int32_t bse_dipole_weights(const bse_problem *p, const void *B, int32_t nblk,
  * to O(delta^2 |Hmu|) for an eigenvector error delta; omega[0 .. K) then holds
  * the refined values (ascending) and the poles of clusters inside that range
  * are re-centred.  It removes the eigensolver's rounding, not errors already
- * in Hmu.  The workspace grows by about n^2 16 B (all reflectors) plus
- * 400 K n B (inverse-iteration scratch) for K > 0.
+ * in Hmu.  The workspace grows by about n^2 16 B (all reflectors of either
+ * reduction) plus 400 K n B (inverse-iteration scratch) for K > 0.
  * Errors: n < 1 or n > 65536 (BSE_ESHAPE), NULL pointers or nrefine outside
  * 0 .. 256 (BSE_EINVAL), ws_bytes < bse_block_eigh_ws (BSE_EWORKSPACE).  The
  * call only enqueues kernels; eigenvalues it could not refine (clusters of
@@ -309,7 +309,7 @@ int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, c
 
 /* ---------------------------------------------------------------------------
  * Two-stage reduction of large blocks (the same outputs as bse_block_eigh).
- * Solves with nrefine = 0 and n >= the switch point reduce H_mu in two
+ * Solves with n >= the switch point reduce H_mu in two
  * stages that both leave e_1 fixed: first to a lower band of half-width 32
  * (panels of 32 columns: a QR of the panel below the band with one reduction
  * per column, then the two-sided update A22 - V W^dag - W V^dag of the
@@ -319,7 +319,12 @@ int32_t bse_block_eigh(int64_t n, const void *Hmu, int64_t ld, int32_t h_fp64, c
  * 2 i + k = t).  The tridiagonal step is the one above.  FP32 storage keeps
  * the working copy in FP32 (its products summed in FP64 every 128 terms);
  * the panel, the band and the chase are FP64.  The workspace grows by about
- * 6.5 KB per row of the block (66 MB at n = 10080).
+ * 6.5 KB per row of the block (66 MB at n = 10080).  With nrefine > 0 the
+ * chase keeps every reflector it makes (n (n - 1) / 2 entries of 16 B) and
+ * stage 1 every panel (about n^2 / 2 entries); the eigenvectors of T go back
+ * through both, in reverse order, before the Rayleigh quotients.  The kept
+ * chase is compiled apart from the plain one: the unrefined part of the
+ * spectrum may differ from an unrefined solve in the last FP64 bits.
  * bse_block_eigh_set_two_stage(nmin) sets the switch point to nmin (>= 2;
  * default 4096) and returns the previous one; nmin < 0 only returns it.  It
  * is process-wide: query bse_block_eigh_ws after setting it, and do not
