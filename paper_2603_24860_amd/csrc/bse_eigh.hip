@@ -1827,7 +1827,7 @@ __global__ __launch_bounds__(RNT) void k_tri_prep_b(const Desc *__restrict__ Ds,
 //             orthonormal basis of its invariant subspace
 //   k_backxf  x = Q0 H(0) H(1) ... H(n-2) z, applying the stored reflectors
 //             a panel at a time (block form below)
-//   k_hx_part partial sums of x^dag H_mu x and |x|^2 (one wave per row)
+//   k_hx_part partial sums of x^dag H_mu x and |x|^2 (HXR rows, HXV vectors)
 //   k_rq_fin  theta = Re(x^dag H_mu x) / |x|^2 replaces omega[l]; the pole of
 //             a cluster inside the refined range becomes the mean of its members
 // The Rayleigh quotient of an approximate eigenvector with error delta is
@@ -2182,37 +2182,76 @@ __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
   }
 }
 
-// partial sums over 4 rows per workgroup (one wave per row): grid (cdiv(n, 4), K)
+// partial sums of x^dag H_mu x and |x|^2 over HXR rows for HXV vectors per
+// workgroup: grid (cdiv(n, HXR), cdiv(K, HXV)).  Wave w takes rows
+// HXR bx + 4 w .. + 3; each H_mu entry read serves HXV vectors and each x
+// entry four rows, so H_mu is read K / HXV times instead of K times.  Rows
+// past n and vectors past K read row n - 1 and vector K - 1 and are dropped.
 template <typename TH>
 __global__ __launch_bounds__(ENT) void k_hx_part(Desc D) {
   typedef typename C2T<TH>::t CH;
-  __shared__ double sh[ENT / 64];
-  const int64_t n = D.n, l = blockIdx.y;
+  constexpr int RW = HXR / (ENT / 64);  // rows per wave
+  static_assert(RW * (ENT / 64) == HXR, "k_hx_part: rows split evenly over the waves");
+  __shared__ double sh[ENT / 64][HXV][2];
+  const int64_t n = D.n, K = D.K, l0 = int64_t(blockIdx.y) * HXV;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t r = int64_t(blockIdx.x) * 4 + wv;
-  const double2 *x = D.X + size_t(l) * n;
-  double num = 0, den = 0;
-  if (r < n) {
-    const CH *h = reinterpret_cast<const CH *>(D.H) + r * D.ld;
-    double yr = 0, yi = 0;
-    for (int64_t c = lane; c < n; c += 64) {
-      const double2 a = to_d2(h[c]), b = x[c];
-      yr += a.x * b.x - a.y * b.y;
-      yi += a.x * b.y + a.y * b.x;
-    }
-    yr = wave_sum(yr);
-    yi = wave_sum(yi);
-    const double2 xr = x[r];
-    num = xr.x * yr + xr.y * yi;  // Re(conj(x_r) y_r)
-    den = xr.x * xr.x + xr.y * xr.y;
+  const int64_t r0 = int64_t(blockIdx.x) * HXR + RW * wv;
+  const CH *h[RW];
+  const double2 *x[HXV];
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
+    h[q] = reinterpret_cast<const CH *>(D.H) + std::min<int64_t>(r0 + q, n - 1) * D.ld;
+#pragma unroll
+  for (int v = 0; v < HXV; ++v) x[v] = D.X + size_t(std::min<int64_t>(l0 + v, K - 1)) * n;
+  double yr[RW][HXV], yi[RW][HXV];
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int v = 0; v < HXV; ++v) yr[q][v] = yi[q][v] = 0;
+  for (int64_t c = lane; c < n; c += 64) {
+    double2 a[RW], b[HXV];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) a[q] = to_d2(h[q][c]);
+#pragma unroll
+    for (int v = 0; v < HXV; ++v) b[v] = x[v][c];
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+      for (int v = 0; v < HXV; ++v) {
+        yr[q][v] += a[q].x * b[v].x - a[q].y * b[v].y;
+        yi[q][v] += a[q].x * b[v].y + a[q].y * b[v].x;
+      }
   }
-  if (lane != 0) num = den = 0;
-  num = block_sum<ENT>(num, sh);
-  den = block_sum<ENT>(den, sh);
-  if (tid == 0) {
-    double *p = D.rqp + (size_t(l) * size_t(cdiv(n, 4)) + blockIdx.x) * 2;
-    p[0] = num;
-    p[1] = den;
+  // Re(conj(x_r) y_r) and |x_r|^2 over this wave's rows, on every lane
+  double num[HXV], den[HXV];
+#pragma unroll
+  for (int v = 0; v < HXV; ++v) num[v] = den[v] = 0;
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    const bool in = r0 + q < n;
+    const int64_t rc = std::min<int64_t>(r0 + q, n - 1);
+#pragma unroll
+    for (int v = 0; v < HXV; ++v) {
+      const double sr = wave_sum(yr[q][v]), si = wave_sum(yi[q][v]);
+      const double2 xr = x[v][rc];
+      num[v] += in ? xr.x * sr + xr.y * si : 0.0;
+      den[v] += in ? xr.x * xr.x + xr.y * xr.y : 0.0;
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < HXV; ++v) {
+      sh[wv][v][0] = num[v];
+      sh[wv][v][1] = den[v];
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * HXV) {
+    const int v = tid >> 1, f = tid & 1;
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < ENT / 64; ++w) t += sh[w][v][f];
+    if (l0 + v < K) D.rqp[(size_t(l0 + v) * size_t(cdiv(n, HXR)) + blockIdx.x) * 2 + f] = t;
   }
 }
 
@@ -2221,7 +2260,7 @@ __global__ __launch_bounds__(ENT) void k_hx_part(Desc D) {
 __global__ __launch_bounds__(ENT) void k_rq_fin(Desc D) {
   __shared__ double sh[ENT / 64];
   __shared__ double th[KMAX];
-  const int64_t n = D.n, K = D.K, nw = cdiv(n, 4);
+  const int64_t n = D.n, K = D.K, nw = cdiv(n, HXR);
   const int tid = threadIdx.x;
   for (int64_t l = 0; l < K; ++l) {
     double num = 0, den = 0;
@@ -2358,7 +2397,8 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
     if (n >= 2)
       BSE_LAUNCH("k_bx_tmat", k_bx_tmat, dim3((unsigned)cdiv(n - 1, NBK)), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_backxf", k_backxf<1>, dim3((unsigned)K), dim3(ENT), 0, s, D);
-    BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, 4), (unsigned)K), dim3(ENT), 0,
+    BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, HXR), (unsigned)cdiv(K, HXV)),
+               dim3(ENT), 0,
                s, D);
     BSE_LAUNCH("k_rq_fin", k_rq_fin, dim3(1), dim3(ENT), 0, s, D);
     BSE_HIP_CHECK(hipGetLastError());
@@ -2441,7 +2481,8 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
     else
       BSE_LAUNCH("k_bx_chase", k_bx_chase, dim3((unsigned)K), dim3(BXC), 0, s, D);
     BSE_LAUNCH("k_backxf", k_backxf<SBW>, dim3((unsigned)K), dim3(ENT), 0, s, D);
-    BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, 4), (unsigned)K), dim3(ENT), 0,
+    BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, HXR), (unsigned)cdiv(K, HXV)),
+               dim3(ENT), 0,
                s, D);
     BSE_LAUNCH("k_rq_fin", k_rq_fin, dim3(1), dim3(ENT), 0, s, D);
     BSE_HIP_CHECK(hipGetLastError());

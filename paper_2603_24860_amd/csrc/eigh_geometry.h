@@ -88,7 +88,7 @@ struct Desc {
   double2 *Vall;             // [n][ldv] every reflector (column j: reflector of column j)
   double *Z;                 // [K][n] eigenvectors of T
   double2 *X;                // [K][n] their back-transforms
-  double *rqp;               // [K][cdiv(n, 4)][2] partial Rayleigh quotients
+  double *rqp;               // [K][cdiv(n, HXR)][2] partial Rayleigh quotients
   double *scr;               // [K][6 CMAX n] inverse-iteration scratch
   double *wref;              // [K] refined eigenvalues
   double2 *Tm;               // [cdiv(n - 1, NBK)][NBK][NBK] block-reflector factors T
@@ -241,6 +241,10 @@ __host__ __device__ __forceinline__ int64_t g_bc_nks(int64_t n) {
 __host__ __device__ __forceinline__ int64_t g_sb_npan(int64_t n) {
   return n > SBW ? cdiv(n - SBW, SBW) : 0;
 }
+// Rayleigh quotients of the refinement: k_hx_part takes HXR rows of H_mu
+// (HXR / 4 per wave) against HXV vectors per workgroup
+constexpr int HXR = 16;
+constexpr int HXV = 4;
 // back-transformation through the chase: k_bx_chase_lds (x in LDS) for
 // blocks up to BXL rows, k_bx_chase above
 constexpr int BXL = 10240;                // rows of x held in LDS
@@ -312,7 +316,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     t.Vall = two_stage ? nullptr : (double2 *)take(size_t(n) * ldv * 16);
     t.Z = (double *)take(size_t(K) * n * 8);
     t.X = (double2 *)take(size_t(K) * n * 16);
-    t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, 4)) * 16);
+    t.rqp = (double *)take(size_t(K) * size_t(cdiv(n, HXR)) * 16);
     t.scr = (double *)take(size_t(K) * (6 * CMAX) * n * 8);
     t.wref = (double *)take(size_t(K) * 8);
     t.Tm = (double2 *)take(size_t(std::max<int64_t>(cdiv(n - 1, NBK), 1)) * NBK * NBK * 16);

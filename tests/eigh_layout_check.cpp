@@ -372,7 +372,7 @@ int run(int64_t n, bool a64, int64_t K) {
     C.add("Vall", D.Vall, 16, D.Vall ? n * D.ldv : 0);
     C.add("Z", D.Z, 8, K * n);
     C.add("X", D.X, 16, K * n);
-    C.add("rqp", D.rqp, 16, K * cdiv(n, 4));
+    C.add("rqp", D.rqp, 16, K * cdiv(n, HXR));
     C.add("scr", D.scr, 8, K * 6 * CMAX * n);
     C.add("wref", D.wref, 8, K);
     C.add("Tm", D.Tm, 16, std::max<int64_t>(cdiv(n - 1, NBK), 1) * NBK * NBK);
@@ -538,7 +538,7 @@ int run(int64_t n, bool a64, int64_t K) {
     C.range("scr", 0, K * 6 * CMAX * n, "k_invit");
     if (!two) C.range("Tm", 0, std::max<int64_t>(cdiv(n - 1, NBK), 1) * NBK * NBK, "k_bx_tmat");
     C.range("X", 0, K * n, "k_backxf");
-    C.range("rqp", 0, K * cdiv(n, 4), "k_hx_part");
+    C.range("rqp", 0, K * cdiv(n, HXR), "k_hx_part");
     C.range("wref", 0, K, "k_rq_fin");
   }
   std::printf("n = %lld %s K = %lld%s: workspace %zu B, %zu regions, %lld accesses in bounds\n",
