@@ -2080,48 +2080,37 @@ __global__ __launch_bounds__(ENT) void k_bx_tmat(Desc D) {
   for (int q = tid; q < NBK * NBK; q += ENT) T[q] = ts[q / NBK][q % NBK];
 }
 
-// OFF = 1: the one-stage reduction (reflector of column j from row j + 1,
-// x starts as z); OFF = SBW: stage 1 of the two-stage one (reflector c of
-// the panel at j0 from row j0 + c + SBW, stored with its zeros and unit entry
-// over the panel's m rows, T kept by k_sb_tmat, x already holds the
-// back-transform through the bulge chase).
-template <int OFF>
 __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
   __shared__ double sh[ENT / 64];
   __shared__ double2 sw[ENT / 64][NBK];
   __shared__ double2 st[NBK];
   const int64_t n = D.n, ldv = D.ldv, l = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double *z = D.Z + size_t(l) * n;
   double2 *x = D.X + size_t(l) * n;
-  if (OFF == 1) {
-    const double *z = D.Z + size_t(l) * n;
-    for (int64_t k = tid; k < n; k += ENT) x[k] = double2{z[k], 0.0};
-  }
-  const int64_t npan = OFF == 1 ? (n >= 2 ? cdiv(n - 1, NBK) : 0) : g_sb_npan(n);
+  for (int64_t k = tid; k < n; k += ENT) x[k] = double2{z[k], 0.0};
+  const int64_t npan = n >= 2 ? cdiv(n - 1, NBK) : 0;
   for (int64_t p = npan - 1; p >= 0; --p) {
     const int64_t j0 = p * NBK;
-    const int bp = int(std::min<int64_t>(NBK, n - OFF - j0));
-    // entry (row r, reflector c): Vall[j0 + c][r], or vrow's panel [c][r - j0 - OFF]
-    const double2 *V = OFF == 1 ? D.Vall + j0 * ldv : D.vrow;
-    const int64_t vo = OFF == 1 ? 0 : g_sb_voff(n, p) * NBK - j0 - OFF;  // + r >= 0
-    const int64_t sr = 1, sc = OFF == 1 ? ldv : n - j0 - OFF;
+    const int bp = int(std::min<int64_t>(NBK, n - 1 - j0));
+    const double2 *V = D.Vall + j0 * ldv;
     const double2 *T = D.Tm + size_t(p) * NBK * NBK;
-    // w = V^dag x over the panel's rows (v_c is zero above row j0 + c + OFF)
+    // w = V^dag x over the panel's rows (v_c is zero above row j0 + c + 1)
     double2 w[NBK];
 #pragma unroll
     for (int c = 0; c < NBK; ++c) w[c] = double2{0, 0};
     // every load is unconditional (column index clamped in bounds) and the
     // support mask is applied to the value, so the loads of a row overlap
-    for (int64_t r = (j0 + OFF) / ENT * ENT + tid; r < n; r += ENT) {
-      if (r < j0 + OFF) continue;
+    for (int64_t r = (j0 + 1) / ENT * ENT + tid; r < n; r += ENT) {
+      if (r < j0 + 1) continue;
       const double2 xr = x[r];
       double2 vr[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) vr[c] = V[vo + std::min(c, bp - 1) * sc + r * sr];
+      for (int c = 0; c < NBK; ++c) vr[c] = V[std::min(c, bp - 1) * ldv + r];
 #pragma unroll
       for (int c = 0; c < NBK; ++c) {
         const double2 t = cmulc(vr[c], xr);
-        const bool ok = c < bp && r >= j0 + c + OFF;
+        const bool ok = c < bp && r >= j0 + c + 1;
         w[c].x += ok ? t.x : 0.0;
         w[c].y += ok ? t.y : 0.0;
       }
@@ -2149,16 +2138,16 @@ __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
     double2 tc[NBK];
 #pragma unroll
     for (int c = 0; c < NBK; ++c) tc[c] = st[c];
-    for (int64_t r = (j0 + OFF) / ENT * ENT + tid; r < n; r += ENT) {
-      if (r < j0 + OFF) continue;
+    for (int64_t r = (j0 + 1) / ENT * ENT + tid; r < n; r += ENT) {
+      if (r < j0 + 1) continue;
       double2 xr = x[r];
       double2 vr[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) vr[c] = V[vo + std::min(c, bp - 1) * sc + r * sr];
+      for (int c = 0; c < NBK; ++c) vr[c] = V[std::min(c, bp - 1) * ldv + r];
 #pragma unroll
       for (int c = 0; c < NBK; ++c) {
         const double2 t = cmul(vr[c], tc[c]);
-        const bool ok = c < bp && r >= j0 + c + OFF;
+        const bool ok = c < bp && r >= j0 + c + 1;
         xr.x -= ok ? t.x : 0.0;
         xr.y -= ok ? t.y : 0.0;
       }
@@ -2180,6 +2169,130 @@ __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
     const double2 f = cmul(t, double2{sr, si});
     for (int64_t r = tid; r < n; r += ENT) x[r] = csub(x[r], cmul(f, v[r]));
   }
+}
+
+// Back-transformation through the stage-1 panels of the two-stage reduction
+// (refinement): x -= V T (V^dag x) for the panels from the last to the first,
+// then the initial reflection.  Per panel two launches over (row blocks of
+// BPR rows) x (groups of BPV vectors), so every compute unit takes part and
+// the panel's reflectors are read once per launch for BPV vectors:
+//   k_bp_part   partial w = V^dag x over the block's rows (thread (c, g):
+//               column c, rows g, g + 8, ...; the eight row groups of a
+//               column summed by xor shuffles)
+//   k_bp_apply  w summed over the blocks, s = T w, x -= V s over the block's
+//               rows (one row per thread at a time)
+// The panel's reflector c is stored with its zeros and unit entry over the
+// panel's m rows (column c of [SBW][m]), and T is upper triangular.
+__global__ __launch_bounds__(ENT) void k_bp_part(Desc D, int64_t p) {
+  static_assert(ENT == SBW * 8, "k_bp_part: eight row groups per column");
+  const int64_t n = D.n, K = D.K, j0 = p * SBW, p0 = j0 + SBW, m = n - p0;
+  const int64_t rb = int64_t(blockIdx.x) * BPR, l0 = int64_t(blockIdx.y) * BPV;
+  const int tid = threadIdx.x, c = tid / 8, g = tid % 8;
+  const double2 *V = D.vrow + g_sb_voff(n, p) * SBW + c * m;
+  const double2 *x[BPV];
+#pragma unroll
+  for (int v = 0; v < BPV; ++v) x[v] = D.X + size_t(std::min<int64_t>(l0 + v, K - 1)) * n + p0;
+  double2 w[BPV];
+#pragma unroll
+  for (int v = 0; v < BPV; ++v) w[v] = double2{0, 0};
+  const int64_t rend = std::min<int64_t>(rb + BPR, m);
+  constexpr int U = 4;  // rows of a thread with their loads in flight together
+  for (int64_t r0 = rb + g; r0 < rend; r0 += 8 * U) {
+    double2 vr[U], xv[U][BPV];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {  // rows past the block read its last row, with v = 0
+      const int64_t r = std::min<int64_t>(r0 + 8 * u, rend - 1);
+      vr[u] = csel(r0 + 8 * u < rend, V[r], double2{0, 0});
+#pragma unroll
+      for (int v = 0; v < BPV; ++v) xv[u][v] = x[v][r];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < BPV; ++v) w[v] = cadd(w[v], cmulc(vr[u], xv[u][v]));
+  }
+#pragma unroll
+  for (int v = 0; v < BPV; ++v)
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      w[v].x += __shfl_xor(w[v].x, o, 64);
+      w[v].y += __shfl_xor(w[v].y, o, 64);
+    }
+  if (g == 0) {
+#pragma unroll
+    for (int v = 0; v < BPV; ++v)
+      if (l0 + v < K) D.bxw[(size_t(blockIdx.x) * K + l0 + v) * SBW + c] = w[v];
+  }
+}
+
+__global__ __launch_bounds__(ENT) void k_bp_apply(Desc D, int64_t p) {
+  __shared__ double2 ws_[BPV][SBW], ss[SBW][BPV];
+  const int64_t n = D.n, K = D.K, j0 = p * SBW, p0 = j0 + SBW, m = n - p0;
+  const int64_t rb = int64_t(blockIdx.x) * BPR, l0 = int64_t(blockIdx.y) * BPV;
+  const int64_t nb = cdiv(m, BPR);
+  const int tid = threadIdx.x;
+  const double2 *T = D.Tm + size_t(p) * SBW * SBW;
+  if (tid < BPV * SBW) {  // w of vector v, entry c: the sum over the row blocks
+    const int v = tid / SBW, c = tid % SBW;
+    const int64_t l = std::min<int64_t>(l0 + v, K - 1);
+    double2 a = {0, 0};
+    for (int64_t b0 = 0; b0 < nb; b0 += 8) {  // eight loads in flight
+      double2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        t[u] = D.bxw[(size_t(std::min<int64_t>(b0 + u, nb - 1)) * K + l) * SBW + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a = cadd(a, csel(b0 + u < nb, t[u], double2{0, 0}));
+    }
+    ws_[v][c] = a;
+  }
+  __syncthreads();
+  if (tid < BPV * SBW) {  // s = T w (T upper triangular)
+    const int v = tid / SBW, c = tid % SBW;
+    double2 a = {0, 0};
+    for (int e = c; e < SBW; ++e) a = cadd(a, cmul(T[c * SBW + e], ws_[v][e]));
+    ss[c][v] = a;
+  }
+  __syncthreads();
+  const double2 *V = D.vrow + g_sb_voff(n, p) * SBW;
+  double2 *x[BPV];
+#pragma unroll
+  for (int v = 0; v < BPV; ++v) x[v] = D.X + size_t(std::min<int64_t>(l0 + v, K - 1)) * n + p0;
+  const int64_t rend = std::min<int64_t>(rb + BPR, m);
+  for (int64_t r = rb + tid; r < rend; r += ENT) {
+    double2 a[BPV];
+#pragma unroll
+    for (int v = 0; v < BPV; ++v) a[v] = double2{0, 0};
+#pragma unroll 8
+    for (int c = 0; c < SBW; ++c) {
+      const double2 vr = V[c * m + r];
+#pragma unroll
+      for (int v = 0; v < BPV; ++v) a[v] = cadd(a[v], cmul(vr, ss[c][v]));
+    }
+#pragma unroll
+    for (int v = 0; v < BPV; ++v)
+      if (l0 + v < K) x[v][r] = csub(x[v][r], a[v]);
+  }
+}
+
+// the initial reflection of each back-transformed vector (one workgroup per vector)
+__global__ __launch_bounds__(ENT) void k_bx_q0(Desc D) {
+  __shared__ double sh[ENT / 64];
+  const int64_t n = D.n, l = blockIdx.x;
+  const int tid = threadIdx.x;
+  double2 *x = D.X + size_t(l) * n;
+  const double2 *v = D.vbuf;
+  const double2 t = D.tau[0];
+  double sr = 0, si = 0;
+  for (int64_t r = tid; r < n; r += ENT) {
+    const double2 c = cmulc(v[r], x[r]);
+    sr += c.x;
+    si += c.y;
+  }
+  sr = block_sum<ENT>(sr, sh);
+  si = block_sum<ENT>(si, sh);
+  const double2 f = cmul(t, double2{sr, si});
+  for (int64_t r = tid; r < n; r += ENT) x[r] = csub(x[r], cmul(f, v[r]));
 }
 
 // partial sums of x^dag H_mu x and |x|^2 over HXR rows for HXV vectors per
@@ -2396,7 +2509,7 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
     BSE_LAUNCH("k_invit", k_invit, dim3((unsigned)K), dim3(ENT), 0, s, D);
     if (n >= 2)
       BSE_LAUNCH("k_bx_tmat", k_bx_tmat, dim3((unsigned)cdiv(n - 1, NBK)), dim3(ENT), 0, s, D);
-    BSE_LAUNCH("k_backxf", k_backxf<1>, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    BSE_LAUNCH("k_backxf", k_backxf, dim3((unsigned)K), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, HXR), (unsigned)cdiv(K, HXV)),
                dim3(ENT), 0,
                s, D);
@@ -2409,8 +2522,8 @@ int32_t eigh_run(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double
 // ---------------------------------------------------------------------------
 // single block, two-stage reduction; with refinement (K > 0) every reflector
 // of both stages is kept and the eigenvectors of T are carried back through
-// the chase (k_bx_chase), then through the stage-1 panels and the initial
-// reflection (k_backxf<SBW>)
+// the chase (k_bx_chase), then through the stage-1 panels (k_bp_part,
+// k_bp_apply) and the initial reflection (k_bx_q0)
 // ---------------------------------------------------------------------------
 template <typename TH, typename TA>
 int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, double *omega,
@@ -2480,7 +2593,12 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
       BSE_LAUNCH("k_bx_chase", k_bx_chase_lds, dim3((unsigned)K), dim3(BXT), 0, s, D);
     else
       BSE_LAUNCH("k_bx_chase", k_bx_chase, dim3((unsigned)K), dim3(BXC), 0, s, D);
-    BSE_LAUNCH("k_backxf", k_backxf<SBW>, dim3((unsigned)K), dim3(ENT), 0, s, D);
+    for (int64_t p = g_sb_npan(n) - 1; p >= 0; --p) {
+      const dim3 g((unsigned)cdiv(n - SBW * (p + 1), BPR), (unsigned)cdiv(K, BPV));
+      BSE_LAUNCH("k_bp_part", k_bp_part, g, dim3(ENT), 0, s, D, p);
+      BSE_LAUNCH("k_bp_apply", k_bp_apply, g, dim3(ENT), 0, s, D, p);
+    }
+    BSE_LAUNCH("k_bx_q0", k_bx_q0, dim3((unsigned)K), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, HXR), (unsigned)cdiv(K, HXV)),
                dim3(ENT), 0,
                s, D);

@@ -113,6 +113,7 @@ struct Desc {
   double2 *rall;             // chase, packed: sweep i at g_bc_off(n, i), rows i + 1 .. n - 1;
                              // each task's first entry (u_0 = 1) holds its tau
   double2 *vrow;             // stage 1, panel p (m rows) at g_sb_voff(n, p) SBW: [SBW][m]
+  double2 *bxw;              // [cdiv(n, BPR)][K][SBW] partial V^dag x of the stage-1 back-transformation
 };
 
 // Two-stage reduction of large single blocks.  Stage 1 reduces A to a lower
@@ -241,6 +242,10 @@ __host__ __device__ __forceinline__ int64_t g_bc_nks(int64_t n) {
 __host__ __device__ __forceinline__ int64_t g_sb_npan(int64_t n) {
   return n > SBW ? cdiv(n - SBW, SBW) : 0;
 }
+// back-transformation through the stage-1 panels: k_bp_part / k_bp_apply
+// take BPR panel rows and BPV vectors per workgroup
+constexpr int BPR = 512;
+constexpr int BPV = 4;
 // Rayleigh quotients of the refinement: k_hx_part takes HXR rows of H_mu
 // (HXR / 4 per wave) against HXV vectors per workgroup
 constexpr int HXR = 16;
@@ -340,6 +345,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     if (K > 0) {
       t.rall = (double2 *)take(size_t(std::max<int64_t>(g_bc_off(n, n - 1), 1)) * 16);
       t.vrow = (double2 *)take(size_t(std::max<int64_t>(g_sb_voff(n, g_sb_npan(n)), 1)) * SBW * 16);
+      t.bxw = (double2 *)take(size_t(cdiv(n, BPR)) * K * SBW * 16);
     }
   }
   if (w) *w = t;

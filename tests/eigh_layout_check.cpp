@@ -130,6 +130,7 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
   if (K > 0) {
     C.add("rall", D.rall, 16, std::max<int64_t>(g_bc_off(n, n - 1), 1));
     C.add("vrow", D.vrow, 16, std::max<int64_t>(g_sb_voff(n, g_sb_npan(n)), 1) * SBW);
+    C.add("bxw", D.bxw, 16, cdiv(n, BPR) * K * SBW);
     if (D.Vall) return 1;  // the two-stage path keeps its reflectors by rows only
   }
   C.layout_ok();
@@ -319,14 +320,27 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
       C.at("rall", g_bc_off(n, i), "k_bx_chase masked lanes");
     }
     C.range("Z", 0, K * n, "k_bx_chase z");
-    // k_backxf<SBW>: panel p, rows j0 + SBW .. n of vrow (all SBW entries)
+    // k_bp_part / k_bp_apply: panel p, grid (cdiv(m, BPR), cdiv(K, BPV)); rows
+    // rb .. min(rb + BPR, m) of every column of the panel and of the group's
+    // vectors (clamped to K - 1), the partial sums of every block
     for (int64_t p = g_sb_npan(n) - 1; p >= 0; --p) {
-      const int64_t pj = p * NBK, m = n - SBW - pj;
-      if (m < 1) return 1;
+      const int64_t pj = p * NBK, p0 = pj + SBW, m = n - p0, nb = cdiv(m, BPR);
+      if (m < 1 || nb > cdiv(n, BPR)) return 1;
       const int64_t o = g_sb_voff(n, p) * SBW;
-      C.range("vrow", o, o + m * SBW, "k_backxf<SBW> V");
-      C.range("Tm", p * NBK * NBK, (p + 1) * NBK * NBK, "k_backxf<SBW> T");
+      for (int64_t b = 0; b < nb; ++b) {
+        const int64_t rb = b * BPR, re = std::min<int64_t>(rb + BPR, m);
+        for (int c = 0; c < SBW; c += SBW - 1) C.range("vrow", o + c * m + rb, o + c * m + re, "k_bp V");
+        for (int64_t g = 0; g < cdiv(K, BPV); ++g)
+          for (int v = 0; v < BPV; ++v) {
+            const int64_t l = std::min<int64_t>(g * BPV + v, K - 1);
+            C.range("X", l * n + p0 + rb, l * n + p0 + re, "k_bp x");
+            C.range("bxw", (b * K + l) * SBW, (b * K + l) * SBW + SBW, "k_bp partial");
+          }
+      }
+      C.range("Tm", p * NBK * NBK, (p + 1) * NBK * NBK, "k_bp_apply T");
     }
+    C.range("X", 0, K * n, "k_bx_q0");
+    C.range("vbuf", 0, n, "k_bx_q0");
   }
   return 0;
 }
