@@ -894,20 +894,45 @@ __global__ __launch_bounds__(ENT) void k_sb_diag(Desc D) {
 // written by one lane only; a barrier separates the sweeps.
 //   k_bx_chase_lds  blocks of up to BXL rows: x in LDS (FP64); BXW lanes per
 //                   task, BXQ consecutive rows per lane, u^dag x summed over
-//                   the lane's rows and then over the task's lanes (xor
-//                   shuffles); the reflectors of the next sweep are loaded
+//                   the lane's rows and then over the task's lanes (DPP
+//                   moves); the reflectors of the next sweep are loaded
 //                   while the current one is applied (they do not depend on x)
 //   k_bx_chase      larger blocks: x in global memory, SBW lanes per task
 //                   (one row each), BXU tasks per group with their loads in
 //                   flight together
 // ---------------------------------------------------------------------------
 
+// cross-lane moves within groups of eight lanes (DPP, no LDS round trip):
+// quad_perm [1,0,3,2] (lane ^ 1), [2,3,0,1] (lane ^ 2), [0,0,0,0] (lane 0 of
+// the quad) and row_half_mirror (lane i <-> 7 - i of each eight)
+constexpr int DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_Q0 = 0x00, DPP_HM = 0x141;
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+// sum over the eight lanes of a group, on every lane: the quad sums by two
+// exchanges, then the mirrored quad's sum
+__device__ __forceinline__ double sum8(double v) {
+  v += dppd<DPP_X1>(v);
+  v += dppd<DPP_X2>(v);
+  return v + dppd<DPP_HM>(v);
+}
+// the value of lane 0 of the group of eight, on every lane (pl: lane in the group)
+__device__ __forceinline__ double bcast8(double v, int pl) {
+  const double q = dppd<DPP_Q0>(v);
+  const double m = dppd<DPP_HM>(q);
+  return pl < 4 ? q : m;
+}
+static_assert(BXW == 8, "k_bx_chase_lds: tasks of eight lanes");
+
 __global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
   __shared__ double2 xs[BXL];
   const int n = (int)D.n;  // <= BXL: every index below fits in 32 bits
   const int64_t l = blockIdx.x;
   const int tid = threadIdx.x, pl = tid % BXW, grp = tid / BXW;
-  const int base = (tid & 63) & ~(BXW - 1);  // lane 0 of this task in the wave
   const double *z = D.Z + l * n;
   double2 *x = D.X + l * n;
   for (int r = tid; r < n; r += BXT) xs[r] = double2{z[r], 0.0};
@@ -935,7 +960,7 @@ __global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
       const int k = grp + BXGL * j;                                          \
       if (k < nt) { /* the same for the lanes of a task */                       \
         const int r0 = sw_ + 1 + k * SBW + BXQ * pl;                           \
-        const double2 tau = {__shfl(WC[j][0].x, base, 64), __shfl(WC[j][0].y, base, 64)}; \
+        const double2 tau = {bcast8(WC[j][0].x, pl), bcast8(WC[j][0].y, pl)};   \
         double2 u[BXQ], xv[BXQ], y = {0, 0};                                     \
         _Pragma("unroll") for (int q = 0; q < BXQ; ++q) {                        \
           const bool in = r0 + q < n;                                            \
@@ -943,10 +968,8 @@ __global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
           xv[q] = xs[in ? r0 + q : sw_ + 1];                                       \
           y = cadd(y, cmulc(u[q], xv[q]));                                       \
         }                                                                        \
-        _Pragma("unroll") for (int o = 1; o < BXW; o <<= 1) {                    \
-          y.x += __shfl_xor(y.x, o, 64);                                         \
-          y.y += __shfl_xor(y.y, o, 64);                                         \
-        }                                                                        \
+        y.x = sum8(y.x);                                                         \
+        y.y = sum8(y.y);                                                         \
         const double2 f = cmul(tau, y);                                          \
         _Pragma("unroll") for (int q = 0; q < BXQ; ++q)                          \
           if (r0 + q < n) xs[r0 + q] = csub(xv[q], cmul(f, u[q]));              \
