@@ -2589,7 +2589,7 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
   BSE_HIP_CHECK(hipGetLastError());
   if (K > 0) {
     BSE_LAUNCH("k_invit", k_invit, dim3((unsigned)K), dim3(ENT), 0, s, D);
-    if (n <= BXL)
+    if (n <= BXL - SBW)
       BSE_LAUNCH("k_bx_chase", k_bx_chase_lds, dim3((unsigned)K), dim3(BXT), 0, s, D);
     else
       BSE_LAUNCH("k_bx_chase", k_bx_chase, dim3((unsigned)K), dim3(BXC), 0, s, D);

@@ -892,7 +892,7 @@ __global__ __launch_bounds__(ENT) void k_sb_diag(Desc D) {
 // first is the reverse order.  One workgroup per vector.  The stored entry of
 // row 0 of a task holds its tau (u_0 = 1).  Within a sweep a row is read and
 // written by one lane only; a barrier separates the sweeps.
-//   k_bx_chase_lds  blocks of up to BXL rows: x in LDS (FP64); BXW lanes per
+//   k_bx_chase_lds  blocks of up to BXL - SBW rows: x in LDS (FP64); BXW lanes per
 //                   task, BXQ consecutive rows per lane, u^dag x summed over
 //                   the lane's rows and then over the task's lanes (DPP
 //                   moves); the reflectors of the next sweep are loaded
@@ -935,7 +935,9 @@ __global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
   const int tid = threadIdx.x, pl = tid % BXW, grp = tid / BXW;
   const double *z = D.Z + l * n;
   double2 *x = D.X + l * n;
-  for (int r = tid; r < n; r += BXT) xs[r] = double2{z[r], 0.0};
+  // rows n .. n + SBW - 1 (n <= BXL - SBW) are zero padding: the lanes of the
+  // last task of a sweep past row n - 1 read and write there with u = 0
+  for (int r = tid; r < n + SBW; r += BXT) xs[r] = double2{r < n ? z[r] : 0.0, 0.0};
   // stored entries of a sweep, this lane's rows: two sets, the one of the
   // sweep being applied and the one being loaded for the next sweep
   double2 wa[BXRL][BXQ], wb[BXRL][BXQ];
@@ -965,14 +967,14 @@ __global__ __launch_bounds__(BXT) void k_bx_chase_lds(Desc D) {
         _Pragma("unroll") for (int q = 0; q < BXQ; ++q) {                        \
           const bool in = r0 + q < n;                                            \
           u[q] = csel(in, csel(pl == 0 && q == 0, double2{1, 0}, WC[j][q]), double2{0, 0}); \
-          xv[q] = xs[in ? r0 + q : sw_ + 1];                                       \
+          xv[q] = xs[r0 + q];                                                    \
           y = cadd(y, cmulc(u[q], xv[q]));                                       \
         }                                                                        \
         y.x = sum8(y.x);                                                         \
         y.y = sum8(y.y);                                                         \
         const double2 f = cmul(tau, y);                                          \
         _Pragma("unroll") for (int q = 0; q < BXQ; ++q)                          \
-          if (r0 + q < n) xs[r0 + q] = csub(xv[q], cmul(f, u[q]));              \
+          xs[r0 + q] = csub(xv[q], cmul(f, u[q]));                               \
       }                                                                          \
     }                                                                            \
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");              \

@@ -250,8 +250,8 @@ constexpr int BPV = 4;
 // (HXR / 4 per wave) against HXV vectors per workgroup
 constexpr int HXR = 16;
 constexpr int HXV = 4;
-// back-transformation through the chase: k_bx_chase_lds (x in LDS) for
-// blocks up to BXL rows, k_bx_chase above
+// back-transformation through the chase: k_bx_chase_lds (x in LDS, with
+// SBW rows of padding) for blocks up to BXL - SBW rows, k_bx_chase above
 constexpr int BXL = 10240;                // rows of x held in LDS
 constexpr int BXT = 512;                  // threads of k_bx_chase_lds
 constexpr int BXQ = 4;                    // rows per lane

@@ -306,10 +306,13 @@ int run_two_stage(Check &C, const Desc &D, int64_t n, bool a64) {
   if (K > 0) {
     // k_bx_chase / k_bx_chase_lds: every task of every sweep (its rows, the
     // entry of its row 0 with tau), loads of masked lanes from the sweep's
-    // first entry; the LDS form's x covers rows 0 .. n <= BXL
+    // first entry; the LDS form's x covers rows 0 .. n + SBW <= BXL
     for (int64_t i = n - 2; i >= 0; --i) {
       const int64_t nt = g_bc_kmax(n, i) + 1;
-      if (n <= BXL && nt > int64_t(BXGL) * BXRL) return 1;  // tasks beyond the rounds
+      if (n <= BXL - SBW) {  // the LDS form: its rounds cover the tasks, its rows fit with padding
+        if (nt > int64_t(BXGL) * BXRL) return 1;
+        if (i + 1 + (nt - 1) * SBW + SBW > BXL) return 1;
+      }
       for (int64_t k = 0; k < nt; ++k) {
         const int64_t r0 = i + 1 + k * SBW, r1 = std::min<int64_t>(r0 + SBW, n);
         C.range("rall", g_bc_off(n, i) + (r0 - i - 1), g_bc_off(n, i) + (r1 - i - 1), "k_bx_chase u");
