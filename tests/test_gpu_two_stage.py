@@ -294,11 +294,16 @@ def test_two_stage_block_of_40000(lib):
     Eigenvalues within the FP32 storage bar of the large-block tests
     (1e-4 sqrt(n / 4500) eV), total oscillator strength within 1e-5 of
     |Q^dag b|^2 summed, and a weighted pole near each of ten exact
-    eigenvalues spread over the spectrum."""
+    eigenvalues spread over the spectrum.  Then with FP64 refinement of the
+    lowest 100 (two-stage back-transformation at this size)."""
     n = 40000
     say("two-stage n =", n)
     rng = np.random.default_rng(40000)
     lam = np.sort(rng.uniform(-10, 10, n))
+    # the lowest 100 spaced by 0.02 below the rest: with FP32 storage, gaps
+    # under 8 eps32 sqrt(n) |T| (1.9e-3 here) chain eigenvalues into one
+    # cluster, and clusters of more than 8 are reported unrefined
+    lam[:100] = -12.0 + 0.02 * np.arange(100)
     A = torch.diag(torch.as_tensor(lam, dtype=torch.complex128, device="cuda"))
     us = []
     for _ in range(3):
@@ -333,3 +338,21 @@ def test_two_stage_block_of_40000(lib):
     keep = os_ > 0
     for i in np.linspace(0, n - 1, 10).astype(int):
         assert np.abs(po[keep] - lam[i]).min() < 1e-3
+    # the same block with FP64 refinement of the lowest 100: the chase's
+    # reflectors applied to x in global memory (n above the LDS form), 1249
+    # stage-1 panels; the Rayleigh quotients against the FP32 H_mu remove the
+    # eigensolver's error, not the rounding of H_mu itself (about 1e-6 here)
+    K = 100
+    del ws
+    torch.cuda.empty_cache()
+    ws = torch.empty(lib.bse_block_eigh_ws(n, 0, lib.FP32, K), dtype=torch.uint8, device="cuda")
+    om1 = torch.empty(n, dtype=torch.float64, device="cuda")
+    po1, os1 = torch.empty_like(om1), torch.empty_like(om1)
+    lib.bse_block_eigh(Hmu, Bmu, lib.FP32, om1, po1, os1, ws, nrefine=K)
+    st = lib.bse_block_eigh_status(n, lib.FP32, K, ws, raise_on_noconv=False)
+    om1 = om1.cpu().numpy()
+    e0 = np.abs(om[:K] - lam[:K]).max()
+    e1 = np.abs(om1[:K] - lam[:K]).max()
+    say("  refined lowest", K, "error unrefined", e0, "refined", e1, "status", st)
+    assert st[:2] == [0, 0]
+    assert e1 < 1e-5 and e1 < e0 / 10
