@@ -1417,7 +1417,8 @@ __device__ __forceinline__ void b_weights(int64_t n, const double *__restrict__ 
                                                  const double *__restrict__ beta0,
                                                  const double *__restrict__ omega,
                                                  double *__restrict__ pole,
-                                                 double *__restrict__ osc, int wg) {
+                                                 double *__restrict__ osc,
+                                                 int32_t *__restrict__ clo, int wg) {
   const int lane = threadIdx.x & 63;
   const int64_t i = int64_t(wg) * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= n) return;
@@ -1464,6 +1465,7 @@ __device__ __forceinline__ void b_weights(int64_t n, const double *__restrict__ 
     j = b;
     geometry(i0, j);
   }
+  if (clo && lane == 0) clo[i] = int32_t(i0);  // the cluster, for the refinement
   if (i != i0) {
     if (lane == 0) {
       pole[i] = li;
@@ -1650,7 +1652,7 @@ BSE_PAIR(bisect, int use_grid, {
 })
 BSE_PAIR(weights, int unused_, {
   (void)unused_;
-  b_weights(D.n, D.d, D.e2, D.tsc, D.beta0, D.omega, D.pole, D.osc, wg);
+  b_weights(D.n, D.d, D.e2, D.tsc, D.beta0, D.omega, D.pole, D.osc, D.K > 0 ? D.clo : nullptr, wg);
 })
 #undef BSE_PAIR
 
@@ -1957,11 +1959,10 @@ __global__ __launch_bounds__(ENT) void k_invit(Desc D) {
   __shared__ double sh[ENT / 64];
   const int64_t n = D.n, l = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const double ctol = D.tsc[4], tn = D.tsc[2];
+  const double tn = D.tsc[2];
   const double *om = D.omega;
-  int64_t i = l;
-  while (i > 0 && om[i] - om[i - 1] <= ctol) --i;
-  const int64_t m = l - i;  // member index of l in its cluster
+  const int64_t i = D.clo[l];  // l's cluster as the weights formed it
+  const int64_t m = l - i;     // member index of l in its cluster
   double *scr = D.scr + size_t(l) * (6 * CMAX) * n;
   double *mem = scr + 5 * CMAX * n;  // [CMAX][n] member vectors
   double *z = D.Z + size_t(l) * n;
@@ -2400,12 +2401,11 @@ __global__ __launch_bounds__(ENT) void k_rq_fin(Desc D) {
       }
       th[b + 1] = v;
     }
-    const double ctol = D.tsc[4];
-    // clusters of the unrefined values: heads carry the pole
+    // the clusters of the weights (runs of equal clo): heads carry the pole
     int64_t i = 0;
     while (i < K) {
       int64_t j = i;
-      while (j + 1 < n && D.omega[j + 1] - D.omega[j] <= ctol) ++j;
+      while (j + 1 < n && D.clo[j + 1] == i) ++j;
       if (j < K) {
         double s = 0;
         for (int64_t q = i; q <= j; ++q) s += th[q];

@@ -92,6 +92,7 @@ struct Desc {
   double *scr;               // [K][6 CMAX n] inverse-iteration scratch
   double *wref;              // [K] refined eigenvalues
   double2 *Tm;               // [cdiv(n - 1, NBK)][NBK][NBK] block-reflector factors T
+  int32_t *clo;              // [n] first index of each eigenvalue's cluster in the weights
   // two-stage reduction (full -> band of width SBW -> tridiagonal); null
   // unless the block takes that path
   double2 *pb;               // [n][SBW] current panel, FP64 (reflectors below its diagonal)
@@ -325,6 +326,7 @@ inline size_t ws_layout(int64_t n, bool a_fp64, Desc *w, char *base, int64_t K =
     t.scr = (double *)take(size_t(K) * (6 * CMAX) * n * 8);
     t.wref = (double *)take(size_t(K) * 8);
     t.Tm = (double2 *)take(size_t(std::max<int64_t>(cdiv(n - 1, NBK), 1)) * NBK * NBK * 16);
+    t.clo = (int32_t *)take(size_t(n) * 4);
   }
   if (two_stage) {  // appended, so the regions above keep their offsets
     const size_t nw = size_t(g_sb_nw(n));

@@ -393,6 +393,7 @@ int run(int64_t n, bool a64, int64_t K) {
     C.add("scr", D.scr, 8, K * 6 * CMAX * n);
     C.add("wref", D.wref, 8, K);
     C.add("Tm", D.Tm, 16, std::max<int64_t>(cdiv(n - 1, NBK), 1) * NBK * NBK);
+    C.add("clo", D.clo, 4, n);
   }
   C.layout_ok();
   if (D.ldys != n || D.lda < n || D.ldv < n || D.lda % 16 || D.ldv % 64) {
@@ -551,6 +552,7 @@ int run(int64_t n, bool a64, int64_t K) {
   C.range("status", 0, 4, "k_tri_prep");
   C.range("bgrid", 0, NGRID, "k_bisect_grid");
   if (K > 0) {
+    C.range("clo", 0, n, "k_weights (clusters), k_invit, k_rq_fin");
     C.range("Z", 0, K * n, "k_invit");
     C.range("scr", 0, K * 6 * CMAX * n, "k_invit");
     if (!two) C.range("Tm", 0, std::max<int64_t>(cdiv(n - 1, NBK), 1) * NBK * NBK, "k_bx_tmat");
