@@ -289,7 +289,9 @@ int32_t bse_dipole_weights(const bse_problem *p, const void *B, int32_t nblk,
  * workspace (n > 2049).
  * nrefine = K in 0 .. 256: FP64 refinement of the lowest min(K, n)
  * eigenvalues against the stored Hmu: inverse iteration on T (members of a
- * degenerate cluster orthogonalised), back-transformation through the kept
+ * cluster orthogonalised; the clusters are those of the optical weights:
+ * gaps within 8 eps sqrt(n) |T| of the working storage, split at FP64
+ * resolution where such a chain is wide), back-transformation through the kept
  * reflectors and the Rayleigh quotient Re(x^dag Hmu x) / |x|^2, which is exact
  * to O(delta^2 |Hmu|) for an eigenvector error delta; omega[0 .. K) then holds
  * the refined values (ascending) and the poles of clusters inside that range
