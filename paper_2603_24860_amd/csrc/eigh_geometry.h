@@ -231,13 +231,9 @@ __host__ __device__ __forceinline__ int64_t g_bc_ilo(int64_t n, int64_t t) {
 }
 __host__ __device__ __forceinline__ int64_t g_bc_tmax(int64_t n) { return n < 2 ? -1 : 2 * (n - 2); }
 // stored chase reflectors: sweep i covers rows i + 1 .. n - 1 (its tasks'
-// row blocks, in order), packed after the sweeps before it; most tasks of a
-// sweep
+// row blocks, in order), packed after the sweeps before it
 __host__ __device__ __forceinline__ int64_t g_bc_off(int64_t n, int64_t i) {
   return i * (n - 1) - i * (i - 1) / 2;
-}
-__host__ __device__ __forceinline__ int64_t g_bc_nks(int64_t n) {
-  return n < 2 ? 1 : (n - 2) / SBW + 1;
 }
 // panels of stage 1 (columns j0 = p SBW with rows below the band)
 __host__ __device__ __forceinline__ int64_t g_sb_npan(int64_t n) {
