@@ -2177,40 +2177,43 @@ __global__ __launch_bounds__(ENT) void k_backxf(Desc D) {
 // then the initial reflection.  Per panel two launches over (row blocks of
 // BPR rows) x (groups of BPV vectors), so every compute unit takes part and
 // the panel's reflectors are read once per launch for BPV vectors:
-//   k_bp_part   partial w = V^dag x over the block's rows (thread (c, g):
-//               column c, rows g, g + 8, ...; the eight row groups of a
-//               column summed by xor shuffles)
+//   k_bp_part   partial w = V^dag x over the block's rows (the block's x
+//               staged in LDS; thread (c, g): column c, rows g, g + 8, ...;
+//               the eight row groups of a column summed by xor shuffles)
 //   k_bp_apply  w summed over the blocks, s = T w, x -= V s over the block's
 //               rows (one row per thread at a time)
 // The panel's reflector c is stored with its zeros and unit entry over the
 // panel's m rows (column c of [SBW][m]), and T is upper triangular.
 __global__ __launch_bounds__(ENT) void k_bp_part(Desc D, int64_t p) {
   static_assert(ENT == SBW * 8, "k_bp_part: eight row groups per column");
+  constexpr int U = 8;  // rows of a thread with their loads in flight together
+  static_assert(BPR % (8 * U) == 0, "k_bp_part: whole rounds of rows");
+  __shared__ double2 xs[BPV][BPR];  // the block's rows of the group's vectors
   const int64_t n = D.n, K = D.K, j0 = p * SBW, p0 = j0 + SBW, m = n - p0;
   const int64_t rb = int64_t(blockIdx.x) * BPR, l0 = int64_t(blockIdx.y) * BPV;
+  const int64_t rend = std::min<int64_t>(rb + BPR, m);
   const int tid = threadIdx.x, c = tid / 8, g = tid % 8;
-  const double2 *V = D.vrow + g_sb_voff(n, p) * SBW + c * m;
-  const double2 *x[BPV];
+  // rows past the block (or past m) are staged as zeros and read from its last row
 #pragma unroll
-  for (int v = 0; v < BPV; ++v) x[v] = D.X + size_t(std::min<int64_t>(l0 + v, K - 1)) * n + p0;
+  for (int u = 0; u < BPV * BPR / ENT; ++u) {
+    const int e = tid + ENT * u, v = e / BPR, rr = e % BPR;
+    const double2 *x = D.X + size_t(std::min<int64_t>(l0 + v, K - 1)) * n + p0;
+    const double2 xv = x[std::min<int64_t>(rb + rr, rend - 1)];
+    xs[v][rr] = csel(rb + rr < rend, xv, double2{0, 0});
+  }
+  __syncthreads();
+  const double2 *V = D.vrow + g_sb_voff(n, p) * SBW + c * m;
   double2 w[BPV];
 #pragma unroll
   for (int v = 0; v < BPV; ++v) w[v] = double2{0, 0};
-  const int64_t rend = std::min<int64_t>(rb + BPR, m);
-  constexpr int U = 4;  // rows of a thread with their loads in flight together
-  for (int64_t r0 = rb + g; r0 < rend; r0 += 8 * U) {
-    double2 vr[U], xv[U][BPV];
+  for (int r0 = g; r0 < BPR; r0 += 8 * U) {
+    double2 vr[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {  // rows past the block read its last row, with v = 0
-      const int64_t r = std::min<int64_t>(r0 + 8 * u, rend - 1);
-      vr[u] = csel(r0 + 8 * u < rend, V[r], double2{0, 0});
-#pragma unroll
-      for (int v = 0; v < BPV; ++v) xv[u][v] = x[v][r];
-    }
+    for (int u = 0; u < U; ++u) vr[u] = V[std::min<int64_t>(rb + r0 + 8 * u, rend - 1)];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < BPV; ++v) w[v] = cadd(w[v], cmulc(vr[u], xv[u][v]));
+      for (int v = 0; v < BPV; ++v) w[v] = cadd(w[v], cmulc(vr[u], xs[v][r0 + 8 * u]));
   }
 #pragma unroll
   for (int v = 0; v < BPV; ++v)
@@ -2226,13 +2229,21 @@ __global__ __launch_bounds__(ENT) void k_bp_part(Desc D, int64_t p) {
   }
 }
 
-__global__ __launch_bounds__(ENT) void k_bp_apply(Desc D, int64_t p) {
-  __shared__ double2 ws_[BPV][SBW], ss[SBW][BPV];
+constexpr int BPT = 512;  // threads of k_bp_apply: one block row each
+__global__ __launch_bounds__(BPT) void k_bp_apply(Desc D, int64_t p) {
+  __shared__ double2 ws_[BPV][SBW], ss[SBW][BPV], Ts[SBW][SBW + 1];
   const int64_t n = D.n, K = D.K, j0 = p * SBW, p0 = j0 + SBW, m = n - p0;
   const int64_t rb = int64_t(blockIdx.x) * BPR, l0 = int64_t(blockIdx.y) * BPV;
   const int64_t nb = cdiv(m, BPR);
   const int tid = threadIdx.x;
-  const double2 *T = D.Tm + size_t(p) * SBW * SBW;
+  {  // the panel's T into LDS, its loads in flight with the partial sums below
+    const double2 *T = D.Tm + size_t(p) * SBW * SBW;
+#pragma unroll
+    for (int u = 0; u < SBW * SBW / BPT; ++u) {
+      const int e = tid + BPT * u;
+      Ts[e / SBW][e % SBW] = T[e];
+    }
+  }
   if (tid < BPV * SBW) {  // w of vector v, entry c: the sum over the row blocks
     const int v = tid / SBW, c = tid % SBW;
     const int64_t l = std::min<int64_t>(l0 + v, K - 1);
@@ -2251,7 +2262,7 @@ __global__ __launch_bounds__(ENT) void k_bp_apply(Desc D, int64_t p) {
   if (tid < BPV * SBW) {  // s = T w (T upper triangular)
     const int v = tid / SBW, c = tid % SBW;
     double2 a = {0, 0};
-    for (int e = c; e < SBW; ++e) a = cadd(a, cmul(T[c * SBW + e], ws_[v][e]));
+    for (int e = c; e < SBW; ++e) a = cadd(a, cmul(Ts[c][e], ws_[v][e]));
     ss[c][v] = a;
   }
   __syncthreads();
@@ -2260,7 +2271,7 @@ __global__ __launch_bounds__(ENT) void k_bp_apply(Desc D, int64_t p) {
 #pragma unroll
   for (int v = 0; v < BPV; ++v) x[v] = D.X + size_t(std::min<int64_t>(l0 + v, K - 1)) * n + p0;
   const int64_t rend = std::min<int64_t>(rb + BPR, m);
-  for (int64_t r = rb + tid; r < rend; r += ENT) {
+  for (int64_t r = rb + tid; r < rend; r += BPT) {
     double2 a[BPV];
 #pragma unroll
     for (int v = 0; v < BPV; ++v) a[v] = double2{0, 0};
@@ -2596,7 +2607,7 @@ int32_t eigh_run_2s(int64_t n, const void *Hmu, int64_t ld, const void *Bmu, dou
     for (int64_t p = g_sb_npan(n) - 1; p >= 0; --p) {
       const dim3 g((unsigned)cdiv(n - SBW * (p + 1), BPR), (unsigned)cdiv(K, BPV));
       BSE_LAUNCH("k_bp_part", k_bp_part, g, dim3(ENT), 0, s, D, p);
-      BSE_LAUNCH("k_bp_apply", k_bp_apply, g, dim3(ENT), 0, s, D, p);
+      BSE_LAUNCH("k_bp_apply", k_bp_apply, g, dim3(BPT), 0, s, D, p);
     }
     BSE_LAUNCH("k_bx_q0", k_bx_q0, dim3((unsigned)K), dim3(ENT), 0, s, D);
     BSE_LAUNCH("k_hx_part", k_hx_part<TH>, dim3((unsigned)cdiv(n, HXR), (unsigned)cdiv(K, HXV)),
