@@ -2333,19 +2333,30 @@ __global__ __launch_bounds__(ENT) void k_hx_part(Desc D) {
   for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int v = 0; v < HXV; ++v) yr[q][v] = yi[q][v] = 0;
-  for (int64_t c = lane; c < n; c += 64) {
-    double2 a[RW], b[HXV];
+  constexpr int CU = 4;  // columns per lane with their loads in flight together
+  for (int64_t c0 = lane; c0 < n; c0 += 64 * CU) {
+    double2 a[CU][RW], b[CU][HXV];
 #pragma unroll
-    for (int q = 0; q < RW; ++q) a[q] = to_d2(h[q][c]);
+    for (int u = 0; u < CU; ++u) {  // columns past n read column n - 1 and are dropped
+      const int64_t c = std::min<int64_t>(c0 + 64 * u, n - 1);
 #pragma unroll
-    for (int v = 0; v < HXV; ++v) b[v] = x[v][c];
+      for (int q = 0; q < RW; ++q) a[u][q] = to_d2(h[q][c]);
 #pragma unroll
-    for (int q = 0; q < RW; ++q)
+      for (int v = 0; v < HXV; ++v) b[u][v] = x[v][c];
+    }
 #pragma unroll
-      for (int v = 0; v < HXV; ++v) {
-        yr[q][v] += a[q].x * b[v].x - a[q].y * b[v].y;
-        yi[q][v] += a[q].x * b[v].y + a[q].y * b[v].x;
+    for (int u = 0; u < CU; ++u) {
+      const double f = c0 + 64 * u < n ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+        const double ax = f * a[u][q].x, ay = f * a[u][q].y;
+#pragma unroll
+        for (int v = 0; v < HXV; ++v) {
+          yr[q][v] += ax * b[u][v].x - ay * b[u][v].y;
+          yi[q][v] += ax * b[u][v].y + ay * b[u][v].x;
+        }
       }
+    }
   }
   // Re(conj(x_r) y_r) and |x_r|^2 over this wave's rows, on every lane
   double num[HXV], den[HXV];
